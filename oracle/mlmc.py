@@ -1,0 +1,394 @@
+"""ctypes binding of the oracle's C code, the MLMC combine and Algorithm 1.
+
+TEST INFRASTRUCTURE (see oracle/__init__.py): never imported by the product path.
+
+Paper sections followed:
+  - the telescoping estimator x^L = E[P_l0] + sum_{l>l0} E[P_l - P_{l-1}] and its
+    sample form (section 2.2, the MLMC estimate);
+  - m_l and V_l per level from the samples (Algorithm 2's accumulators, read as the
+    sample mean and the sample variance mean(Y^2) - mean(Y)^2);
+  - Algorithm 1 (pilot run, optimal sample sizes, add a level until the error is
+    below epsilon), with the optimal sample size read in Giles' form
+    M_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k)) and the error test read
+    as Giles' variance and bias test with weak order alpha = 2 (the Strang splitting
+    order of section 4).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+            _build.build()
+        _lib = ctypes.CDLL(path)
+        _declare(_lib)
+    return _lib
+
+
+def _p(t):
+    return ctypes.POINTER(t)
+
+
+def _declare(L):
+    L.orc_philox4x32_10.argtypes = [_p(ctypes.c_uint32), _p(ctypes.c_uint32), _p(ctypes.c_uint32)]
+    L.orc_philox4x32_10.restype = None
+    L.orc_log.argtypes = [ctypes.c_double]
+    L.orc_log.restype = ctypes.c_double
+    L.orc_uniform.argtypes = [ctypes.c_uint32]
+    L.orc_uniform.restype = ctypes.c_double
+    L.orc_decompose.argtypes = [ctypes.c_int64, _p(ctypes.c_int64), _p(ctypes.c_int32),
+                                _p(ctypes.c_double), _p(ctypes.c_double), _p(ctypes.c_double),
+                                _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_int32),
+                                _p(ctypes.c_int32), _p(ctypes.c_uint8), _p(ctypes.c_uint32),
+                                _p(ctypes.c_int32)]
+    L.orc_decompose.restype = ctypes.c_int
+    tables = [_p(ctypes.c_double), _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_int32),
+              _p(ctypes.c_int32), _p(ctypes.c_uint8), _p(ctypes.c_uint32), _p(ctypes.c_int32)]
+    L.orc_walk_trace.argtypes = tables + [ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
+                                          ctypes.c_uint32, ctypes.c_int64, _p(ctypes.c_int64),
+                                          _p(ctypes.c_uint32), _p(ctypes.c_int64),
+                                          _p(ctypes.c_int32), _p(ctypes.c_int64),
+                                          _p(ctypes.c_uint64), _p(ctypes.c_double),
+                                          _p(ctypes.c_double)]
+    L.orc_walk_trace.restype = None
+    L.orc_level_sums.argtypes = tables + [ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_uint64, ctypes.c_uint32, _p(ctypes.c_double),
+                                          ctypes.c_int32, ctypes.c_int64, _p(ctypes.c_int64),
+                                          ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
+                                          _p(ctypes.c_double), _p(ctypes.c_double),
+                                          _p(ctypes.c_int64), ctypes.c_int32]
+    L.orc_level_sums.restype = None
+    L.orc_log_array.argtypes = [ctypes.c_int64, _p(ctypes.c_double), _p(ctypes.c_double)]
+    L.orc_log_array.restype = None
+    L.orc_philox_array.argtypes = [ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_uint32),
+                                   _p(ctypes.c_uint32)]
+    L.orc_philox_array.restype = None
+    L.orc_max_threads.argtypes = []
+    L.orc_max_threads.restype = ctypes.c_int
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(_p(t))
+
+
+# ----------------------------------------------------------------------------------
+# primitives
+# ----------------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                            _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def log(x: float) -> float:
+    return lib().orc_log(float(x))
+
+
+def log_array(x) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib().orc_log_array(x.size, _ptr(x, ctypes.c_double), _ptr(out, ctypes.c_double))
+    return out
+
+
+def philox_array(ctr, key) -> np.ndarray:
+    """ctr: (q, 4) uint32, key: (q, 2) uint32 -> (q, 4) uint32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    out = np.zeros_like(c)
+    lib().orc_philox_array(c.shape[0], _ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                           _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def uniform(w: int) -> float:
+    return lib().orc_uniform(int(w))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
+
+
+# ----------------------------------------------------------------------------------
+# decomposition A = D - T (section 2.1)
+# ----------------------------------------------------------------------------------
+@dataclass
+class Tables:
+    n: int
+    r: np.ndarray
+    d: np.ndarray
+    inv_r: np.ndarray
+    slot_begin: np.ndarray
+    deg: np.ndarray
+    slot_col: np.ndarray
+    slot_sign: np.ndarray
+    slot_thr: np.ndarray
+    slot_alias: np.ndarray
+
+    def args(self):
+        return (_ptr(self.d, ctypes.c_double), _ptr(self.inv_r, ctypes.c_double),
+                _ptr(self.slot_begin, ctypes.c_int64), _ptr(self.deg, ctypes.c_int32),
+                _ptr(self.slot_col, ctypes.c_int32), _ptr(self.slot_sign, ctypes.c_uint8),
+                _ptr(self.slot_thr, ctypes.c_uint32), _ptr(self.slot_alias, ctypes.c_int32))
+
+
+def decompose(n: int, row_ptr, col, val) -> Tables:
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    nnz = int(row_ptr[-1])
+    r = np.zeros(n, np.float64)
+    d = np.zeros(n, np.float64)
+    inv_r = np.zeros(n, np.float64)
+    slot_begin = np.zeros(n + 1, np.int64)
+    deg = np.zeros(n, np.int32)
+    slot_col = np.zeros(max(nnz, 1), np.int32)
+    slot_sign = np.zeros(max(nnz, 1), np.uint8)
+    slot_thr = np.zeros(max(nnz, 1), np.uint32)
+    slot_alias = np.zeros(max(nnz, 1), np.int32)
+    rc = lib().orc_decompose(n, _ptr(row_ptr, ctypes.c_int64), _ptr(col, ctypes.c_int32),
+                             _ptr(val, ctypes.c_double), _ptr(r, ctypes.c_double),
+                             _ptr(d, ctypes.c_double), _ptr(inv_r, ctypes.c_double),
+                             _ptr(slot_begin, ctypes.c_int64), _ptr(deg, ctypes.c_int32),
+                             _ptr(slot_col, ctypes.c_int32), _ptr(slot_sign, ctypes.c_uint8),
+                             _ptr(slot_thr, ctypes.c_uint32), _ptr(slot_alias, ctypes.c_int32))
+    if rc != 0:
+        raise MemoryError("oracle decomposition failed")
+    return Tables(n, r, d, inv_r, slot_begin, deg, slot_col, slot_sign, slot_thr, slot_alias)
+
+
+def default_l0(tables: Tables, beta: float) -> int:
+    """Coarsest level from the paper's practical rule l0 = log2(2 beta d_max) (section 4),
+    read with the jump rate r_i = L_ii in place of d_i and rounded up:
+    l0 = max(0, ceil(log2(2 beta max_i r_i))), so that dt_l0 * r_max <= 1/2."""
+    rmax = float(tables.r.max()) if tables.n else 0.0
+    if rmax <= 0.0 or beta <= 0.0:
+        return 0
+    return max(0, int(math.ceil(math.log2(2.0 * beta * rmax))))
+
+
+# ----------------------------------------------------------------------------------
+# walks and level sums (Algorithm 2)
+# ----------------------------------------------------------------------------------
+@dataclass
+class Trace:
+    final_state: np.ndarray
+    sign: np.ndarray
+    jumps: np.ndarray
+    hash: np.ndarray
+    eta_fine: np.ndarray
+    eta_coarse: np.ndarray
+
+
+def walk_trace(t: Tables, beta: float, level: int, seed: int, rows, walks, instance: int = 0
+               ) -> Trace:
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    walks = np.ascontiguousarray(walks, dtype=np.uint32)
+    q = rows.size
+    assert walks.size == q
+    out = Trace(np.zeros(q, np.int64), np.zeros(q, np.int32), np.zeros(q, np.int64),
+                np.zeros(q, np.uint64), np.zeros(q, np.float64), np.zeros(q, np.float64))
+    lib().orc_walk_trace(*t.args(), float(beta), int(level), int(seed), int(instance), q,
+                         _ptr(rows, ctypes.c_int64), _ptr(walks, ctypes.c_uint32),
+                         _ptr(out.final_state, ctypes.c_int64), _ptr(out.sign, ctypes.c_int32),
+                         _ptr(out.jumps, ctypes.c_int64), _ptr(out.hash, ctypes.c_uint64),
+                         _ptr(out.eta_fine, ctypes.c_double),
+                         _ptr(out.eta_coarse, ctypes.c_double))
+    return out
+
+
+@dataclass
+class LevelSums:
+    sum1: np.ndarray   # (n_rows, R)
+    sum2: np.ndarray   # (n_rows, R)
+    mass: np.ndarray   # (n_rows, R)
+    jumps: np.ndarray  # (n_rows,)
+    walks: int
+    steps_per_walk: int
+
+
+def level_sums(t: Tables, beta: float, level: int, l0: int, seed: int, u, rows=None,
+               walk0: int = 0, M: int = 1, instance: int = 0, threads: int = 0) -> LevelSums:
+    u = np.asarray(u, dtype=np.float64)
+    if u.ndim == 1:
+        u = u[:, None]
+    u = np.ascontiguousarray(u)
+    R = u.shape[1]
+    rows = np.arange(t.n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
+    nr = rows.size
+    s1 = np.zeros((nr, R), np.float64)
+    s2 = np.zeros((nr, R), np.float64)
+    ms = np.zeros((nr, R), np.float64)
+    jp = np.zeros(nr, np.int64)
+    lib().orc_level_sums(*t.args(), float(beta), int(level), int(l0), int(seed), int(instance),
+                         _ptr(u, ctypes.c_double), R, nr, _ptr(rows, ctypes.c_int64),
+                         int(walk0), int(M), _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
+                         _ptr(ms, ctypes.c_double), _ptr(jp, ctypes.c_int64), int(threads))
+    return LevelSums(s1, s2, ms, jp, int(M), 1 << int(level))
+
+
+# ----------------------------------------------------------------------------------
+# the MLMC estimator with a fixed schedule (section 2.2)
+# ----------------------------------------------------------------------------------
+@dataclass
+class LevelStats:
+    level: int
+    M: int
+    s1: np.ndarray
+    s2: np.ndarray
+    mass: np.ndarray
+    jumps: int
+
+    @property
+    def mean(self) -> np.ndarray:          # m_{l,i}
+        return self.s1 / self.M
+
+    @property
+    def var(self) -> np.ndarray:           # V_{l,i} = mean(Y^2) - mean(Y)^2
+        m = self.s1 / self.M
+        return np.maximum(self.s2 / self.M - m * m, 0.0)
+
+
+@dataclass
+class Result:
+    x: np.ndarray                      # (n_rows, R)
+    levels: list = field(default_factory=list)
+    l0: int = 0
+    mass: np.ndarray | None = None     # sum_l mean_w |u|(|eta_f| + |eta_c|)
+    steps: int = 0
+    jumps: int = 0
+
+    def est_mse(self) -> float:
+        """Row-mean estimated variance of the estimator: sum_l mean_i V_{l,i} / M_l."""
+        return float(sum(np.mean(L.var) / L.M for L in self.levels))
+
+
+def mlmc_fixed(t: Tables, beta: float, u, l0: int, L: int, M, seed: int, rows=None,
+               instance: int = 0, threads: int = 0) -> Result:
+    """x^L estimate with M[l - l0] walks per row at level l, l = l0..L."""
+    levels = []
+    x = None
+    mass = None
+    steps = 0
+    jumps = 0
+    for q, lev in enumerate(range(l0, L + 1)):
+        Ml = int(M[q]) if np.ndim(M) else int(M)
+        ls = level_sums(t, beta, lev, l0, seed, u, rows, 0, Ml, instance, threads)
+        st = LevelStats(lev, Ml, ls.sum1, ls.sum2, ls.mass, int(ls.jumps.sum()))
+        levels.append(st)
+        x = st.mean if x is None else x + st.mean
+        mass = ls.mass / Ml if mass is None else mass + ls.mass / Ml
+        steps += Ml * (1 << lev) * ls.sum1.shape[0]
+        jumps += st.jumps
+    return Result(x, levels, l0, mass, steps, jumps)
+
+
+# ----------------------------------------------------------------------------------
+# Algorithm 1 (adaptive driver)
+# ----------------------------------------------------------------------------------
+JUMP_COST = 4.0     # cost model C_l = N_l + JUMP_COST * (mean jumps per walk)
+ALPHA = 2.0         # weak order of the Strang splitting
+
+
+def optimal_M(V, C, eps):
+    """Giles' optimal sample sizes for a variance budget eps^2 / 2."""
+    V = np.asarray(V, np.float64)
+    C = np.asarray(C, np.float64)
+    tot = float(np.sum(np.sqrt(V * C)))
+    return np.ceil(2.0 * eps ** -2 * np.sqrt(V / C) * tot).astype(np.int64)
+
+
+def bias_estimate(mL: float, mLm1: float) -> float:
+    """Extrapolated bias of the finest level, from the RMS level means of the two
+    finest levels with weak order alpha."""
+    return max(abs(mL), abs(mLm1) / 2.0 ** ALPHA) / (2.0 ** ALPHA - 1.0)
+
+
+@dataclass
+class _Acc:
+    M: int
+    s1: np.ndarray
+    s2: np.ndarray
+    mass: np.ndarray
+    jumps: int
+
+
+def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | None = None,
+                  pilot: int = 256, max_levels: int = 20, rows=None, instance: int = 0,
+                  threads: int = 0, max_walks: int | None = None):
+    """Algorithm 1: pilot M0 walks on levels l0..l0+4, then repeat {optimal M_l; run the
+    extra walks; stop when the variance and bias tests pass, else add a level}."""
+    if l0 is None:
+        l0 = default_l0(t, beta)
+    L = l0 + 4
+    acc: dict[int, _Acc] = {}
+
+    def run(lev, extra):
+        prev = acc.get(lev)
+        w0 = prev.M if prev else 0
+        ls = level_sums(t, beta, lev, l0, seed, u, rows, w0, extra, instance, threads)
+        if prev is None:
+            acc[lev] = _Acc(extra, ls.sum1, ls.sum2, ls.mass, int(ls.jumps.sum()))
+        else:
+            prev.M += extra
+            prev.s1 = prev.s1 + ls.sum1
+            prev.s2 = prev.s2 + ls.sum2
+            prev.mass = prev.mass + ls.mass
+            prev.jumps += int(ls.jumps.sum())
+
+    for lev in range(l0, L + 1):
+        run(lev, pilot)
+    converged = False
+    while True:
+        levs = list(range(l0, L + 1))
+        nrows = acc[l0].s1.shape[0]
+        V = []
+        C = []
+        for lev in levs:
+            a = acc[lev]
+            m = a.s1 / a.M
+            V.append(max(float(np.mean(np.maximum(a.s2 / a.M - m * m, 0.0))), 1e-300))
+            C.append((1 << lev) + JUMP_COST * a.jumps / (a.M * nrows))
+        Mopt = optimal_M(V, C, eps)
+        for lev, Mo in zip(levs, Mopt):
+            extra = int(Mo) - acc[lev].M
+            if max_walks is not None:
+                extra = min(extra, max_walks - acc[lev].M)
+            if extra > 0:
+                run(lev, extra)
+        var = sum(float(np.mean(np.maximum(acc[l].s2 / acc[l].M - (acc[l].s1 / acc[l].M) ** 2,
+                                           0.0))) / acc[l].M for l in levs)
+        rms = lambda l: float(np.sqrt(np.mean((acc[l].s1 / acc[l].M) ** 2)))
+        bias = bias_estimate(rms(L), rms(L - 1))
+        if var <= eps * eps / 2.0 * 1.0000001 and bias <= eps / math.sqrt(2.0):
+            converged = True
+            break
+        if L - l0 + 1 >= max_levels:
+            break
+        L += 1
+        run(L, pilot)
+    levels = [LevelStats(l, acc[l].M, acc[l].s1, acc[l].s2, acc[l].mass, acc[l].jumps)
+              for l in range(l0, L + 1)]
+    x = sum(st.mean for st in levels)
+    mass = sum(st.mass / st.M for st in levels)
+    nrows = levels[0].s1.shape[0]
+    steps = sum(st.M * (1 << st.level) * nrows for st in levels)
+    res = Result(x, levels, l0, mass, steps, sum(st.jumps for st in levels))
+    res.converged = converged
+    return res

@@ -1,0 +1,417 @@
+/*
+ * Oracle for the multilevel Monte Carlo (MLMC) estimator of x = exp(beta*A) u of
+ * Acebron, Herrero & Monteiro, "A highly parallel algorithm for computing the action
+ * of a matrix exponential on a vector based on a multilevel Monte Carlo method"
+ * (arXiv:1904.12754).
+ *
+ * TEST INFRASTRUCTURE. This file is a plain, slow CPU implementation that the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark use to check the GPU
+ * library. Nothing in the product path may link, load or call it. It shares no code
+ * with the GPU library: the random-number generator, the logarithm, the
+ * decomposition, the alias tables and the walk are all written here independently
+ * from the paper and from the published definitions named below.
+ *
+ * Arithmetic: FP64 throughout, no contraction (build with -ffp-contract=off); the
+ * fused multiply-adds in the logarithm are explicit calls to C99 fma(), which is
+ * correctly rounded.
+ *
+ * What is computed, and where the paper defines it:
+ *   - decomposition A = D - T (section 2.1, the definitions of L, d, sigma and T);
+ *   - the jump law k_ij = |L_ij| / L_ii and exponential holding times of rate L_ii
+ *     (section 3, the integral form of the backward equation);
+ *   - the coupled fine/coarse path functional of one sample (Algorithm 2, with the
+ *     level terms of the telescoping sum, section 2.2);
+ *   - per-row level sums of Y and Y^2 that give m_l and V_l (Algorithm 2's
+ *     accumulators; the variance read as mean(Y^2) - mean(Y)^2).
+ *
+ * Readings of the paper taken here (each is listed in the design notes):
+ *   - the holding time S after a jump has the rate of the state jumped TO;
+ *   - the final factor uses u at the final state of the path;
+ *   - the base level l0 contributes u*eta_fine only (P_{l0-1} = 0);
+ *   - N = 2^l steps of length dt = beta / 2^l at level l;
+ *   - levels draw independent random streams; within a level the fine and the coarse
+ *     functional share one path.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------------ */
+/* Philox4x32-10: J. K. Salmon, M. A. Moraes, R. O. Dror, D. E. Shaw, "Parallel    */
+/* random numbers: as easy as 1, 2, 3", SC'11. Ten rounds of the 4x32 S-box with   */
+/* multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments 0x9E3779B9 /        */
+/* 0xBB67AE85 (the key is bumped between rounds).                                  */
+/* ------------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Random stream layout. Key = the 64-bit seed (low word first). Counter =
+ * (index, walk, row, level<<26 | instance<<14 | stream). Stream 0 holds the step
+ * tests: step n (0-based) of a walk reads word n%4 of block n/4. Stream 1 holds the
+ * jumps: the walk's j-th jump (0-based over the whole walk) reads block j, words
+ * 0 (slot), 1 (alias coin) and 2 (the next holding time). */
+static uint32_t c3_of(int level, uint32_t instance, uint32_t stream)
+{
+    return ((uint32_t)level << 26) | ((instance & 0xFFFu) << 14) | stream;
+}
+
+static uint32_t step_word(const uint32_t key[2], int level, uint32_t inst, uint32_t row,
+                          uint32_t walk, uint32_t n)
+{
+    uint32_t ctr[4] = {n >> 2, walk, row, c3_of(level, inst, 0)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[n & 3u];
+}
+
+static void jump_words(const uint32_t key[2], int level, uint32_t inst, uint32_t row,
+                       uint32_t walk, uint32_t j, uint32_t w[3])
+{
+    uint32_t ctr[4] = {j, walk, row, c3_of(level, inst, 1)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    w[0] = out[0]; w[1] = out[1]; w[2] = out[2];
+}
+
+/* A 32-bit word as a uniform variate on the open interval (0, 1): (w + 1/2) 2^-32.
+ * It is exact in FP64 and never 0 or 1, so its logarithm is finite and negative. */
+double orc_uniform(uint32_t w)
+{
+    return ((double)w + 0.5) * 0x1p-32;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Natural logarithm on (0, 1), from the series                                    */
+/*     ln m = 2 (s + s^3/3 + s^5/5 + ...),  s = (m - 1) / (m + 1)                  */
+/* (Abramowitz & Stegun, Handbook of Mathematical Functions, 4.1.27), after the    */
+/* reduction x = m 2^e with m in [sqrt(2)/2, sqrt(2)]. Twelve terms reach FP64     */
+/* precision since s^2 <= 0.0295 there. ln 2 is split into a 29-bit head (so that  */
+/* e * head is exact) and a tail.                                                  */
+/* ------------------------------------------------------------------------------ */
+double orc_log(double x)
+{
+    static const double ln2_head = 0x1.62e42ffp-1;
+    static const double ln2_tail = -0x1.718432a1b0e26p-35;
+    static const double sqrt2 = 0x1.6a09e667f3bcdp+0;
+    int e;
+    double m = frexp(x, &e);     /* x = m 2^e, m in [1/2, 1) */
+    m = m * 2.0;                 /* m in [1, 2) */
+    e = e - 1;
+    if (m > sqrt2) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    /* coefficients 1/(2k+1), k = 0..11, Horner in z from the highest term */
+    double p = 1.0 / 23.0;
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    double b = 2.0 * (s * p);
+    double de = (double)e;
+    return de * ln2_head + (de * ln2_tail + b);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Decomposition A = D - T (section 2.1).                                          */
+/*   L_ij = -|a_ij| (j != i),  L_ii = r_i = sum_{j != i} |a_ij|,                   */
+/*   d_i = a_ii + L_ii,        sigma_ij = [a_ij < 0].                              */
+/* The off-diagonal nonzeros of row i, in CSR order, are its "slots"; the jump     */
+/* law from i picks slot k with probability k_ij = |a_ij| / r_i. The law is        */
+/* sampled with a Walker/Vose alias table (A. J. Walker 1977; M. D. Vose, IEEE     */
+/* TSE 17(9), 1991), built as below and stored with 32-bit thresholds.             */
+/* ------------------------------------------------------------------------------ */
+int orc_decompose(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                  double *r, double *d, double *inv_r, int64_t *slot_begin, int32_t *deg,
+                  int32_t *slot_col, uint8_t *slot_sign, uint32_t *slot_thr,
+                  int32_t *slot_alias)
+{
+    int64_t s = 0;
+    double *q = NULL;
+    int32_t *small = NULL, *large = NULL;
+    int64_t maxdeg = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t len = row_ptr[i + 1] - row_ptr[i];
+        if (len > maxdeg) maxdeg = len;
+    }
+    q = (double *)malloc(sizeof(double) * (size_t)(maxdeg + 1));
+    small = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    large = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    if (!q || !small || !large) {
+        free(q); free(small); free(large);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double diag = 0.0, ri = 0.0;
+        int32_t k = 0;
+        slot_begin[i] = s;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col[e] == i) {
+                diag += val[e];
+            } else if (val[e] != 0.0) {
+                ri += fabs(val[e]);
+                slot_col[s + k] = col[e];
+                slot_sign[s + k] = (uint8_t)(val[e] < 0.0);
+                ++k;
+            }
+        }
+        deg[i] = k;
+        r[i] = ri;
+        d[i] = diag + ri;
+        inv_r[i] = (ri > 0.0) ? 1.0 / ri : INFINITY;
+        /* alias table: scaled probabilities q_k = |a_k| * deg / r */
+        int32_t ns = 0, nl = 0;
+        {
+            int32_t kk = 0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                if (col[e] == i || val[e] == 0.0) continue;
+                q[kk] = (fabs(val[e]) * (double)k) / ri;
+                if (q[kk] < 1.0) small[ns++] = kk; else large[nl++] = kk;
+                ++kk;
+            }
+        }
+        while (ns > 0 && nl > 0) {
+            int32_t a = small[--ns];
+            int32_t g = large[--nl];
+            slot_thr[s + a] = (uint32_t)floor(q[a] * 4294967296.0);
+            slot_alias[s + a] = g;
+            q[g] = (q[g] + q[a]) - 1.0;
+            if (q[g] < 1.0) small[ns++] = g; else large[nl++] = g;
+        }
+        while (nl > 0) {
+            int32_t g = large[--nl];
+            slot_thr[s + g] = 0xFFFFFFFFu;
+            slot_alias[s + g] = g;
+        }
+        while (ns > 0) {
+            int32_t a = small[--ns];
+            slot_thr[s + a] = 0xFFFFFFFFu;
+            slot_alias[s + a] = a;
+        }
+        s += k;
+    }
+    slot_begin[n] = s;
+    free(q); free(small); free(large);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* One sample of Algorithm 2 at level `level` (N = 2^level steps of dt = beta/N).  */
+/* ------------------------------------------------------------------------------ */
+typedef struct {
+    const double *d, *inv_r;
+    const int64_t *slot_begin;
+    const int32_t *deg, *slot_col, *slot_alias;
+    const uint8_t *slot_sign;
+    const uint32_t *slot_thr;
+} orc_tables;
+
+typedef struct {
+    int64_t final_state;
+    int32_t sign;            /* +1 / -1: the product of the jump signs */
+    int64_t jumps;
+    uint64_t hash;           /* FNV-1a over (state, step) of every jump */
+    double eta_fine, eta_coarse;
+} orc_walk_out;
+
+#define ORC_FNV_OFFSET 14695981039346656037ull
+#define ORC_FNV_PRIME 1099511628211ull
+
+static void orc_one_walk(const orc_tables *t, double beta, int level, const uint32_t key[2],
+                         uint32_t inst, int64_t row, uint32_t walk, orc_walk_out *o)
+{
+    const int64_t N = (int64_t)1 << level;
+    const double dt = ldexp(beta, -level);
+    double eta2 = 1.0, eta1 = 1.0;   /* fine and coarse functionals */
+    int64_t j = row, jumps = 0;
+    uint64_t h = ORC_FNV_OFFSET;
+    for (int64_t n = 1; n <= N; ++n) {
+        eta2 = eta2 * exp(t->d[j] * dt / 2.0);
+        if (n % 2 != 0) eta1 = eta1 * exp(t->d[j] * dt);
+        /* holding time at the current state: -ln(U) / r_j */
+        double tau = -orc_log(orc_uniform(step_word(key, level, inst, (uint32_t)row, walk,
+                                                    (uint32_t)(n - 1)))) * t->inv_r[j];
+        while (tau < dt) {
+            int64_t k = j;
+            uint32_t w[3];
+            jump_words(key, level, inst, (uint32_t)row, walk, (uint32_t)jumps, w);
+            /* next state from the jump law k_kj (alias table of row k) */
+            uint32_t dg = (uint32_t)t->deg[k];
+            uint32_t slot = (uint32_t)(((uint64_t)w[0] * (uint64_t)dg) >> 32);
+            int64_t sb = t->slot_begin[k];
+            uint32_t pick = (w[1] < t->slot_thr[sb + slot]) ? slot
+                                                             : (uint32_t)t->slot_alias[sb + slot];
+            j = t->slot_col[sb + pick];
+            int neg = t->slot_sign[sb + pick];
+            /* holding time at the new state */
+            double S = -orc_log(orc_uniform(w[2])) * t->inv_r[j];
+            tau = tau + S;
+            if (neg) {
+                eta2 = -eta2;
+                eta1 = -eta1;
+            }
+            ++jumps;
+            h = (h ^ (uint64_t)(uint32_t)j) * ORC_FNV_PRIME;
+            h = (h ^ (uint64_t)n) * ORC_FNV_PRIME;
+        }
+        eta2 = eta2 * exp(t->d[j] * dt / 2.0);
+        if (n % 2 == 0) eta1 = eta1 * exp(t->d[j] * dt);
+    }
+    o->final_state = j;
+    o->sign = (eta2 < 0.0) ? -1 : 1;
+    o->jumps = jumps;
+    o->hash = h;
+    o->eta_fine = eta2;
+    o->eta_coarse = eta1;
+}
+
+/* Trace of individual walks: for each (row[q], walk[q]) the final state, sign, jump
+ * count, path hash and the two functionals. */
+void orc_walk_trace(const double *d, const double *inv_r, const int64_t *slot_begin,
+                    const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
+                    const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                    int level, uint64_t seed, uint32_t instance, int64_t count,
+                    const int64_t *rows, const uint32_t *walks, int64_t *final_state,
+                    int32_t *sign, int64_t *jumps, uint64_t *hash, double *eta_fine,
+                    double *eta_coarse)
+{
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < count; ++q) {
+        orc_walk_out o;
+        orc_one_walk(&t, beta, level, key, instance, rows[q], walks[q], &o);
+        final_state[q] = o.final_state;
+        sign[q] = o.sign;
+        jumps[q] = o.jumps;
+        hash[q] = o.hash;
+        eta_fine[q] = o.eta_fine;
+        eta_coarse[q] = o.eta_coarse;
+    }
+}
+
+/* Neumaier's compensated summation (improved Kahan). */
+typedef struct { double s, c; } orc_sum;
+static void orc_add(orc_sum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Per-row level sums (Algorithm 2's accumulators). For each requested row i and   */
+/* walk w in [walk0, walk0 + M), the sample is                                     */
+/*     Y = u_j (eta_fine - eta_coarse)   (level > l0)                              */
+/*     Y = u_j  eta_fine                 (level = l0)                              */
+/* with j the final state, for each of the R right-hand sides (u is n x R, row     */
+/* major). Outputs per (row, rhs): sum Y, sum Y^2 and the magnitude                */
+/* sum |u_j| (|eta_fine| + |eta_coarse|) (the scale of the rounding in Y); per     */
+/* row: the total jump count, and the total step count M * N.                      */
+/* ------------------------------------------------------------------------------ */
+void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
+                    const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
+                    const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                    int level, int l0, uint64_t seed, uint32_t instance, const double *u,
+                    int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
+                    uint32_t M, double *sum1, double *sum2, double *mass, int64_t *jumps,
+                    int32_t nthreads)
+{
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        orc_sum *a1 = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
+        orc_sum *a2 = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
+        orc_sum *am = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < n_rows; ++q) {
+            int64_t i = rows[q];
+            int64_t nj = 0;
+            memset(a1, 0, sizeof(orc_sum) * (size_t)R);
+            memset(a2, 0, sizeof(orc_sum) * (size_t)R);
+            memset(am, 0, sizeof(orc_sum) * (size_t)R);
+            for (uint32_t w = 0; w < M; ++w) {
+                orc_walk_out o;
+                orc_one_walk(&t, beta, level, key, instance, i, walk0 + w, &o);
+                nj += o.jumps;
+                for (int32_t rr = 0; rr < R; ++rr) {
+                    double uj = u[o.final_state * R + rr];
+                    double y, m;
+                    if (level > l0) {
+                        y = uj * (o.eta_fine - o.eta_coarse);
+                        m = fabs(uj) * (fabs(o.eta_fine) + fabs(o.eta_coarse));
+                    } else {
+                        y = uj * o.eta_fine;
+                        m = fabs(uj) * fabs(o.eta_fine);
+                    }
+                    orc_add(&a1[rr], y);
+                    orc_add(&a2[rr], y * y);
+                    orc_add(&am[rr], m);
+                }
+            }
+            for (int32_t rr = 0; rr < R; ++rr) {
+                sum1[q * R + rr] = a1[rr].s + a1[rr].c;
+                sum2[q * R + rr] = a2[rr].s + a2[rr].c;
+                mass[q * R + rr] = am[rr].s + am[rr].c;
+            }
+            jumps[q] = nj;
+        }
+        free(a1); free(a2); free(am);
+    }
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Vectorised helpers for the tests: log of count values, and the uniform variate of
+ * count words. */
+void orc_log_array(int64_t count, const double *x, double *out)
+{
+    for (int64_t q = 0; q < count; ++q) out[q] = orc_log(x[q]);
+}
+
+void orc_philox_array(int64_t count, const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    for (int64_t q = 0; q < count; ++q) orc_philox4x32_10(ctr + 4 * q, key + 2 * q, out + 4 * q);
+}

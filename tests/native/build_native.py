@@ -1,0 +1,30 @@
+"""Build the host-side helper programs the CPU tests use (not GPU code).
+
+rocrand_philox_ref: rocRAND's Philox4x32-10 engine run on the host, an implementation
+independent of the oracle's, used to pin the oracle's generator.
+"""
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+OUT = os.path.join(ROOT, "_build")
+
+
+def rocrand_ref(force: bool = False) -> str | None:
+    src = os.path.join(HERE, "rocrand_philox_ref.cpp")
+    exe = os.path.join(OUT, "rocrand_philox_ref")
+    if not force and os.path.exists(exe) and os.path.getmtime(exe) >= os.path.getmtime(src):
+        return exe
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        return None
+    os.makedirs(OUT, exist_ok=True)
+    subprocess.check_call([hipcc, "-O1", "-o", exe + ".tmp", src])
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
+if __name__ == "__main__":
+    print(rocrand_ref(force=True))

@@ -1,0 +1,388 @@
+"""Pins of the oracle against facts fixed by the paper, by mathematics or by independent
+implementations. None of these tests touches the GPU library.
+
+Each test names the passage of the paper (or the external definition) it checks, and is
+chosen so that a plausible slip in the oracle fails it: a wrong Philox constant or round
+order (rocRAND cross-check), a wrong logarithm (ulp bound), a wrong sign or rate in the
+decomposition (dense identity A = D - T), a wrong alias table (exact reconstruction of
+the jump law), a wrong holding-time rate or jump law (one-step law against the
+Kolmogorov solution e^{-dt L} and its signed version e^{-dt T}), a dropped weight
+factor or an off-by-one in the fine/coarse coupling (level means against the dense
+Strang products), and a broken combine (rates and error decay).
+"""
+import math
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import mlmc, reference
+from paper_1904_12754_amd import inputs
+from tests.native import build_native
+
+
+# ----------------------------------------------------------------------------------
+# Philox4x32-10 (Salmon et al., SC'11) against rocRAND's independent implementation
+# ----------------------------------------------------------------------------------
+def test_philox_matches_rocrand():
+    exe = build_native.rocrand_ref()
+    if exe is None:
+        pytest.skip("hipcc not available to build the rocRAND reference")
+    rng = np.random.default_rng(7)
+    ctr = rng.integers(0, 2 ** 32, size=(300, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(300, 2), dtype=np.uint64).astype(np.uint32)
+    # the reference is addressed by (seed, subsequence, offset) with offset = 4 (c0 + 2^32 c1),
+    # which must not wrap 64 bits: c1 < 2^30 (walk indices stay far below that)
+    ctr[:, 1] &= (1 << 30) - 1
+    ctr[0] = 0
+    key[0] = 0
+    ctr[1] = [0xFFFFFFFF, (1 << 30) - 1, 0xFFFFFFFF, 0xFFFFFFFF]
+    key[1] = 0xFFFFFFFF
+    # counters of the kind the walks use: small step/walk indices, level/stream bits
+    ctr[2:40, 0] = np.arange(38)
+    ctr[2:40, 3] = (np.arange(38) % 7) << 26 | (np.arange(38) % 2)
+    lines = "\n".join(" ".join(str(int(x)) for x in list(c) + list(k)) for c, k in zip(ctr, key))
+    out = subprocess.run([exe], input=lines, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(t) for t in ln.split()] for ln in out.strip().splitlines()], np.uint64)
+    got = mlmc.philox_array(ctr, key).astype(np.uint64)
+    assert np.array_equal(got, ref)
+
+
+def test_philox_words_uniform_and_counter_sensitive():
+    # chi-square of the top byte over 2^18 words, and single-bit counter flips change
+    # about half of the output bits (avalanche)
+    q = 1 << 16
+    ctr = np.zeros((q, 4), np.uint32)
+    ctr[:, 0] = np.arange(q)
+    ctr[:, 3] = 3 << 26
+    key = np.tile(np.array([12345, 678], np.uint32), (q, 1))
+    w = mlmc.philox_array(ctr, key).reshape(-1)
+    hist = np.bincount(w >> 24, minlength=256)
+    exp = w.size / 256
+    chi2 = float(((hist - exp) ** 2 / exp).sum())
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+    flip = ctr.copy()
+    flip[:, 1] ^= 1
+    w2 = mlmc.philox_array(flip, key)
+    diff = np.unpackbits((w.reshape(-1, 4) ^ w2).view(np.uint8)).mean()
+    assert abs(diff - 0.5) < 0.01
+
+
+# ----------------------------------------------------------------------------------
+# the logarithm behind the exponential holding times (series of A&S 4.1.27)
+# ----------------------------------------------------------------------------------
+def test_log_within_two_ulp_on_the_uniform_grid():
+    rng = np.random.default_rng(11)
+    w = np.concatenate([rng.integers(0, 2 ** 32, size=200_000, dtype=np.uint64),
+                        np.arange(0, 4096, dtype=np.uint64),
+                        2 ** 32 - 1 - np.arange(0, 4096, dtype=np.uint64),
+                        np.uint64(int(2 ** 32 / math.sqrt(2))) + np.arange(-2048, 2048)])
+    x = (w.astype(np.float64) + 0.5) * 2.0 ** -32
+    got = mlmc.log_array(x)
+    ref = np.log(x)
+    ulp = np.array([math.ulp(v) for v in ref])
+    assert np.max(np.abs(got - ref) / ulp) <= 2.0
+    assert np.all(got < 0)
+
+
+def test_log_is_monotone_on_the_uniform_grid():
+    # the integer step thresholds rely on -log(U(w)) decreasing in w
+    rng = np.random.default_rng(12)
+    starts = rng.integers(0, 2 ** 32 - 1024, size=64, dtype=np.uint64)
+    for s in starts:
+        w = s + np.arange(1024, dtype=np.uint64)
+        v = mlmc.log_array((w.astype(np.float64) + 0.5) * 2.0 ** -32)
+        assert np.all(np.diff(v) > 0)
+
+
+# ----------------------------------------------------------------------------------
+# decomposition A = D - T (section 2.1) and the alias tables of the jump law
+# ----------------------------------------------------------------------------------
+def _signed_matrix(n, seed, density=0.5, diag=True):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(n, n)) * (rng.random((n, n)) < density)
+    if not diag:
+        np.fill_diagonal(a, 0.0)
+    return a
+
+
+def test_decomposition_identity_and_fields():
+    a = _signed_matrix(9, 1)
+    a[3, :] = 0.0           # an absorbing row (no off-diagonal)
+    a[3, 3] = -0.7
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    D, T = reference.decomposition(a)
+    assert np.allclose(D - T, a, rtol=0, atol=1e-15)
+    # equal up to the order of the row sums
+    assert np.allclose(t.d, np.diag(D), rtol=1e-14, atol=1e-15)
+    assert np.allclose(t.r, np.diag(T), rtol=1e-14, atol=0)
+    assert t.inv_r[3] == np.inf and t.deg[3] == 0
+    for i in range(C.n):
+        sb, k = t.slot_begin[i], t.deg[i]
+        cols = t.slot_col[sb:sb + k]
+        assert np.all(cols != i)
+        # -T_ij = a_ij and the sign bit is [a_ij < 0]
+        assert np.array_equal(t.slot_sign[sb:sb + k], (a[i, cols] < 0).astype(np.uint8))
+        assert np.allclose(-T[i, cols], a[i, cols])
+
+
+def _alias_law(t, i):
+    """Exact probability of each slot of row i under the jump rule: slot =
+    floor(w deg / 2^32), own column if coin < thr else the alias."""
+    sb, k = int(t.slot_begin[i]), int(t.deg[i])
+    thr = t.slot_thr[sb:sb + k].astype(np.float64) / 2.0 ** 32
+    alias = t.slot_alias[sb:sb + k]
+    edges = np.array([-(-(s * 2 ** 32) // k) for s in range(k + 1)], dtype=np.float64)
+    p_slot = np.diff(edges) / 2.0 ** 32
+    law = np.zeros(k)
+    for s in range(k):
+        law[s] += p_slot[s] * thr[s]
+        law[alias[s]] += p_slot[s] * (1.0 - thr[s])
+    return law
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4])
+def test_alias_tables_reproduce_the_jump_law(seed):
+    rng = np.random.default_rng(seed)
+    n = 40
+    a = _signed_matrix(n, seed, density=0.6)
+    a[0, 1:] = rng.exponential(size=n - 1) ** 3      # a skewed row
+    a[1, :] = 0.0
+    a[1, 2] = 5.0                                      # a single-slot row
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    for i in range(n):
+        k = int(t.deg[i])
+        if k == 0:
+            continue
+        sb = int(t.slot_begin[i])
+        p = np.abs(a[i, t.slot_col[sb:sb + k]]) / t.r[i]
+        assert np.max(np.abs(_alias_law(t, i) - p)) <= 2.0 * k * 2.0 ** -32
+
+
+# ----------------------------------------------------------------------------------
+# the walk's one-step law against the Kolmogorov backward solution (section 2.1)
+# ----------------------------------------------------------------------------------
+def test_one_step_law_matches_the_ctmc_transition_matrix():
+    """A level-0 walk is one step of length beta: its final state follows
+    P(beta) = e^{-beta L} (generator Q = -L), and E[phi 1{X = j}] = (e^{-beta T})_ij.
+    Rates differ per row, so drawing the holding time after a jump with the old
+    state's rate, or a wrong jump law, shows up here."""
+    a = _signed_matrix(6, 21, density=0.8)
+    a[2, :] *= 4.0                                      # uneven jump rates
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    D, T = reference.decomposition(a)
+    L = np.diag(np.diag(T)) - np.abs(T - np.diag(np.diag(T)))
+    beta = 0.9
+    P = scipy.linalg.expm(-beta * L)
+    PT = scipy.linalg.expm(-beta * T)
+    M = 200_000
+    for i in range(C.n):
+        tr = mlmc.walk_trace(t, beta, 0, seed=99, rows=np.full(M, i), walks=np.arange(M))
+        cnt = np.bincount(tr.final_state, minlength=C.n).astype(np.float64)
+        assert abs(P[i].sum() - 1.0) < 1e-12
+        exp = M * P[i]
+        ok = exp > 5
+        chi2 = float(((cnt[ok] - exp[ok]) ** 2 / exp[ok]).sum())
+        dof = int(ok.sum()) - 1
+        assert chi2 < dof + 6 * math.sqrt(2 * dof) + 10
+        signed = np.bincount(tr.final_state, weights=tr.sign.astype(np.float64),
+                             minlength=C.n) / M
+        se = np.sqrt(np.maximum(P[i] - PT[i] ** 2, 1e-12) / M)
+        assert np.all(np.abs(signed - PT[i]) < 5 * se + 1e-9)
+        # jumps are counted: E[#jumps] = integral of the rate along the path > 0
+        assert tr.jumps.mean() > 0
+
+
+# ----------------------------------------------------------------------------------
+# level terms against the dense Strang products (sections 2.1-2.2, Algorithm 2)
+# ----------------------------------------------------------------------------------
+def _z_scores(res, a, u, beta):
+    lm = reference.level_means(a, u, beta, res.l0, res.levels[-1].level)
+    zs = []
+    for st, m in zip(res.levels, lm):
+        se = np.sqrt(st.var[:, 0] / st.M)
+        ok = se > 1e-13 * (np.abs(m) + 1)
+        # rows whose samples never varied: the event that moves them has probability
+        # below ~10/M, and |Y| <= 2 max|u| e^{beta max|d|}
+        bound = 2 * np.abs(u).max() * np.exp(beta * np.abs(np.diag(a)).max()) * 10 / st.M
+        assert np.all(np.abs(st.mean[~ok, 0] - m[~ok]) < bound)
+        zs.append((st.mean[ok, 0] - m[ok]) / se[ok])
+    return np.concatenate(zs)
+
+
+@pytest.mark.parametrize("case", ["signed", "laplace1d", "nonneg_network"])
+def test_level_means_match_dense_strang_products(case):
+    rng = np.random.default_rng(31)
+    if case == "signed":
+        a = _signed_matrix(8, 5, density=0.6)
+        beta = 0.5
+    elif case == "laplace1d":
+        a = inputs.laplacian_1d(12).to_dense()
+        beta = 2e-3
+    else:
+        a = (rng.random((10, 10)) < 0.4).astype(float)
+        a = np.triu(a, 1)
+        a = a + a.T
+        beta = 1.0 / a.sum(1).max()
+    u = rng.normal(size=a.shape[0])
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    l0 = mlmc.default_l0(t, beta)
+    res = mlmc.mlmc_fixed(t, beta, u, l0, l0 + 3, [60_000] * 4, seed=5)
+    z = _z_scores(res, a, u, beta)
+    assert np.max(np.abs(z)) < 5.0
+    assert 0.5 < np.mean(z * z) < 1.7
+
+
+def test_diagonal_matrix_is_exact():
+    """A diagonal A never jumps: every sample equals e^{beta a_ii} u_i, the level
+    differences vanish and the variance is zero."""
+    dvals = np.array([-3.0, 0.0, 0.4, 1.5, -0.2])
+    a = np.diag(dvals)
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    u = np.array([1.0, -2.0, 0.5, 3.0, 0.25])
+    beta = 0.8
+    res = mlmc.mlmc_fixed(t, beta, u, 0, 4, [50] * 5, seed=3)
+    assert res.jumps == 0
+    assert np.allclose(res.x[:, 0], np.exp(beta * dvals) * u, rtol=1e-13, atol=0)
+    for st in res.levels[1:]:
+        assert np.max(np.abs(st.mean)) < 1e-14 * np.max(np.abs(u * np.exp(beta * dvals)))
+    for st in res.levels:
+        # mean(Y^2) - mean(Y)^2 of identical samples: zero up to cancellation
+        assert np.all(st.var <= 1e-14 * st.mean ** 2 + 1e-300)
+
+
+def test_no_jump_walks_contribute_zero_to_level_differences():
+    """Fig. 1 case (d): a path with no transition gives P_l - P_{l-1} = 0."""
+    a = _signed_matrix(7, 8)
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    M = 4000
+    tr = mlmc.walk_trace(t, 0.05, 4, seed=1, rows=np.repeat(np.arange(7), M),
+                         walks=np.tile(np.arange(M), 7))
+    none = tr.jumps == 0
+    assert none.sum() > 1000 and (~none).sum() > 100
+    diff = np.abs(tr.eta_fine - tr.eta_coarse)
+    assert np.all(diff[none] <= 1e-14 * np.abs(tr.eta_fine[none]))
+    assert np.all(tr.sign[none] == 1)
+
+
+# ----------------------------------------------------------------------------------
+# the reference Strang products themselves: weak order 2 against the exact exponential
+# ----------------------------------------------------------------------------------
+def test_strang_bias_is_second_order_and_dst_reference_is_exact():
+    n = 30
+    A = inputs.laplacian_1d(n)
+    a = A.to_dense()
+    v = inputs.rhs_sine_noise(n, 4)
+    t = 0.5 / (n + 1) ** 2 * 4
+    x = reference.expm_action(a, v, t)
+    assert np.max(np.abs(reference.laplace1d_exact(v, t) - x)) < 1e-13
+    errs = [np.max(np.abs(reference.strang_level(a, v, t, l) - x)) for l in range(2, 8)]
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    assert np.all(np.abs(np.log2(ratios) - 2.0) < 0.15)
+    # 2D closed form against the dense exponential
+    A2 = inputs.laplacian_2d(6)
+    v2 = np.random.default_rng(1).normal(size=36)
+    t2 = 1.0 / 49 / 2
+    assert np.max(np.abs(reference.laplace2d_exact(v2, t2) -
+                         reference.expm_action(A2.to_dense(), v2, t2))) < 1e-13
+
+
+def test_eigenvector_closed_form():
+    """1D Laplacian eigenvector v_k = sin(k pi i h): exp(tA) v_k = e^{t lambda_k} v_k;
+    the MLMC estimate of x^L tends to it with the splitting bias."""
+    n = 15
+    A = inputs.laplacian_1d(n)
+    h = 1.0 / (n + 1)
+    i = np.arange(1, n + 1)
+    v = np.sin(2 * np.pi * i * h)
+    lam = -(4 / h ** 2) * np.sin(2 * np.pi * h / 2) ** 2
+    t = 1.0 / (n + 1) ** 2
+    exact = np.exp(t * lam) * v
+    a = A.to_dense()
+    L = 6
+    xl = reference.strang_level(a, v, t, L)
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    l0 = mlmc.default_l0(tt, t)
+    Ms = [100_000, 50_000, 30_000, 20_000, 15_000, 10_000, 10_000][:L - l0 + 1]
+    res = mlmc.mlmc_fixed(tt, t, v, l0, L, Ms, seed=8)
+    se = math.sqrt(res.est_mse())
+    assert np.sqrt(np.mean((res.x[:, 0] - xl) ** 2)) < 4 * se
+    assert np.sqrt(np.mean((res.x[:, 0] - exact) ** 2)) < 4 * se + np.max(np.abs(xl - exact))
+
+
+# ----------------------------------------------------------------------------------
+# rates (section 4: the mean and the variance of P_l - P_{l-1} decay with slope -2)
+# ----------------------------------------------------------------------------------
+def test_level_mean_and_variance_decay_with_slope_minus_two():
+    a = _signed_matrix(10, 17, density=0.5)
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    beta = 0.5
+    u = np.random.default_rng(2).normal(size=10)
+    l0 = mlmc.default_l0(t, beta)
+    L = l0 + 5
+    res = mlmc.mlmc_fixed(t, beta, u, l0, L, [40_000] * (L - l0 + 1), seed=13)
+    lv = np.array([st.level for st in res.levels[1:]])
+    V = np.array([np.mean(st.var) for st in res.levels[1:]])
+    m_exact = reference.level_means(a, u, beta, l0, L)[1:]
+    mm = np.array([np.sqrt(np.mean(m ** 2)) for m in m_exact])
+    sv = np.polyfit(lv[1:], np.log2(V[1:]), 1)[0]
+    sm = np.polyfit(lv[1:], np.log2(mm[1:]), 1)[0]
+    assert -2.5 < sv < -1.5, sv
+    assert -2.3 < sm < -1.7, sm
+
+
+def test_statistical_error_decays_as_inverse_square_root():
+    a = _signed_matrix(6, 23, density=0.7)
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    beta = 0.3
+    u = np.ones(6)
+    l0 = mlmc.default_l0(t, beta)
+    exact = reference.strang_level(a, u, beta, l0)
+    Ms = [1000, 4000, 16000, 64000]
+    errs = []
+    for M in Ms:
+        e2 = []
+        for s in range(24):
+            ls = mlmc.level_sums(t, beta, l0, l0, 1000 + s, u, None, 0, M)
+            e2.append(np.mean((ls.sum1[:, 0] / M - exact) ** 2))
+        errs.append(math.sqrt(np.mean(e2)))
+    slope = np.polyfit(np.log(Ms), np.log(errs), 1)[0]
+    assert -0.62 < slope < -0.38, slope
+
+
+# ----------------------------------------------------------------------------------
+# Algorithm 1 (driver)
+# ----------------------------------------------------------------------------------
+def test_optimal_sample_sizes_meet_the_variance_budget():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        V = rng.exponential(size=5) * 2.0 ** -np.arange(0, 10, 2)
+        C = 2.0 ** np.arange(5)
+        eps = 10 ** rng.uniform(-4, -2)
+        M = mlmc.optimal_M(V, C, eps)
+        tot = float(np.sum(V / M))
+        assert tot <= eps * eps / 2 * (1 + 1e-12)
+        # the unrounded optimum spends the whole budget
+        Mr = 2.0 * eps ** -2 * np.sqrt(V / C) * np.sum(np.sqrt(V * C))
+        assert abs(np.sum(V / Mr) - eps * eps / 2) < 1e-9 * eps * eps
+
+
+def test_adaptive_driver_reaches_the_target():
+    A, t, v = inputs.workload_laplace1d()
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    eps = 2e-3
+    res = mlmc.mlmc_adaptive(tt, t, v, eps, seed=4, pilot=200)
+    assert res.converged
+    assert res.est_mse() <= eps * eps / 2 * 1.01
+    exact = reference.laplace1d_exact(v, t)
+    rmse = float(np.sqrt(np.mean((res.x[:, 0] - exact) ** 2)))
+    assert rmse < 3 * eps
