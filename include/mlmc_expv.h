@@ -1,0 +1,185 @@
+/*
+ * mlmc_expv: multilevel Monte Carlo action of the matrix exponential on MI355X (gfx950).
+ *
+ * Computes x = exp(beta A) u for a general sparse n x n matrix A (CSR) and one or more
+ * right-hand sides u, by the multilevel Monte Carlo method of Acebron, Herrero &
+ * Monteiro (arXiv:1904.12754):
+ *   - A is split as A = D - T (section 2.1): r_i = sum_{j != i} |a_ij| is the jump rate
+ *     of row i, d_i = a_ii + r_i its diagonal weight, sigma_ij = [a_ij < 0] the sign of a
+ *     jump i -> j;
+ *   - x_i is the expectation of a multiplicative functional of a continuous-time Markov
+ *     chain started at i, with exponential holding times of rate r and jump law
+ *     |a_ij| / r_i (section 3, the integral form of the backward equation), sampled on
+ *     N = 2^l steps of length dt_l = beta / 2^l with the Strang-split weights
+ *     (section 2.1, the single-entry representation);
+ *   - levels l0..L are combined by the telescoping estimator (section 2.2); level l > l0
+ *     draws P_l - P_{l-1} from one path (the coupling of Algorithm 2);
+ *   - sample sizes are either given (fixed schedule) or chosen by Algorithm 1.
+ *
+ * All entry points return an int status (MLMC_OK = 0). On failure a thread-local detail
+ * string is available from mlmc_last_error(). Nothing here allocates on behalf of the
+ * caller: A and the plan options are read (host memory) and copied, u and x are caller
+ * owned device buffers. A plan owns its device tables until mlmc_expv_destroy.
+ *
+ * Streams: every call that takes `stream` (a hipStream_t, or NULL for the default
+ * stream) orders its device work on that stream. Fixed-schedule runs are asynchronous
+ * except that filling `stats` waits for the stream once; adaptive runs (Algorithm 1)
+ * wait for the stream once per driver iteration. A plan is not re-entrant: calls on one
+ * plan must not overlap. Distinct plans may run concurrently.
+ *
+ * Random numbers: walks draw from Philox4x32-10 (Salmon et al., SC'11) keyed by the
+ * 64-bit seed, with counter (index, walk, row, level<<26 | instance<<14 | stream):
+ * stream 0 gives the per-step holding-time tests (step n reads word n%4 of block n/4),
+ * stream 1 the jumps (the walk's j-th jump reads block j: slot, alias coin, next holding
+ * time). Results are therefore a pure function of (A, u, beta, levels, walks, seed,
+ * instance), independent of launch shape and of how walk ranges are split.
+ */
+#ifndef MLMC_EXPV_H
+#define MLMC_EXPV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define MLMC_OK 0
+#define MLMC_ERR_INVALID_ARG 1     /* a null pointer, a size or an option out of range     */
+#define MLMC_ERR_INVALID_MATRIX 2  /* CSR not well formed: row_ptr not monotone, column out
+                                      of range, repeated column in a row, non-finite value */
+#define MLMC_ERR_OUT_OF_MEMORY 3   /* a device or host allocation failed                    */
+#define MLMC_ERR_HIP 4             /* a HIP runtime call failed                             */
+#define MLMC_ERR_NONFINITE 5       /* some samples overflowed (count in stats->nonfinite);
+                                      the result is still written                           */
+#define MLMC_ERR_NOT_CONVERGED 6   /* Algorithm 1 hit its level or walk cap before reaching
+                                      eps; the best estimate is still written               */
+#define MLMC_ERR_UNSUPPORTED 7     /* a valid request this build does not serve             */
+
+/* ---- element types and precision --------------------------------------------------- */
+#define MLMC_DTYPE_F32 0
+#define MLMC_DTYPE_F64 1
+
+/* Weights along a path (the exponents of the Strang factors and the sample Y):
+ * FP64, or FP32 with compensated (Kahan) FP32 per-lane sums. Path decisions (holding
+ * times, jump choice) are FP64/integer in both modes, so both modes follow identical
+ * paths. Per-row and cross-level combination is always FP64. */
+#define MLMC_PRECISION_FP64 0
+#define MLMC_PRECISION_FP32 1
+
+#define MLMC_MAX_LEVELS 40
+
+typedef struct mlmc_plan mlmc_plan_t;
+
+/* A general sparse matrix in CSR form, in HOST memory. Columns within a row need not be
+ * sorted but must not repeat. A missing diagonal entry means a_ii = 0; explicit zeros
+ * are ignored. n < 2^31, number of off-diagonal nonzeros < 2^32. */
+typedef struct {
+    int64_t n;
+    const int64_t *row_ptr;   /* n + 1 entries, row_ptr[0] = 0 */
+    const int32_t *col_idx;   /* row_ptr[n] entries */
+    const void *values;       /* row_ptr[n] entries of values_dtype */
+    int32_t values_dtype;     /* MLMC_DTYPE_F32 or MLMC_DTYPE_F64 */
+} mlmc_csr_t;
+
+/* Options fixed when a plan is built. */
+typedef struct {
+    double beta;              /* the scalar in exp(beta A) (time, or inverse temperature); > 0 */
+    int32_t precision;        /* MLMC_PRECISION_FP64 or MLMC_PRECISION_FP32 */
+    int32_t l0;               /* coarsest level; < 0 selects the rule of section 4,
+                                 l0 = max(0, ceil(log2(2 beta max_i r_i))) */
+    const int64_t *rows;      /* host array of the requested rows (estimates x_i for these i
+                                 only), or NULL for all n rows */
+    int64_t n_rows;           /* entries in rows (ignored when rows is NULL) */
+} mlmc_plan_opts_t;
+
+/* Read-only facts about a plan. */
+typedef struct {
+    int64_t n, n_rows, n_slots;   /* rows of A, requested rows, off-diagonal nonzeros */
+    int32_t l0, precision;
+    double beta, r_max, d_min, d_max;
+    int64_t device_bytes;         /* device memory the plan holds */
+} mlmc_plan_info_t;
+
+/* Options of one run. */
+typedef struct {
+    uint64_t seed;            /* Philox key */
+    int32_t instance;         /* 0..4095, selects an independent family of streams */
+    int32_t num_levels;       /* fixed schedule: levels l0 .. l0 + num_levels - 1 */
+    const int64_t *walks;     /* fixed schedule: walks per requested row at each level
+                                 (host array of num_levels entries, each in [1, 2^32)) */
+    double eps;               /* > 0 selects Algorithm 1 with target RMSE eps (the fixed
+                                 schedule fields are then ignored) */
+    int64_t pilot_walks;      /* Algorithm 1: walks per row per level of the pilot run */
+    int32_t max_levels;       /* Algorithm 1: cap on the number of levels */
+    int64_t max_walks;        /* Algorithm 1: cap on walks per row per level (0 = 2^32 - 1) */
+} mlmc_run_opts_t;
+
+/* Statistics of one run (host struct, filled when non-NULL). Level q holds level l0 + q.
+ * Level moments are averaged over requested rows and right-hand sides. */
+typedef struct {
+    int32_t l0, num_levels, converged, driver_iterations;
+    int64_t walks[MLMC_MAX_LEVELS];          /* M_l per row */
+    int64_t jumps[MLMC_MAX_LEVELS];          /* total jumps taken at the level */
+    double level_mean_rms[MLMC_MAX_LEVELS];  /* sqrt(mean m_{l,i}^2) */
+    double level_var[MLMC_MAX_LEVELS];       /* mean V_{l,i} (per-walk variance) */
+    double level_cost[MLMC_MAX_LEVELS];      /* cost model N_l + 4 * jumps per walk */
+    int64_t steps;                           /* sum over walks of N_l */
+    int64_t total_jumps;
+    int64_t nonfinite;                       /* samples that were not finite */
+    double est_variance;                     /* sum_l level_var / M_l */
+    double est_bias;                         /* Algorithm 1's extrapolated bias (0 if fixed) */
+    double kernel_ms;                        /* device time of the walk kernels */
+} mlmc_stats_t;
+
+/* Build a plan: validate A, split A = D - T, build the alias tables of the jump law and
+ * the per-level step thresholds, and upload them. `stream` orders the uploads.
+ * Returns INVALID_ARG for beta <= 0 or a coarsest level so coarse that some row would
+ * jump in every step with certainty at 32-bit resolution (r_i dt_l0 > 22). */
+int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_t *opts,
+                   void *stream);
+
+int mlmc_expv_plan_info(const mlmc_plan_t *plan, mlmc_plan_info_t *info);
+
+/* Estimate x = exp(beta A) u at the plan's requested rows.
+ *   u: DEVICE, n x nrhs row major, u_dtype MLMC_DTYPE_F32 or MLMC_DTYPE_F64.
+ *   x: DEVICE, n_rows x nrhs row major FP64, overwritten.
+ * Fixed schedule (opts->eps <= 0): levels l0 .. l0 + num_levels - 1 with walks[q] walks
+ * per row at level l0 + q. Adaptive (opts->eps > 0): Algorithm 1 of the paper, with
+ * Giles' optimal sample sizes and a bias test of weak order 2 (section 4). */
+int mlmc_expv_run(mlmc_plan_t *plan, const void *u, int32_t nrhs, int32_t u_dtype,
+                  const mlmc_run_opts_t *opts, double *x, mlmc_stats_t *stats, void *stream);
+
+/* Algorithm 2's accumulators for one level: for walks walk0 .. walk0 + walks - 1 of every
+ * requested row, sum1 = sum Y and sum2 = sum Y^2 per (row, rhs), where Y = u_j (eta_fine -
+ * eta_coarse) at levels above l0 and Y = u_j eta_fine at l0 (j the final state).
+ *   sum1, sum2: DEVICE, n_rows x nrhs FP64, overwritten.
+ *   jumps: HOST, nullable; receives the jump count (waits for the stream). */
+int mlmc_expv_level_sums(mlmc_plan_t *plan, const void *u, int32_t nrhs, int32_t u_dtype,
+                         uint64_t seed, int32_t instance, int32_t level, uint32_t walk0,
+                         uint32_t walks, double *sum1, double *sum2, int64_t *jumps,
+                         void *stream);
+
+/* Individual walks at one level, for inspection: walk walks[q] from row rows[q]
+ * (rows[q] is a row index of A, not an index into the requested rows).
+ * All arrays DEVICE, count entries: final state, sign (+1/-1), jump count, a 64-bit
+ * FNV-1a hash of the (state, step) pair of every jump (offset 14695981039346656037,
+ * prime 1099511628211; per jump hash ^= state, *= prime, ^= 1-based step, *= prime),
+ * and the natural logs of |eta_fine| and |eta_coarse| (the latter is meaningful for
+ * level > 0). Path decisions are identical in both precisions; the logs are computed in
+ * the plan's precision. */
+int mlmc_expv_trace(mlmc_plan_t *plan, uint64_t seed, int32_t instance, int32_t level,
+                    int64_t count, const int64_t *rows, const uint32_t *walks,
+                    int64_t *final_state, int32_t *sign, int64_t *jumps, uint64_t *hash,
+                    double *log_eta_fine, double *log_eta_coarse, void *stream);
+
+void mlmc_expv_destroy(mlmc_plan_t *plan);
+
+const char *mlmc_status_string(int status);
+const char *mlmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLMC_EXPV_H */

@@ -69,7 +69,7 @@ def _declare(L):
                                           ctypes.c_int32, ctypes.c_int64, _p(ctypes.c_int64),
                                           ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
                                           _p(ctypes.c_double), _p(ctypes.c_double),
-                                          _p(ctypes.c_int64), ctypes.c_int32]
+                                          _p(ctypes.c_double), _p(ctypes.c_int64), ctypes.c_int32]
     L.orc_level_sums.restype = None
     L.orc_log_array.argtypes = [ctypes.c_int64, _p(ctypes.c_double), _p(ctypes.c_double)]
     L.orc_log_array.restype = None
@@ -217,7 +217,8 @@ def walk_trace(t: Tables, beta: float, level: int, seed: int, rows, walks, insta
 class LevelSums:
     sum1: np.ndarray   # (n_rows, R)
     sum2: np.ndarray   # (n_rows, R)
-    mass: np.ndarray   # (n_rows, R)
+    mass: np.ndarray   # (n_rows, R)  sum_w |u_j| (|eta_fine| + |eta_coarse|)
+    mass2: np.ndarray  # (n_rows, R)  sum_w of the square of that magnitude
     jumps: np.ndarray  # (n_rows,)
     walks: int
     steps_per_walk: int
@@ -235,12 +236,14 @@ def level_sums(t: Tables, beta: float, level: int, l0: int, seed: int, u, rows=N
     s1 = np.zeros((nr, R), np.float64)
     s2 = np.zeros((nr, R), np.float64)
     ms = np.zeros((nr, R), np.float64)
+    ms2 = np.zeros((nr, R), np.float64)
     jp = np.zeros(nr, np.int64)
     lib().orc_level_sums(*t.args(), float(beta), int(level), int(l0), int(seed), int(instance),
                          _ptr(u, ctypes.c_double), R, nr, _ptr(rows, ctypes.c_int64),
                          int(walk0), int(M), _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
-                         _ptr(ms, ctypes.c_double), _ptr(jp, ctypes.c_int64), int(threads))
-    return LevelSums(s1, s2, ms, jp, int(M), 1 << int(level))
+                         _ptr(ms, ctypes.c_double), _ptr(ms2, ctypes.c_double),
+                         _ptr(jp, ctypes.c_int64), int(threads))
+    return LevelSums(s1, s2, ms, ms2, jp, int(M), 1 << int(level))
 
 
 # ----------------------------------------------------------------------------------

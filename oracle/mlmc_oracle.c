@@ -334,8 +334,9 @@ static void orc_add(orc_sum *a, double x)
 /*     Y = u_j (eta_fine - eta_coarse)   (level > l0)                              */
 /*     Y = u_j  eta_fine                 (level = l0)                              */
 /* with j the final state, for each of the R right-hand sides (u is n x R, row     */
-/* major). Outputs per (row, rhs): sum Y, sum Y^2 and the magnitude                */
-/* sum |u_j| (|eta_fine| + |eta_coarse|) (the scale of the rounding in Y); per     */
+/* major). Outputs per (row, rhs): sum Y, sum Y^2, the magnitude                  */
+/* m = |u_j| (|eta_fine| + |eta_coarse|) (the scale of the rounding in Y) summed,  */
+/* and sum m^2; per                                                                */
 /* row: the total jump count, and the total step count M * N.                      */
 /* ------------------------------------------------------------------------------ */
 void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
@@ -343,8 +344,8 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                     const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
                     int level, int l0, uint64_t seed, uint32_t instance, const double *u,
                     int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
-                    uint32_t M, double *sum1, double *sum2, double *mass, int64_t *jumps,
-                    int32_t nthreads)
+                    uint32_t M, double *sum1, double *sum2, double *mass, double *mass2,
+                    int64_t *jumps, int32_t nthreads)
 {
     orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -358,6 +359,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
         orc_sum *a1 = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
         orc_sum *a2 = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
         orc_sum *am = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
+        orc_sum *am2 = (orc_sum *)malloc(sizeof(orc_sum) * (size_t)R);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t q = 0; q < n_rows; ++q) {
             int64_t i = rows[q];
@@ -365,6 +367,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
             memset(a1, 0, sizeof(orc_sum) * (size_t)R);
             memset(a2, 0, sizeof(orc_sum) * (size_t)R);
             memset(am, 0, sizeof(orc_sum) * (size_t)R);
+            memset(am2, 0, sizeof(orc_sum) * (size_t)R);
             for (uint32_t w = 0; w < M; ++w) {
                 orc_walk_out o;
                 orc_one_walk(&t, beta, level, key, instance, i, walk0 + w, &o);
@@ -382,16 +385,18 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                     orc_add(&a1[rr], y);
                     orc_add(&a2[rr], y * y);
                     orc_add(&am[rr], m);
+                    orc_add(&am2[rr], m * m);
                 }
             }
             for (int32_t rr = 0; rr < R; ++rr) {
                 sum1[q * R + rr] = a1[rr].s + a1[rr].c;
                 sum2[q * R + rr] = a2[rr].s + a2[rr].c;
                 mass[q * R + rr] = am[rr].s + am[rr].c;
+                mass2[q * R + rr] = am2[rr].s + am2[rr].c;
             }
             jumps[q] = nj;
         }
-        free(a1); free(a2); free(am);
+        free(a1); free(a2); free(am); free(am2);
     }
 }
 

@@ -1,0 +1,152 @@
+"""Python binding of the mlmc_expv C-ABI (marshalling only; every step of the walks runs
+in the library's HIP kernels). PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _u_args(u: torch.Tensor, n: int):
+    if not u.is_cuda:
+        raise ValueError("u must be a device tensor")
+    if u.dtype not in (torch.float32, torch.float64):
+        raise ValueError("u must be float32 or float64")
+    if u.dim() == 1:
+        u = u[:, None]
+    if u.shape[0] != n:
+        raise ValueError(f"u has {u.shape[0]} rows, the matrix {n}")
+    u = u.contiguous()
+    dt = _abi.MLMC_DTYPE_F64 if u.dtype == torch.float64 else _abi.MLMC_DTYPE_F32
+    return u, int(u.shape[1]), dt
+
+
+class Plan:
+    """A prepared matrix: A = D - T split, alias tables and step thresholds in HBM.
+
+    A: an object with n, row_ptr, col_idx, values (numpy arrays, host).
+    precision: "fp32" (FP32 path weights, compensated FP32 sums, FP64 combine) or "fp64".
+    """
+
+    def __init__(self, A, beta: float, precision: str = "fp32", l0: int | None = None,
+                 rows=None, values_dtype=np.float64, stream=None):
+        self._lib = _abi.load()
+        self._handle = ctypes.c_void_p()
+        self.n = int(A.n)
+        self._row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+        self._col_idx = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+        self._values = np.ascontiguousarray(A.values, dtype=values_dtype)
+        csr = _abi.CSR(self.n, self._row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                       self._col_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                       ctypes.c_void_p(self._values.ctypes.data),
+                       _abi.MLMC_DTYPE_F64 if self._values.dtype == np.float64 else _abi.MLMC_DTYPE_F32)
+        prec = {"fp64": _abi.MLMC_PRECISION_FP64, "fp32": _abi.MLMC_PRECISION_FP32}[precision]
+        self._rows = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+        opts = _abi.PlanOpts(float(beta), prec, -1 if l0 is None else int(l0),
+                             None if self._rows is None else
+                             self._rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             0 if self._rows is None else int(self._rows.size))
+        check(self._lib.mlmc_expv_plan(ctypes.byref(self._handle), ctypes.byref(csr),
+                                       ctypes.byref(opts), _stream_ptr(stream)))
+        info = _abi.PlanInfo()
+        check(self._lib.mlmc_expv_plan_info(self._handle, ctypes.byref(info)))
+        self.n_rows = int(info.n_rows)
+        self.l0 = int(info.l0)
+        self.beta = float(info.beta)
+        self.info = {f: getattr(info, f) for f, _ in _abi.PlanInfo._fields_}
+
+    # ------------------------------------------------------------------------------
+    def run(self, u: torch.Tensor, walks=None, eps: float | None = None, seed: int = 0,
+            instance: int = 0, pilot_walks: int = 1024, max_levels: int = 20,
+            max_walks: int = 0, out: torch.Tensor | None = None, stream=None,
+            want_stats: bool = True, allow=()):
+        """x = exp(beta A) u at the plan's rows. Fixed schedule: walks[q] walks per row at
+        level l0 + q. Adaptive (Algorithm 1): eps > 0."""
+        u, R, dt = _u_args(u, self.n)
+        x = out if out is not None else torch.empty((self.n_rows, R), dtype=torch.float64,
+                                                    device=u.device)
+        if eps is not None and eps > 0:
+            opts = _abi.RunOpts(seed, instance, 0, None, float(eps), int(pilot_walks),
+                                int(max_levels), int(max_walks))
+            walks_arr = None
+        else:
+            walks_arr = np.ascontiguousarray(walks, dtype=np.int64)
+            opts = _abi.RunOpts(seed, instance, int(walks_arr.size),
+                                walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0,
+                                0, 0, 0)
+        stats = _abi.Stats() if want_stats else None
+        code = self._lib.mlmc_expv_run(self._handle, _dev_ptr(u), R, dt, ctypes.byref(opts),
+                                       _dev_ptr(x), ctypes.byref(stats) if stats else None,
+                                       _stream_ptr(stream))
+        check(code, allow)
+        del walks_arr
+        return x, (stats.to_dict() if stats else None)
+
+    def level_sums(self, u: torch.Tensor, level: int, walk0: int, walks: int, seed: int = 0,
+                   instance: int = 0, stream=None):
+        """Algorithm 2's accumulators at one level: (sum Y, sum Y^2) per (row, rhs), jumps."""
+        u, R, dt = _u_args(u, self.n)
+        s1 = torch.empty((self.n_rows, R), dtype=torch.float64, device=u.device)
+        s2 = torch.empty_like(s1)
+        jumps = ctypes.c_int64()
+        check(self._lib.mlmc_expv_level_sums(self._handle, _dev_ptr(u), R, dt, seed, instance,
+                                             level, walk0, walks, _dev_ptr(s1), _dev_ptr(s2),
+                                             ctypes.byref(jumps), _stream_ptr(stream)))
+        return s1, s2, int(jumps.value)
+
+    def trace(self, level: int, rows, walks, seed: int = 0, instance: int = 0, stream=None):
+        dev = torch.device("cuda")
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        if rows.size and (rows.min() < 0 or rows.max() >= self.n):
+            raise ValueError("trace rows must be rows of A")
+        rows_t = torch.as_tensor(rows, device=dev)
+        walks_t = torch.as_tensor(np.ascontiguousarray(walks, dtype=np.uint32).view(np.int32),
+                                  device=dev)
+        q = rows_t.numel()
+        out = {
+            "final_state": torch.empty(q, dtype=torch.int64, device=dev),
+            "sign": torch.empty(q, dtype=torch.int32, device=dev),
+            "jumps": torch.empty(q, dtype=torch.int64, device=dev),
+            "hash": torch.empty(q, dtype=torch.int64, device=dev),
+            "log_eta_fine": torch.empty(q, dtype=torch.float64, device=dev),
+            "log_eta_coarse": torch.empty(q, dtype=torch.float64, device=dev),
+        }
+        check(self._lib.mlmc_expv_trace(self._handle, seed, instance, level, q,
+                                        _dev_ptr(rows_t), _dev_ptr(walks_t),
+                                        *(_dev_ptr(out[k]) for k in ("final_state", "sign",
+                                                                     "jumps", "hash",
+                                                                     "log_eta_fine",
+                                                                     "log_eta_coarse")),
+                                        _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self._lib.mlmc_expv_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,622 @@
+// C-ABI of the library (include/mlmc_expv.h): plan construction (the decomposition
+// A = D - T of section 2.1 and the alias tables of the jump law), fixed-schedule and
+// adaptive runs (the estimator of section 2.2 and Algorithm 1), level sums and traces.
+#include "../../include/mlmc_expv.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace mlmc {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace mlmc
+
+using namespace mlmc;
+
+namespace {
+
+constexpr int kMaxLevel = 28;                   // N = 2^28 steps per walk at most
+constexpr size_t kPartialCapBytes = 256u << 20;  // per sub-launch scratch
+constexpr int64_t kTargetItems = 16384;          // (row, chunk) items per launch, to fill 256 CUs
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+}  // namespace
+
+struct mlmc_plan {
+    int64_t n = 0, n_rows = 0, n_slots = 0;
+    int32_t l0 = 0, precision = 0;
+    double beta = 0, r_max = 0, d_min = 0, d_max = 0;
+    SlotRec *slots = nullptr;
+    RowRec *rows_base = nullptr;
+    RowRec *level_rec[kMaxLevel + 1] = {};
+    int64_t *req_rows = nullptr;             // device; null = all rows
+    double *partial = nullptr;
+    size_t partial_bytes = 0;
+    unsigned long long *counters = nullptr;  // 2 per level
+    unsigned int *bad = nullptr;
+    double *moments = nullptr;               // 3 per level
+    double *acc = nullptr;                   // 2 * n_rows * nrhs per level
+    size_t acc_doubles = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int64_t bytes = 0;
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(mlmc_plan *p, T **ptr, size_t count)
+{
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(ptr), count * sizeof(T));
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? MLMC_ERR_OUT_OF_MEMORY : MLMC_ERR_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    p->bytes += static_cast<int64_t>(count * sizeof(T));
+    return MLMC_OK;
+}
+
+void free_plan(mlmc_plan *p)
+{
+    if (!p) return;
+    hipFree(p->slots);
+    hipFree(p->rows_base);
+    for (auto &r : p->level_rec) hipFree(r);
+    hipFree(p->req_rows);
+    hipFree(p->partial);
+    hipFree(p->counters);
+    hipFree(p->bad);
+    hipFree(p->moments);
+    hipFree(p->acc);
+    if (p->ev0) hipEventDestroy(p->ev0);
+    if (p->ev1) hipEventDestroy(p->ev1);
+    delete p;
+}
+
+double value_at(const mlmc_csr_t *A, int64_t e)
+{
+    return A->values_dtype == MLMC_DTYPE_F64 ? static_cast<const double *>(A->values)[e]
+                                              : static_cast<double>(static_cast<const float *>(A->values)[e]);
+}
+
+// Walker/Vose alias table of one row. q holds the scaled probabilities deg * p_k and is
+// consumed. Entries are processed with two LIFO work lists filled in slot order, so the
+// table is a deterministic function of the row.
+void build_alias(std::vector<double> &q, std::vector<uint32_t> &thr, std::vector<uint32_t> &alias,
+                 std::vector<uint32_t> &small, std::vector<uint32_t> &large)
+{
+    const uint32_t k = static_cast<uint32_t>(q.size());
+    thr.assign(k, 0xFFFFFFFFu);
+    alias.resize(k);
+    small.clear();
+    large.clear();
+    for (uint32_t s = 0; s < k; ++s) {
+        alias[s] = s;
+        (q[s] < 1.0 ? small : large).push_back(s);
+    }
+    while (!small.empty() && !large.empty()) {
+        const uint32_t lo = small.back();
+        small.pop_back();
+        const uint32_t hi = large.back();
+        large.pop_back();
+        thr[lo] = static_cast<uint32_t>(std::floor(q[lo] * 4294967296.0));
+        alias[lo] = hi;
+        q[hi] = (q[hi] + q[lo]) - 1.0;
+        (q[hi] < 1.0 ? small : large).push_back(hi);
+    }
+    // whatever remains has probability one of keeping its own column (thr, alias preset)
+}
+
+int upload_level(mlmc_plan *p, int level, hipStream_t s)
+{
+    if (level < 0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level out of range [0, 28]");
+    if (p->level_rec[level]) return MLMC_OK;
+    RowRec *rec = nullptr;
+    int rc = dev_alloc(p, &rec, static_cast<size_t>(p->n));
+    if (rc) return rc;
+    p->level_rec[level] = rec;
+    if (p->n) {
+        MLMC_HIP_TRY(hipMemcpyAsync(rec, p->rows_base, sizeof(RowRec) * p->n, hipMemcpyDeviceToDevice, s));
+        MLMC_HIP_TRY(launch_thresholds(rec, p->n, std::ldexp(p->beta, -level), p->bad, s));
+    }
+    return MLMC_OK;
+}
+
+LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
+{
+    LevelArgs L;
+    L.rec = p->level_rec[level];
+    L.slots = p->slots;
+    L.n = p->n;
+    L.N = 1u << level;
+    L.level = level;
+    L.base = (level == p->l0);
+    L.dt = std::ldexp(p->beta, -level);
+    L.half_dt = L.dt * 0.5;
+    L.k0 = static_cast<uint32_t>(seed);
+    L.k1 = static_cast<uint32_t>(seed >> 32);
+    L.c3_step = stream_word(level, instance, 0);
+    L.c3_jump = stream_word(level, instance, 1);
+    return L;
+}
+
+int ensure_partial(mlmc_plan *p, size_t bytes)
+{
+    if (bytes <= p->partial_bytes) return MLMC_OK;
+    hipFree(p->partial);
+    p->bytes -= static_cast<int64_t>(p->partial_bytes);
+    p->partial = nullptr;
+    p->partial_bytes = 0;
+    int rc = dev_alloc(p, reinterpret_cast<char **>(&p->partial), bytes);
+    if (rc) return rc;
+    p->partial_bytes = bytes;
+    return MLMC_OK;
+}
+
+// Walks [walk0, walk0 + M) of every requested row at `level`: per-(row, rhs) sums of Y and
+// Y^2 into out1/out2 (overwritten, or added to when accumulate). Jump and non-finite
+// counts are added to counters[0..1].
+int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void *u, int u_f64,
+               int32_t nrhs, uint32_t walk0, uint64_t M, double *out1, double *out2, int accumulate,
+               unsigned long long *counters, hipStream_t s)
+{
+    if (M == 0 || p->n_rows == 0) {
+        if (!accumulate && p->n_rows) {
+            MLMC_HIP_TRY(hipMemsetAsync(out1, 0, sizeof(double) * p->n_rows * nrhs, s));
+            MLMC_HIP_TRY(hipMemsetAsync(out2, 0, sizeof(double) * p->n_rows * nrhs, s));
+        }
+        return MLMC_OK;
+    }
+    if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
+        return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
+    int rc = upload_level(p, level, s);
+    if (rc) return rc;
+    const LevelArgs L = level_args(p, level, seed, instance);
+    const Prec prec = p->precision == MLMC_PRECISION_FP64 ? Prec::FP64 : Prec::FP32;
+    // walks per item: enough items to fill the chip, at most 64 walks per lane
+    const int64_t per_row_items = std::max<int64_t>(1, (kTargetItems + p->n_rows - 1) / p->n_rows);
+    uint64_t chunk = (M + per_row_items - 1) / per_row_items;
+    chunk = std::min<uint64_t>(std::max<uint64_t>((chunk + 63) / 64 * 64, 64), 64 * 64);
+    // bound the scratch: sub-launches over walk ranges
+    const uint64_t bytes_per_item = static_cast<uint64_t>(nrhs) * 2 * sizeof(double);
+    uint64_t max_items = std::max<uint64_t>(1, kPartialCapBytes / bytes_per_item);
+    uint64_t chunks_per_launch = std::max<uint64_t>(1, max_items / static_cast<uint64_t>(p->n_rows));
+    const uint64_t total_chunks = (M + chunk - 1) / chunk;
+    chunks_per_launch = std::min(chunks_per_launch, total_chunks);
+    rc = ensure_partial(p, chunks_per_launch * p->n_rows * bytes_per_item);
+    if (rc) return rc;
+    bool first = true;
+    for (uint64_t c0 = 0; c0 < total_chunks; c0 += chunks_per_launch) {
+        const uint64_t nch = std::min(chunks_per_launch, total_chunks - c0);
+        const uint64_t wb = c0 * chunk;
+        const uint64_t Msub = std::min<uint64_t>(M - wb, nch * chunk);
+        MLMC_HIP_TRY(launch_level_walks(L, prec, u, u_f64, nrhs, p->req_rows, p->n_rows,
+                                        walk0 + static_cast<uint32_t>(wb), static_cast<uint32_t>(Msub),
+                                        static_cast<uint32_t>(chunk), static_cast<uint32_t>(nch),
+                                        p->partial, counters, s));
+        MLMC_HIP_TRY(launch_finalize(p->partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
+                                     out2, (first && !accumulate) ? 0 : 1, s));
+        first = false;
+    }
+    return MLMC_OK;
+}
+
+int check_u(const void *u, int32_t nrhs, int32_t u_dtype)
+{
+    if (!u) return fail(MLMC_ERR_INVALID_ARG, "u is null");
+    if (nrhs < 1 || nrhs > 256) return fail(MLMC_ERR_INVALID_ARG, "nrhs must be in [1, 256]");
+    if (u_dtype != MLMC_DTYPE_F32 && u_dtype != MLMC_DTYPE_F64)
+        return fail(MLMC_ERR_INVALID_ARG, "u_dtype must be MLMC_DTYPE_F32 or MLMC_DTYPE_F64");
+    return MLMC_OK;
+}
+
+int ensure_acc(mlmc_plan *p, int levels, int32_t nrhs)
+{
+    const size_t need = static_cast<size_t>(levels) * 2 * p->n_rows * nrhs;
+    if (need <= p->acc_doubles) return MLMC_OK;
+    hipFree(p->acc);
+    p->bytes -= static_cast<int64_t>(p->acc_doubles * sizeof(double));
+    p->acc = nullptr;
+    p->acc_doubles = 0;
+    int rc = dev_alloc(p, &p->acc, need);
+    if (rc) return rc;
+    p->acc_doubles = need;
+    return MLMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mlmc_status_string(int status)
+{
+    switch (status) {
+    case MLMC_OK: return "ok";
+    case MLMC_ERR_INVALID_ARG: return "invalid argument";
+    case MLMC_ERR_INVALID_MATRIX: return "invalid matrix";
+    case MLMC_ERR_OUT_OF_MEMORY: return "out of memory";
+    case MLMC_ERR_HIP: return "HIP runtime error";
+    case MLMC_ERR_NONFINITE: return "non-finite samples";
+    case MLMC_ERR_NOT_CONVERGED: return "not converged";
+    case MLMC_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *mlmc_last_error(void) { return g_last_error.c_str(); }
+
+int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_t *o, void *stream)
+{
+    if (!out || !A || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->n;
+    if (n < 0 || n >= (int64_t(1) << 31)) return fail(MLMC_ERR_INVALID_ARG, "n out of range");
+    if (n > 0 && (!A->row_ptr || !A->col_idx)) return fail(MLMC_ERR_INVALID_ARG, "null CSR array");
+    if (A->values_dtype != MLMC_DTYPE_F32 && A->values_dtype != MLMC_DTYPE_F64)
+        return fail(MLMC_ERR_INVALID_ARG, "values_dtype must be MLMC_DTYPE_F32 or MLMC_DTYPE_F64");
+    if (!(o->beta > 0.0) || !std::isfinite(o->beta)) return fail(MLMC_ERR_INVALID_ARG, "beta must be finite and > 0");
+    if (o->precision != MLMC_PRECISION_FP64 && o->precision != MLMC_PRECISION_FP32)
+        return fail(MLMC_ERR_INVALID_ARG, "precision must be MLMC_PRECISION_FP64 or MLMC_PRECISION_FP32");
+    if (o->l0 > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "l0 out of range");
+    // ---- validate the CSR structure
+    if (n > 0 && A->row_ptr[0] != 0) return fail(MLMC_ERR_INVALID_MATRIX, "row_ptr[0] != 0");
+    const int64_t nnz = n > 0 ? A->row_ptr[n] : 0;
+    if (nnz > 0 && !A->values) return fail(MLMC_ERR_INVALID_ARG, "null values");
+    std::vector<int64_t> stamp(static_cast<size_t>(n), -1);
+    int64_t n_slots = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t b = A->row_ptr[i], e = A->row_ptr[i + 1];
+        if (e < b || e > nnz) return fail(MLMC_ERR_INVALID_MATRIX, "row_ptr not monotone at row " + std::to_string(i));
+        for (int64_t t = b; t < e; ++t) {
+            const int32_t c = A->col_idx[t];
+            if (c < 0 || c >= n) return fail(MLMC_ERR_INVALID_MATRIX, "column out of range in row " + std::to_string(i));
+            if (stamp[c] == i) return fail(MLMC_ERR_INVALID_MATRIX, "repeated column in row " + std::to_string(i));
+            stamp[c] = i;
+            const double v = value_at(A, t);
+            if (!std::isfinite(v)) return fail(MLMC_ERR_INVALID_MATRIX, "non-finite value in row " + std::to_string(i));
+            if (c != i && v != 0.0) ++n_slots;
+        }
+    }
+    if (n_slots >= (int64_t(1) << 32)) return fail(MLMC_ERR_UNSUPPORTED, "more than 2^32 - 1 off-diagonal nonzeros");
+    // ---- requested rows
+    std::vector<int64_t> req;
+    if (o->rows) {
+        if (o->n_rows < 0) return fail(MLMC_ERR_INVALID_ARG, "n_rows < 0");
+        req.assign(o->rows, o->rows + o->n_rows);
+        for (int64_t r : req)
+            if (r < 0 || r >= n) return fail(MLMC_ERR_INVALID_ARG, "requested row out of range");
+    }
+    // ---- decomposition A = D - T and alias tables (section 2.1; jump law of section 3)
+    std::vector<SlotRec> slots(static_cast<size_t>(std::max<int64_t>(n_slots, 1)));
+    std::vector<RowRec> rows(static_cast<size_t>(n));
+    std::vector<double> q;
+    std::vector<uint32_t> cols, signs, thr, alias, small, large;
+    double r_max = 0.0, d_min = INFINITY, d_max = -INFINITY;
+    uint32_t sb = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        double diag = 0.0, r = 0.0;
+        cols.clear();
+        signs.clear();
+        for (int64_t t = A->row_ptr[i]; t < A->row_ptr[i + 1]; ++t) {
+            const double v = value_at(A, t);
+            if (A->col_idx[t] == i) {
+                diag += v;
+            } else if (v != 0.0) {
+                r += std::fabs(v);
+                cols.push_back(static_cast<uint32_t>(A->col_idx[t]));
+                signs.push_back(v < 0.0 ? 1u : 0u);
+            }
+        }
+        const uint32_t deg = static_cast<uint32_t>(cols.size());
+        q.clear();
+        for (int64_t t = A->row_ptr[i]; t < A->row_ptr[i + 1]; ++t) {
+            const double v = value_at(A, t);
+            if (A->col_idx[t] != i && v != 0.0) q.push_back((std::fabs(v) * static_cast<double>(deg)) / r);
+        }
+        build_alias(q, thr, alias, small, large);
+        for (uint32_t k = 0; k < deg; ++k) {
+            SlotRec &sr = slots[sb + k];
+            sr.own = cols[k] | (signs[k] << 31);
+            sr.alias = cols[alias[k]] | (signs[alias[k]] << 31);
+            sr.thr = thr[k];
+            sr.pad = 0;
+        }
+        RowRec &rr = rows[static_cast<size_t>(i)];
+        const double d = diag + r;
+        rr.slot_begin = sb;
+        rr.deg = deg;
+        rr.thr = 0xFFFFFFFFu;
+        rr.d32 = static_cast<float>(d);
+        rr.inv_r = r > 0.0 ? 1.0 / r : INFINITY;
+        rr.d64 = d;
+        r_max = std::max(r_max, r);
+        d_min = std::min(d_min, d);
+        d_max = std::max(d_max, d);
+        sb += deg;
+    }
+    int l0 = o->l0;
+    if (l0 < 0) {
+        l0 = 0;
+        if (r_max > 0.0) l0 = std::max(0, static_cast<int>(std::ceil(std::log2(2.0 * o->beta * r_max))));
+    }
+    if (l0 > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "coarsest level from the l0 rule exceeds 28");
+    // ---- upload
+    auto *p = new (std::nothrow) mlmc_plan;
+    if (!p) return fail(MLMC_ERR_OUT_OF_MEMORY, "host allocation");
+    std::unique_ptr<mlmc_plan, void (*)(mlmc_plan *)> guard(p, free_plan);
+    p->n = n;
+    p->n_rows = o->rows ? o->n_rows : n;
+    p->n_slots = n_slots;
+    p->l0 = l0;
+    p->precision = o->precision;
+    p->beta = o->beta;
+    p->r_max = r_max;
+    p->d_min = n ? d_min : 0.0;
+    p->d_max = n ? d_max : 0.0;
+    int rc;
+    if ((rc = dev_alloc(p, &p->slots, slots.size()))) return rc;
+    if ((rc = dev_alloc(p, &p->rows_base, rows.size()))) return rc;
+    if ((rc = dev_alloc(p, &p->counters, 2 * (kMaxLevel + 1)))) return rc;
+    if ((rc = dev_alloc(p, &p->bad, 1))) return rc;
+    if ((rc = dev_alloc(p, &p->moments, 3 * (kMaxLevel + 1)))) return rc;
+    MLMC_HIP_TRY(hipEventCreate(&p->ev0));
+    MLMC_HIP_TRY(hipEventCreate(&p->ev1));
+    MLMC_HIP_TRY(hipMemcpyAsync(p->slots, slots.data(), sizeof(SlotRec) * slots.size(), hipMemcpyHostToDevice, s));
+    if (n) MLMC_HIP_TRY(hipMemcpyAsync(p->rows_base, rows.data(), sizeof(RowRec) * rows.size(), hipMemcpyHostToDevice, s));
+    if (o->rows && o->n_rows > 0) {
+        if ((rc = dev_alloc(p, &p->req_rows, req.size()))) return rc;
+        MLMC_HIP_TRY(hipMemcpyAsync(p->req_rows, req.data(), sizeof(int64_t) * req.size(), hipMemcpyHostToDevice, s));
+    }
+    MLMC_HIP_TRY(hipMemsetAsync(p->bad, 0, sizeof(unsigned int), s));
+    if ((rc = upload_level(p, l0, s))) return rc;
+    unsigned int bad = 0;
+    MLMC_HIP_TRY(hipMemcpyAsync(&bad, p->bad, sizeof bad, hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return fail(MLMC_ERR_INVALID_ARG, "coarsest level too coarse: some row jumps in every step (r dt > 22)");
+    *out = guard.release();
+    return MLMC_OK;
+}
+
+int mlmc_expv_plan_info(const mlmc_plan_t *p, mlmc_plan_info_t *info)
+{
+    if (!p || !info) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    info->n = p->n;
+    info->n_rows = p->n_rows;
+    info->n_slots = p->n_slots;
+    info->l0 = p->l0;
+    info->precision = p->precision;
+    info->beta = p->beta;
+    info->r_max = p->r_max;
+    info->d_min = p->d_min;
+    info->d_max = p->d_max;
+    info->device_bytes = p->bytes;
+    return MLMC_OK;
+}
+
+void mlmc_expv_destroy(mlmc_plan_t *p) { free_plan(p); }
+
+int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, uint64_t seed,
+                         int32_t instance, int32_t level, uint32_t walk0, uint32_t walks, double *sum1,
+                         double *sum2, int64_t *jumps, void *stream)
+{
+    if (!p || !sum1 || !sum2) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    int rc = check_u(u, nrhs, u_dtype);
+    if (rc) return rc;
+    if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long), s));
+    rc = level_sums(p, level, seed, instance, u, u_dtype == MLMC_DTYPE_F64, nrhs, walk0, walks, sum1,
+                    sum2, 0, p->counters, s);
+    if (rc) return rc;
+    if (jumps) {
+        unsigned long long c[2];
+        MLMC_HIP_TRY(hipMemcpyAsync(c, p->counters, sizeof c, hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+        *jumps = static_cast<int64_t>(c[0]);
+        if (c[1]) return fail(MLMC_ERR_NONFINITE, std::to_string(c[1]) + " non-finite samples");
+    }
+    return MLMC_OK;
+}
+
+int mlmc_expv_trace(mlmc_plan_t *p, uint64_t seed, int32_t instance, int32_t level, int64_t count,
+                    const int64_t *rows, const uint32_t *walks, int64_t *final_state, int32_t *sign,
+                    int64_t *jumps, uint64_t *hash, double *log_fine, double *log_coarse, void *stream)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    if (count < 0) return fail(MLMC_ERR_INVALID_ARG, "count < 0");
+    if (count > 0 && (!rows || !walks || !final_state || !sign || !jumps || !hash || !log_fine || !log_coarse))
+        return fail(MLMC_ERR_INVALID_ARG, "null array");
+    if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = upload_level(p, level, s);
+    if (rc) return rc;
+    const LevelArgs L = level_args(p, level, seed, instance);
+    MLMC_HIP_TRY(launch_trace(L, p->precision == MLMC_PRECISION_FP64 ? Prec::FP64 : Prec::FP32, count, rows,
+                              walks, final_state, sign, jumps, hash, log_fine, log_coarse, s));
+    return MLMC_OK;
+}
+
+int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, const mlmc_run_opts_t *o,
+                  double *x, mlmc_stats_t *stats, void *stream)
+{
+    if (!p || !o || !x) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    int rc = check_u(u, nrhs, u_dtype);
+    if (rc) return rc;
+    if (o->instance < 0 || o->instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int u_f64 = u_dtype == MLMC_DTYPE_F64;
+    const int64_t count = p->n_rows * nrhs;
+    const bool adaptive = o->eps > 0.0;
+    int max_levels;
+    if (adaptive) {
+        if (o->pilot_walks < 2 || o->pilot_walks >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be in [2, 2^32)");
+        max_levels = o->max_levels > 0 ? o->max_levels : 20;
+        max_levels = std::min(max_levels, std::min(MLMC_MAX_LEVELS, kMaxLevel - p->l0 + 1));
+        if (max_levels < 2) return fail(MLMC_ERR_INVALID_ARG, "max_levels must allow at least two levels");
+    } else {
+        if (o->num_levels < 1 || o->num_levels > MLMC_MAX_LEVELS || p->l0 + o->num_levels - 1 > kMaxLevel)
+            return fail(MLMC_ERR_INVALID_ARG, "num_levels out of range");
+        if (!o->walks) return fail(MLMC_ERR_INVALID_ARG, "walks is null");
+        for (int qq = 0; qq < o->num_levels; ++qq)
+            if (o->walks[qq] < 1 || o->walks[qq] >= (int64_t(1) << 32))
+                return fail(MLMC_ERR_INVALID_ARG, "walks per level must be in [1, 2^32)");
+        max_levels = o->num_levels;
+    }
+    if ((rc = ensure_acc(p, max_levels, nrhs))) return rc;
+    const size_t stride = static_cast<size_t>(2) * count;
+    auto s1_of = [&](int qq) { return p->acc + qq * stride; };
+    auto s2_of = [&](int qq) { return p->acc + qq * stride + count; };
+    std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
+    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long) * (kMaxLevel + 1), s));
+    MLMC_HIP_TRY(hipEventRecord(p->ev0, s));
+    // add `extra` walks at level index qq
+    auto add_walks = [&](int qq, int64_t extra) -> int {
+        const int level = p->l0 + qq;
+        const int r2 = level_sums(p, level, o->seed, o->instance, u, u_f64, nrhs,
+                                  static_cast<uint32_t>(M[qq]), static_cast<uint64_t>(extra), s1_of(qq),
+                                  s2_of(qq), M[qq] > 0 ? 1 : 0, p->counters + 2 * qq, s);
+        if (r2) return r2;
+        M[qq] += extra;
+        return MLMC_OK;
+    };
+    struct Mom { double sum_m, sum_m2, sum_v; };
+    std::vector<Mom> mom(static_cast<size_t>(max_levels));
+    std::vector<unsigned long long> ctr(2 * static_cast<size_t>(kMaxLevel + 1));
+    auto read_moments = [&](int levels) -> int {
+        for (int qq = 0; qq < levels; ++qq)
+            MLMC_HIP_TRY(launch_level_moments(s1_of(qq), s2_of(qq), count, static_cast<double>(M[qq]),
+                                              p->moments + 3 * qq, s));
+        std::vector<double> h(3 * static_cast<size_t>(levels));
+        MLMC_HIP_TRY(hipMemcpyAsync(h.data(), p->moments, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), p->counters, sizeof(unsigned long long) * ctr.size(),
+                                    hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+        for (int qq = 0; qq < levels; ++qq) mom[qq] = Mom{h[3 * qq], h[3 * qq + 1], h[3 * qq + 2]};
+        return MLMC_OK;
+    };
+    const double cnt = static_cast<double>(std::max<int64_t>(count, 1));
+    auto level_var = [&](int qq) { return mom[qq].sum_v / cnt; };
+    auto level_rms = [&](int qq) { return std::sqrt(mom[qq].sum_m2 / cnt); };
+    auto level_cost = [&](int qq) {
+        const double walks_total = static_cast<double>(M[qq]) * std::max<int64_t>(p->n_rows, 1);
+        return std::ldexp(1.0, p->l0 + qq) + 4.0 * static_cast<double>(ctr[2 * qq]) / walks_total;
+    };
+    int levels = 0;
+    bool converged = false;
+    int iterations = 0;
+    double bias = 0.0;
+    if (!adaptive) {
+        levels = o->num_levels;
+        for (int qq = 0; qq < levels; ++qq)
+            if ((rc = add_walks(qq, o->walks[qq]))) return rc;
+        MLMC_HIP_TRY(hipEventRecord(p->ev1, s));
+        converged = true;
+    } else {
+        // Algorithm 1: pilot on l0 .. l0 + 4, then optimal M_l, variance and bias tests
+        const int64_t cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
+        const double eps2 = o->eps * o->eps;
+        levels = std::min(5, max_levels);
+        for (int qq = 0; qq < levels; ++qq)
+            if ((rc = add_walks(qq, o->pilot_walks))) return rc;
+        for (;;) {
+            ++iterations;
+            if ((rc = read_moments(levels))) return rc;
+            std::vector<double> V(levels), C(levels);
+            double tot = 0.0;
+            for (int qq = 0; qq < levels; ++qq) {
+                V[qq] = std::max(level_var(qq), 1e-300);
+                C[qq] = level_cost(qq);
+                tot += std::sqrt(V[qq] * C[qq]);
+            }
+            bool added = false;
+            for (int qq = 0; qq < levels; ++qq) {
+                const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(V[qq] / C[qq]) * tot);
+                int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
+                if (target > M[qq]) {
+                    if ((rc = add_walks(qq, target - M[qq]))) return rc;
+                    added = true;
+                }
+            }
+            if (added && (rc = read_moments(levels))) return rc;
+            double var = 0.0;
+            for (int qq = 0; qq < levels; ++qq) var += level_var(qq) / static_cast<double>(M[qq]);
+            bias = std::max(level_rms(levels - 1), level_rms(levels - 2) / 4.0) / 3.0;
+            const bool capped = [&] {
+                for (int qq = 0; qq < levels; ++qq)
+                    if (M[qq] >= cap) return true;
+                return false;
+            }();
+            if (var <= eps2 / 2.0 * 1.0000001 && bias <= o->eps / std::sqrt(2.0)) {
+                converged = true;
+                break;
+            }
+            if (levels >= max_levels || (capped && var > eps2 / 2.0 * 1.0000001)) break;
+            ++levels;
+            if ((rc = add_walks(levels - 1, o->pilot_walks))) return rc;
+        }
+        MLMC_HIP_TRY(hipEventRecord(p->ev1, s));
+    }
+    // x = sum_l m_l (FP64 combine)
+    CombineArgs ca{};
+    ca.levels = levels;
+    for (int qq = 0; qq < levels; ++qq) {
+        ca.s1[qq] = s1_of(qq);
+        ca.inv_M[qq] = 1.0 / static_cast<double>(M[qq]);
+    }
+    MLMC_HIP_TRY(launch_combine(ca, count, x, s));
+    if (stats || adaptive) {
+        if ((rc = read_moments(levels))) return rc;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->l0 = p->l0;
+        stats->num_levels = levels;
+        stats->converged = converged ? 1 : 0;
+        stats->driver_iterations = iterations;
+        double var = 0.0;
+        for (int qq = 0; qq < levels; ++qq) {
+            stats->walks[qq] = M[qq];
+            stats->jumps[qq] = static_cast<int64_t>(ctr[2 * qq]);
+            stats->level_mean_rms[qq] = level_rms(qq);
+            stats->level_var[qq] = level_var(qq);
+            stats->level_cost[qq] = level_cost(qq);
+            stats->steps += M[qq] * p->n_rows * (int64_t(1) << (p->l0 + qq));
+            stats->total_jumps += static_cast<int64_t>(ctr[2 * qq]);
+            stats->nonfinite += static_cast<int64_t>(ctr[2 * qq + 1]);
+            var += level_var(qq) / static_cast<double>(M[qq]);
+        }
+        stats->est_variance = var;
+        stats->est_bias = adaptive ? bias : 0.0;
+        float ms = 0.0f;
+        MLMC_HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+        stats->kernel_ms = ms;
+        if (stats->nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(stats->nonfinite) + " non-finite samples");
+    }
+    if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
+    return MLMC_OK;
+}
+
+}  // extern "C"

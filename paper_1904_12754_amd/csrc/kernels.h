@@ -1,0 +1,60 @@
+// Host-side launchers of the walk, threshold and reduction kernels (kernels.hip).
+#pragma once
+
+#include "common.h"
+
+namespace mlmc {
+
+// Everything a walk at one level reads.
+struct LevelArgs {
+    const RowRec *rec;       // the level's row records
+    const SlotRec *slots;    // alias tables of all rows
+    int64_t n;               // rows of A
+    uint32_t N;              // steps, 2^level
+    int32_t level;
+    int32_t base;            // 1 at the coarsest level l0 (sample u eta_fine only)
+    double dt;               // beta / 2^level
+    double half_dt;
+    uint32_t k0, k1;         // Philox key (seed)
+    uint32_t c3_step, c3_jump;
+};
+
+enum class Prec { FP64, FP32 };
+
+// Fill rec[i].thr for one level: the largest word w with -ln U(w) / r_i >= dt (no jump).
+// Sets *bad if some row jumps at every word (r_i dt too large for 32-bit words).
+hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *bad,
+                             hipStream_t s);
+
+// Per-(row, chunk) partial sums of Y and Y^2 for walks [walk0, walk0 + M) of each
+// requested row. partial: n_rows * chunks * nrhs * 2 doubles. counters[0] += jumps,
+// counters[1] += non-finite samples.
+hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
+                              int32_t nrhs, const int64_t *rows, int64_t n_rows,
+                              uint32_t walk0, uint32_t M, uint32_t chunk, uint32_t chunks,
+                              double *partial, unsigned long long *counters, hipStream_t s);
+
+// out1/out2[q * nrhs + r] (=, or += when accumulate) the chunk sums of the partials.
+hipError_t launch_finalize(const double *partial, int64_t n_rows, uint32_t chunks,
+                           int32_t nrhs, double *out1, double *out2, int accumulate,
+                           hipStream_t s);
+
+// One level's moments over all (row, rhs): out[0] = sum m, out[1] = sum m^2,
+// out[2] = sum V, with m = s1 / M and V = max(s2 / M - m^2, 0). Deterministic order.
+hipError_t launch_level_moments(const double *s1, const double *s2, int64_t count, double M,
+                                double *out, hipStream_t s);
+
+// x[idx] = sum_q s1[q][idx] / M[q] over `levels` accumulators.
+struct CombineArgs {
+    const double *s1[64];
+    double inv_M[64];
+    int32_t levels;
+};
+hipError_t launch_combine(const CombineArgs &a, int64_t count, double *x, hipStream_t s);
+
+hipError_t launch_trace(const LevelArgs &L, Prec prec, int64_t count, const int64_t *rows,
+                        const uint32_t *walks, int64_t *final_state, int32_t *sign,
+                        int64_t *jumps, uint64_t *hash, double *log_fine, double *log_coarse,
+                        hipStream_t s);
+
+}  // namespace mlmc

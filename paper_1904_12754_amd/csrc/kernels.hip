@@ -1,0 +1,507 @@
+// Walk kernels for gfx950: the sampling of Algorithm 2 (one coupled fine/coarse path per
+// walk), per-row level sums, thresholds, moments and the FP64 level combine.
+//
+// Walk (section 2.1, section 3, Algorithm 2). A walk at level l starts at row i and takes
+// N = 2^l steps of length dt = beta / N. In each step the chain holds at its state k for
+// an exponential time of rate r_k and, while the accumulated time stays below dt, jumps
+// to j with probability |a_kj| / r_k, flipping its sign when a_kj < 0; the holding time
+// after a jump has the rate of the state jumped to. Only the states at the grid points
+// 0..N enter the weights:
+//   fine   (level l):    E_f = dt * sum_n (d_{s_{n-1}} + d_{s_n}) / 2
+//   coarse (level l-1):  E_c = dt * sum_m (d_{s_{2m-2}} + d_{s_{2m}})
+// i.e. the Strang factors of section 2.1 multiplied out (the products of Algorithm 2's
+// eta_2 and eta_1). A run of grid points [a, b] held at one state k adds d_k times an
+// integer count to 2 E_f / dt, 2 E_c / dt and 2 (E_f - E_c) / dt, so the work on
+// weights is O(jumps), and steps without a jump touch no memory. The sample is
+//   Y = phi u_{s_N} e^{E_f}                       at l = l0,
+//   Y = phi u_{s_N} (e^{E_f} - e^{E_c})
+//     = phi u_{s_N} e^{E_c} expm1(E_f - E_c)      at l > l0,
+// and a walk with no jump has E_f = E_c exactly, so Y = 0 (the "no transition" case of
+// the paper's Fig. 1).
+//
+// Step test. A step of state k jumps iff the holding time -ln U(w) / r_k drawn from the
+// step's word w is below dt. Because -ln U(w) decreases in w, this is the integer test
+// w > thr_k(l) with thr from launch_thresholds, evaluated with the very same logarithm;
+// so a step without a jump costs only its share of one Philox block (four steps per
+// block) and a compare.
+#include "common.h"
+#include "kernels.h"
+
+#include <cmath>
+
+namespace mlmc {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+template <typename R>
+__device__ __forceinline__ R d_of(const RowRec &r);
+template <>
+__device__ __forceinline__ float d_of<float>(const RowRec &r) { return r.d32; }
+template <>
+__device__ __forceinline__ double d_of<double>(const RowRec &r) { return r.d64; }
+
+__device__ __forceinline__ float expR(float x) { return expf(x); }
+__device__ __forceinline__ double expR(double x) { return exp(x); }
+__device__ __forceinline__ float expm1R(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1R(double x) { return expm1(x); }
+
+template <typename R>
+struct WalkOut {
+    uint32_t k;       // final state
+    uint32_t neg;     // 1 if the product of jump signs is -1
+    uint32_t jumps;
+    uint64_t hash;
+    R ef2, ec2, ed2;  // 2/dt times E_f, E_c, E_f - E_c
+};
+
+// Add the grid points a..b (held at one state with weight d) to the three sums.
+template <typename R>
+__device__ __forceinline__ void add_run(R d, uint32_t a, uint32_t b, uint32_t N, R &ef2, R &ec2,
+                                        R &ed2)
+{
+    const int a0 = (a == 0), bN = (b == N);
+    const int f2 = 2 * static_cast<int>(b - a + 1) - a0 - bN;                 // 2 sum w_f
+    const int even = static_cast<int>(b >> 1) - static_cast<int>((a + 1) >> 1) + 1;
+    const int c2 = 4 * even - 2 * a0 - 2 * bN;                                 // 2 sum w_c
+    ef2 += d * static_cast<R>(f2);
+    ec2 += d * static_cast<R>(c2);
+    ed2 += d * static_cast<R>(f2 - c2);
+}
+
+template <typename R, bool kHash>
+__device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row, uint32_t walk)
+{
+    RowRec cur = L.rec[row];
+    uint32_t k = row, neg = 0, J = 0, run_start = 0;
+    uint64_t h = kFnvOffset;
+    R ef2 = 0, ec2 = 0, ed2 = 0;
+    const uint32_t nblk = (L.N + 3) >> 2;
+    for (uint32_t q = 0; q < nblk; ++q) {
+        Word4 w = philox10(Word4{q, walk, row, L.c3_step}, L.k0, L.k1);
+        if (L.N < 4) {          // levels 0 and 1: words past step N never jump
+            w.w = 0;
+            w.z = 0;
+            if (L.N < 2) w.y = 0;
+        }
+        const uint32_t mx = max(max(w.x, w.y), max(w.z, w.w));
+        if (mx <= cur.thr) continue;
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (ws[m] <= cur.thr) continue;
+            const uint32_t n = 4 * q + m;   // 0-based step: the jump falls between grid n and n+1
+            add_run<R>(d_of<R>(cur), run_start, n, L.N, ef2, ec2, ed2);
+            double tau = neg_log_uniform(ws[m]) * cur.inv_r;
+            do {
+                const Word4 jw = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
+                const uint32_t slot = mulhi32(jw.x, cur.deg);
+                const SlotRec s = L.slots[cur.slot_begin + slot];
+                const uint32_t cs = (jw.y < s.thr) ? s.own : s.alias;
+                k = cs & kColMask;
+                neg ^= cs >> 31;
+                cur = L.rec[k];
+                ++J;
+                if (kHash) {
+                    h = (h ^ static_cast<uint64_t>(k)) * kFnvPrime;
+                    h = (h ^ static_cast<uint64_t>(n + 1)) * kFnvPrime;
+                }
+                tau = tau + neg_log_uniform(jw.z) * cur.inv_r;
+            } while (tau < L.dt);
+            run_start = n + 1;
+        }
+    }
+    add_run<R>(d_of<R>(cur), run_start, L.N, L.N, ef2, ec2, ed2);
+    WalkOut<R> o;
+    o.k = k;
+    o.neg = neg;
+    o.jumps = J;
+    o.hash = h;
+    o.ef2 = ef2;
+    o.ec2 = ec2;
+    o.ed2 = ed2;
+    return o;
+}
+
+// The sample without its u factor: +-e^{E_f} at the base level, +-e^{E_c} expm1(E_f - E_c)
+// above it.
+template <typename R>
+__device__ __forceinline__ R weight_of(const WalkOut<R> &o, int base, R hd)
+{
+    R v = base ? expR(o.ef2 * hd) : expR(o.ec2 * hd) * expm1R(o.ed2 * hd);
+    return o.neg ? -v : v;
+}
+
+template <typename R>
+struct Kahan {
+    R s = 0, c = 0;
+    __device__ __forceinline__ void add(R x)
+    {
+        const R y = x - c;
+        const R t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const
+    {
+        return static_cast<double>(s) - static_cast<double>(c);
+    }
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename U>
+__device__ __forceinline__ double load_u(const U *u, uint64_t idx)
+{
+    return static_cast<double>(u[idx]);
+}
+
+// One wave per (row, chunk) item, lanes stride over the chunk's walks; single RHS.
+template <typename R, typename U>
+__global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
+                                                         const int64_t *__restrict__ rows,
+                                                         uint32_t n_rows, uint32_t walk0,
+                                                         uint32_t M, uint32_t chunk,
+                                                         uint32_t chunks, double *partial,
+                                                         unsigned long long *counters)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
+    const uint32_t q = static_cast<uint32_t>(item / chunks);
+    const uint32_t c = static_cast<uint32_t>(item % chunks);
+    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
+    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
+    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    const R hd = static_cast<R>(L.half_dt);
+    Kahan<R> s1, s2;
+    unsigned long long jumps = 0, nonfinite = 0;
+    for (uint64_t w = wb + lane; w < we; w += kWave) {
+        const WalkOut<R> o = run_walk<R, false>(L, row, walk0 + static_cast<uint32_t>(w));
+        jumps += o.jumps;
+        const R y = weight_of<R>(o, L.base, hd) * static_cast<R>(load_u(u, o.k));
+        nonfinite += !isfinite(y);
+        s1.add(y);
+        s2.add(y * y);
+    }
+    const double a = wave_sum(s1.value());
+    const double b = wave_sum(s2.value());
+    jumps = wave_sum_u(jumps);
+    nonfinite = wave_sum_u(nonfinite);
+    if (lane == 0) {
+        partial[item * 2 + 0] = a;
+        partial[item * 2 + 1] = b;
+        atomicAdd(&counters[0], jumps);
+        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+    }
+}
+
+// Several right-hand sides: each lane runs a walk, then the wave walks through the 64
+// results and lane r accumulates right-hand side r (+64 g) from the contiguous row
+// u[k, :]. Walks without a jump all end at the start row with the same weight, so they
+// are counted and added once at the end.
+constexpr int kMaxRhsGroups = 4;   // up to 256 right-hand sides
+
+template <typename R, typename U>
+__global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
+                                                          int32_t nrhs,
+                                                          const int64_t *__restrict__ rows,
+                                                          uint32_t n_rows, uint32_t walk0,
+                                                          uint32_t M, uint32_t chunk,
+                                                          uint32_t chunks, double *partial,
+                                                          unsigned long long *counters)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
+    const uint32_t q = static_cast<uint32_t>(item / chunks);
+    const uint32_t c = static_cast<uint32_t>(item % chunks);
+    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
+    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
+    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    const R hd = static_cast<R>(L.half_dt);
+    const int groups = (nrhs + kWave - 1) / kWave;
+    Kahan<R> s1[kMaxRhsGroups], s2[kMaxRhsGroups];
+    unsigned long long jumps = 0, nojump = 0, nonfinite = 0;
+    for (uint64_t base = wb; base < we; base += kWave) {
+        const uint64_t w = base + lane;
+        uint32_t k = row;
+        R W = 0;
+        if (w < we) {
+            const WalkOut<R> o = run_walk<R, false>(L, row, walk0 + static_cast<uint32_t>(w));
+            jumps += o.jumps;
+            if (o.jumps == 0) {
+                ++nojump;
+            } else {
+                k = o.k;
+                W = weight_of<R>(o, L.base, hd);
+            }
+        }
+        for (int t = 0; t < kWave; ++t) {
+            const R Wt = __shfl(W, t, kWave);
+            if (Wt == static_cast<R>(0)) continue;     // wave-uniform
+            const uint32_t kt = __shfl(k, t, kWave);
+#pragma unroll
+            for (int g = 0; g < kMaxRhsGroups; ++g) {
+                const int r = static_cast<int>(lane) + g * kWave;
+                if (g < groups && r < nrhs) {
+                    const R y = Wt * static_cast<R>(load_u(u, static_cast<uint64_t>(kt) * nrhs + r));
+                    nonfinite += !isfinite(y);
+                    s1[g].add(y);
+                    s2[g].add(y * y);
+                }
+            }
+        }
+    }
+    jumps = wave_sum_u(jumps);
+    nojump = wave_sum_u(nojump);
+    // walks without a jump: Y = u_row e^{d_row beta} at the base level, 0 above it
+    double y0 = 0.0;
+    if (nojump && L.base) {
+        const RowRec rr = L.rec[row];
+        const R ef2 = d_of<R>(rr) * static_cast<R>(2 * L.N);
+        y0 = static_cast<double>(expR(ef2 * hd));
+    }
+#pragma unroll
+    for (int g = 0; g < kMaxRhsGroups; ++g) {
+        const int r = static_cast<int>(lane) + g * kWave;
+        if (g < groups && r < nrhs) {
+            double a = s1[g].value(), b = s2[g].value();
+            if (y0 != 0.0) {
+                const double yr = static_cast<double>(
+                    static_cast<R>(y0) * static_cast<R>(load_u(u, static_cast<uint64_t>(row) * nrhs + r)));
+                a += static_cast<double>(nojump) * yr;
+                b += static_cast<double>(nojump) * yr * yr;
+            }
+            partial[(item * nrhs + r) * 2 + 0] = a;
+            partial[(item * nrhs + r) * 2 + 1] = b;
+        }
+    }
+    nonfinite = wave_sum_u(nonfinite);
+    if (lane == 0) {
+        atomicAdd(&counters[0], jumps);
+        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+    }
+}
+
+__global__ void thresholds_kernel(RowRec *rec, int64_t n, double dt, unsigned int *bad)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv_r = rec[i].inv_r;
+    uint32_t thr;
+    if (!(inv_r < INFINITY)) {
+        thr = 0xFFFFFFFFu;                                    // absorbing: never jumps
+    } else if (neg_log_uniform(0xFFFFFFFFu) * inv_r >= dt) {
+        thr = 0xFFFFFFFFu;                                    // no word is small enough
+    } else if (neg_log_uniform(0u) * inv_r < dt) {
+        atomicOr(bad, 1u);                                    // every word jumps
+        thr = 0u;
+    } else {
+        // largest w with -ln U(w) / r >= dt: invariant tau(lo) >= dt > tau(hi)
+        uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+        while (hi - lo > 1u) {
+            const uint32_t mid = lo + (hi - lo) / 2u;
+            if (neg_log_uniform(mid) * inv_r >= dt) lo = mid;
+            else hi = mid;
+        }
+        thr = lo;
+    }
+    rec[i].thr = thr;
+}
+
+__global__ void finalize_kernel(const double *__restrict__ partial, int64_t n_rows,
+                                uint32_t chunks, int32_t nrhs, double *out1, double *out2,
+                                int accumulate)
+{
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n_rows * nrhs) return;
+    const int64_t q = idx / nrhs;
+    const int64_t r = idx % nrhs;
+    double a = 0.0, b = 0.0;
+    for (uint32_t c = 0; c < chunks; ++c) {
+        const int64_t p = ((q * chunks + c) * nrhs + r) * 2;
+        a += partial[p];
+        b += partial[p + 1];
+    }
+    if (accumulate) {
+        out1[idx] += a;
+        out2[idx] += b;
+    } else {
+        out1[idx] = a;
+        out2[idx] = b;
+    }
+}
+
+constexpr int kMomentThreads = 1024;
+
+__global__ __launch_bounds__(kMomentThreads) void moments_kernel(const double *__restrict__ s1,
+                                                                 const double *__restrict__ s2,
+                                                                 int64_t count, double M,
+                                                                 double *out)
+{
+    __shared__ double sh[3][kMomentThreads];
+    double a = 0.0, b = 0.0, v = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kMomentThreads) {
+        const double m = s1[i] / M;
+        a += m;
+        b += m * m;
+        v += fmax(s2[i] / M - m * m, 0.0);
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    sh[2][threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kMomentThreads / 2; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0][0];
+        out[1] = sh[1][0];
+        out[2] = sh[2][0];
+    }
+}
+
+__global__ void combine_kernel(CombineArgs a, int64_t count, double *x)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double v = 0.0;
+    for (int q = 0; q < a.levels; ++q) v += a.s1[q][i] * a.inv_M[q];
+    x[i] = v;
+}
+
+template <typename R>
+__global__ void trace_kernel(LevelArgs L, int64_t count, const int64_t *__restrict__ rows,
+                             const uint32_t *__restrict__ walks, int64_t *final_state,
+                             int32_t *sign, int64_t *jumps, uint64_t *hash, double *log_fine,
+                             double *log_coarse)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t row = rows[i];
+    if (row < 0 || row >= L.n) {       // not a row of A: no walk
+        final_state[i] = -1;
+        sign[i] = 0;
+        jumps[i] = 0;
+        hash[i] = 0;
+        log_fine[i] = 0.0;
+        log_coarse[i] = 0.0;
+        return;
+    }
+    const WalkOut<R> o = run_walk<R, true>(L, static_cast<uint32_t>(row), walks[i]);
+    const R hd = static_cast<R>(L.half_dt);
+    final_state[i] = o.k;
+    sign[i] = o.neg ? -1 : 1;
+    jumps[i] = o.jumps;
+    hash[i] = o.hash;
+    log_fine[i] = static_cast<double>(o.ef2 * hd);
+    log_coarse[i] = static_cast<double>(o.ec2 * hd);
+}
+
+uint32_t blocks_for(int64_t n, int threads)
+{
+    return static_cast<uint32_t>((n + threads - 1) / threads);
+}
+
+}  // namespace
+
+hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *bad, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(thresholds_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, rec, n, dt, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
+                              int32_t nrhs, const int64_t *rows, int64_t n_rows, uint32_t walk0,
+                              uint32_t M, uint32_t chunk, uint32_t chunks, double *partial,
+                              unsigned long long *counters, hipStream_t s)
+{
+    const uint64_t items = static_cast<uint64_t>(n_rows) * chunks;
+    if (items == 0) return hipSuccess;
+    const dim3 grid(static_cast<uint32_t>((items + kWavesPerBlock - 1) / kWavesPerBlock));
+    const dim3 block(kBlock);
+    const uint32_t nr = static_cast<uint32_t>(n_rows);
+#define MLMC_LAUNCH_WALKS(R, U)                                                               \
+    do {                                                                                      \
+        if (nrhs == 1)                                                                        \
+            hipLaunchKernelGGL((level_walks_r1<R, U>), grid, block, 0, s, L,                  \
+                               static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
+                               partial, counters);                                            \
+        else                                                                                  \
+            hipLaunchKernelGGL((level_walks_rhs<R, U>), grid, block, 0, s, L,                 \
+                               static_cast<const U *>(u), nrhs, rows, nr, walk0, M, chunk,    \
+                               chunks, partial, counters);                                    \
+    } while (0)
+    if (prec == Prec::FP64) {
+        if (u_f64) MLMC_LAUNCH_WALKS(double, double);
+        else MLMC_LAUNCH_WALKS(double, float);
+    } else {
+        if (u_f64) MLMC_LAUNCH_WALKS(float, double);
+        else MLMC_LAUNCH_WALKS(float, float);
+    }
+#undef MLMC_LAUNCH_WALKS
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partial, int64_t n_rows, uint32_t chunks, int32_t nrhs,
+                           double *out1, double *out2, int accumulate, hipStream_t s)
+{
+    const int64_t count = n_rows * nrhs;
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, partial,
+                       n_rows, chunks, nrhs, out1, out2, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_moments(const double *s1, const double *s2, int64_t count, double M,
+                                double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(kMomentThreads), 0, s, s1, s2, count, M, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineArgs &a, int64_t count, double *x, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, count, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const LevelArgs &L, Prec prec, int64_t count, const int64_t *rows,
+                        const uint32_t *walks, int64_t *final_state, int32_t *sign,
+                        int64_t *jumps, uint64_t *hash, double *log_fine, double *log_coarse,
+                        hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const dim3 grid(blocks_for(count, 256));
+    if (prec == Prec::FP64)
+        hipLaunchKernelGGL(trace_kernel<double>, grid, dim3(256), 0, s, L, count, rows, walks,
+                           final_state, sign, jumps, hash, log_fine, log_coarse);
+    else
+        hipLaunchKernelGGL(trace_kernel<float>, grid, dim3(256), 0, s, L, count, rows, walks,
+                           final_state, sign, jumps, hash, log_fine, log_coarse);
+    return hipGetLastError();
+}
+
+}  // namespace mlmc

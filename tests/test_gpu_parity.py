@@ -1,0 +1,215 @@
+"""Parity of the HIP path (through the C-ABI) with the oracle, on identical seeded inputs.
+
+Bars (derived in the design doc):
+  - paths: final state, sign, jump count and the FNV path hash are bit-exact;
+  - FP64 weights: per-row level sums within 1e-12 of the oracle's, relative to the row's
+    absolute mass  sum_w |u_j| (|eta_fine| + |eta_coarse|)  (the scale of the rounding of
+    each sample; the oracle multiplies factors, the kernel sums exponents);
+  - FP32 weights: within 1e-5 of the same mass.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlmc as orc
+from oracle import reference
+from paper_1904_12754_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1904_12754_amd import api as _api
+    return _api
+
+
+def _tables(A):
+    return orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+
+
+def _signed(n, seed, density=0.5, scale=1.0):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(n, n)) * (rng.random((n, n)) < density) * scale
+    return a
+
+
+def _check_trace(api, A, beta, precision, levels, rows, walks, seed, l0=None, instance=0):
+    plan = api.Plan(A, beta, precision=precision, l0=l0)
+    t = _tables(A)
+    for lev in levels:
+        _say(f"trace n={A.n} prec={precision} level={lev} walks={len(rows)}")
+        g = plan.trace(lev, rows, walks, seed=seed, instance=instance)
+        o = orc.walk_trace(t, beta, lev, seed, rows, walks, instance=instance)
+        assert np.array_equal(g["final_state"].cpu().numpy(), o.final_state)
+        assert np.array_equal(g["sign"].cpu().numpy(), o.sign)
+        assert np.array_equal(g["jumps"].cpu().numpy(), o.jumps)
+        assert np.array_equal(g["hash"].cpu().numpy().view(np.uint64), o.hash)
+        lf = g["log_eta_fine"].cpu().numpy()
+        ref = np.log(np.abs(o.eta_fine))
+        tol = 1e-12 if precision == "fp64" else 1e-5
+        assert np.max(np.abs(lf - ref) / (1.0 + np.abs(ref))) < tol
+        if lev > 0:
+            lc = g["log_eta_coarse"].cpu().numpy()
+            refc = np.log(np.abs(o.eta_coarse))
+            assert np.max(np.abs(lc - refc) / (1.0 + np.abs(refc))) < tol
+        assert o.jumps.sum() > 0
+    plan.close()
+
+
+def test_trace_bit_exact_laplace1d_fp64(api):
+    A, t, v = inputs.workload_laplace1d()
+    M = 2000
+    rows = np.repeat(np.arange(A.n), M // 20)[:M]
+    walks = np.arange(M, dtype=np.uint32) * 7919
+    _check_trace(api, A, t, "fp64", range(3, 7), rows, walks, seed=123)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trace_bit_exact_signed_all_levels(api, precision):
+    a = _signed(40, 3, density=0.3)
+    a[5, :] = 0.0
+    a[5, 5] = 0.3                        # absorbing row
+    a[7, :] *= 6.0                       # a fast row
+    A = inputs.from_dense(a)
+    beta = 0.5
+    M = 4096
+    rng = np.random.default_rng(1)
+    rows = rng.integers(0, A.n, size=M)
+    walks = rng.integers(0, 2 ** 32, size=M, dtype=np.uint64).astype(np.uint32)
+    # levels 0 and 1 have fewer than four steps (partial Philox block)
+    _check_trace(api, A, beta, precision, range(0, 7), rows, walks, seed=2 ** 40 + 17, l0=0,
+                 instance=9)
+
+
+def _mass_tol(o_ls, prec):
+    return TOL[prec] * (o_ls.mass + 1e-300)
+
+
+def _check_level_sums(api, A, beta, u, precision, levels, walks, seed, rows=None,
+                      values_dtype=np.float64, walk0=0):
+    plan = api.Plan(A, beta, precision=precision, rows=rows, values_dtype=values_dtype)
+    vals = np.asarray(A.values, dtype=values_dtype).astype(np.float64)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, vals)
+    ut = torch.as_tensor(np.ascontiguousarray(u), device="cuda")
+    for lev in levels:
+        _say(f"level_sums n={A.n} prec={precision} level={lev} M={walks} R={ut.shape[-1] if ut.dim() > 1 else 1}")
+        s1, s2, jumps = plan.level_sums(ut, lev, walk0, walks, seed=seed)
+        o = orc.level_sums(t, beta, lev, plan.l0, seed, u, rows, walk0, walks)
+        assert jumps == int(o.jumps.sum())
+        g1 = s1.cpu().numpy()
+        g2 = s2.cpu().numpy()
+        assert np.all(np.abs(g1 - o.sum1) <= _mass_tol(o, precision))
+        # sums of squares: the error of each Y^2 is below 2 tol m_w^2
+        assert np.all(np.abs(g2 - o.sum2) <= 4 * TOL[precision] * (o.mass2 + 1e-300))
+    plan.close()
+
+
+def test_level_sums_fp64_laplace1d_ragged(api):
+    A, t, v = inputs.workload_laplace1d()
+    _check_level_sums(api, A, t, v, "fp64", range(3, 7), 3001, seed=5)
+
+
+def test_level_sums_fp32_laplace1d(api):
+    A, t, v = inputs.workload_laplace1d()
+    _check_level_sums(api, A, t, v, "fp32", range(3, 7), 2048, seed=6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_level_sums_signed_u32_walk_offset(api, precision):
+    a = _signed(60, 11, density=0.2)
+    A = inputs.from_dense(a)
+    u = np.random.default_rng(2).normal(size=60)
+    beta = 0.7
+    # walk indices near the top of the 32-bit range
+    _check_level_sums(api, A, beta, u, precision, range(2, 5), 777, seed=9,
+                      walk0=2 ** 32 - 800)
+
+
+@pytest.mark.parametrize("R", [3, 64, 130])
+def test_level_sums_multi_rhs(api, R):
+    A = inputs.barabasi_albert(3000, 3, seed=4)
+    dmax = float(np.diff(A.row_ptr).max())
+    beta = 1.0 / dmax
+    u = inputs.rhs_ones_rademacher(A.n, R, seed=7)
+    rows = np.random.default_rng(3).choice(A.n, size=300, replace=False)
+    rows[0] = int(np.argmax(np.diff(A.row_ptr)))            # the hub
+    _check_level_sums(api, A, beta, u, "fp32", range(1, 4), 200, seed=3, rows=rows,
+                      values_dtype=np.float32)
+
+
+def test_level_sums_full_size_laplace2d_sampled_rows(api):
+    """The 256 x 256 workload at its full size, in the launch configuration of the
+    benchmark, on 384 sampled rows (FP32 weights, levels 2..7)."""
+    A, t, v = inputs.workload_laplace2d(256)
+    rows = np.random.default_rng(8).choice(A.n, size=384, replace=False)
+    _check_level_sums(api, A, t, v, "fp32", range(2, 8), 256, seed=77, rows=rows)
+
+
+def test_walk_ranges_split_exactly(api):
+    """Walks are addressed by counters: [0, M) = [0, a) + [a, M) in counts and sums."""
+    A, t, v = inputs.workload_laplace1d()
+    plan = api.Plan(A, t, precision="fp64")
+    u = torch.as_tensor(v, device="cuda")
+    lev = plan.l0 + 1
+    s1, s2, j = plan.level_sums(u, lev, 0, 5000, seed=1)
+    a1, a2, ja = plan.level_sums(u, lev, 0, 1234, seed=1)
+    b1, b2, jb = plan.level_sums(u, lev, 1234, 5000 - 1234, seed=1)
+    assert j == ja + jb
+    assert torch.allclose(s1, a1 + b1, rtol=1e-13, atol=1e-15)
+    plan.close()
+
+
+def test_run_fixed_schedule_matches_oracle(api):
+    A, t, v = inputs.workload_laplace1d()
+    walks = [8000, 4000, 2000, 1000]
+    plan = api.Plan(A, t, precision="fp64")
+    x, st = plan.run(torch.as_tensor(v, device="cuda"), walks=walks, seed=31)
+    tt = _tables(A)
+    res = orc.mlmc_fixed(tt, t, v, plan.l0, plan.l0 + 3, walks, seed=31)
+    assert st["steps"] == res.steps
+    assert st["total_jumps"] == res.jumps
+    assert st["walks"] == walks
+    xg = x.cpu().numpy()[:, 0]
+    assert np.all(np.abs(xg - res.x[:, 0]) <= 1e-12 * res.mass[:, 0])
+    plan.close()
+
+
+def test_diagonal_matrix_and_empty_rows(api):
+    d = np.array([-1.0, 0.0, 0.5, 2.0])
+    A = inputs.from_dense(np.diag(d))
+    u = np.array([1.0, 2.0, -3.0, 0.5])
+    plan = api.Plan(A, 0.3, precision="fp64")
+    x, st = plan.run(torch.as_tensor(u, device="cuda"), walks=[64, 64, 64], seed=1)
+    assert st["total_jumps"] == 0
+    assert np.allclose(x.cpu().numpy()[:, 0], np.exp(0.3 * d) * u, rtol=1e-14, atol=0)
+    plan.close()
+    empty = api.Plan(A, 0.3, precision="fp32", rows=np.zeros(0, np.int64))
+    x, st = empty.run(torch.as_tensor(u, device="cuda"), walks=[64, 64], seed=1)
+    assert x.shape == (0, 1) and st["steps"] == 0
+    empty.close()
+
+
+def test_adaptive_run_reaches_target(api):
+    A, t, v = inputs.workload_laplace1d()
+    plan = api.Plan(A, t, precision="fp64")
+    eps = 1e-3
+    x, st = plan.run(torch.as_tensor(v, device="cuda"), eps=eps, seed=2, pilot_walks=1000)
+    assert st["converged"]
+    assert st["est_variance"] <= eps * eps / 2 * 1.0001
+    exact = reference.laplace1d_exact(v, t)
+    rmse = math.sqrt(float(np.mean((x.cpu().numpy()[:, 0] - exact) ** 2)))
+    _say(f"adaptive eps={eps}: rmse={rmse:.3e} levels={st['num_levels']} walks={st['walks']}")
+    assert rmse < 3 * eps
+    plan.close()
