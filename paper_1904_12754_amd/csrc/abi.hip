@@ -419,7 +419,8 @@ int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_
                          int32_t instance, int32_t level, uint32_t walk0, uint32_t walks, double *sum1,
                          double *sum2, int64_t *jumps, void *stream)
 {
-    if (!p || !sum1 || !sum2) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    if (p->n_rows > 0 && (!sum1 || !sum2)) return fail(MLMC_ERR_INVALID_ARG, "null output");
     int rc = check_u(u, nrhs, u_dtype);
     if (rc) return rc;
     if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
@@ -461,7 +462,8 @@ int mlmc_expv_trace(mlmc_plan_t *p, uint64_t seed, int32_t instance, int32_t lev
 int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, const mlmc_run_opts_t *o,
                   double *x, mlmc_stats_t *stats, void *stream)
 {
-    if (!p || !o || !x) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (!p || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (!x && p->n_rows > 0) return fail(MLMC_ERR_INVALID_ARG, "x is null");
     int rc = check_u(u, nrhs, u_dtype);
     if (rc) return rc;
     if (o->instance < 0 || o->instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
