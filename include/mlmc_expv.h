@@ -129,7 +129,12 @@ typedef struct {
     int64_t nonfinite;                       /* samples that were not finite */
     double est_variance;                     /* sum_l level_var / M_l */
     double est_bias;                         /* Algorithm 1's extrapolated bias (0 if fixed) */
-    double kernel_ms;                        /* device time of the walk kernels */
+    double kernel_ms;                        /* device time from the first walk launch to the
+                                                last (includes reductions and, in adaptive
+                                                runs, host round trips between iterations) */
+    double walk_kernel_ms;                   /* sum of the walk-kernel durations alone, timed
+                                                with a pair of events around each launch */
+    int64_t walk_launches;                   /* walk-kernel launches in the run */
 } mlmc_stats_t;
 
 /* Build a plan: validate A, split A = D - T, build the alias tables of the jump law and

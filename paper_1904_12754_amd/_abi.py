@@ -77,7 +77,9 @@ class Stats(ctypes.Structure):
                 ("steps", ctypes.c_int64), ("total_jumps", ctypes.c_int64),
                 ("nonfinite", ctypes.c_int64),
                 ("est_variance", ctypes.c_double), ("est_bias", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double),
+                ("walk_kernel_ms", ctypes.c_double),
+                ("walk_launches", ctypes.c_int64)]
 
     def to_dict(self) -> dict:
         L = self.num_levels
@@ -90,6 +92,7 @@ class Stats(ctypes.Structure):
             "steps": self.steps, "total_jumps": self.total_jumps, "nonfinite": self.nonfinite,
             "est_variance": self.est_variance, "est_bias": self.est_bias,
             "kernel_ms": self.kernel_ms,
+            "walk_kernel_ms": self.walk_kernel_ms, "walk_launches": self.walk_launches,
         }
 
 

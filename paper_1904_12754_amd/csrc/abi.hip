@@ -55,6 +55,10 @@ struct mlmc_plan {
     double *acc = nullptr;                   // 2 * n_rows * nrhs per level
     size_t acc_doubles = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-launch timing of the walk kernel (pairs of events around each launch)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
     int64_t bytes = 0;
 };
 
@@ -89,6 +93,7 @@ void free_plan(mlmc_plan *p)
     hipFree(p->acc);
     if (p->ev0) hipEventDestroy(p->ev0);
     if (p->ev1) hipEventDestroy(p->ev1);
+    for (hipEvent_t e : p->tev) hipEventDestroy(e);
     delete p;
 }
 
@@ -209,10 +214,22 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
         const uint64_t nch = std::min(chunks_per_launch, total_chunks - c0);
         const uint64_t wb = c0 * chunk;
         const uint64_t Msub = std::min<uint64_t>(M - wb, nch * chunk);
+        if (p->timing) {
+            while (p->tev.size() < p->tev_used + 2) {
+                hipEvent_t e;
+                MLMC_HIP_TRY(hipEventCreate(&e));
+                p->tev.push_back(e);
+            }
+            MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used], s));
+        }
         MLMC_HIP_TRY(launch_level_walks(L, prec, u, u_f64, nrhs, p->req_rows, p->n_rows,
                                         walk0 + static_cast<uint32_t>(wb), static_cast<uint32_t>(Msub),
                                         static_cast<uint32_t>(chunk), static_cast<uint32_t>(nch),
                                         p->partial, counters, s));
+        if (p->timing) {
+            MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used + 1], s));
+            p->tev_used += 2;
+        }
         MLMC_HIP_TRY(launch_finalize(p->partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
                                      out2, (first && !accumulate) ? 0 : 1, s));
         first = false;
@@ -492,6 +509,8 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     auto s1_of = [&](int qq) { return p->acc + qq * stride; };
     auto s2_of = [&](int qq) { return p->acc + qq * stride + count; };
     std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
+    p->timing = stats != nullptr;
+    p->tev_used = 0;
     MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long) * (kMaxLevel + 1), s));
     MLMC_HIP_TRY(hipEventRecord(p->ev0, s));
     // add `extra` walks at level index qq
@@ -615,6 +634,14 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
         float ms = 0.0f;
         MLMC_HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
         stats->kernel_ms = ms;
+        double wk = 0.0;
+        for (size_t e = 0; e + 1 < p->tev_used; e += 2) {
+            float t = 0.0f;
+            MLMC_HIP_TRY(hipEventElapsedTime(&t, p->tev[e], p->tev[e + 1]));
+            wk += t;
+        }
+        stats->walk_kernel_ms = wk;
+        stats->walk_launches = static_cast<int64_t>(p->tev_used / 2);
         if (stats->nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(stats->nonfinite) + " non-finite samples");
     }
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
