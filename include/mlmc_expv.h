@@ -159,11 +159,14 @@ int mlmc_expv_run(mlmc_plan_t *plan, const void *u, int32_t nrhs, int32_t u_dtyp
  * requested row, sum1 = sum Y and sum2 = sum Y^2 per (row, rhs), where Y = u_j (eta_fine -
  * eta_coarse) at levels above l0 and Y = u_j eta_fine at l0 (j the final state).
  *   sum1, sum2: DEVICE, n_rows x nrhs FP64, overwritten.
- *   jumps: HOST, nullable; receives the jump count (waits for the stream). */
+ *   jumps: HOST, nullable; receives the jump count (waits for the stream).
+ *   hash_sums: DEVICE, nullable, n_rows entries; receives per requested row the sum
+ *     (mod 2^64) of the path hashes of its walks, the hash of mlmc_expv_trace. Asking for
+ *     it selects a kernel variant that also hashes; the walks are the same. */
 int mlmc_expv_level_sums(mlmc_plan_t *plan, const void *u, int32_t nrhs, int32_t u_dtype,
                          uint64_t seed, int32_t instance, int32_t level, uint32_t walk0,
                          uint32_t walks, double *sum1, double *sum2, int64_t *jumps,
-                         void *stream);
+                         uint64_t *hash_sums, void *stream);
 
 /* Individual walks at one level, for inspection: walk walks[q] from row rows[q]
  * (rows[q] is a row index of A, not an index into the requested rows).

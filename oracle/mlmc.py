@@ -69,7 +69,8 @@ def _declare(L):
                                           ctypes.c_int32, ctypes.c_int64, _p(ctypes.c_int64),
                                           ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
                                           _p(ctypes.c_double), _p(ctypes.c_double),
-                                          _p(ctypes.c_double), _p(ctypes.c_int64), ctypes.c_int32]
+                                          _p(ctypes.c_double), _p(ctypes.c_int64),
+                                          _p(ctypes.c_uint64), ctypes.c_int32]
     L.orc_level_sums.restype = None
     L.orc_log_array.argtypes = [ctypes.c_int64, _p(ctypes.c_double), _p(ctypes.c_double)]
     L.orc_log_array.restype = None
@@ -220,6 +221,7 @@ class LevelSums:
     mass: np.ndarray   # (n_rows, R)  sum_w |u_j| (|eta_fine| + |eta_coarse|)
     mass2: np.ndarray  # (n_rows, R)  sum_w of the square of that magnitude
     jumps: np.ndarray  # (n_rows,)
+    hash_sum: np.ndarray  # (n_rows,) uint64: sum of the FNV path hashes mod 2^64
     walks: int
     steps_per_walk: int
 
@@ -238,12 +240,13 @@ def level_sums(t: Tables, beta: float, level: int, l0: int, seed: int, u, rows=N
     ms = np.zeros((nr, R), np.float64)
     ms2 = np.zeros((nr, R), np.float64)
     jp = np.zeros(nr, np.int64)
+    hs = np.zeros(nr, np.uint64)
     lib().orc_level_sums(*t.args(), float(beta), int(level), int(l0), int(seed), int(instance),
                          _ptr(u, ctypes.c_double), R, nr, _ptr(rows, ctypes.c_int64),
                          int(walk0), int(M), _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
                          _ptr(ms, ctypes.c_double), _ptr(ms2, ctypes.c_double),
-                         _ptr(jp, ctypes.c_int64), int(threads))
-    return LevelSums(s1, s2, ms, ms2, jp, int(M), 1 << int(level))
+                         _ptr(jp, ctypes.c_int64), _ptr(hs, ctypes.c_uint64), int(threads))
+    return LevelSums(s1, s2, ms, ms2, jp, hs, int(M), 1 << int(level))
 
 
 # ----------------------------------------------------------------------------------

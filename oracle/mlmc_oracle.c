@@ -336,8 +336,8 @@ static void orc_add(orc_sum *a, double x)
 /* with j the final state, for each of the R right-hand sides (u is n x R, row     */
 /* major). Outputs per (row, rhs): sum Y, sum Y^2, the magnitude                  */
 /* m = |u_j| (|eta_fine| + |eta_coarse|) (the scale of the rounding in Y) summed,  */
-/* and sum m^2; per                                                                */
-/* row: the total jump count, and the total step count M * N.                      */
+/* and sum m^2; per row: the total jump count and the sum (mod 2^64) of the path  */
+/* hashes.                                                                         */
 /* ------------------------------------------------------------------------------ */
 void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
                     const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
@@ -345,7 +345,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                     int level, int l0, uint64_t seed, uint32_t instance, const double *u,
                     int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
                     uint32_t M, double *sum1, double *sum2, double *mass, double *mass2,
-                    int64_t *jumps, int32_t nthreads)
+                    int64_t *jumps, uint64_t *hash_sum, int32_t nthreads)
 {
     orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -364,6 +364,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
         for (int64_t q = 0; q < n_rows; ++q) {
             int64_t i = rows[q];
             int64_t nj = 0;
+            uint64_t hs = 0;
             memset(a1, 0, sizeof(orc_sum) * (size_t)R);
             memset(a2, 0, sizeof(orc_sum) * (size_t)R);
             memset(am, 0, sizeof(orc_sum) * (size_t)R);
@@ -372,6 +373,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                 orc_walk_out o;
                 orc_one_walk(&t, beta, level, key, instance, i, walk0 + w, &o);
                 nj += o.jumps;
+                hs += o.hash;
                 for (int32_t rr = 0; rr < R; ++rr) {
                     double uj = u[o.final_state * R + rr];
                     double y, m;
@@ -395,6 +397,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                 mass2[q * R + rr] = am2[rr].s + am2[rr].c;
             }
             jumps[q] = nj;
+            hash_sum[q] = hs;
         }
         free(a1); free(a2); free(am); free(am2);
     }

@@ -120,7 +120,7 @@ def load() -> ctypes.CDLL:
                                 ctypes.POINTER(Stats), vp]
     L.mlmc_expv_run.restype = ctypes.c_int
     L.mlmc_expv_level_sums.argtypes = [vp, vp, i32, i32, u64, i32, i32, u32, u32, vp, vp,
-                                       ctypes.POINTER(i64), vp]
+                                       ctypes.POINTER(i64), vp, vp]
     L.mlmc_expv_level_sums.restype = ctypes.c_int
     L.mlmc_expv_trace.argtypes = [vp, u64, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.mlmc_expv_trace.restype = ctypes.c_int

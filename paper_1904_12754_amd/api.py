@@ -97,15 +97,21 @@ class Plan:
         return x, (stats.to_dict() if stats else None)
 
     def level_sums(self, u: torch.Tensor, level: int, walk0: int, walks: int, seed: int = 0,
-                   instance: int = 0, stream=None):
-        """Algorithm 2's accumulators at one level: (sum Y, sum Y^2) per (row, rhs), jumps."""
+                   instance: int = 0, stream=None, hashes: bool = False):
+        """Algorithm 2's accumulators at one level: (sum Y, sum Y^2) per (row, rhs), jumps,
+        and with hashes=True the per-row sum (mod 2^64) of the path hashes."""
         u, R, dt = _u_args(u, self.n)
         s1 = torch.empty((self.n_rows, R), dtype=torch.float64, device=u.device)
         s2 = torch.empty_like(s1)
+        hs = torch.empty(self.n_rows, dtype=torch.int64, device=u.device) if hashes else None
         jumps = ctypes.c_int64()
         check(self._lib.mlmc_expv_level_sums(self._handle, _dev_ptr(u), R, dt, seed, instance,
                                              level, walk0, walks, _dev_ptr(s1), _dev_ptr(s2),
-                                             ctypes.byref(jumps), _stream_ptr(stream)))
+                                             ctypes.byref(jumps),
+                                             _dev_ptr(hs) if hashes else None,
+                                             _stream_ptr(stream)))
+        if hashes:
+            return s1, s2, int(jumps.value), hs
         return s1, s2, int(jumps.value)
 
     def trace(self, level: int, rows, walks, seed: int = 0, instance: int = 0, stream=None):

@@ -182,7 +182,7 @@ int ensure_partial(mlmc_plan *p, size_t bytes)
 // counts are added to counters[0..1].
 int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void *u, int u_f64,
                int32_t nrhs, uint32_t walk0, uint64_t M, double *out1, double *out2, int accumulate,
-               unsigned long long *counters, hipStream_t s)
+               unsigned long long *counters, unsigned long long *hash_sums, hipStream_t s)
 {
     if (M == 0 || p->n_rows == 0) {
         if (!accumulate && p->n_rows) {
@@ -225,7 +225,7 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
         MLMC_HIP_TRY(launch_level_walks(L, prec, u, u_f64, nrhs, p->req_rows, p->n_rows,
                                         walk0 + static_cast<uint32_t>(wb), static_cast<uint32_t>(Msub),
                                         static_cast<uint32_t>(chunk), static_cast<uint32_t>(nch),
-                                        p->partial, counters, s));
+                                        p->partial, counters, hash_sums, s));
         if (p->timing) {
             MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used + 1], s));
             p->tev_used += 2;
@@ -434,7 +434,7 @@ void mlmc_expv_destroy(mlmc_plan_t *p) { free_plan(p); }
 
 int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, uint64_t seed,
                          int32_t instance, int32_t level, uint32_t walk0, uint32_t walks, double *sum1,
-                         double *sum2, int64_t *jumps, void *stream)
+                         double *sum2, int64_t *jumps, uint64_t *hash_sums, void *stream)
 {
     if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
     if (p->n_rows > 0 && (!sum1 || !sum2)) return fail(MLMC_ERR_INVALID_ARG, "null output");
@@ -444,8 +444,10 @@ int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_
     if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long), s));
+    if (hash_sums && p->n_rows > 0)
+        MLMC_HIP_TRY(hipMemsetAsync(hash_sums, 0, sizeof(uint64_t) * p->n_rows, s));
     rc = level_sums(p, level, seed, instance, u, u_dtype == MLMC_DTYPE_F64, nrhs, walk0, walks, sum1,
-                    sum2, 0, p->counters, s);
+                    sum2, 0, p->counters, reinterpret_cast<unsigned long long *>(hash_sums), s);
     if (rc) return rc;
     if (jumps) {
         unsigned long long c[2];
@@ -518,7 +520,7 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
         const int level = p->l0 + qq;
         const int r2 = level_sums(p, level, o->seed, o->instance, u, u_f64, nrhs,
                                   static_cast<uint32_t>(M[qq]), static_cast<uint64_t>(extra), s1_of(qq),
-                                  s2_of(qq), M[qq] > 0 ? 1 : 0, p->counters + 2 * qq, s);
+                                  s2_of(qq), M[qq] > 0 ? 1 : 0, p->counters + 2 * qq, nullptr, s);
         if (r2) return r2;
         M[qq] += extra;
         return MLMC_OK;

@@ -59,11 +59,13 @@ __host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b)
 
 __host__ __device__ __forceinline__ Word4 philox10(Word4 c, uint32_t k0, uint32_t k1)
 {
+    // the 32x32->64 products map to one v_mad_u64_u32 each on gfx950
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t hi_a = mulhi32(0xD2511F53u, c.x), lo_a = 0xD2511F53u * c.x;
-        const uint32_t hi_b = mulhi32(0xCD9E8D57u, c.z), lo_b = 0xCD9E8D57u * c.z;
-        c = Word4{hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a};
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c.x;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+        c = Word4{static_cast<uint32_t>(pb >> 32) ^ c.y ^ k0, static_cast<uint32_t>(pb),
+                  static_cast<uint32_t>(pa >> 32) ^ c.w ^ k1, static_cast<uint32_t>(pa)};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -28,11 +28,13 @@ hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *ba
 
 // Per-(row, chunk) partial sums of Y and Y^2 for walks [walk0, walk0 + M) of each
 // requested row. partial: n_rows * chunks * nrhs * 2 doubles. counters[0] += jumps,
-// counters[1] += non-finite samples.
+// counters[1] += non-finite samples; hash_sums (nullable) [q] += the path hashes of row
+// q's walks (mod 2^64).
 hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
                               int32_t nrhs, const int64_t *rows, int64_t n_rows,
                               uint32_t walk0, uint32_t M, uint32_t chunk, uint32_t chunks,
-                              double *partial, unsigned long long *counters, hipStream_t s);
+                              double *partial, unsigned long long *counters,
+                              unsigned long long *hash_sums, hipStream_t s);
 
 // out1/out2[q * nrhs + r] (=, or += when accumulate) the chunk sums of the partials.
 hipError_t launch_finalize(const double *partial, int64_t n_rows, uint32_t chunks,

@@ -170,96 +170,230 @@ __device__ __forceinline__ double load_u(const U *u, uint64_t idx)
     return static_cast<double>(u[idx]);
 }
 
-// One wave per (row, chunk) item, lanes stride over the chunk's walks; single RHS.
-template <typename R, typename U>
-__global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
-                                                         const int64_t *__restrict__ rows,
-                                                         uint32_t n_rows, uint32_t walk0,
-                                                         uint32_t M, uint32_t chunk,
-                                                         uint32_t chunks, double *partial,
-                                                         unsigned long long *counters)
+// ------------------------------------------------------------------------------------
+// Lane-refilling walk engine. A wave owns the walks [wb, we) of one row; each lane runs
+// one walk at a time and takes the next unassigned walk as soon as its walk ends. Every
+// iteration gives every busy lane exactly one Philox block: the next step block while
+// it scans for the next jump, or the jump block (slot, alias coin, next holding time)
+// while it jumps. The divergent work between the blocks (threshold tests, one alias
+// gather, one logarithm, the end of a walk) is short, so the wave stays busy on the
+// generator instead of waiting on its slowest lane.
+// ------------------------------------------------------------------------------------
+struct ScanOut {
+    bool jump;       // a step of the block jumps
+    uint32_t word;   // that step's word
+};
+
+// First step n' >= n of the cached block (b0..b3, block q = n >> 2) whose word exceeds
+// thr. On a jump, n is set to that step; otherwise n moves to the end of the block (or N).
+__device__ __forceinline__ ScanOut scan_block(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,
+                                              uint32_t thr, uint32_t &n, uint32_t N)
+{
+    const uint32_t m0 = n & 3u;
+    const uint32_t base = n - m0;
+    // words past step N were zeroed when the block was loaded and never exceed thr
+    const bool j0 = m0 == 0 && b0 > thr;
+    const bool j1 = m0 <= 1 && b1 > thr;
+    const bool j2 = m0 <= 2 && b2 > thr;
+    const bool j3 = b3 > thr;
+    ScanOut o;
+    o.jump = j0 || j1 || j2 || j3;
+    const uint32_t m = j0 ? 0u : j1 ? 1u : j2 ? 2u : 3u;
+    o.word = j0 ? b0 : j1 ? b1 : j2 ? b2 : b3;
+    n = o.jump ? base + m : min(base + 4u, N);
+    return o;
+}
+
+template <typename R, bool kHash>
+struct Walker {
+    // per-lane state of the current walk
+    bool active = false;
+    uint32_t w = 0, k = 0, neg = 0, J = 0, run_start = 0, n = 0;
+    uint32_t jumping = 0;                 // 1 while a jump of step n is pending
+    uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
+    uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    RowRec cur;
+    double tau = 0.0;
+    R ef2 = 0, ec2 = 0, ed2 = 0;
+    uint64_t hash = kFnvOffset;
+};
+
+// Result of a finished walk, handed to the sink.
+template <typename R>
+struct Finished {
+    uint32_t k;        // final state
+    uint32_t jumps;
+    R W;               // the sample without its u factor (sign included)
+    uint64_t hash;
+};
+
+template <typename R, bool kHash, typename Sink>
+__device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
+                                           uint64_t wb, uint64_t we, Sink &sink)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
-    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
-    const uint32_t q = static_cast<uint32_t>(item / chunks);
-    const uint32_t c = static_cast<uint32_t>(item % chunks);
-    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
-    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
-    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes below
+    const RowRec start = L.rec[row];
     const R hd = static_cast<R>(L.half_dt);
+    Walker<R, kHash> s;
+    uint64_t pool = wb;                    // next unassigned walk (wave-uniform)
+    for (;;) {
+        // ---- refill idle lanes with the next walks of the range
+        const uint64_t idle = __ballot(!s.active);
+        if (idle) {
+            const uint64_t mine = pool + __popcll(idle & lower);
+            if (!s.active && mine < we) {
+                s.active = true;
+                s.w = walk0 + static_cast<uint32_t>(mine);
+                s.k = row;
+                s.cur = start;
+                s.neg = 0;
+                s.J = 0;
+                s.run_start = 0;
+                s.n = 0;
+                s.jumping = 0;
+                s.bq = 0xFFFFFFFFu;
+                s.ef2 = s.ec2 = s.ed2 = 0;
+                if (kHash) s.hash = kFnvOffset;
+            }
+            pool += __popcll(idle);
+        }
+        if (__ballot(s.active) == 0) break;
+
+        // ---- one Philox block per busy lane
+        const bool jumping = s.active && s.jumping;
+        const bool scanning = s.active && !s.jumping;
+        const uint32_t q = s.n >> 2;
+        Word4 ph{0u, 0u, 0u, 0u};
+        if (jumping || (scanning && s.bq != q))
+            ph = philox10(Word4{jumping ? s.J : q, s.w, row, jumping ? L.c3_jump : L.c3_step},
+                          L.k0, L.k1);
+
+        uint32_t logword = 0;
+        double logmul = 0.0;
+        bool need_log = false;
+        bool finish = false;
+        if (jumping) {
+            // jump from k by the alias table of row k: slot, coin, then the new state's record
+            const uint32_t slot = mulhi32(ph.x, s.cur.deg);
+            const SlotRec sr = L.slots[s.cur.slot_begin + slot];
+            const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
+            s.k = cs & kColMask;
+            s.neg ^= cs >> 31;
+            s.cur = L.rec[s.k];
+            ++s.J;
+            if (kHash) {
+                s.hash = (s.hash ^ static_cast<uint64_t>(s.k)) * kFnvPrime;
+                s.hash = (s.hash ^ static_cast<uint64_t>(s.n + 1)) * kFnvPrime;
+            }
+            logword = ph.z;                 // holding time at the new state
+            logmul = s.cur.inv_r;
+            need_log = true;
+        } else if (scanning) {
+            if (s.bq != q) {
+                const bool short_walk = L.N < 4;   // levels 0, 1: words past step N never jump
+                s.b0 = ph.x;
+                s.b1 = (short_walk && L.N < 2) ? 0u : ph.y;
+                s.b2 = short_walk ? 0u : ph.z;
+                s.b3 = short_walk ? 0u : ph.w;
+                s.bq = q;
+            }
+            const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
+            if (so.jump) {
+                add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
+                s.tau = 0.0;
+                logword = so.word;          // holding time at k, known to be below dt
+                logmul = s.cur.inv_r;
+                need_log = true;
+                s.jumping = 1;
+            } else {
+                finish = s.n == L.N;
+            }
+        }
+        if (need_log) s.tau = s.tau + neg_log_uniform(logword) * logmul;
+
+        if (jumping && !(s.tau < L.dt)) {
+            // the chain of step n ends: scan on from step n + 1 in the cached block
+            s.jumping = 0;
+            s.n = s.n + 1;
+            s.run_start = s.n;
+            finish = s.n == L.N;
+            if (!finish && (s.n >> 2) == s.bq) {
+                const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
+                if (so.jump) {
+                    add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
+                    s.tau = neg_log_uniform(so.word) * s.cur.inv_r;
+                    s.jumping = 1;
+                } else {
+                    finish = s.n == L.N;
+                }
+            }
+        }
+
+        Finished<R> f{0u, 0u, static_cast<R>(0), 0ull};
+        if (finish) {
+            add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
+            R v = L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd);
+            f.k = s.k;
+            f.jumps = s.J;
+            f.W = s.neg ? -v : v;
+            f.hash = s.hash;
+            s.active = false;
+        }
+        sink.take(finish, f);
+    }
+}
+
+// Single right-hand side: each lane adds its own samples to compensated sums.
+template <typename R, typename U>
+struct SinkR1 {
+    const U *u;
     Kahan<R> s1, s2;
-    unsigned long long jumps = 0, nonfinite = 0;
-    for (uint64_t w = wb + lane; w < we; w += kWave) {
-        const WalkOut<R> o = run_walk<R, false>(L, row, walk0 + static_cast<uint32_t>(w));
-        jumps += o.jumps;
-        const R y = weight_of<R>(o, L.base, hd) * static_cast<R>(load_u(u, o.k));
+    unsigned long long jumps = 0, nonfinite = 0, hash = 0;
+    __device__ __forceinline__ void take(bool done, const Finished<R> &f)
+    {
+        if (!done) return;
+        const R y = f.W * static_cast<R>(u[f.k]);
+        jumps += f.jumps;
+        hash += f.hash;
         nonfinite += !isfinite(y);
         s1.add(y);
         s2.add(y * y);
     }
-    const double a = wave_sum(s1.value());
-    const double b = wave_sum(s2.value());
-    jumps = wave_sum_u(jumps);
-    nonfinite = wave_sum_u(nonfinite);
-    if (lane == 0) {
-        partial[item * 2 + 0] = a;
-        partial[item * 2 + 1] = b;
-        atomicAdd(&counters[0], jumps);
-        if (nonfinite) atomicAdd(&counters[1], nonfinite);
-    }
-}
+};
 
-// Several right-hand sides: each lane runs a walk, then the wave walks through the 64
-// results and lane r accumulates right-hand side r (+64 g) from the contiguous row
-// u[k, :]. Walks without a jump all end at the start row with the same weight, so they
-// are counted and added once at the end.
+// Several right-hand sides: the finished walks of an iteration are broadcast one by one
+// and lane r adds right-hand side r (+64 g) from the contiguous row u[k, :]. Walks
+// without a jump all end at the start row with the same weight; they are only counted.
 constexpr int kMaxRhsGroups = 4;   // up to 256 right-hand sides
 
 template <typename R, typename U>
-__global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
-                                                          int32_t nrhs,
-                                                          const int64_t *__restrict__ rows,
-                                                          uint32_t n_rows, uint32_t walk0,
-                                                          uint32_t M, uint32_t chunk,
-                                                          uint32_t chunks, double *partial,
-                                                          unsigned long long *counters)
-{
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
-    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
-    const uint32_t q = static_cast<uint32_t>(item / chunks);
-    const uint32_t c = static_cast<uint32_t>(item % chunks);
-    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
-    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
-    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
-    const R hd = static_cast<R>(L.half_dt);
-    const int groups = (nrhs + kWave - 1) / kWave;
+struct SinkRhs {
+    const U *u;
+    int32_t nrhs;
+    int groups;
     Kahan<R> s1[kMaxRhsGroups], s2[kMaxRhsGroups];
-    unsigned long long jumps = 0, nojump = 0, nonfinite = 0;
-    for (uint64_t base = wb; base < we; base += kWave) {
-        const uint64_t w = base + lane;
-        uint32_t k = row;
-        R W = 0;
-        if (w < we) {
-            const WalkOut<R> o = run_walk<R, false>(L, row, walk0 + static_cast<uint32_t>(w));
-            jumps += o.jumps;
-            if (o.jumps == 0) {
-                ++nojump;
-            } else {
-                k = o.k;
-                W = weight_of<R>(o, L.base, hd);
-            }
+    unsigned long long jumps = 0, nojump = 0, nonfinite = 0, hash = 0;
+    __device__ __forceinline__ void take(bool done, const Finished<R> &f)
+    {
+        const bool moved = done && f.jumps > 0;
+        if (done) {
+            jumps += f.jumps;
+            hash += f.hash;
+            nojump += f.jumps == 0;
         }
-        for (int t = 0; t < kWave; ++t) {
-            const R Wt = __shfl(W, t, kWave);
-            if (Wt == static_cast<R>(0)) continue;     // wave-uniform
-            const uint32_t kt = __shfl(k, t, kWave);
+        uint64_t pending = __ballot(moved && f.W != static_cast<R>(0));
+        const uint32_t lane = threadIdx.x & (kWave - 1);
+        while (pending) {
+            const int t = __ffsll(static_cast<unsigned long long>(pending)) - 1;
+            pending &= pending - 1;
+            const R Wt = __shfl(f.W, t, kWave);
+            const uint32_t kt = __shfl(f.k, t, kWave);
 #pragma unroll
             for (int g = 0; g < kMaxRhsGroups; ++g) {
                 const int r = static_cast<int>(lane) + g * kWave;
                 if (g < groups && r < nrhs) {
-                    const R y = Wt * static_cast<R>(load_u(u, static_cast<uint64_t>(kt) * nrhs + r));
+                    const R y = Wt * static_cast<R>(u[static_cast<uint64_t>(kt) * nrhs + r]);
                     nonfinite += !isfinite(y);
                     s1[g].add(y);
                     s2[g].add(y * y);
@@ -267,23 +401,81 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
             }
         }
     }
-    jumps = wave_sum_u(jumps);
-    nojump = wave_sum_u(nojump);
+};
+
+// One wave per (row, chunk) item.
+template <typename R, typename U, bool kHash>
+__global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
+                                                         const int64_t *__restrict__ rows,
+                                                         uint32_t n_rows, uint32_t walk0,
+                                                         uint32_t M, uint32_t chunk,
+                                                         uint32_t chunks, double *partial,
+                                                         unsigned long long *counters,
+                                                         unsigned long long *hash_sums)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
+    const uint32_t q = static_cast<uint32_t>(item / chunks);
+    const uint32_t c = static_cast<uint32_t>(item % chunks);
+    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
+    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
+    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    SinkR1<R, U> sink{u};
+    walk_range<R, kHash>(L, row, walk0, wb, we, sink);
+    const double a = wave_sum(sink.s1.value());
+    const double b = wave_sum(sink.s2.value());
+    const unsigned long long jumps = wave_sum_u(sink.jumps);
+    const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
+    const unsigned long long hsum = wave_sum_u(sink.hash);
+    if (lane == 0) {
+        partial[item * 2 + 0] = a;
+        partial[item * 2 + 1] = b;
+        atomicAdd(&counters[0], jumps);
+        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+        if (kHash) atomicAdd(&hash_sums[q], hsum);
+    }
+}
+
+template <typename R, typename U, bool kHash>
+__global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
+                                                          int32_t nrhs,
+                                                          const int64_t *__restrict__ rows,
+                                                          uint32_t n_rows, uint32_t walk0,
+                                                          uint32_t M, uint32_t chunk,
+                                                          uint32_t chunks, double *partial,
+                                                          unsigned long long *counters,
+                                                          unsigned long long *hash_sums)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
+    const uint32_t q = static_cast<uint32_t>(item / chunks);
+    const uint32_t c = static_cast<uint32_t>(item % chunks);
+    const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
+    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
+    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    SinkRhs<R, U> sink{u, nrhs, (nrhs + kWave - 1) / kWave};
+    walk_range<R, kHash>(L, row, walk0, wb, we, sink);
+    const unsigned long long jumps = wave_sum_u(sink.jumps);
+    const unsigned long long nojump = wave_sum_u(sink.nojump);
+    const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
+    const unsigned long long hsum = wave_sum_u(sink.hash);
     // walks without a jump: Y = u_row e^{d_row beta} at the base level, 0 above it
-    double y0 = 0.0;
+    const R hd = static_cast<R>(L.half_dt);
+    R y0 = 0;
     if (nojump && L.base) {
         const RowRec rr = L.rec[row];
-        const R ef2 = d_of<R>(rr) * static_cast<R>(2 * L.N);
-        y0 = static_cast<double>(expR(ef2 * hd));
+        y0 = expR(d_of<R>(rr) * static_cast<R>(2 * L.N) * hd);
     }
 #pragma unroll
     for (int g = 0; g < kMaxRhsGroups; ++g) {
         const int r = static_cast<int>(lane) + g * kWave;
-        if (g < groups && r < nrhs) {
-            double a = s1[g].value(), b = s2[g].value();
-            if (y0 != 0.0) {
+        if (g < sink.groups && r < nrhs) {
+            double a = sink.s1[g].value(), b = sink.s2[g].value();
+            if (y0 != static_cast<R>(0)) {
                 const double yr = static_cast<double>(
-                    static_cast<R>(y0) * static_cast<R>(load_u(u, static_cast<uint64_t>(row) * nrhs + r)));
+                    y0 * static_cast<R>(u[static_cast<uint64_t>(row) * nrhs + r]));
                 a += static_cast<double>(nojump) * yr;
                 b += static_cast<double>(nojump) * yr * yr;
             }
@@ -291,10 +483,10 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
             partial[(item * nrhs + r) * 2 + 1] = b;
         }
     }
-    nonfinite = wave_sum_u(nonfinite);
     if (lane == 0) {
         atomicAdd(&counters[0], jumps);
         if (nonfinite) atomicAdd(&counters[1], nonfinite);
+        if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
 }
 
@@ -435,31 +627,38 @@ hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *ba
 hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
                               int32_t nrhs, const int64_t *rows, int64_t n_rows, uint32_t walk0,
                               uint32_t M, uint32_t chunk, uint32_t chunks, double *partial,
-                              unsigned long long *counters, hipStream_t s)
+                              unsigned long long *counters, unsigned long long *hash_sums,
+                              hipStream_t s)
 {
     const uint64_t items = static_cast<uint64_t>(n_rows) * chunks;
     if (items == 0) return hipSuccess;
     const dim3 grid(static_cast<uint32_t>((items + kWavesPerBlock - 1) / kWavesPerBlock));
     const dim3 block(kBlock);
     const uint32_t nr = static_cast<uint32_t>(n_rows);
-#define MLMC_LAUNCH_WALKS(R, U)                                                               \
+#define MLMC_LAUNCH_WALKS(R, U, H)                                                            \
     do {                                                                                      \
         if (nrhs == 1)                                                                        \
-            hipLaunchKernelGGL((level_walks_r1<R, U>), grid, block, 0, s, L,                  \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H>), grid, block, 0, s, L,               \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
-                               partial, counters);                                            \
+                               partial, counters, hash_sums);                                 \
         else                                                                                  \
-            hipLaunchKernelGGL((level_walks_rhs<R, U>), grid, block, 0, s, L,                 \
+            hipLaunchKernelGGL((level_walks_rhs<R, U, H>), grid, block, 0, s, L,              \
                                static_cast<const U *>(u), nrhs, rows, nr, walk0, M, chunk,    \
-                               chunks, partial, counters);                                    \
+                               chunks, partial, counters, hash_sums);                         \
+    } while (0)
+#define MLMC_LAUNCH_WALKS_H(R, U)                                                             \
+    do {                                                                                      \
+        if (hash_sums) MLMC_LAUNCH_WALKS(R, U, true);                                         \
+        else MLMC_LAUNCH_WALKS(R, U, false);                                                  \
     } while (0)
     if (prec == Prec::FP64) {
-        if (u_f64) MLMC_LAUNCH_WALKS(double, double);
-        else MLMC_LAUNCH_WALKS(double, float);
+        if (u_f64) MLMC_LAUNCH_WALKS_H(double, double);
+        else MLMC_LAUNCH_WALKS_H(double, float);
     } else {
-        if (u_f64) MLMC_LAUNCH_WALKS(float, double);
-        else MLMC_LAUNCH_WALKS(float, float);
+        if (u_f64) MLMC_LAUNCH_WALKS_H(float, double);
+        else MLMC_LAUNCH_WALKS_H(float, float);
     }
+#undef MLMC_LAUNCH_WALKS_H
 #undef MLMC_LAUNCH_WALKS
     return hipGetLastError();
 }

@@ -98,7 +98,7 @@ def _mass_tol(o_ls, prec):
 
 
 def _check_level_sums(api, A, beta, u, precision, nlev, walks, seed, rows=None,
-                      values_dtype=np.float64, walk0=0):
+                      values_dtype=np.float64, walk0=0, hashes_only_check=True):
     """Levels l0 .. l0 + nlev - 1 of the plan."""
     plan = api.Plan(A, beta, precision=precision, rows=rows, values_dtype=values_dtype)
     vals = np.asarray(A.values, dtype=values_dtype).astype(np.float64)
@@ -107,9 +107,14 @@ def _check_level_sums(api, A, beta, u, precision, nlev, walks, seed, rows=None,
     ut = torch.as_tensor(np.ascontiguousarray(u), device="cuda")
     for lev in range(plan.l0, plan.l0 + nlev):
         _say(f"level_sums n={A.n} prec={precision} level={lev} M={walks} R={ut.shape[-1] if ut.dim() > 1 else 1}")
-        s1, s2, jumps = plan.level_sums(ut, lev, walk0, walks, seed=seed)
+        s1, s2, jumps, hs = plan.level_sums(ut, lev, walk0, walks, seed=seed, hashes=True)
         o = orc.level_sums(t, beta, lev, plan.l0, seed, u, rows, walk0, walks)
         assert jumps == int(o.jumps.sum())
+        # the production kernel's paths: per-row sums of the path hashes, bit-exact
+        assert np.array_equal(hs.cpu().numpy().view(np.uint64), o.hash_sum)
+        if hashes_only_check:
+            s1b, s2b, jb = plan.level_sums(ut, lev, walk0, walks, seed=seed)
+            assert jb == jumps and torch.equal(s1b, s1) and torch.equal(s2b, s2)
         g1 = s1.cpu().numpy()
         g2 = s2.cpu().numpy()
         assert np.all(np.abs(g1 - o.sum1) <= _mass_tol(o, precision))
