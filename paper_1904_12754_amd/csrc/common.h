@@ -147,6 +147,29 @@ __host__ __device__ __forceinline__ double neg_log_uniform(uint32_t w)
 }
 
 // ------------------------------------------------------------------------------------
+// Fast bracket of -ln U(w) in FP32 from the hardware base-2 logarithm. For every 32-bit
+// word w,
+//     |neg_log_uniform_fast(w) - neg_log_uniform(w)| <= kFastLogAbs + kFastLogRel * E
+// with E = neg_log_uniform_fast(w); the bound is checked exhaustively over all 2^32
+// words by a GPU test. The walk kernel decides "accumulated holding time < dt" from
+// these brackets and falls back to the exact FP64 sequence only when the bracket
+// straddles dt, so its decisions equal the exact ones.
+// ------------------------------------------------------------------------------------
+constexpr float kFastLogAbs = 0x1p-20f;
+constexpr float kFastLogRel = 0x1p-20f;
+
+__device__ __forceinline__ float neg_log_uniform_fast(uint32_t w)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float u = fmaf(static_cast<float>(w), 0x1p-32f, 0x1p-33f);
+    return __builtin_amdgcn_logf(u) * -0x1.62e430p-1f;
+#else
+    (void)w;
+    return 0.0f;   // device only
+#endif
+}
+
+// ------------------------------------------------------------------------------------
 // Errors
 // ------------------------------------------------------------------------------------
 void set_error(const std::string &msg);

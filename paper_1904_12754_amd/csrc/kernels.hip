@@ -213,7 +213,11 @@ struct Walker {
     uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
     uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
     RowRec cur;
-    double tau = 0.0;
+    // the holding time accumulated in step n: bracket [tau_h - tau_e, tau_h + tau_e] around
+    // the exact FP64 value, and what is needed to replay it exactly (state and jump count
+    // at the start of the chain, and the step's word)
+    float tau_h = 0.0f, tau_e = 0.0f;
+    uint32_t chain_k = 0, chain_J = 0, chain_word = 0;
     R ef2 = 0, ec2 = 0, ed2 = 0;
     uint64_t hash = kFnvOffset;
 };
@@ -226,6 +230,39 @@ struct Finished {
     R W;               // the sample without its u factor (sign included)
     uint64_t hash;
 };
+
+// Holding time of the current step's chain in the exact FP64 sequence: the step's word at
+// the chain's first state, then the next-holding-time word of each jump J0 .. J1 - 1 at
+// the state that jump reached (the jumps are replayed from their blocks).
+__device__ __forceinline__ double chain_tau_exact(const LevelArgs &L, uint32_t row, uint32_t walk,
+                                                  uint32_t k0, uint32_t J0, uint32_t J1,
+                                                  uint32_t word)
+{
+    RowRec rk = L.rec[k0];
+    double tau = neg_log_uniform(word) * rk.inv_r;
+    for (uint32_t J = J0; J < J1; ++J) {
+        const Word4 ph = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
+        const uint32_t slot = mulhi32(ph.x, rk.deg);
+        const SlotRec sr = L.slots[rk.slot_begin + slot];
+        const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
+        rk = L.rec[cs & kColMask];
+        tau = tau + neg_log_uniform(ph.z) * rk.inv_r;
+    }
+    return tau;
+}
+
+// Start the bracket of a new chain with the holding time of its first state.
+template <typename R, bool kHash>
+__device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
+{
+    const float e = neg_log_uniform_fast(word);
+    const float ir = static_cast<float>(s.cur.inv_r);      // finite: this state jumps
+    s.tau_h = e * ir;
+    s.tau_e = (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
+    s.chain_k = s.k;
+    s.chain_J = s.J;
+    s.chain_word = word;
+}
 
 template <typename R, bool kHash, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
@@ -269,10 +306,8 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             ph = philox10(Word4{jumping ? s.J : q, s.w, row, jumping ? L.c3_jump : L.c3_step},
                           L.k0, L.k1);
 
-        uint32_t logword = 0;
-        double logmul = 0.0;
-        bool need_log = false;
         bool finish = false;
+        bool chain_over = false;
         if (jumping) {
             // jump from k by the alias table of row k: slot, coin, then the new state's record
             const uint32_t slot = mulhi32(ph.x, s.cur.deg);
@@ -286,9 +321,22 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 s.hash = (s.hash ^ static_cast<uint64_t>(s.k)) * kFnvPrime;
                 s.hash = (s.hash ^ static_cast<uint64_t>(s.n + 1)) * kFnvPrime;
             }
-            logword = ph.z;                 // holding time at the new state
-            logmul = s.cur.inv_r;
-            need_log = true;
+            // add the holding time at the new state; the chain goes on while the total is
+            // below dt (an absorbing state holds forever)
+            const float ir = static_cast<float>(s.cur.inv_r);
+            if (!(ir < INFINITY)) {
+                chain_over = true;
+            } else {
+                const float e = neg_log_uniform_fast(ph.z);
+                s.tau_h = s.tau_h + e * ir;
+                s.tau_e = s.tau_e + (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
+                const double hi = static_cast<double>(s.tau_h) + static_cast<double>(s.tau_e);
+                const double lo = static_cast<double>(s.tau_h) - static_cast<double>(s.tau_e);
+                if (hi < L.dt) chain_over = false;
+                else if (lo >= L.dt) chain_over = true;
+                else chain_over = !(chain_tau_exact(L, row, s.w, s.chain_k, s.chain_J, s.J,
+                                                    s.chain_word) < L.dt);
+            }
         } else if (scanning) {
             if (s.bq != q) {
                 const bool short_walk = L.N < 4;   // levels 0, 1: words past step N never jump
@@ -300,19 +348,16 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             }
             const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
             if (so.jump) {
+                // the step's holding time at k is below dt: a chain of jumps starts
                 add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                s.tau = 0.0;
-                logword = so.word;          // holding time at k, known to be below dt
-                logmul = s.cur.inv_r;
-                need_log = true;
+                chain_start(s, so.word);
                 s.jumping = 1;
             } else {
                 finish = s.n == L.N;
             }
         }
-        if (need_log) s.tau = s.tau + neg_log_uniform(logword) * logmul;
 
-        if (jumping && !(s.tau < L.dt)) {
+        if (chain_over) {
             // the chain of step n ends: scan on from step n + 1 in the cached block
             s.jumping = 0;
             s.n = s.n + 1;
@@ -322,7 +367,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
                 if (so.jump) {
                     add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                    s.tau = neg_log_uniform(so.word) * s.cur.inv_r;
+                    chain_start(s, so.word);
                     s.jumping = 1;
                 } else {
                     finish = s.n == L.N;

@@ -26,5 +26,26 @@ def rocrand_ref(force: bool = False) -> str | None:
     return exe
 
 
+def log_bound(force: bool = False) -> str | None:
+    """GPU program checking the fast holding-time log bracket over all 2^32 words."""
+    src = os.path.join(HERE, "log_bound.hip")
+    dep = os.path.join(ROOT, "paper_1904_12754_amd", "csrc", "common.h")
+    exe = os.path.join(OUT, "log_bound")
+    if (not force and os.path.exists(exe)
+            and os.path.getmtime(exe) >= max(os.path.getmtime(src), os.path.getmtime(dep))):
+        return exe
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        return None
+    os.makedirs(OUT, exist_ok=True)
+    subprocess.check_call([hipcc, "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "--offload-arch=gfx950", "-o", exe + ".tmp", src],
+                          stderr=subprocess.DEVNULL)
+    os.replace(exe + ".tmp", exe)
+    return exe
+
+
 if __name__ == "__main__":
     print(rocrand_ref(force=True))
+    print(log_bound(force=True))
