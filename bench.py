@@ -23,19 +23,40 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Algorithmic VALU work of the walk kernel, in lane-instructions of a minimal gfx950
-# implementation: a step consumes one 32-bit Philox word (a Philox4x32-10 block is 10
-# rounds of 2 32x32->64 multiplies and 2 three-input xors, so 10 instructions per word)
-# plus its threshold compare; a jump draws one block for slot, coin and holding time
-# (40), evaluates two FP64 logarithms (about 40 each, division included), gathers and
-# selects the alias entry and updates the weights (about 30); a walk evaluates exp and
-# expm1 of its weights and adds to the compensated sums (about 50).
-OPS_PER_STEP = 11
-OPS_PER_JUMP = 150
-OPS_PER_WALK = 50
-# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions per second
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# sequence: a step consumes a quarter of a Philox4x32-10 block (10 rounds of two
+# v_mad_u64_u32 and four v_xor_b32: 60 per block, 15 per step) and one compare; a jump
+# consumes one block (60), the alias selection and gather addressing (~8), the holding-time
+# bracket (~8) and the run update of the weights (~9); a walk end evaluates exp/expm1 of
+# its weights and adds to the compensated sums (~45).
+OPS_PER_STEP = 16
+OPS_PER_JUMP = 85
+OPS_PER_WALK = 45
+# MI355X vector ALU: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz (the FP32 vector rate
+# of 157.3 TFLOP/s counts two flops per FMA lane)
+VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
 # bytes the jumps must gather: one 16-byte alias slot and one 32-byte row record
 BYTES_PER_JUMP = 48
+# HBM traffic of the walk kernel from the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
+# plain copy), recorded with the hash of the kernel source it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_12754_amd", "csrc", "kernels.hip")
+
+
+def kernel_traffic(launches_walks):
+    """Calibrated HBM bytes per walk-kernel launch, or None when the counters were taken on
+    another version of the kernel source."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_sha256") != sha:
+        return None
+    return rec["bytes_per_walk"] * launches_walks
 
 
 def parse():
@@ -48,7 +69,55 @@ def parse():
     ap.add_argument("--pilot", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
+                    help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
+                         "--walks per row), for counter runs; copy: a plain device copy of "
+                         "--bytes, the calibration for the traffic counters")
+    ap.add_argument("--level", type=int, default=0)
+    ap.add_argument("--walks", type=int, default=65536)
+    ap.add_argument("--bytes", type=int, default=1 << 30)
     return ap.parse_args()
+
+
+def kernel_only(args):
+    """Two launches of the walk kernel at one level of the benchmark workload."""
+    import numpy as np
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    A, t, v = inputs.workload_laplace2d(args.grid)
+    plan = api.Plan(A, t, precision="fp32")
+    u = torch.as_tensor(v.astype(np.float32), device="cuda")
+    lev = plan.l0 + args.level
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, jumps = plan.level_sums(u, lev, 0, args.walks, seed=rep)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        walks = args.walks * A.n
+        print(json.dumps({"mode": "kernel", "level": lev, "walks": walks, "steps": walks << lev,
+                          "jumps": jumps, "seconds": el, "steps_per_s": (walks << lev) / el}),
+              flush=True)
+    plan.close()
+
+
+def copy_only(args):
+    """A plain device-to-device copy of a known size (the traffic-counter calibration)."""
+    import torch
+
+    n = args.bytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for rep in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"mode": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "seconds": el, "GBps": 8 * n / el / 1e9}), flush=True)
 
 
 def cpu_baseline(A, t, v, l0, walks, target_s):
@@ -88,6 +157,10 @@ def cpu_baseline(A, t, v, l0, walks, target_s):
 
 def main():
     args = parse()
+    if args.mode == "kernel":
+        return kernel_only(args)
+    if args.mode == "copy":
+        return copy_only(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "
                                    "measured at one GPU's share of the work (--gpus 1)"}))
@@ -137,7 +210,7 @@ def main():
         "peak": VALU_PEAK_LANE_OPS / 1e12,
         "unit": "T lane-ops/s",
         "frac": achieved / VALU_PEAK_LANE_OPS,
-        "traffic": None,
+        "traffic": kernel_traffic(walks_total / max(launches, 1)),
         "per_unit": {"ops_per_step": OPS_PER_STEP, "ops_per_jump": OPS_PER_JUMP,
                      "ops_per_walk": OPS_PER_WALK},
         "launch_avg_ms": wk_ms / max(launches, 1),
