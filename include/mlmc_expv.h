@@ -183,6 +183,58 @@ int mlmc_expv_trace(mlmc_plan_t *plan, uint64_t seed, int32_t instance, int32_t 
 
 void mlmc_expv_destroy(mlmc_plan_t *plan);
 
+/* ---- batched runs ------------------------------------------------------------------
+ * Many plans (different matrices, right-hand sides or times) with fixed level schedules
+ * in one persistent launch: every (instance, level) is split into items of whole walks of
+ * one row, and a persistent grid pulls items from one atomic counter, so instances of very
+ * different sizes share the chip in a single launch. The sequence (reset, walks, per-row
+ * sums, per-instance FP64 combine of the levels, section 2.2) is captured once in a
+ * hipGraph at creation and replayed by mlmc_expv_batch_launch. Instance b draws the
+ * random streams of instance number b (the `instance` of a single run), so its estimate
+ * follows the same paths as mlmc_expv_run(plans[b], ..., instance = b) with the same seed
+ * and schedule. */
+typedef struct mlmc_batch mlmc_batch_t;
+
+typedef struct {
+    int32_t count;                    /* instances, 1..4096 */
+    mlmc_plan_t *const *plans;        /* count plans, all of one precision; a plan may appear
+                                         in only one live batch at a time */
+    const void *const *u;             /* count DEVICE pointers, n_b x nrhs_b row major */
+    const int32_t *nrhs;              /* count entries in [1, 256] */
+    int32_t u_dtype;                  /* one element type for every u */
+    double *const *x;                 /* count DEVICE outputs, n_rows_b x nrhs_b FP64 */
+    int32_t num_levels;               /* levels l0_b .. l0_b + num_levels - 1 of each plan */
+    const int64_t *walks;             /* HOST, count x num_levels walks per row (row major) */
+    int32_t autotune;                 /* 1: time candidate launch shapes on this batch (sample
+                                         sizes cut by 8) and keep the fastest; the choice is
+                                         cached per class of batch for the process */
+} mlmc_batch_desc_t;
+
+typedef struct {
+    int32_t count, segments, walks_per_item, waves_per_cu, graph_nodes, pad;
+    int64_t items;                    /* (row, walk chunk) items per launch */
+    int64_t device_bytes;
+    double tune_ms[9];                /* autotuner timings of the candidate shapes (ms), in the
+                                         order (walks per item, waves per CU) = (256, 8),
+                                         (256, 16), (256, 32), (1024, 8), ..., (4096, 32) */
+} mlmc_batch_info_t;
+
+/* Validate, upload the levels' tables, optionally autotune, lay out the work, and capture
+ * and instantiate the graph. The pointers in `desc` (u, x) are baked into the graph: they
+ * must stay valid for the life of the batch. Waits for `stream`. */
+int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *desc, void *stream);
+
+/* Replay the graph with Philox key `seed` on `stream` (asynchronous). Overwrites every x. */
+int mlmc_expv_batch_launch(mlmc_batch_t *batch, uint64_t seed, void *stream);
+
+/* Statistics of the last launch, one struct per instance (HOST array of count). Waits for
+ * `stream`. kernel_ms is the device time of the whole graph. */
+int mlmc_expv_batch_stats(mlmc_batch_t *batch, mlmc_stats_t *per_instance, void *stream);
+
+int mlmc_expv_batch_info(const mlmc_batch_t *batch, mlmc_batch_info_t *info);
+
+void mlmc_expv_batch_destroy(mlmc_batch_t *batch);
+
 const char *mlmc_status_string(int status);
 const char *mlmc_last_error(void);
 

@@ -28,7 +28,9 @@ MLMC_MAX_LEVELS = 40
 
 # every symbol the header declares
 EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_level_sums",
-           "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_status_string", "mlmc_last_error")
+           "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_expv_batch_create",
+           "mlmc_expv_batch_launch", "mlmc_expv_batch_stats", "mlmc_expv_batch_info",
+           "mlmc_expv_batch_destroy", "mlmc_status_string", "mlmc_last_error")
 
 
 class CSR(ctypes.Structure):
@@ -96,6 +98,26 @@ class Stats(ctypes.Structure):
         }
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32),
+                ("plans", ctypes.POINTER(ctypes.c_void_p)),
+                ("u", ctypes.POINTER(ctypes.c_void_p)),
+                ("nrhs", ctypes.POINTER(ctypes.c_int32)),
+                ("u_dtype", ctypes.c_int32),
+                ("x", ctypes.POINTER(ctypes.c_void_p)),
+                ("num_levels", ctypes.c_int32),
+                ("walks", ctypes.POINTER(ctypes.c_int64)),
+                ("autotune", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("segments", ctypes.c_int32),
+                ("walks_per_item", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
+                ("graph_nodes", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("items", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("tune_ms", ctypes.c_double * 9)]
+
+
 _lib = None
 
 
@@ -126,6 +148,16 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_trace.restype = ctypes.c_int
     L.mlmc_expv_destroy.argtypes = [vp]
     L.mlmc_expv_destroy.restype = None
+    L.mlmc_expv_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(BatchDesc), vp]
+    L.mlmc_expv_batch_create.restype = ctypes.c_int
+    L.mlmc_expv_batch_launch.argtypes = [vp, u64, vp]
+    L.mlmc_expv_batch_launch.restype = ctypes.c_int
+    L.mlmc_expv_batch_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
+    L.mlmc_expv_batch_stats.restype = ctypes.c_int
+    L.mlmc_expv_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.mlmc_expv_batch_info.restype = ctypes.c_int
+    L.mlmc_expv_batch_destroy.argtypes = [vp]
+    L.mlmc_expv_batch_destroy.restype = None
     L.mlmc_status_string.argtypes = [ctypes.c_int]
     L.mlmc_status_string.restype = ctypes.c_char_p
     L.mlmc_last_error.argtypes = []

@@ -156,3 +156,76 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Many plans with fixed level schedules in one persistent, graph-captured launch.
+
+    plans: list of Plan (one precision); us: list of device tensors (n_b or n_b x R_b, one
+    dtype); walks: (count, num_levels) walks per row at levels l0_b + q. Instance b draws
+    the streams of instance number b, so its paths are those of plans[b].run(us[b],
+    walks=walks[b], instance=b) with the same seed.
+    """
+
+    def __init__(self, plans, us, walks, autotune: bool = True, stream=None):
+        self._lib = _abi.load()
+        self._handle = ctypes.c_void_p()
+        walks = np.ascontiguousarray(walks, dtype=np.int64)
+        count = len(plans)
+        if walks.shape[0] != count or len(us) != count:
+            raise ValueError("one u and one row of walks per plan")
+        self.plans = plans
+        self.us = []
+        nrhs = []
+        dts = set()
+        for p, u in zip(plans, us):
+            u2, R, dt = _u_args(u, p.n)
+            self.us.append(u2)
+            nrhs.append(R)
+            dts.add(dt)
+        if len(dts) != 1:
+            raise ValueError("all right-hand sides of a batch must share one dtype")
+        self.xs = [torch.empty((p.n_rows, R), dtype=torch.float64, device=self.us[0].device)
+                   for p, R in zip(plans, nrhs)]
+        self._plan_ptrs = (ctypes.c_void_p * count)(*[p._handle.value for p in plans])
+        self._u_ptrs = (ctypes.c_void_p * count)(*[u.data_ptr() for u in self.us])
+        self._x_ptrs = (ctypes.c_void_p * count)(*[x.data_ptr() for x in self.xs])
+        self._nrhs = (ctypes.c_int32 * count)(*nrhs)
+        self._walks = walks
+        desc = _abi.BatchDesc(count, self._plan_ptrs, self._u_ptrs, self._nrhs, dts.pop(),
+                              self._x_ptrs, int(walks.shape[1]),
+                              walks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                              1 if autotune else 0)
+        check(self._lib.mlmc_expv_batch_create(ctypes.byref(self._handle), ctypes.byref(desc),
+                                               _stream_ptr(stream)))
+        info = _abi.BatchInfo()
+        check(self._lib.mlmc_expv_batch_info(self._handle, ctypes.byref(info)))
+        self.info = {f: (list(getattr(info, f)) if f == "tune_ms" else getattr(info, f))
+                     for f, _ in _abi.BatchInfo._fields_ if f != "pad"}
+
+    def launch(self, seed: int = 0, stream=None):
+        """Replay the captured graph; every x in self.xs is overwritten (asynchronous)."""
+        check(self._lib.mlmc_expv_batch_launch(self._handle, seed, _stream_ptr(stream)))
+        return self.xs
+
+    def stats(self, stream=None):
+        arr = (_abi.Stats * len(self.plans))()
+        check(self._lib.mlmc_expv_batch_stats(self._handle, arr, _stream_ptr(stream)))
+        return [s.to_dict() for s in arr]
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self._lib.mlmc_expv_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

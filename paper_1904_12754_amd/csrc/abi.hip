@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "plan.h"
 
 namespace mlmc {
 
@@ -25,11 +26,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 using namespace mlmc;
 
-namespace {
-
-constexpr int kMaxLevel = 28;                   // N = 2^28 steps per walk at most
-constexpr size_t kPartialCapBytes = 256u << 20;  // per sub-launch scratch
-constexpr int64_t kTargetItems = 16384;          // (row, chunk) items per launch, to fill 256 CUs
+namespace mlmc {
 
 int fail(int code, const std::string &msg)
 {
@@ -37,30 +34,16 @@ int fail(int code, const std::string &msg)
     return code;
 }
 
+}  // namespace mlmc
+
+namespace {
+
+constexpr size_t kPartialCapBytes = 256u << 20;  // per sub-launch scratch
+constexpr int64_t kTargetItems = 16384;          // (row, chunk) items per launch, to fill 256 CUs
+
 }  // namespace
 
-struct mlmc_plan {
-    int64_t n = 0, n_rows = 0, n_slots = 0;
-    int32_t l0 = 0, precision = 0;
-    double beta = 0, r_max = 0, d_min = 0, d_max = 0;
-    SlotRec *slots = nullptr;
-    RowRec *rows_base = nullptr;
-    RowRec *level_rec[kMaxLevel + 1] = {};
-    int64_t *req_rows = nullptr;             // device; null = all rows
-    double *partial = nullptr;
-    size_t partial_bytes = 0;
-    unsigned long long *counters = nullptr;  // 2 per level
-    unsigned int *bad = nullptr;
-    double *moments = nullptr;               // 3 per level
-    double *acc = nullptr;                   // 2 * n_rows * nrhs per level
-    size_t acc_doubles = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // per-launch timing of the walk kernel (pairs of events around each launch)
-    bool timing = false;
-    std::vector<hipEvent_t> tev;
-    size_t tev_used = 0;
-    int64_t bytes = 0;
-};
+
 
 namespace {
 
@@ -131,6 +114,10 @@ void build_alias(std::vector<double> &q, std::vector<uint32_t> &thr, std::vector
     // whatever remains has probability one of keeping its own column (thr, alias preset)
 }
 
+}  // namespace
+
+namespace mlmc {
+
 int upload_level(mlmc_plan *p, int level, hipStream_t s)
 {
     if (level < 0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level out of range [0, 28]");
@@ -163,6 +150,10 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
     L.c3_jump = stream_word(level, instance, 1);
     return L;
 }
+
+}  // namespace mlmc
+
+namespace {
 
 int ensure_partial(mlmc_plan *p, size_t bytes)
 {

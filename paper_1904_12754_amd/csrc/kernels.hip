@@ -1,454 +1,15 @@
-// Walk kernels for gfx950: the sampling of Algorithm 2 (one coupled fine/coarse path per
-// walk), per-row level sums, thresholds, moments and the FP64 level combine.
-//
-// Walk (section 2.1, section 3, Algorithm 2). A walk at level l starts at row i and takes
-// N = 2^l steps of length dt = beta / N. In each step the chain holds at its state k for
-// an exponential time of rate r_k and, while the accumulated time stays below dt, jumps
-// to j with probability |a_kj| / r_k, flipping its sign when a_kj < 0; the holding time
-// after a jump has the rate of the state jumped to. Only the states at the grid points
-// 0..N enter the weights:
-//   fine   (level l):    E_f = dt * sum_n (d_{s_{n-1}} + d_{s_n}) / 2
-//   coarse (level l-1):  E_c = dt * sum_m (d_{s_{2m-2}} + d_{s_{2m}})
-// i.e. the Strang factors of section 2.1 multiplied out (the products of Algorithm 2's
-// eta_2 and eta_1). A run of grid points [a, b] held at one state k adds d_k times an
-// integer count to 2 E_f / dt, 2 E_c / dt and 2 (E_f - E_c) / dt, so the work on
-// weights is O(jumps), and steps without a jump touch no memory. The sample is
-//   Y = phi u_{s_N} e^{E_f}                       at l = l0,
-//   Y = phi u_{s_N} (e^{E_f} - e^{E_c})
-//     = phi u_{s_N} e^{E_c} expm1(E_f - E_c)      at l > l0,
-// and a walk with no jump has E_f = E_c exactly, so Y = 0 (the "no transition" case of
-// the paper's Fig. 1).
-//
-// Step test. A step of state k jumps iff the holding time -ln U(w) / r_k drawn from the
-// step's word w is below dt. Because -ln U(w) decreases in w, this is the integer test
-// w > thr_k(l) with thr from launch_thresholds, evaluated with the very same logarithm;
-// so a step without a jump costs only its share of one Philox block (four steps per
-// block) and a compare.
+// Kernels of the single-level path for gfx950: per-row level sums of the walks of one level
+// (the sampling of Algorithm 2, see walk_engine.h), step thresholds, moments, the FP64
+// level combine and path traces.
 #include "common.h"
 #include "kernels.h"
+#include "walk_engine.h"
 
 #include <cmath>
 
 namespace mlmc {
 namespace {
 
-constexpr int kWave = 64;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
-
-template <typename R>
-__device__ __forceinline__ R d_of(const RowRec &r);
-template <>
-__device__ __forceinline__ float d_of<float>(const RowRec &r) { return r.d32; }
-template <>
-__device__ __forceinline__ double d_of<double>(const RowRec &r) { return r.d64; }
-
-__device__ __forceinline__ float expR(float x) { return expf(x); }
-__device__ __forceinline__ double expR(double x) { return exp(x); }
-__device__ __forceinline__ float expm1R(float x) { return expm1f(x); }
-__device__ __forceinline__ double expm1R(double x) { return expm1(x); }
-
-template <typename R>
-struct WalkOut {
-    uint32_t k;       // final state
-    uint32_t neg;     // 1 if the product of jump signs is -1
-    uint32_t jumps;
-    uint64_t hash;
-    R ef2, ec2, ed2;  // 2/dt times E_f, E_c, E_f - E_c
-};
-
-// Add the grid points a..b (held at one state with weight d) to the three sums.
-template <typename R>
-__device__ __forceinline__ void add_run(R d, uint32_t a, uint32_t b, uint32_t N, R &ef2, R &ec2,
-                                        R &ed2)
-{
-    const int a0 = (a == 0), bN = (b == N);
-    const int f2 = 2 * static_cast<int>(b - a + 1) - a0 - bN;                 // 2 sum w_f
-    const int even = static_cast<int>(b >> 1) - static_cast<int>((a + 1) >> 1) + 1;
-    const int c2 = 4 * even - 2 * a0 - 2 * bN;                                 // 2 sum w_c
-    ef2 += d * static_cast<R>(f2);
-    ec2 += d * static_cast<R>(c2);
-    ed2 += d * static_cast<R>(f2 - c2);
-}
-
-template <typename R, bool kHash>
-__device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row, uint32_t walk)
-{
-    RowRec cur = L.rec[row];
-    uint32_t k = row, neg = 0, J = 0, run_start = 0;
-    uint64_t h = kFnvOffset;
-    R ef2 = 0, ec2 = 0, ed2 = 0;
-    const uint32_t nblk = (L.N + 3) >> 2;
-    for (uint32_t q = 0; q < nblk; ++q) {
-        Word4 w = philox10(Word4{q, walk, row, L.c3_step}, L.k0, L.k1);
-        if (L.N < 4) {          // levels 0 and 1: words past step N never jump
-            w.w = 0;
-            w.z = 0;
-            if (L.N < 2) w.y = 0;
-        }
-        const uint32_t mx = max(max(w.x, w.y), max(w.z, w.w));
-        if (mx <= cur.thr) continue;
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (ws[m] <= cur.thr) continue;
-            const uint32_t n = 4 * q + m;   // 0-based step: the jump falls between grid n and n+1
-            add_run<R>(d_of<R>(cur), run_start, n, L.N, ef2, ec2, ed2);
-            double tau = neg_log_uniform(ws[m]) * cur.inv_r;
-            do {
-                const Word4 jw = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
-                const uint32_t slot = mulhi32(jw.x, cur.deg);
-                const SlotRec s = L.slots[cur.slot_begin + slot];
-                const uint32_t cs = (jw.y < s.thr) ? s.own : s.alias;
-                k = cs & kColMask;
-                neg ^= cs >> 31;
-                cur = L.rec[k];
-                ++J;
-                if (kHash) {
-                    h = (h ^ static_cast<uint64_t>(k)) * kFnvPrime;
-                    h = (h ^ static_cast<uint64_t>(n + 1)) * kFnvPrime;
-                }
-                tau = tau + neg_log_uniform(jw.z) * cur.inv_r;
-            } while (tau < L.dt);
-            run_start = n + 1;
-        }
-    }
-    add_run<R>(d_of<R>(cur), run_start, L.N, L.N, ef2, ec2, ed2);
-    WalkOut<R> o;
-    o.k = k;
-    o.neg = neg;
-    o.jumps = J;
-    o.hash = h;
-    o.ef2 = ef2;
-    o.ec2 = ec2;
-    o.ed2 = ed2;
-    return o;
-}
-
-// The sample without its u factor: +-e^{E_f} at the base level, +-e^{E_c} expm1(E_f - E_c)
-// above it.
-template <typename R>
-__device__ __forceinline__ R weight_of(const WalkOut<R> &o, int base, R hd)
-{
-    R v = base ? expR(o.ef2 * hd) : expR(o.ec2 * hd) * expm1R(o.ed2 * hd);
-    return o.neg ? -v : v;
-}
-
-template <typename R>
-struct Kahan {
-    R s = 0, c = 0;
-    __device__ __forceinline__ void add(R x)
-    {
-        const R y = x - c;
-        const R t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const
-    {
-        return static_cast<double>(s) - static_cast<double>(c);
-    }
-};
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v)
-{
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-template <typename U>
-__device__ __forceinline__ double load_u(const U *u, uint64_t idx)
-{
-    return static_cast<double>(u[idx]);
-}
-
-// ------------------------------------------------------------------------------------
-// Lane-refilling walk engine. A wave owns the walks [wb, we) of one row; each lane runs
-// one walk at a time and takes the next unassigned walk as soon as its walk ends. Every
-// iteration gives every busy lane exactly one Philox block: the next step block while
-// it scans for the next jump, or the jump block (slot, alias coin, next holding time)
-// while it jumps. The divergent work between the blocks (threshold tests, one alias
-// gather, one logarithm, the end of a walk) is short, so the wave stays busy on the
-// generator instead of waiting on its slowest lane.
-// ------------------------------------------------------------------------------------
-struct ScanOut {
-    bool jump;       // a step of the block jumps
-    uint32_t word;   // that step's word
-};
-
-// First step n' >= n of the cached block (b0..b3, block q = n >> 2) whose word exceeds
-// thr. On a jump, n is set to that step; otherwise n moves to the end of the block (or N).
-__device__ __forceinline__ ScanOut scan_block(uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,
-                                              uint32_t thr, uint32_t &n, uint32_t N)
-{
-    const uint32_t m0 = n & 3u;
-    const uint32_t base = n - m0;
-    // words past step N were zeroed when the block was loaded and never exceed thr
-    const bool j0 = m0 == 0 && b0 > thr;
-    const bool j1 = m0 <= 1 && b1 > thr;
-    const bool j2 = m0 <= 2 && b2 > thr;
-    const bool j3 = b3 > thr;
-    ScanOut o;
-    o.jump = j0 || j1 || j2 || j3;
-    const uint32_t m = j0 ? 0u : j1 ? 1u : j2 ? 2u : 3u;
-    o.word = j0 ? b0 : j1 ? b1 : j2 ? b2 : b3;
-    n = o.jump ? base + m : min(base + 4u, N);
-    return o;
-}
-
-template <typename R, bool kHash>
-struct Walker {
-    // per-lane state of the current walk
-    bool active = false;
-    uint32_t w = 0, k = 0, neg = 0, J = 0, run_start = 0, n = 0;
-    uint32_t jumping = 0;                 // 1 while a jump of step n is pending
-    uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
-    uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-    RowRec cur;
-    // the holding time accumulated in step n: bracket [tau_h - tau_e, tau_h + tau_e] around
-    // the exact FP64 value, and what is needed to replay it exactly (state and jump count
-    // at the start of the chain, and the step's word)
-    float tau_h = 0.0f, tau_e = 0.0f;
-    uint32_t chain_k = 0, chain_J = 0, chain_word = 0;
-    R ef2 = 0, ec2 = 0, ed2 = 0;
-    uint64_t hash = kFnvOffset;
-};
-
-// Result of a finished walk, handed to the sink.
-template <typename R>
-struct Finished {
-    uint32_t k;        // final state
-    uint32_t jumps;
-    R W;               // the sample without its u factor (sign included)
-    uint64_t hash;
-};
-
-// Holding time of the current step's chain in the exact FP64 sequence: the step's word at
-// the chain's first state, then the next-holding-time word of each jump J0 .. J1 - 1 at
-// the state that jump reached (the jumps are replayed from their blocks).
-__device__ __forceinline__ double chain_tau_exact(const LevelArgs &L, uint32_t row, uint32_t walk,
-                                                  uint32_t k0, uint32_t J0, uint32_t J1,
-                                                  uint32_t word)
-{
-    RowRec rk = L.rec[k0];
-    double tau = neg_log_uniform(word) * rk.inv_r;
-    for (uint32_t J = J0; J < J1; ++J) {
-        const Word4 ph = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
-        const uint32_t slot = mulhi32(ph.x, rk.deg);
-        const SlotRec sr = L.slots[rk.slot_begin + slot];
-        const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
-        rk = L.rec[cs & kColMask];
-        tau = tau + neg_log_uniform(ph.z) * rk.inv_r;
-    }
-    return tau;
-}
-
-// Start the bracket of a new chain with the holding time of its first state.
-template <typename R, bool kHash>
-__device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
-{
-    const float e = neg_log_uniform_fast(word);
-    const float ir = static_cast<float>(s.cur.inv_r);      // finite: this state jumps
-    s.tau_h = e * ir;
-    s.tau_e = (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
-    s.chain_k = s.k;
-    s.chain_J = s.J;
-    s.chain_word = word;
-}
-
-template <typename R, bool kHash, typename Sink>
-__device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
-                                           uint64_t wb, uint64_t we, Sink &sink)
-{
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes below
-    const RowRec start = L.rec[row];
-    const R hd = static_cast<R>(L.half_dt);
-    Walker<R, kHash> s;
-    uint64_t pool = wb;                    // next unassigned walk (wave-uniform)
-    for (;;) {
-        // ---- refill idle lanes with the next walks of the range
-        const uint64_t idle = __ballot(!s.active);
-        if (idle) {
-            const uint64_t mine = pool + __popcll(idle & lower);
-            if (!s.active && mine < we) {
-                s.active = true;
-                s.w = walk0 + static_cast<uint32_t>(mine);
-                s.k = row;
-                s.cur = start;
-                s.neg = 0;
-                s.J = 0;
-                s.run_start = 0;
-                s.n = 0;
-                s.jumping = 0;
-                s.bq = 0xFFFFFFFFu;
-                s.ef2 = s.ec2 = s.ed2 = 0;
-                if (kHash) s.hash = kFnvOffset;
-            }
-            pool += __popcll(idle);
-        }
-        if (__ballot(s.active) == 0) break;
-
-        // ---- one Philox block per busy lane
-        const bool jumping = s.active && s.jumping;
-        const bool scanning = s.active && !s.jumping;
-        const uint32_t q = s.n >> 2;
-        Word4 ph{0u, 0u, 0u, 0u};
-        if (jumping || (scanning && s.bq != q))
-            ph = philox10(Word4{jumping ? s.J : q, s.w, row, jumping ? L.c3_jump : L.c3_step},
-                          L.k0, L.k1);
-
-        bool finish = false;
-        bool chain_over = false;
-        if (jumping) {
-            // jump from k by the alias table of row k: slot, coin, then the new state's record
-            const uint32_t slot = mulhi32(ph.x, s.cur.deg);
-            const SlotRec sr = L.slots[s.cur.slot_begin + slot];
-            const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
-            s.k = cs & kColMask;
-            s.neg ^= cs >> 31;
-            s.cur = L.rec[s.k];
-            ++s.J;
-            if (kHash) {
-                s.hash = (s.hash ^ static_cast<uint64_t>(s.k)) * kFnvPrime;
-                s.hash = (s.hash ^ static_cast<uint64_t>(s.n + 1)) * kFnvPrime;
-            }
-            // add the holding time at the new state; the chain goes on while the total is
-            // below dt (an absorbing state holds forever)
-            const float ir = static_cast<float>(s.cur.inv_r);
-            if (!(ir < INFINITY)) {
-                chain_over = true;
-            } else {
-                const float e = neg_log_uniform_fast(ph.z);
-                s.tau_h = s.tau_h + e * ir;
-                s.tau_e = s.tau_e + (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
-                const double hi = static_cast<double>(s.tau_h) + static_cast<double>(s.tau_e);
-                const double lo = static_cast<double>(s.tau_h) - static_cast<double>(s.tau_e);
-                if (hi < L.dt) chain_over = false;
-                else if (lo >= L.dt) chain_over = true;
-                else chain_over = !(chain_tau_exact(L, row, s.w, s.chain_k, s.chain_J, s.J,
-                                                    s.chain_word) < L.dt);
-            }
-        } else if (scanning) {
-            if (s.bq != q) {
-                const bool short_walk = L.N < 4;   // levels 0, 1: words past step N never jump
-                s.b0 = ph.x;
-                s.b1 = (short_walk && L.N < 2) ? 0u : ph.y;
-                s.b2 = short_walk ? 0u : ph.z;
-                s.b3 = short_walk ? 0u : ph.w;
-                s.bq = q;
-            }
-            const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
-            if (so.jump) {
-                // the step's holding time at k is below dt: a chain of jumps starts
-                add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                chain_start(s, so.word);
-                s.jumping = 1;
-            } else {
-                finish = s.n == L.N;
-            }
-        }
-
-        if (chain_over) {
-            // the chain of step n ends: scan on from step n + 1 in the cached block
-            s.jumping = 0;
-            s.n = s.n + 1;
-            s.run_start = s.n;
-            finish = s.n == L.N;
-            if (!finish && (s.n >> 2) == s.bq) {
-                const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
-                if (so.jump) {
-                    add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                    chain_start(s, so.word);
-                    s.jumping = 1;
-                } else {
-                    finish = s.n == L.N;
-                }
-            }
-        }
-
-        Finished<R> f{0u, 0u, static_cast<R>(0), 0ull};
-        if (finish) {
-            add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
-            R v = L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd);
-            f.k = s.k;
-            f.jumps = s.J;
-            f.W = s.neg ? -v : v;
-            f.hash = s.hash;
-            s.active = false;
-        }
-        sink.take(finish, f);
-    }
-}
-
-// Single right-hand side: each lane adds its own samples to compensated sums.
-template <typename R, typename U>
-struct SinkR1 {
-    const U *u;
-    Kahan<R> s1, s2;
-    unsigned long long jumps = 0, nonfinite = 0, hash = 0;
-    __device__ __forceinline__ void take(bool done, const Finished<R> &f)
-    {
-        if (!done) return;
-        const R y = f.W * static_cast<R>(u[f.k]);
-        jumps += f.jumps;
-        hash += f.hash;
-        nonfinite += !isfinite(y);
-        s1.add(y);
-        s2.add(y * y);
-    }
-};
-
-// Several right-hand sides: the finished walks of an iteration are broadcast one by one
-// and lane r adds right-hand side r (+64 g) from the contiguous row u[k, :]. Walks
-// without a jump all end at the start row with the same weight; they are only counted.
-constexpr int kMaxRhsGroups = 4;   // up to 256 right-hand sides
-
-template <typename R, typename U>
-struct SinkRhs {
-    const U *u;
-    int32_t nrhs;
-    int groups;
-    Kahan<R> s1[kMaxRhsGroups], s2[kMaxRhsGroups];
-    unsigned long long jumps = 0, nojump = 0, nonfinite = 0, hash = 0;
-    __device__ __forceinline__ void take(bool done, const Finished<R> &f)
-    {
-        const bool moved = done && f.jumps > 0;
-        if (done) {
-            jumps += f.jumps;
-            hash += f.hash;
-            nojump += f.jumps == 0;
-        }
-        uint64_t pending = __ballot(moved && f.W != static_cast<R>(0));
-        const uint32_t lane = threadIdx.x & (kWave - 1);
-        while (pending) {
-            const int t = __ffsll(static_cast<unsigned long long>(pending)) - 1;
-            pending &= pending - 1;
-            const R Wt = __shfl(f.W, t, kWave);
-            const uint32_t kt = __shfl(f.k, t, kWave);
-#pragma unroll
-            for (int g = 0; g < kMaxRhsGroups; ++g) {
-                const int r = static_cast<int>(lane) + g * kWave;
-                if (g < groups && r < nrhs) {
-                    const R y = Wt * static_cast<R>(u[static_cast<uint64_t>(kt) * nrhs + r]);
-                    nonfinite += !isfinite(y);
-                    s1[g].add(y);
-                    s2[g].add(y * y);
-                }
-            }
-        }
-    }
-};
-
-// One wave per (row, chunk) item.
 template <typename R, typename U, bool kHash>
 __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,

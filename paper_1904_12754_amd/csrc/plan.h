@@ -1,0 +1,56 @@
+// Internal layout of a plan (the object behind mlmc_plan_t) and the helpers the C-ABI
+// translation units share. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlmc_expv.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace mlmc {
+
+constexpr int kMaxLevel = 28;   // N = 2^28 steps per walk at most
+
+int fail(int code, const std::string &msg);
+
+}  // namespace mlmc
+
+struct mlmc_plan {
+    using RowRec = mlmc::RowRec;
+    using SlotRec = mlmc::SlotRec;
+    static constexpr int kMaxLevel = mlmc::kMaxLevel;
+    int64_t n = 0, n_rows = 0, n_slots = 0;
+    int32_t l0 = 0, precision = 0;
+    double beta = 0, r_max = 0, d_min = 0, d_max = 0;
+    SlotRec *slots = nullptr;
+    RowRec *rows_base = nullptr;
+    RowRec *level_rec[kMaxLevel + 1] = {};
+    int64_t *req_rows = nullptr;             // device; null = all rows
+    double *partial = nullptr;
+    size_t partial_bytes = 0;
+    unsigned long long *counters = nullptr;  // 2 per level
+    unsigned int *bad = nullptr;
+    double *moments = nullptr;               // 3 per level
+    double *acc = nullptr;                   // 2 * n_rows * nrhs per level
+    size_t acc_doubles = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // per-launch timing of the walk kernel (pairs of events around each launch)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;
+    size_t tev_used = 0;
+    int64_t bytes = 0;
+};
+
+namespace mlmc {
+
+// Upload the row records of `level` (thresholds included) if not done yet.
+int upload_level(mlmc_plan *p, int level, hipStream_t s);
+// Everything a walk of `level` of this plan reads.
+LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance);
+
+}  // namespace mlmc

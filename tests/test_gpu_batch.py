@@ -1,0 +1,99 @@
+"""Batched persistent launch captured in a hipGraph: every instance matches the oracle run
+with the same instance number, seed and schedule (jump counts exactly, estimates within the
+FP32 bar), and graph replays interleaved with eager work reproduce the result exactly."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlmc as orc
+from paper_1904_12754_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1904_12754_amd import api as _api
+    return _api
+
+
+def _instances(count, seed, nmin=200, nmax=3000):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        kind = q % 3
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        if kind == 0:
+            A = inputs.laplacian_1d(n)
+        elif kind == 1:
+            A = inputs.laplacian_2d(max(2, int(round(np.sqrt(n)))))
+        else:
+            A = inputs.erdos_renyi(n, 8.0, int(rng.integers(0, 2 ** 31)))
+        c = float(np.exp(rng.uniform(np.log(0.5), np.log(8.0))))
+        out.append((A, c / A.norm1(), rng.normal(size=A.n)))
+    return out
+
+
+def _walks(count, levels=4, base=96):
+    return np.array([[int(round(base * 2 ** (1.5 * (levels - 1 - q)))) for q in range(levels)]
+                     for _ in range(count)], dtype=np.int64)
+
+
+def _oracle_x(A, t, u, l0, walks, seed, instance):
+    tt = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    res = orc.mlmc_fixed(tt, t, u, l0, l0 + len(walks) - 1, walks, seed, instance=instance)
+    return res
+
+
+@pytest.mark.parametrize("R", [1, 3])
+def test_batch_matches_oracle_and_graph_replays_are_exact(api, R):
+    insts = _instances(9, seed=40 + R)
+    walks = _walks(len(insts))
+    plans, us = [], []
+    for A, t, v in insts:
+        plans.append(api.Plan(A, t, precision="fp32"))
+        u = v if R == 1 else np.stack([v, np.cos(v), -v], axis=1)
+        us.append(torch.as_tensor(np.ascontiguousarray(u, dtype=np.float32), device="cuda"))
+    _say(f"batch R={R}: {len(insts)} instances, sizes {[A.n for A, _, _ in insts]}")
+    batch = api.Batch(plans, us, walks, autotune=True)
+    _say(f"batch info {batch.info}")
+    assert batch.info["graph_nodes"] >= 3
+    seed = 777
+    xs = [x.clone() for x in batch.launch(seed)]
+    st = batch.stats()
+    # every instance against the oracle with the same instance number
+    for b, ((A, t, v), p) in enumerate(zip(insts, plans)):
+        _say(f"  oracle instance {b}: n={A.n} l0={p.l0} walks={list(walks[b])}")
+        u = us[b].double().cpu().numpy()
+        res = _oracle_x(A, t, u, p.l0, walks[b], seed, instance=b)
+        assert st[b]["total_jumps"] == res.jumps, b
+        assert st[b]["steps"] == res.steps, b
+        xg = xs[b].cpu().numpy()
+        assert np.all(np.abs(xg - res.x) <= TOL32 * res.mass + 1e-300), b
+    # replays with eager work and synchronisation between them are bit-identical
+    side = api.Plan(insts[0][0], insts[0][1], precision="fp32")
+    for rep in range(3):
+        side.run(us[0], walks=[64, 64], seed=rep)
+        torch.cuda.synchronize()
+        again = batch.launch(seed)
+        torch.cuda.synchronize()
+        for b in range(len(insts)):
+            assert torch.equal(again[b], xs[b]), (rep, b)
+    # another seed gives another estimate
+    other = batch.launch(seed + 1)
+    torch.cuda.synchronize()
+    assert not torch.equal(other[0], xs[0])
+    side.close()
+    batch.close()
+    for p in plans:
+        p.close()
