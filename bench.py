@@ -69,7 +69,8 @@ def parse():
     ap.add_argument("--pilot", type=int, default=4096)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc"], default="bench",
                     help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
                          "--walks per row), for counter runs; copy: a plain device copy of "
                          "--bytes, the calibration for the traffic counters")
@@ -100,6 +101,105 @@ def kernel_only(args):
         print(json.dumps({"mode": "kernel", "level": lev, "walks": walks, "steps": walks << lev,
                           "jumps": jumps, "seconds": el, "steps_per_s": (walks << lev) / el}),
               flush=True)
+    plan.close()
+
+
+def batch_bench(args):
+    """The uneven batch: 512 instances (1D/2D Laplacians and Erdos-Renyi graphs, n
+    log-uniform in [1e3, 1e5], ||tA||_1 log-uniform in [0.5, 8], v ~ N(0, 1)), four levels
+    from each instance's l0 with 64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32
+    weights, in one graph-captured persistent launch. Also times the same work as one
+    fixed-schedule run per instance."""
+    import numpy as np
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    t0 = time.perf_counter()
+    insts = inputs.workload_uneven_batch(args.instances)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plans = [api.Plan(A, t, precision="fp32") for A, t, v in insts]
+    us = [torch.as_tensor(v.astype(np.float32), device="cuda") for A, t, v in insts]
+    t_plan = time.perf_counter() - t0
+    walks = np.array([[int(round(64 * 2 ** (1.5 * (3 - q)))) for q in range(4)]
+                      for _ in insts], dtype=np.int64)
+    t0 = time.perf_counter()
+    batch = api.Batch(plans, us, walks, autotune=True)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    batch.launch(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        batch.launch(100 + k)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    st = batch.stats()
+    steps = sum(x["steps"] for x in st)
+    jumps = sum(x["total_jumps"] for x in st)
+    # the same work, one fixed-schedule run per instance
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, p in enumerate(plans):
+        p.run(us[b], walks=walks[b], seed=100, instance=b, want_stats=False)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    print(json.dumps({
+        "metric": "walk steps/s", "value": steps / el, "unit": "steps/s",
+        "ms_per_launch": el * 1e3, "steps_per_launch": steps, "jumps_per_launch": jumps,
+        "one_run_per_instance_ms": el_seq * 1e3, "speedup_vs_one_run_per_instance": el_seq / el,
+        "config": {"workload": f"{len(insts)} uneven instances (1D/2D Laplacian, ER mean degree 8), "
+                               "4 levels, FP32 weights, one graph-captured persistent launch",
+                   "rows_total": int(sum(A.n for A, _, _ in insts)),
+                   "walks_per_row_per_level": walks[0].tolist(),
+                   "batch": batch.info,
+                   "host_s": {"generate": t_gen, "plans": t_plan, "create_with_autotune": t_create}},
+    }), flush=True)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def tc_bench(args):
+    """Total communicability with many right-hand sides: exp(beta A) [1, r_1..r_63] on a
+    Barabasi-Albert graph (n = 1e6, m = 5, symmetric 0/1 adjacency stored as FP32),
+    beta = 1/d_max, levels l0..l0+4 with 128 walks per row per level, FP32 weights, 64
+    right-hand sides carried by every path."""
+    import numpy as np
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    t0 = time.perf_counter()
+    A, beta, U = inputs.workload_ba_tc(n=args.grid if args.grid > 256 else 1_000_000)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = api.Plan(A, beta, precision="fp32", values_dtype=np.float32)
+    u = torch.as_tensor(U.astype(np.float32), device="cuda")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    walks = [128] * 5
+    plan.run(u, walks=walks, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x, st = plan.run(u, walks=walks, seed=10 + k)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    tc = float(x[:, 0].sum().item())
+    print(json.dumps({
+        "metric": "walk steps/s", "value": st["steps"] / el, "unit": "steps/s",
+        "ms_per_run": el * 1e3, "walk_kernel_ms": st["walk_kernel_ms"],
+        "rhs_samples_per_s": st["steps"] * u.shape[1] / el,
+        "jumps": st["total_jumps"], "steps": st["steps"],
+        "total_communicability_estimate": tc,
+        "config": {"workload": f"Barabasi-Albert n={A.n} m=5, beta=1/d_max={beta:.3e}, "
+                               f"{u.shape[1]} right-hand sides (ones + Rademacher), "
+                               f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level",
+                   "nnz": A.nnz, "d_max": int(round(1 / beta)),
+                   "host_s": {"generate": t_gen, "plan": t_plan}},
+    }), flush=True)
     plan.close()
 
 
@@ -161,6 +261,10 @@ def main():
         return kernel_only(args)
     if args.mode == "copy":
         return copy_only(args)
+    if args.mode == "batch":
+        return batch_bench(args)
+    if args.mode == "tc":
+        return tc_bench(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "
                                    "measured at one GPU's share of the work (--gpus 1)"}))

@@ -73,6 +73,7 @@ void free_plan(mlmc_plan *p)
     hipFree(p->counters);
     hipFree(p->bad);
     hipFree(p->moments);
+    hipFree(p->moment_scratch);
     hipFree(p->acc);
     if (p->ev0) hipEventDestroy(p->ev0);
     if (p->ev1) hipEventDestroy(p->ev1);
@@ -387,6 +388,7 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     if ((rc = dev_alloc(p, &p->counters, 2 * (kMaxLevel + 1)))) return rc;
     if ((rc = dev_alloc(p, &p->bad, 1))) return rc;
     if ((rc = dev_alloc(p, &p->moments, 3 * (kMaxLevel + 1)))) return rc;
+    if ((rc = dev_alloc(p, &p->moment_scratch, 3 * kMomentBlocks))) return rc;
     MLMC_HIP_TRY(hipEventCreate(&p->ev0));
     MLMC_HIP_TRY(hipEventCreate(&p->ev1));
     MLMC_HIP_TRY(hipMemcpyAsync(p->slots, slots.data(), sizeof(SlotRec) * slots.size(), hipMemcpyHostToDevice, s));
@@ -522,7 +524,7 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     auto read_moments = [&](int levels) -> int {
         for (int qq = 0; qq < levels; ++qq)
             MLMC_HIP_TRY(launch_level_moments(s1_of(qq), s2_of(qq), count, static_cast<double>(M[qq]),
-                                              p->moments + 3 * qq, s));
+                                              p->moments + 3 * qq, p->moment_scratch, s));
         std::vector<double> h(3 * static_cast<size_t>(levels));
         MLMC_HIP_TRY(hipMemcpyAsync(h.data(), p->moments, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), p->counters, sizeof(unsigned long long) * ctr.size(),

@@ -232,6 +232,7 @@ struct mlmc_batch {
     double *d_partial = nullptr;
     double *d_acc = nullptr;
     double *d_moments = nullptr;
+    double *d_moment_scratch = nullptr;
     uint64_t total_items = 0, total_pairs = 0, total_out_pairs = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -260,6 +261,7 @@ void free_batch(mlmc_batch *b)
     hipFree(b->d_partial);
     hipFree(b->d_acc);
     hipFree(b->d_moments);
+    hipFree(b->d_moment_scratch);
     delete b;
 }
 
@@ -356,6 +358,7 @@ int build_tables(mlmc_batch *b, hipStream_t s)
     if ((rc = balloc(b, &b->d_acc, 2 * b->total_pairs))) return rc;
     if ((rc = balloc(b, &b->d_counters, 2 * b->h_segs.size()))) return rc;
     if ((rc = balloc(b, &b->d_moments, 3 * b->h_segs.size()))) return rc;
+    if ((rc = balloc(b, &b->d_moment_scratch, 3 * kMomentBlocks))) return rc;
     uint64_t acc_off = 0;
     for (size_t g = 0; g < b->h_segs.size(); ++g) {
         Segment &sg = b->h_segs[g];
@@ -565,7 +568,7 @@ int mlmc_expv_batch_stats(mlmc_batch_t *b, mlmc_stats_t *per_instance, void *str
         const Segment &sg = b->h_segs[g];
         const int64_t cnt = static_cast<int64_t>(sg.n_rows) * sg.nrhs;
         MLMC_HIP_TRY(launch_level_moments(sg.acc, sg.acc + cnt, cnt, static_cast<double>(sg.M),
-                                          b->d_moments + 3 * g, s));
+                                          b->d_moments + 3 * g, b->d_moment_scratch, s));
     }
     std::vector<double> mom(3 * nseg);
     std::vector<unsigned long long> ctr(2 * nseg);

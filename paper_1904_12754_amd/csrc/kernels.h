@@ -43,8 +43,10 @@ hipError_t launch_finalize(const double *partial, int64_t n_rows, uint32_t chunk
 
 // One level's moments over all (row, rhs): out[0] = sum m, out[1] = sum m^2,
 // out[2] = sum V, with m = s1 / M and V = max(s2 / M - m^2, 0). Deterministic order.
+// scratch: kMomentBlocks * 3 doubles, reusable once the call's work has run.
+constexpr int kMomentBlocks = 1024;
 hipError_t launch_level_moments(const double *s1, const double *s2, int64_t count, double M,
-                                double *out, hipStream_t s);
+                                double *out, double *scratch, hipStream_t s);
 
 // x[idx] = sum_q s1[q][idx] / M[q] over `levels` accumulators.
 struct CombineArgs {

@@ -5,6 +5,7 @@
 #include "kernels.h"
 #include "walk_engine.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mlmc {
@@ -145,21 +146,13 @@ __global__ void finalize_kernel(const double *__restrict__ partial, int64_t n_ro
     }
 }
 
-constexpr int kMomentThreads = 1024;
+constexpr int kMomentThreads = 256;
 
-__global__ __launch_bounds__(kMomentThreads) void moments_kernel(const double *__restrict__ s1,
-                                                                 const double *__restrict__ s2,
-                                                                 int64_t count, double M,
-                                                                 double *out)
+// Block sums of (m, m^2, V) over a contiguous range of (row, rhs) pairs per block, then a
+// fixed-order tree: deterministic for a given count.
+__device__ __forceinline__ void block_reduce3(double &a, double &b, double &v)
 {
     __shared__ double sh[3][kMomentThreads];
-    double a = 0.0, b = 0.0, v = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += kMomentThreads) {
-        const double m = s1[i] / M;
-        a += m;
-        b += m * m;
-        v += fmax(s2[i] / M - m * m, 0.0);
-    }
     sh[0][threadIdx.x] = a;
     sh[1][threadIdx.x] = b;
     sh[2][threadIdx.x] = v;
@@ -172,10 +165,47 @@ __global__ __launch_bounds__(kMomentThreads) void moments_kernel(const double *_
         }
         __syncthreads();
     }
+    a = sh[0][0];
+    b = sh[1][0];
+    v = sh[2][0];
+}
+
+__global__ __launch_bounds__(kMomentThreads) void moments_partial(const double *__restrict__ s1,
+                                                                  const double *__restrict__ s2,
+                                                                  int64_t count, double M,
+                                                                  int64_t per_block, double *part)
+{
+    const int64_t begin = static_cast<int64_t>(blockIdx.x) * per_block;
+    const int64_t end = min(begin + per_block, count);
+    double a = 0.0, b = 0.0, v = 0.0;
+    for (int64_t i = begin + threadIdx.x; i < end; i += kMomentThreads) {
+        const double m = s1[i] / M;
+        a += m;
+        b += m * m;
+        v += fmax(s2[i] / M - m * m, 0.0);
+    }
+    block_reduce3(a, b, v);
     if (threadIdx.x == 0) {
-        out[0] = sh[0][0];
-        out[1] = sh[1][0];
-        out[2] = sh[2][0];
+        part[3 * blockIdx.x + 0] = a;
+        part[3 * blockIdx.x + 1] = b;
+        part[3 * blockIdx.x + 2] = v;
+    }
+}
+
+__global__ __launch_bounds__(kMomentThreads) void moments_final(const double *__restrict__ part,
+                                                                int32_t blocks, double *out)
+{
+    double a = 0.0, b = 0.0, v = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += kMomentThreads) {
+        a += part[3 * i + 0];
+        b += part[3 * i + 1];
+        v += part[3 * i + 2];
+    }
+    block_reduce3(a, b, v);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+        out[2] = v;
     }
 }
 
@@ -280,9 +310,14 @@ hipError_t launch_finalize(const double *partial, int64_t n_rows, uint32_t chunk
 }
 
 hipError_t launch_level_moments(const double *s1, const double *s2, int64_t count, double M,
-                                double *out, hipStream_t s)
+                                double *out, double *scratch, hipStream_t s)
 {
-    hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(kMomentThreads), 0, s, s1, s2, count, M, out);
+    const int64_t target = (count + kMomentBlocks - 1) / kMomentBlocks;
+    const int64_t per_block = std::max<int64_t>(target, 4096);
+    const int32_t blocks = static_cast<int32_t>(std::max<int64_t>(1, (count + per_block - 1) / per_block));
+    hipLaunchKernelGGL(moments_partial, dim3(blocks), dim3(kMomentThreads), 0, s, s1, s2, count, M,
+                       per_block, scratch);
+    hipLaunchKernelGGL(moments_final, dim3(1), dim3(kMomentThreads), 0, s, scratch, blocks, out);
     return hipGetLastError();
 }
 

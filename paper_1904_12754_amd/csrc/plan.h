@@ -36,6 +36,7 @@ struct mlmc_plan {
     unsigned long long *counters = nullptr;  // 2 per level
     unsigned int *bad = nullptr;
     double *moments = nullptr;               // 3 per level
+    double *moment_scratch = nullptr;        // 3 * kMomentBlocks
     double *acc = nullptr;                   // 2 * n_rows * nrhs per level
     size_t acc_doubles = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
