@@ -56,7 +56,8 @@ def _declare(L):
                                 _p(ctypes.c_int32)]
     L.orc_decompose.restype = ctypes.c_int
     tables = [_p(ctypes.c_double), _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_int32),
-              _p(ctypes.c_int32), _p(ctypes.c_uint8), _p(ctypes.c_uint32), _p(ctypes.c_int32)]
+              _p(ctypes.c_int32), _p(ctypes.c_uint8), _p(ctypes.c_uint32), _p(ctypes.c_int32),
+              _p(ctypes.c_uint32), _p(ctypes.c_int32), _p(ctypes.c_double)]
     L.orc_walk_trace.argtypes = tables + [ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.c_int64, _p(ctypes.c_int64),
                                           _p(ctypes.c_uint32), _p(ctypes.c_int64),
@@ -77,6 +78,9 @@ def _declare(L):
     L.orc_philox_array.argtypes = [ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_uint32),
                                    _p(ctypes.c_uint32)]
     L.orc_philox_array.restype = None
+    L.orc_alias_tables.argtypes = [ctypes.c_int64, _p(ctypes.c_int64), _p(ctypes.c_int32),
+                                   _p(ctypes.c_double), _p(ctypes.c_uint32), _p(ctypes.c_int32)]
+    L.orc_alias_tables.restype = None
     L.orc_max_threads.argtypes = []
     L.orc_max_threads.restype = ctypes.c_int
 
@@ -141,12 +145,33 @@ class Tables:
     slot_sign: np.ndarray
     slot_thr: np.ndarray
     slot_alias: np.ndarray
+    # importance sampling: proposal alias tables and per-slot likelihood ratios p/q
+    q_thr: np.ndarray | None = None
+    q_alias: np.ndarray | None = None
+    q_ratio: np.ndarray | None = None
 
     def args(self):
+        nil = lambda t: ctypes.cast(None, _p(t))
         return (_ptr(self.d, ctypes.c_double), _ptr(self.inv_r, ctypes.c_double),
                 _ptr(self.slot_begin, ctypes.c_int64), _ptr(self.deg, ctypes.c_int32),
                 _ptr(self.slot_col, ctypes.c_int32), _ptr(self.slot_sign, ctypes.c_uint8),
-                _ptr(self.slot_thr, ctypes.c_uint32), _ptr(self.slot_alias, ctypes.c_int32))
+                _ptr(self.slot_thr, ctypes.c_uint32), _ptr(self.slot_alias, ctypes.c_int32),
+                nil(ctypes.c_uint32) if self.q_thr is None else _ptr(self.q_thr, ctypes.c_uint32),
+                nil(ctypes.c_int32) if self.q_alias is None else _ptr(self.q_alias, ctypes.c_int32),
+                nil(ctypes.c_double) if self.q_ratio is None else _ptr(self.q_ratio, ctypes.c_double))
+
+    def slot_probs(self) -> np.ndarray:
+        """The plain jump law p per slot (|a_kj| / r_k), recomputed from the tables."""
+        return np.asarray(self._p_slot)
+
+    def with_proposal(self, q_thr, q_alias, q_ratio) -> "Tables":
+        """The same tables walking under a proposal law (alias tables + ratios p/q)."""
+        import copy
+        t = copy.copy(self)
+        t.q_thr = np.ascontiguousarray(q_thr, dtype=np.uint32)
+        t.q_alias = np.ascontiguousarray(q_alias, dtype=np.int32)
+        t.q_ratio = np.ascontiguousarray(q_ratio, dtype=np.float64)
+        return t
 
 
 def decompose(n: int, row_ptr, col, val) -> Tables:
@@ -171,7 +196,29 @@ def decompose(n: int, row_ptr, col, val) -> Tables:
                              _ptr(slot_thr, ctypes.c_uint32), _ptr(slot_alias, ctypes.c_int32))
     if rc != 0:
         raise MemoryError("oracle decomposition failed")
-    return Tables(n, r, d, inv_r, slot_begin, deg, slot_col, slot_sign, slot_thr, slot_alias)
+    t = Tables(n, r, d, inv_r, slot_begin, deg, slot_col, slot_sign, slot_thr, slot_alias)
+    # plain jump law per slot, |a_kj| / r_k, in CSR slot order
+    p_slot = np.zeros(max(int(slot_begin[-1]), 1), np.float64)
+    for i in range(n):
+        b, e = row_ptr[i], row_ptr[i + 1]
+        cols, vals = col[b:e], val[b:e]
+        keep = (cols != i) & (vals != 0.0)
+        if keep.any():
+            p_slot[slot_begin[i]:slot_begin[i + 1]] = np.abs(vals[keep]) / r[i]
+    t._p_slot = p_slot
+    return t
+
+
+def alias_tables(t: Tables, prob) -> tuple[np.ndarray, np.ndarray]:
+    """Alias tables (thr, alias slot) of an arbitrary per-slot law."""
+    prob = np.ascontiguousarray(prob, dtype=np.float64)
+    ns = max(int(t.slot_begin[-1]), 1)
+    thr = np.zeros(ns, np.uint32)
+    alias = np.zeros(ns, np.int32)
+    lib().orc_alias_tables(t.n, _ptr(t.slot_begin, ctypes.c_int64), _ptr(t.deg, ctypes.c_int32),
+                           _ptr(prob, ctypes.c_double), _ptr(thr, ctypes.c_uint32),
+                           _ptr(alias, ctypes.c_int32))
+    return thr, alias
 
 
 def default_l0(tables: Tables, beta: float) -> int:

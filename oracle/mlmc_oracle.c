@@ -232,6 +232,12 @@ typedef struct {
     const int32_t *deg, *slot_col, *slot_alias;
     const uint8_t *slot_sign;
     const uint32_t *slot_thr;
+    /* importance sampling (NULL = the plain jump law): a proposal law q given by its own
+     * alias tables, and per slot the likelihood ratio p/q multiplied into the functional
+     * whenever that slot is taken */
+    const uint32_t *q_thr;
+    const int32_t *q_alias;
+    const double *q_ratio;
 } orc_tables;
 
 typedef struct {
@@ -267,8 +273,15 @@ static void orc_one_walk(const orc_tables *t, double beta, int level, const uint
             uint32_t dg = (uint32_t)t->deg[k];
             uint32_t slot = (uint32_t)(((uint64_t)w[0] * (uint64_t)dg) >> 32);
             int64_t sb = t->slot_begin[k];
-            uint32_t pick = (w[1] < t->slot_thr[sb + slot]) ? slot
-                                                             : (uint32_t)t->slot_alias[sb + slot];
+            uint32_t pick;
+            if (t->q_thr) {
+                pick = (w[1] < t->q_thr[sb + slot]) ? slot : (uint32_t)t->q_alias[sb + slot];
+                /* likelihood ratio of the proposal: keeps the estimator unbiased */
+                eta2 = eta2 * t->q_ratio[sb + pick];
+                eta1 = eta1 * t->q_ratio[sb + pick];
+            } else {
+                pick = (w[1] < t->slot_thr[sb + slot]) ? slot : (uint32_t)t->slot_alias[sb + slot];
+            }
             j = t->slot_col[sb + pick];
             int neg = t->slot_sign[sb + pick];
             /* holding time at the new state */
@@ -297,13 +310,15 @@ static void orc_one_walk(const orc_tables *t, double beta, int level, const uint
  * count, path hash and the two functionals. */
 void orc_walk_trace(const double *d, const double *inv_r, const int64_t *slot_begin,
                     const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
-                    const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                    const uint32_t *slot_thr, const int32_t *slot_alias, const uint32_t *q_thr,
+                    const int32_t *q_alias, const double *q_ratio, double beta,
                     int level, uint64_t seed, uint32_t instance, int64_t count,
                     const int64_t *rows, const uint32_t *walks, int64_t *final_state,
                     int32_t *sign, int64_t *jumps, uint64_t *hash, double *eta_fine,
                     double *eta_coarse)
 {
-    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr,
+                    q_thr, q_alias, q_ratio};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t q = 0; q < count; ++q) {
@@ -341,13 +356,15 @@ static void orc_add(orc_sum *a, double x)
 /* ------------------------------------------------------------------------------ */
 void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
                     const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
-                    const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                    const uint32_t *slot_thr, const int32_t *slot_alias, const uint32_t *q_thr,
+                    const int32_t *q_alias, const double *q_ratio, double beta,
                     int level, int l0, uint64_t seed, uint32_t instance, const double *u,
                     int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
                     uint32_t M, double *sum1, double *sum2, double *mass, double *mass2,
                     int64_t *jumps, uint64_t *hash_sum, int32_t nthreads)
 {
-    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr};
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr,
+                    q_thr, q_alias, q_ratio};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -410,6 +427,38 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* Alias tables (the construction of orc_decompose) for an arbitrary law given per slot:
+ * prob[s] for the slots of each row (summing to one per row). */
+void orc_alias_tables(int64_t n, const int64_t *slot_begin, const int32_t *deg, const double *prob,
+                      uint32_t *thr, int32_t *alias)
+{
+    int32_t maxdeg = 0;
+    for (int64_t i = 0; i < n; ++i) if (deg[i] > maxdeg) maxdeg = deg[i];
+    double *q = (double *)malloc(sizeof(double) * (size_t)(maxdeg + 1));
+    int32_t *small = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    int32_t *large = (int32_t *)malloc(sizeof(int32_t) * (size_t)(maxdeg + 1));
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t sb = slot_begin[i];
+        const int32_t k = deg[i];
+        int32_t ns = 0, nl = 0;
+        for (int32_t s = 0; s < k; ++s) {
+            q[s] = prob[sb + s] * (double)k;
+            if (q[s] < 1.0) small[ns++] = s; else large[nl++] = s;
+        }
+        while (ns > 0 && nl > 0) {
+            int32_t a = small[--ns];
+            int32_t g = large[--nl];
+            thr[sb + a] = (uint32_t)floor(q[a] * 4294967296.0);
+            alias[sb + a] = g;
+            q[g] = (q[g] + q[a]) - 1.0;
+            if (q[g] < 1.0) small[ns++] = g; else large[nl++] = g;
+        }
+        while (nl > 0) { int32_t g = large[--nl]; thr[sb + g] = 0xFFFFFFFFu; alias[sb + g] = g; }
+        while (ns > 0) { int32_t a = small[--ns]; thr[sb + a] = 0xFFFFFFFFu; alias[sb + a] = a; }
+    }
+    free(q); free(small); free(large);
 }
 
 /* Vectorised helpers for the tests: log of count values, and the uniform variate of
