@@ -186,8 +186,9 @@ void mlmc_expv_destroy(mlmc_plan_t *plan);
 /* ---- batched runs ------------------------------------------------------------------
  * Many plans (different matrices, right-hand sides or times) with fixed level schedules
  * in one persistent launch: every (instance, level) is split into items of whole walks of
- * one row, and a persistent grid pulls items from one atomic counter, so instances of very
- * different sizes share the chip in a single launch. The sequence (reset, walks, per-row
+ * one row, and the waves of a persistent grid take the items in a fixed interleaved order
+ * (wave w takes items w, w + waves, ...), so instances of very different sizes share the
+ * chip in a single launch. Plans with an active proposal are rejected. The sequence (reset, walks, per-row
  * sums, per-instance FP64 combine of the levels, section 2.2) is captured once in a
  * hipGraph at creation and replayed by mlmc_expv_batch_launch. Instance b draws the
  * random streams of instance number b (the `instance` of a single run), so its estimate
@@ -234,6 +235,85 @@ int mlmc_expv_batch_stats(mlmc_batch_t *batch, mlmc_stats_t *per_instance, void 
 int mlmc_expv_batch_info(const mlmc_batch_t *batch, mlmc_batch_info_t *info);
 
 void mlmc_expv_batch_destroy(mlmc_batch_t *batch);
+
+/* ---- learned proposal (importance sampling of the jump law) ------------------------
+ * The walks may draw their jumps from a law q instead of the jump law p_s = |a_ks| / r_k of
+ * section 3, with the path's functional multiplied by p/q of every jump taken. Any q with
+ * the support of p leaves each level's expectation, and so the estimator of section 2.2,
+ * unchanged; a q close to |Y| p lowers the variance. q is a small network of row features:
+ *   features of row k (16): p_s and |xhat(col_s)| / max|xhat| for slots s = 0..5, r_k dt,
+ *     d_k dt, |xhat_k| / max|xhat|, (l - l0) / 8   (xhat: a pilot estimate of x)
+ *   16 -> 64 (ReLU) -> 64 (ReLU) -> 7;  q_s = alpha softmax(z)_s + (1 - alpha) p_s over
+ *     the row's slots, z = outputs 0..5, alpha = 0.9 sigmoid(output 6)
+ * Rows with more than 6 off-diagonal entries keep q = p. The defensive mixture bounds the
+ * ratio p/q by 10. Tables are built on the device (BF16 matrix-core inference, FP32
+ * accumulation), one alias table per level. Walks of levels with tables use them while the
+ * proposal is enabled; runs, level sums and traces all follow it. Path decisions under a
+ * proposal are integer (alias thresholds) as without one. */
+#define MLMC_PROPOSAL_PARAMS 5703   /* W1 16x64, b1 64, W2 64x64, b2 64, W3 64x7, b3 7 (row
+                                       major, in this order; W maps inputs to outputs) */
+
+/* Set the proposal of levels l0 .. l0 + num_levels - 1 and enable it.
+ *   params: HOST, MLMC_PROPOSAL_PARAMS floats, copied; NULL selects the identity proposal
+ *     (the plain tables with ratio 1: walks and results are those without a proposal).
+ *   xhat: DEVICE, n FP64, copied; NULL means zeros.
+ * Levels at or above l0 + num_levels walk with the plain law. */
+int mlmc_expv_proposal_set(mlmc_plan_t *plan, const float *params, const double *xhat,
+                           int32_t num_levels, void *stream);
+
+/* Switch a set proposal off (0) or on again (1). */
+int mlmc_expv_proposal_enable(mlmc_plan_t *plan, int32_t on);
+
+/* Export the proposal tables of one level (rebuilding them from the parameters).
+ * All arrays DEVICE, n_slots entries in the plan's slot order (rows in order, the row's
+ * off-diagonal entries in CSR order): alias threshold (the own slot is kept iff the coin
+ * word is below it), alias slot index within the row, ratio p/q and q (FP32). */
+int mlmc_expv_proposal_tables(mlmc_plan_t *plan, int32_t level, uint32_t *thr,
+                              int32_t *alias_slot, float *ratio, float *q, void *stream);
+
+/* Training loss and its gradient for given parameters, in FP32 on the device:
+ *   L = - sum_b w_b log q_{slot_b}(row_b) / sum_b w_b
+ * (the cross-entropy method; its minimiser over all laws is q ~ |Y| p). Transitions with
+ * slot -1, or a slot past the row's entries, contribute nothing.
+ *   params: HOST; xhat: DEVICE n FP64 or NULL; rows, slots, weights: HOST, count entries
+ *   (rows in [0, n), slots in [-1, 6), weights finite >= 0); grad: HOST
+ *   MLMC_PROPOSAL_PARAMS floats; loss: HOST. Waits for the stream. */
+int mlmc_expv_proposal_loss_grad(mlmc_plan_t *plan, const float *params, const double *xhat,
+                                 int32_t level, int32_t count, const int64_t *rows,
+                                 const int32_t *slots, const float *weights, float *grad,
+                                 double *loss, void *stream);
+
+typedef struct {
+    uint64_t seed;              /* Philox key of the pilot and capture walks (instances 4095
+                                   and 4094, kept apart from runs that use other instances) */
+    const float *init_params;   /* HOST, MLMC_PROPOSAL_PARAMS floats */
+    int64_t pilot_walks;        /* level-l0 walks per row of the pilot estimate xhat */
+    int32_t capture_walks;      /* level-l0 walks per sampled row whose jumps are recorded
+                                   (the first 8 jumps out of rows with <= 6 entries) */
+    int32_t sample_stride;      /* rows 0, stride, 2 stride, ... are sampled */
+    int32_t steps;              /* Adam steps */
+    int32_t batch;              /* transitions per step, <= 2^20 */
+    double lr;                  /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+    int32_t num_levels;         /* levels that get tables, as in mlmc_expv_proposal_set */
+    int32_t pad;
+} mlmc_train_opts_t;
+
+typedef struct {
+    int64_t transitions;        /* recorded transitions with a nonzero weight */
+    int32_t steps, n_losses;
+    double train_ms;            /* device time of the whole call */
+    double first_loss, last_loss;
+    double losses[64];          /* the last n_losses minibatch losses, every 16 steps */
+} mlmc_train_stats_t;
+
+/* Train the proposal and set it (as mlmc_expv_proposal_set with the trained parameters and
+ * the pilot estimate): pilot estimate of x from plain level-l0 walks, capture of their
+ * jumps with |Y| weights, minibatch Adam on the loss of mlmc_expv_proposal_loss_grad.
+ * Needs a plan over all rows and an FP32 right-hand side (u: DEVICE, n entries).
+ * params_out: HOST, nullable. Waits for the stream. */
+int mlmc_expv_proposal_train(mlmc_plan_t *plan, const void *u, int32_t u_dtype,
+                             const mlmc_train_opts_t *opts, float *params_out,
+                             mlmc_train_stats_t *stats, void *stream);
 
 const char *mlmc_status_string(int status);
 const char *mlmc_last_error(void);

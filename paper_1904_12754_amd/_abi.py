@@ -30,7 +30,11 @@ MLMC_MAX_LEVELS = 40
 EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_level_sums",
            "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_expv_batch_create",
            "mlmc_expv_batch_launch", "mlmc_expv_batch_stats", "mlmc_expv_batch_info",
-           "mlmc_expv_batch_destroy", "mlmc_status_string", "mlmc_last_error")
+           "mlmc_expv_batch_destroy", "mlmc_expv_proposal_set", "mlmc_expv_proposal_enable",
+           "mlmc_expv_proposal_tables", "mlmc_expv_proposal_loss_grad",
+           "mlmc_expv_proposal_train", "mlmc_status_string", "mlmc_last_error")
+
+MLMC_PROPOSAL_PARAMS = 5703
 
 
 class CSR(ctypes.Structure):
@@ -118,6 +122,26 @@ class BatchInfo(ctypes.Structure):
                 ("tune_ms", ctypes.c_double * 9)]
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("init_params", ctypes.POINTER(ctypes.c_float)),
+                ("pilot_walks", ctypes.c_int64), ("capture_walks", ctypes.c_int32),
+                ("sample_stride", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("num_levels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("transitions", ctypes.c_int64), ("steps", ctypes.c_int32),
+                ("n_losses", ctypes.c_int32), ("train_ms", ctypes.c_double),
+                ("first_loss", ctypes.c_double), ("last_loss", ctypes.c_double),
+                ("losses", ctypes.c_double * 64)]
+
+    def to_dict(self) -> dict:
+        return {"transitions": self.transitions, "steps": self.steps,
+                "train_ms": self.train_ms, "first_loss": self.first_loss,
+                "last_loss": self.last_loss, "losses": list(self.losses[:self.n_losses])}
+
+
 _lib = None
 
 
@@ -158,6 +182,20 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_batch_info.restype = ctypes.c_int
     L.mlmc_expv_batch_destroy.argtypes = [vp]
     L.mlmc_expv_batch_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.mlmc_expv_proposal_set.argtypes = [vp, fp, vp, i32, vp]
+    L.mlmc_expv_proposal_set.restype = ctypes.c_int
+    L.mlmc_expv_proposal_enable.argtypes = [vp, i32]
+    L.mlmc_expv_proposal_enable.restype = ctypes.c_int
+    L.mlmc_expv_proposal_tables.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.mlmc_expv_proposal_tables.restype = ctypes.c_int
+    L.mlmc_expv_proposal_loss_grad.argtypes = [vp, fp, vp, i32, i32, ctypes.POINTER(i64),
+                                               ctypes.POINTER(i32), fp, fp,
+                                               ctypes.POINTER(f64), vp]
+    L.mlmc_expv_proposal_loss_grad.restype = ctypes.c_int
+    L.mlmc_expv_proposal_train.argtypes = [vp, vp, i32, ctypes.POINTER(TrainOpts), fp,
+                                           ctypes.POINTER(TrainStats), vp]
+    L.mlmc_expv_proposal_train.restype = ctypes.c_int
     L.mlmc_status_string.argtypes = [ctypes.c_int]
     L.mlmc_status_string.restype = ctypes.c_char_p
     L.mlmc_last_error.argtypes = []

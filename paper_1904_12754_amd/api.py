@@ -140,6 +140,92 @@ class Plan:
                                         _stream_ptr(stream)))
         return out
 
+    # ---- learned proposal (importance sampling of the jump law) -----------------------
+    @staticmethod
+    def _params(params):
+        if params is None:
+            return None, None
+        P = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if P.size != _abi.MLMC_PROPOSAL_PARAMS:
+            raise ValueError(f"params must hold {_abi.MLMC_PROPOSAL_PARAMS} floats")
+        return P, P.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def _xhat(self, xhat):
+        if xhat is None:
+            return None, None
+        x = torch.as_tensor(xhat, dtype=torch.float64, device="cuda").reshape(-1).contiguous()
+        if x.numel() != self.n:
+            raise ValueError("xhat must have n entries")
+        return x, _dev_ptr(x)
+
+    def set_proposal(self, params=None, xhat=None, num_levels: int = 1, stream=None):
+        """Proposal tables for levels l0 .. l0 + num_levels - 1 from the flat parameters
+        (W1, b1, W2, b2, W3, b3; None = identity proposal) and a pilot estimate xhat."""
+        P, pp = self._params(params)
+        x, xp = self._xhat(xhat)
+        check(self._lib.mlmc_expv_proposal_set(self._handle, pp, xp, int(num_levels),
+                                               _stream_ptr(stream)))
+        (stream if stream is not None else torch.cuda.current_stream()).synchronize()
+        del P, x
+
+    def enable_proposal(self, on: bool = True):
+        check(self._lib.mlmc_expv_proposal_enable(self._handle, 1 if on else 0))
+
+    def proposal_tables(self, level: int, stream=None):
+        """(thr uint32, alias slot int32, ratio p/q float32, q float32) per slot, on host."""
+        ns = max(int(self.info["n_slots"]), 1)
+        dev = torch.device("cuda")
+        thr = torch.empty(ns, dtype=torch.int32, device=dev)
+        al = torch.empty(ns, dtype=torch.int32, device=dev)
+        ratio = torch.empty(ns, dtype=torch.float32, device=dev)
+        q = torch.empty(ns, dtype=torch.float32, device=dev)
+        check(self._lib.mlmc_expv_proposal_tables(self._handle, int(level), _dev_ptr(thr),
+                                                  _dev_ptr(al), _dev_ptr(ratio), _dev_ptr(q),
+                                                  _stream_ptr(stream)))
+        k = int(self.info["n_slots"])
+        return (thr.cpu().numpy().view(np.uint32)[:k], al.cpu().numpy()[:k],
+                ratio.cpu().numpy()[:k], q.cpu().numpy()[:k])
+
+    def proposal_loss_grad(self, params, xhat, level: int, rows, slots, weights, stream=None):
+        """(flat FP32 gradient, loss) of the cross-entropy training loss on given transitions."""
+        P, pp = self._params(params)
+        x, xp = self._xhat(xhat)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        slots = np.ascontiguousarray(slots, dtype=np.int32)
+        weights = np.ascontiguousarray(weights, dtype=np.float32)
+        g = np.zeros(_abi.MLMC_PROPOSAL_PARAMS, np.float32)
+        loss = ctypes.c_double()
+        check(self._lib.mlmc_expv_proposal_loss_grad(
+            self._handle, pp, xp, int(level), int(rows.size),
+            rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+            slots.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss),
+            _stream_ptr(stream)))
+        del P, x
+        return g, float(loss.value)
+
+    def train_proposal(self, u: torch.Tensor, init_params, seed: int = 0,
+                       pilot_walks: int = 256, capture_walks: int = 64, sample_stride: int = 1,
+                       steps: int = 200, batch: int = 4096, lr: float = 1e-3,
+                       num_levels: int = 1, stream=None):
+        """Train the proposal on the device and set it; returns (params, stats)."""
+        u, R, dt = _u_args(u, self.n)
+        if R != 1:
+            raise ValueError("training reads one right-hand side")
+        P, pp = self._params(init_params)
+        out = np.zeros(_abi.MLMC_PROPOSAL_PARAMS, np.float32)
+        opts = _abi.TrainOpts(int(seed), pp, int(pilot_walks), int(capture_walks),
+                              int(sample_stride), int(steps), int(batch), float(lr),
+                              int(num_levels), 0)
+        st = _abi.TrainStats()
+        check(self._lib.mlmc_expv_proposal_train(
+            self._handle, _dev_ptr(u), dt, ctypes.byref(opts),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(st),
+            _stream_ptr(stream)))
+        del P
+        return out, st.to_dict()
+
     def close(self):
         if getattr(self, "_handle", None) and self._handle.value:
             self._lib.mlmc_expv_destroy(self._handle)

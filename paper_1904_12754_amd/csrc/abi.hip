@@ -68,6 +68,12 @@ void free_plan(mlmc_plan *p)
     hipFree(p->slots);
     hipFree(p->rows_base);
     for (auto &r : p->level_rec) hipFree(r);
+    for (auto *t : p->is_slots) hipFree(t);
+    hipFree(p->p_slot);
+    hipFree(p->prop_P);
+    hipFree(p->prop_frag);
+    hipFree(p->prop_xhat);
+    hipFree(p->prop_xmax);
     hipFree(p->req_rows);
     hipFree(p->partial);
     hipFree(p->counters);
@@ -139,6 +145,8 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
     LevelArgs L;
     L.rec = p->level_rec[level];
     L.slots = p->slots;
+    L.is_slots = (p->proposal_on && level < static_cast<int>(p->is_slots.size())) ? p->is_slots[level]
+                                                                                   : nullptr;
     L.n = p->n;
     L.N = 1u << level;
     L.level = level;
@@ -318,6 +326,7 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     // ---- decomposition A = D - T and alias tables (section 2.1; jump law of section 3)
     std::vector<SlotRec> slots(static_cast<size_t>(std::max<int64_t>(n_slots, 1)));
     std::vector<RowRec> rows(static_cast<size_t>(n));
+    std::vector<float> p_slot(static_cast<size_t>(std::max<int64_t>(n_slots, 1)), 0.0f);
     std::vector<double> q;
     std::vector<uint32_t> cols, signs, thr, alias, small, large;
     double r_max = 0.0, d_min = INFINITY, d_max = -INFINITY;
@@ -340,7 +349,10 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
         q.clear();
         for (int64_t t = A->row_ptr[i]; t < A->row_ptr[i + 1]; ++t) {
             const double v = value_at(A, t);
-            if (A->col_idx[t] != i && v != 0.0) q.push_back((std::fabs(v) * static_cast<double>(deg)) / r);
+            if (A->col_idx[t] != i && v != 0.0) {
+                p_slot[sb + q.size()] = static_cast<float>(std::fabs(v) / r);
+                q.push_back((std::fabs(v) * static_cast<double>(deg)) / r);
+            }
         }
         build_alias(q, thr, alias, small, large);
         for (uint32_t k = 0; k < deg; ++k) {
@@ -382,6 +394,7 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     p->r_max = r_max;
     p->d_min = n ? d_min : 0.0;
     p->d_max = n ? d_max : 0.0;
+    p->p_slot_host.swap(p_slot);
     int rc;
     if ((rc = dev_alloc(p, &p->slots, slots.size()))) return rc;
     if ((rc = dev_alloc(p, &p->rows_base, rows.size()))) return rc;

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict_
         unsigned long long jumps, nonfinite;
         if (!kMulti) {
             SinkR1<R, U> sink{u};
-            walk_range<R, false>(L, row, 0u, wb, we, sink);
+            walk_range<R, false, false>(L, row, 0u, wb, we, sink);
             const double a = wave_sum(sink.s1.value());
             const double b = wave_sum(sink.s2.value());
             jumps = wave_sum_u(sink.jumps);
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict_
         } else {
             const int32_t nrhs = sg.nrhs;
             SinkRhs<R, U> sink{u, nrhs, (nrhs + kWave - 1) / kWave};
-            walk_range<R, false>(L, row, 0u, wb, we, sink);
+            walk_range<R, false, false>(L, row, 0u, wb, we, sink);
             jumps = wave_sum_u(sink.jumps);
             nonfinite = wave_sum_u(sink.nonfinite);
             const unsigned long long nojump = wave_sum_u(sink.nojump);
@@ -495,6 +495,7 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     for (int i = 0; i < d->count; ++i) {
         mlmc_plan *p = b->plans[i];
         if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan in the batch");
+        if (p->proposal_on) return fail(MLMC_ERR_UNSUPPORTED, "batched runs walk with the plain jump law; disable the proposal");
         if (i == 0) b->precision = p->precision;
         if (p->precision != b->precision)
             return fail(MLMC_ERR_UNSUPPORTED, "all plans of a batch must share one precision");
@@ -547,6 +548,8 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
 int mlmc_expv_batch_launch(mlmc_batch_t *b, uint64_t seed, void *stream)
 {
     if (!b) return fail(MLMC_ERR_INVALID_ARG, "null batch");
+    for (const mlmc_plan *p : b->plans)
+        if (p->proposal_on) return fail(MLMC_ERR_UNSUPPORTED, "a plan of the batch has an active proposal");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, static_cast<uint32_t>(seed),
                        static_cast<uint32_t>(seed >> 32));

@@ -36,6 +36,19 @@ struct alignas(32) RowRec {
     double d64;
 };
 
+// The same slot under a learned proposal q (importance sampling): the alias table of q,
+// and the likelihood ratios p/q of the slot's own column and of its alias, one of which
+// multiplies the path's functional when the jump takes it.
+struct alignas(32) SlotRecIS {
+    uint32_t own;
+    uint32_t alias;
+    uint32_t thr;
+    uint32_t pad;
+    float ratio_own;
+    float ratio_alias;
+    uint32_t pad2[2];
+};
+
 constexpr uint32_t kColMask = 0x7FFFFFFFu;
 constexpr uint64_t kFnvOffset = 14695981039346656037ull;
 constexpr uint64_t kFnvPrime = 1099511628211ull;

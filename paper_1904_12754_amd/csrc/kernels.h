@@ -9,6 +9,7 @@ namespace mlmc {
 struct LevelArgs {
     const RowRec *rec;       // the level's row records
     const SlotRec *slots;    // alias tables of all rows
+    const SlotRecIS *is_slots;  // the level's proposal tables (used by the proposal kernels)
     int64_t n;               // rows of A
     uint32_t N;              // steps, 2^level
     int32_t level;

@@ -11,7 +11,7 @@
 namespace mlmc {
 namespace {
 
-template <typename R, typename U, bool kHash>
+template <typename R, typename U, bool kHash, bool kIS>
 __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     const uint64_t wb = static_cast<uint64_t>(c) * chunk;
     const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
     SinkR1<R, U> sink{u};
-    walk_range<R, kHash>(L, row, walk0, wb, we, sink);
+    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink);
     const double a = wave_sum(sink.s1.value());
     const double b = wave_sum(sink.s2.value());
     const unsigned long long jumps = wave_sum_u(sink.jumps);
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     }
 }
 
-template <typename R, typename U, bool kHash>
+template <typename R, typename U, bool kHash, bool kIS>
 __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
                                                           int32_t nrhs,
                                                           const int64_t *__restrict__ rows,
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
     const uint64_t wb = static_cast<uint64_t>(c) * chunk;
     const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
     SinkRhs<R, U> sink{u, nrhs, (nrhs + kWave - 1) / kWave};
-    walk_range<R, kHash>(L, row, walk0, wb, we, sink);
+    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
     const unsigned long long nojump = wave_sum_u(sink.nojump);
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
@@ -218,7 +218,7 @@ __global__ void combine_kernel(CombineArgs a, int64_t count, double *x)
     x[i] = v;
 }
 
-template <typename R>
+template <typename R, bool kIS>
 __global__ void trace_kernel(LevelArgs L, int64_t count, const int64_t *__restrict__ rows,
                              const uint32_t *__restrict__ walks, int64_t *final_state,
                              int32_t *sign, int64_t *jumps, uint64_t *hash, double *log_fine,
@@ -236,14 +236,15 @@ __global__ void trace_kernel(LevelArgs L, int64_t count, const int64_t *__restri
         log_coarse[i] = 0.0;
         return;
     }
-    const WalkOut<R> o = run_walk<R, true>(L, static_cast<uint32_t>(row), walks[i]);
+    const WalkOut<R> o = run_walk<R, true, kIS>(L, static_cast<uint32_t>(row), walks[i]);
     const R hd = static_cast<R>(L.half_dt);
+    const double lw = kIS ? log(static_cast<double>(o.wr)) : 0.0;
     final_state[i] = o.k;
     sign[i] = o.neg ? -1 : 1;
     jumps[i] = o.jumps;
     hash[i] = o.hash;
-    log_fine[i] = static_cast<double>(o.ef2 * hd);
-    log_coarse[i] = static_cast<double>(o.ec2 * hd);
+    log_fine[i] = static_cast<double>(o.ef2 * hd) + lw;
+    log_coarse[i] = static_cast<double>(o.ec2 * hd) + lw;
 }
 
 uint32_t blocks_for(int64_t n, int threads)
@@ -271,21 +272,26 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
     const dim3 grid(static_cast<uint32_t>((items + kWavesPerBlock - 1) / kWavesPerBlock));
     const dim3 block(kBlock);
     const uint32_t nr = static_cast<uint32_t>(n_rows);
-#define MLMC_LAUNCH_WALKS(R, U, H)                                                            \
+#define MLMC_LAUNCH_WALKS(R, U, H, IS)                                                        \
     do {                                                                                      \
         if (nrhs == 1)                                                                        \
-            hipLaunchKernelGGL((level_walks_r1<R, U, H>), grid, block, 0, s, L,               \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS>), grid, block, 0, s, L,           \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
                                partial, counters, hash_sums);                                 \
         else                                                                                  \
-            hipLaunchKernelGGL((level_walks_rhs<R, U, H>), grid, block, 0, s, L,              \
+            hipLaunchKernelGGL((level_walks_rhs<R, U, H, IS>), grid, block, 0, s, L,          \
                                static_cast<const U *>(u), nrhs, rows, nr, walk0, M, chunk,    \
                                chunks, partial, counters, hash_sums);                         \
     } while (0)
 #define MLMC_LAUNCH_WALKS_H(R, U)                                                             \
     do {                                                                                      \
-        if (hash_sums) MLMC_LAUNCH_WALKS(R, U, true);                                         \
-        else MLMC_LAUNCH_WALKS(R, U, false);                                                  \
+        if (L.is_slots) {                                                                     \
+            if (hash_sums) MLMC_LAUNCH_WALKS(R, U, true, true);                               \
+            else MLMC_LAUNCH_WALKS(R, U, false, true);                                        \
+        } else {                                                                              \
+            if (hash_sums) MLMC_LAUNCH_WALKS(R, U, true, false);                              \
+            else MLMC_LAUNCH_WALKS(R, U, false, false);                                       \
+        }                                                                                     \
     } while (0)
     if (prec == Prec::FP64) {
         if (u_f64) MLMC_LAUNCH_WALKS_H(double, double);
@@ -335,12 +341,15 @@ hipError_t launch_trace(const LevelArgs &L, Prec prec, int64_t count, const int6
 {
     if (count == 0) return hipSuccess;
     const dim3 grid(blocks_for(count, 256));
-    if (prec == Prec::FP64)
-        hipLaunchKernelGGL(trace_kernel<double>, grid, dim3(256), 0, s, L, count, rows, walks,
-                           final_state, sign, jumps, hash, log_fine, log_coarse);
-    else
-        hipLaunchKernelGGL(trace_kernel<float>, grid, dim3(256), 0, s, L, count, rows, walks,
-                           final_state, sign, jumps, hash, log_fine, log_coarse);
+#define MLMC_LAUNCH_TRACE(R, IS)                                                              \
+    hipLaunchKernelGGL((trace_kernel<R, IS>), grid, dim3(256), 0, s, L, count, rows, walks,   \
+                       final_state, sign, jumps, hash, log_fine, log_coarse)
+    if (prec == Prec::FP64) {
+        if (L.is_slots) MLMC_LAUNCH_TRACE(double, true); else MLMC_LAUNCH_TRACE(double, false);
+    } else {
+        if (L.is_slots) MLMC_LAUNCH_TRACE(float, true); else MLMC_LAUNCH_TRACE(float, false);
+    }
+#undef MLMC_LAUNCH_TRACE
     return hipGetLastError();
 }
 

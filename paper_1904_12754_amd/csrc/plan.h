@@ -23,6 +23,7 @@ int fail(int code, const std::string &msg);
 struct mlmc_plan {
     using RowRec = mlmc::RowRec;
     using SlotRec = mlmc::SlotRec;
+    using SlotRecIS = mlmc::SlotRecIS;
     static constexpr int kMaxLevel = mlmc::kMaxLevel;
     int64_t n = 0, n_rows = 0, n_slots = 0;
     int32_t l0 = 0, precision = 0;
@@ -44,6 +45,18 @@ struct mlmc_plan {
     bool timing = false;
     std::vector<hipEvent_t> tev;
     size_t tev_used = 0;
+    // learned proposal: per-level importance-sampling slot tables (empty until set) and
+    // whether walks use them
+    std::vector<SlotRecIS *> is_slots;
+    bool proposal_on = false;
+    std::vector<float> p_slot_host;          // plain jump law per slot, |a_kj| / r_k
+    float *p_slot = nullptr;                 // device copy, uploaded with the first proposal
+    float *prop_P = nullptr;                 // proposal parameters (FP32)
+    short *prop_frag = nullptr;              // their BF16 MFMA fragments
+    double *prop_xhat = nullptr;             // pilot estimate the features read
+    double *prop_xmax = nullptr;             // max |xhat| (1 when zero)
+    int32_t prop_levels = 0;                 // levels l0 .. l0 + prop_levels - 1 carry tables
+    int32_t prop_identity = 0;               // 1: the tables are the plain ones (ratio 1)
     int64_t bytes = 0;
 };
 

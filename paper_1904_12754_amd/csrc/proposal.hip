@@ -1,0 +1,918 @@
+// Learned proposal for the jump law (importance sampling).
+//
+// The walks jump from row k with the law p_s = |a_ks| / r_k over the row's off-diagonal
+// slots (section 3). Drawing the jump from another law q with the same support and
+// multiplying the path's functional by p/q of the slot taken keeps every level's
+// expectation, so the estimator stays unbiased. q comes from a small MLP of row features:
+//
+//   features (16): p_s and |xhat(col_s)| / max|xhat| for six slots, r_k dt, d_k dt,
+//                  |xhat_k| / max|xhat|, (l - l0) / 8      (xhat: a pilot estimate of x)
+//   16 -> 64 (ReLU) -> 64 (ReLU) -> 7;  q_s = alpha softmax_s(z) + (1 - alpha) p_s over the
+//   valid slots, z = outputs 0..5, alpha = 0.9 sigmoid(output 6)
+//
+// Rows with more than six slots keep q = p. Inference runs on the matrix cores: every wave
+// evaluates 16 rows with v_mfma_f32_16x16x16_bf16 in the transposed form H^T = W^T X^T, so
+// the output fragment of one layer is the input fragment of the next, and the lanes that
+// hold a row's outputs build its alias table and likelihood ratios. Training (the
+// cross-entropy method: minimise the |Y|-weighted negative log-likelihood of the jumps the
+// plain walks took, whose minimiser over all laws is q ~ |Y| p) runs in FP32 with plain
+// per-thread kernels; the parameters are updated by Adam.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlmc_expv.h"
+#include "common.h"
+#include "kernels.h"
+#include "plan.h"
+#include "walk_engine.h"
+
+namespace mlmc {
+namespace {
+
+constexpr int NF = 16, NH = 64, NO = 7, NS = 6;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NO, NPARAM = OFF_B3 + NO;
+constexpr float kAlphaMax = 0.9f;
+constexpr int kCaptureJumps = 8;   // transitions recorded per captured walk
+
+static_assert(NPARAM == MLMC_PROPOSAL_PARAMS, "parameter layout");
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x)
+{
+    // round to nearest even (finite inputs)
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return static_cast<short>(b >> 16);
+}
+
+struct FeatureArgs {
+    const RowRec *rec;        // the level's row records (d, 1/r, slot range)
+    const SlotRec *slots;     // plain slots (own column)
+    const float *p_slot;      // plain law per slot
+    const double *xhat;       // pilot estimate (nullable: zeros)
+    const double *xmax;       // device scalar: max |xhat| (1 when xhat is null or zero)
+    int64_t n;
+    float dt, lvl;            // dt of the level, (l - l0) / 8
+};
+
+// Feature f (0..15) of row `row`; eligible rows only for the slot features.
+__device__ __forceinline__ float feature(const FeatureArgs &a, const RowRec &rr, uint32_t row,
+                                         int f, float inv_xmax)
+{
+    const bool elig = rr.deg >= 1 && rr.deg <= NS;
+    if (f < NS) return (elig && f < static_cast<int>(rr.deg)) ? a.p_slot[rr.slot_begin + f] : 0.0f;
+    if (f < 2 * NS) {
+        const int s = f - NS;
+        if (!elig || s >= static_cast<int>(rr.deg) || !a.xhat) return 0.0f;
+        const uint32_t c = a.slots[rr.slot_begin + s].own & kColMask;
+        return static_cast<float>(fabs(a.xhat[c])) * inv_xmax;
+    }
+    if (f == 12) return (rr.inv_r < INFINITY) ? static_cast<float>(1.0 / rr.inv_r) * a.dt : 0.0f;
+    if (f == 13) return rr.d32 * a.dt;
+    if (f == 14) return a.xhat ? static_cast<float>(fabs(a.xhat[row])) * inv_xmax : 0.0f;
+    return a.lvl;
+}
+
+__global__ void features_kernel(FeatureArgs a, float *F)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const RowRec rr = a.rec[i];
+    const float inv_xmax = static_cast<float>(1.0 / *a.xmax);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) F[i * NF + f] = feature(a, rr, static_cast<uint32_t>(i), f, inv_xmax);
+}
+
+__global__ void absmax_kernel(const double *x, int64_t n, double *out)
+{
+    __shared__ double sh[256];
+    double m = 0.0;
+    if (x)
+        for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(x[i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0] > 0.0 ? sh[0] : 1.0;
+}
+
+// ------------------------------------------------------------------------------------
+// Weight fragments for v_mfma_f32_16x16x16_bf16 in the transposed form. For the A operand
+// of a 16x16x16 MFMA lane l holds A[l % 16][4 (l / 16) + i], i = 0..3; A = W^T, so lane l
+// of the fragment (layer, out tile c, k step kk) holds W[16 kk + 4 (l / 16) + i][16 c + l % 16].
+// ------------------------------------------------------------------------------------
+constexpr int FR1 = 0;                      // [c 0..3][lane][4]
+constexpr int FR2 = FR1 + 4 * 64 * 4;       // [c 0..3][kk 0..3][lane][4]
+constexpr int FR3 = FR2 + 16 * 64 * 4;      // [kk 0..3][lane][4]
+constexpr int NFRAG = FR3 + 4 * 64 * 4;
+
+__global__ void fragments_kernel(const float *P, short *frag)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= NFRAG) return;
+    int idx, lane, i, c = 0, kk = 0, layer;
+    if (t < FR2) { layer = 1; idx = t - FR1; c = idx / 256; }
+    else if (t < FR3) { layer = 2; idx = t - FR2; c = idx / 1024; kk = (idx / 256) % 4; }
+    else { layer = 3; idx = t - FR3; kk = idx / 256; }
+    lane = (idx / 4) % 64;
+    i = idx % 4;
+    const int krow = 16 * kk + 4 * (lane / 16) + i;   // input feature
+    const int ocol = 16 * c + lane % 16;              // output feature
+    float w = 0.0f;
+    if (layer == 1) w = P[OFF_W1 + krow * NH + ocol];
+    else if (layer == 2) w = P[OFF_W2 + krow * NH + ocol];
+    else w = (lane % 16) < NO ? P[OFF_W3 + krow * NO + (lane % 16)] : 0.0f;
+    frag[t] = bf16_bits(w);
+}
+
+struct TableArgs {
+    FeatureArgs fa;
+    const short *frag;
+    const float *P;           // FP32 parameters (biases)
+    SlotRecIS *out;           // the level's proposal slot table
+    // optional per-slot export for inspection: threshold, alias slot, ratio p/q, q
+    uint32_t *x_thr;
+    int32_t *x_alias;
+    float *x_ratio;
+    float *x_q;
+    int identity;             // 1: q = p (copy of the plain tables, ratio 1)
+};
+
+__device__ __forceinline__ float4_t mfma16(short4_t a, short4_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ short4_t pack4(float4_t v)
+{
+    short4_t r;
+    r.x = bf16_bits(v.x);
+    r.y = bf16_bits(v.y);
+    r.z = bf16_bits(v.z);
+    r.w = bf16_bits(v.w);
+    return r;
+}
+
+// Alias table of row `row` for the law q (FP64 scaled probabilities, the construction of
+// the plain plan) with likelihood ratios p/q; copies the plain row when identity.
+__device__ void build_row(const TableArgs &a, const RowRec &rr, const float *q)
+{
+    const uint32_t k = rr.deg, sb = rr.slot_begin;
+    if (k == 0) return;
+    const bool use_q = !a.identity && k <= NS;
+    if (!use_q) {
+        for (uint32_t s = 0; s < k; ++s) {
+            const SlotRec pr = a.fa.slots[sb + s];
+            SlotRecIS o;
+            o.own = pr.own;
+            o.alias = pr.alias;
+            o.thr = pr.thr;
+            o.pad = 0;
+            o.ratio_own = 1.0f;
+            o.ratio_alias = 1.0f;
+            o.pad2[0] = o.pad2[1] = 0;
+            a.out[sb + s] = o;
+            if (a.x_thr) {
+                a.x_thr[sb + s] = pr.thr;
+                // alias slot: the slot of the row whose column is the alias column
+                int32_t al = static_cast<int32_t>(s);
+                for (uint32_t t = 0; t < k; ++t)
+                    if ((a.fa.slots[sb + t].own & kColMask) == (pr.alias & kColMask)) al = static_cast<int32_t>(t);
+                a.x_alias[sb + s] = al;
+                a.x_ratio[sb + s] = 1.0f;
+                a.x_q[sb + s] = a.fa.p_slot[sb + s];
+            }
+        }
+        return;
+    }
+    double qs[NS];
+    uint32_t thr[NS];
+    uint32_t alias[NS];
+    int small[NS], large[NS];
+    int ns = 0, nl = 0;
+    for (uint32_t s = 0; s < k; ++s) {
+        qs[s] = static_cast<double>(q[s]) * static_cast<double>(k);
+        thr[s] = 0xFFFFFFFFu;
+        alias[s] = s;
+        if (qs[s] < 1.0) small[ns++] = static_cast<int>(s); else large[nl++] = static_cast<int>(s);
+    }
+    while (ns > 0 && nl > 0) {
+        const int lo = small[--ns];
+        const int hi = large[--nl];
+        thr[lo] = static_cast<uint32_t>(floor(qs[lo] * 4294967296.0));
+        alias[lo] = static_cast<uint32_t>(hi);
+        qs[hi] = (qs[hi] + qs[lo]) - 1.0;
+        if (qs[hi] < 1.0) small[ns++] = hi; else large[nl++] = hi;
+    }
+    for (uint32_t s = 0; s < k; ++s) {
+        const float ratio_s = a.fa.p_slot[sb + s] / q[s];
+        const float ratio_a = a.fa.p_slot[sb + alias[s]] / q[alias[s]];
+        SlotRecIS o;
+        o.own = a.fa.slots[sb + s].own;
+        o.alias = a.fa.slots[sb + alias[s]].own;
+        o.thr = thr[s];
+        o.pad = 0;
+        o.ratio_own = ratio_s;
+        o.ratio_alias = ratio_a;
+        o.pad2[0] = o.pad2[1] = 0;
+        a.out[sb + s] = o;
+        if (a.x_thr) {
+            a.x_thr[sb + s] = thr[s];
+            a.x_alias[sb + s] = static_cast<int32_t>(alias[s]);
+            a.x_ratio[sb + s] = ratio_s;
+            a.x_q[sb + s] = q[s];
+        }
+    }
+}
+
+// One wave per 16 rows: features -> MFMA MLP -> q -> alias tables and ratios.
+__global__ __launch_bounds__(256) void tables_kernel(TableArgs a)
+{
+    const int lane = static_cast<int>(threadIdx.x & 63);
+    const int r = lane % 16, g = lane / 16;
+    const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
+    const int64_t row64 = tile * 16 + r;
+    const bool inrow = row64 < a.fa.n;
+    const uint32_t row = inrow ? static_cast<uint32_t>(row64) : 0u;
+    const RowRec rr = a.fa.rec[row];
+    if (a.identity) {           // uniform over the launch
+        if (g == 0 && inrow) build_row(a, rr, nullptr);
+        return;
+    }
+    const float inv_xmax = static_cast<float>(1.0 / *a.fa.xmax);
+    float4_t xf;
+    xf.x = inrow ? feature(a.fa, rr, row, 4 * g + 0, inv_xmax) : 0.0f;
+    xf.y = inrow ? feature(a.fa, rr, row, 4 * g + 1, inv_xmax) : 0.0f;
+    xf.z = inrow ? feature(a.fa, rr, row, 4 * g + 2, inv_xmax) : 0.0f;
+    xf.w = inrow ? feature(a.fa, rr, row, 4 * g + 3, inv_xmax) : 0.0f;
+    const short4_t x = pack4(xf);
+    const short4_t *fr = reinterpret_cast<const short4_t *>(a.frag);
+    // layer 1: H1^T (64 x 16) in four 16-row tiles
+    short4_t h1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        acc = mfma16(fr[(FR1 / 4) + c * 64 + lane], x, acc);
+        float4_t v;
+        v.x = fmaxf(acc.x + a.P[OFF_B1 + 16 * c + 4 * g + 0], 0.0f);
+        v.y = fmaxf(acc.y + a.P[OFF_B1 + 16 * c + 4 * g + 1], 0.0f);
+        v.z = fmaxf(acc.z + a.P[OFF_B1 + 16 * c + 4 * g + 2], 0.0f);
+        v.w = fmaxf(acc.w + a.P[OFF_B1 + 16 * c + 4 * g + 3], 0.0f);
+        h1[c] = pack4(v);
+    }
+    // layer 2
+    short4_t h2[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = mfma16(fr[(FR2 / 4) + (c * 4 + kk) * 64 + lane], h1[kk], acc);
+        float4_t v;
+        v.x = fmaxf(acc.x + a.P[OFF_B2 + 16 * c + 4 * g + 0], 0.0f);
+        v.y = fmaxf(acc.y + a.P[OFF_B2 + 16 * c + 4 * g + 1], 0.0f);
+        v.z = fmaxf(acc.z + a.P[OFF_B2 + 16 * c + 4 * g + 2], 0.0f);
+        v.w = fmaxf(acc.w + a.P[OFF_B2 + 16 * c + 4 * g + 3], 0.0f);
+        h2[c] = pack4(v);
+    }
+    // layer 3: outputs 4g + i of row r in this lane (valid for 4g + i < 7)
+    float4_t o = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) o = mfma16(fr[(FR3 / 4) + kk * 64 + lane], h2[kk], o);
+    float ov[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ov[i] += (4 * g + i < NO) ? a.P[OFF_B3 + 4 * g + i] : 0.0f;
+    // gather outputs 4..6 of row r from lane r + 16
+    const float o4 = __shfl(ov[0], r + 16, 64);
+    const float o5 = __shfl(ov[1], r + 16, 64);
+    const float o6 = __shfl(ov[2], r + 16, 64);
+    if (g != 0 || !inrow) return;
+    const float out[NO] = {ov[0], ov[1], ov[2], ov[3], o4, o5, o6};
+    float q[NS] = {0, 0, 0, 0, 0, 0};
+    const uint32_t k = rr.deg;
+    if (k >= 1 && k <= NS) {
+        float zmax = -INFINITY;
+        for (uint32_t s = 0; s < k; ++s) zmax = fmaxf(zmax, out[s]);
+        float den = 0.0f, e[NS];
+        for (uint32_t s = 0; s < k; ++s) {
+            e[s] = expf(out[s] - zmax);
+            den += e[s];
+        }
+        const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
+        for (uint32_t s = 0; s < k; ++s)
+            q[s] = alpha * (e[s] / den) + (1.0f - alpha) * a.fa.p_slot[rr.slot_begin + s];
+    }
+    build_row(a, rr, q);
+}
+
+// ------------------------------------------------------------------------------------
+// Transition capture: plain walks at one level record, for each of their first jumps out
+// of an eligible row, the row and the slot taken, and the walk's |Y| as the weight.
+// ------------------------------------------------------------------------------------
+// Records the first kCaptureJumps jumps out of eligible rows: the row and the slot taken.
+struct CaptureObs {
+    const SlotRec *slots;
+    uint32_t count = 0;
+    uint32_t rows[kCaptureJumps];
+    int32_t taken[kCaptureJumps];
+    __device__ __forceinline__ void jump(uint32_t from, const RowRec &rr, uint32_t cs)
+    {
+        if (count >= kCaptureJumps || rr.deg > NS) return;
+        int32_t t = -1;
+        for (uint32_t s = 0; s < rr.deg; ++s)
+            if (((slots[rr.slot_begin + s].own ^ cs) & kColMask) == 0) t = static_cast<int32_t>(s);
+        rows[count] = from;
+        taken[count] = t;
+        ++count;
+    }
+};
+
+__global__ void capture_kernel(LevelArgs L, const float *__restrict__ u, uint32_t stride_rows,
+                               uint32_t n_sample, uint32_t walks, uint32_t *t_row, int32_t *t_slot,
+                               float *t_w)
+{
+    const uint64_t id = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (id >= static_cast<uint64_t>(n_sample) * walks) return;
+    const uint64_t row64 = (id / walks) * stride_rows;
+    const uint32_t walk = static_cast<uint32_t>(id % walks);
+    CaptureObs obs;
+    obs.slots = L.slots;
+    float wy = 0.0f;
+    if (row64 < static_cast<uint64_t>(L.n)) {
+        const WalkOut<float> o = run_walk<float, false, false, CaptureObs>(L, static_cast<uint32_t>(row64), walk, &obs);
+        wy = fabsf(weight_of<float>(o, L.base, static_cast<float>(L.half_dt)) * u[o.k]);
+    }
+    for (uint32_t j = 0; j < kCaptureJumps; ++j) {
+        const uint64_t o = id * kCaptureJumps + j;
+        const bool has = j < obs.count;
+        t_row[o] = has ? obs.rows[j] : 0u;
+        t_slot[o] = has ? obs.taken[j] : -1;
+        t_w[o] = has ? wy : 0.0f;
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// Training: FP32 forward / backward on a batch of B transitions (fixed summation order).
+// ------------------------------------------------------------------------------------
+struct TrainBuf {
+    float *X, *p6, *H1, *H2, *dO, *dH2, *dH1, *G, *lossb, *wsum;
+    int32_t *slot;
+    uint8_t *valid;
+};
+
+// Gather the batch: features, plain law and valid mask of the transition's row.
+__global__ void gather_kernel(const float *__restrict__ F, FeatureArgs fa, const uint32_t *t_row,
+                              const int32_t *t_slot, const float *t_w, uint64_t T, uint64_t begin,
+                              uint64_t mult, int B, TrainBuf tb, float *w_batch)
+{
+    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= B) return;
+    const uint64_t src = ((begin + static_cast<uint64_t>(b)) * mult) % T;
+    const uint32_t row = t_row[src];
+    const RowRec rr = fa.rec[row];
+    for (int f = 0; f < NF; ++f) tb.X[b * NF + f] = F[static_cast<uint64_t>(row) * NF + f];
+    for (int s = 0; s < NS; ++s) {
+        const bool ok = s < static_cast<int>(rr.deg) && rr.deg <= NS;
+        tb.p6[b * NS + s] = ok ? fa.p_slot[rr.slot_begin + s] : 0.0f;
+        tb.valid[b * NS + s] = ok ? 1 : 0;
+    }
+    tb.slot[b] = t_slot[src];
+    w_batch[b] = t_w[src];
+}
+
+__global__ void batch_from_arrays_kernel(const float *__restrict__ F, FeatureArgs fa,
+                                         const int64_t *rows, const int32_t *slots, const float *w,
+                                         int B, TrainBuf tb, float *w_batch)
+{
+    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= B) return;
+    const uint32_t row = static_cast<uint32_t>(rows[b]);
+    const RowRec rr = fa.rec[row];
+    for (int f = 0; f < NF; ++f) tb.X[b * NF + f] = F[static_cast<uint64_t>(row) * NF + f];
+    for (int s = 0; s < NS; ++s) {
+        const bool ok = s < static_cast<int>(rr.deg) && rr.deg <= NS;
+        tb.p6[b * NS + s] = ok ? fa.p_slot[rr.slot_begin + s] : 0.0f;
+        tb.valid[b * NS + s] = ok ? 1 : 0;
+    }
+    tb.slot[b] = slots[b];
+    w_batch[b] = w[b];
+}
+
+// out[b][j] = relu(sum_i in[b][i] W[i][j] + bias[j])
+__global__ void dense_relu_kernel(const float *in, int nin, const float *W, const float *bias,
+                                  int nout, int B, float *out)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= B * nout) return;
+    const int b = t / nout, j = t % nout;
+    float acc = bias[j];
+    for (int i = 0; i < nin; ++i) acc += in[b * nin + i] * W[i * nout + j];
+    out[t] = fmaxf(acc, 0.0f);
+}
+
+__global__ void wsum_kernel(const float *w, int B, float *out)
+{
+    __shared__ float sh[256];
+    float s = 0.0f;
+    for (int b = threadIdx.x; b < B; b += 256) s += w[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// Output layer, loss and its gradient with respect to the 7 outputs, per transition.
+__global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w_batch)
+{
+    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= B) return;
+    float o[NO];
+    for (int j = 0; j < NO; ++j) {
+        float acc = P[OFF_B3 + j];
+        for (int i = 0; i < NH; ++i) acc += tb.H2[b * NH + i] * P[OFF_W3 + i * NO + j];
+        o[j] = acc;
+    }
+    const int s = tb.slot[b];
+    const float W = *tb.wsum;
+    float dO[NO] = {0, 0, 0, 0, 0, 0, 0};
+    float lb = 0.0f;
+    if (s >= 0 && W > 0.0f && tb.valid[b * NS + s]) {
+        float zmax = -INFINITY;
+        for (int t = 0; t < NS; ++t)
+            if (tb.valid[b * NS + t]) zmax = fmaxf(zmax, o[t]);
+        float e[NS], den = 0.0f;
+        for (int t = 0; t < NS; ++t) {
+            e[t] = tb.valid[b * NS + t] ? expf(o[t] - zmax) : 0.0f;
+            den += e[t];
+        }
+        float soft[NS];
+        for (int t = 0; t < NS; ++t) soft[t] = e[t] / den;
+        const float sg = 1.0f / (1.0f + expf(-o[NS]));
+        const float alpha = kAlphaMax * sg;
+        const float ps = tb.p6[b * NS + s];
+        const float qs = alpha * soft[s] + (1.0f - alpha) * ps;
+        const float wb = w_batch[b];
+        lb = -wb * logf(qs) / W;
+        const float coef = -(wb / W) / qs;
+        for (int t = 0; t < NS; ++t)
+            dO[t] = tb.valid[b * NS + t] ? coef * alpha * soft[s] * ((t == s ? 1.0f : 0.0f) - soft[t]) : 0.0f;
+        dO[NS] = coef * (soft[s] - ps) * kAlphaMax * sg * (1.0f - sg);
+    }
+    for (int j = 0; j < NO; ++j) tb.dO[b * NO + j] = dO[j];
+    tb.lossb[b] = lb;
+}
+
+// dIn[b][i] = (sum_j dOut[b][j] W[i][j]) * [act[b][i] > 0]
+__global__ void back_act_kernel(const float *dOut, int nout, const float *W, const float *act, int nin,
+                                int B, float *dIn)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= B * nin) return;
+    const int b = t / nin, i = t % nin;
+    float acc = 0.0f;
+    for (int j = 0; j < nout; ++j) acc += dOut[b * nout + j] * W[i * nout + j];
+    dIn[t] = act[t] > 0.0f ? acc : 0.0f;
+}
+
+// dW[i][j] = sum_b in[b][i] d[b][j] (into G + offW), db[j] = sum_b d[b][j] (into G + offb)
+__global__ void weight_grad_kernel(const float *in, int nin, const float *d, int nout, int B, float *G,
+                                   int offW, int offb)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t < nin * nout) {
+        const int i = t / nout, j = t % nout;
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += in[b * nin + i] * d[b * nout + j];
+        G[offW + t] = acc;
+    } else if (t < nin * nout + nout) {
+        const int j = t - nin * nout;
+        float acc = 0.0f;
+        for (int b = 0; b < B; ++b) acc += d[b * nout + j];
+        G[offb + j] = acc;
+    }
+}
+
+__global__ void adam_kernel(float *P, const float *G, float *m, float *v, float lr, float b1, float b2,
+                            float eps, float c1, float c2)
+{
+    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= NPARAM) return;
+    const float g = G[t];
+    m[t] = b1 * m[t] + (1.0f - b1) * g;
+    v[t] = b2 * v[t] + (1.0f - b2) * g * g;
+    P[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
+}
+
+uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
+
+// One forward/backward pass: G = dL/dP, lossb[b] = the terms of L.
+hipError_t train_pass(const float *P, int B, TrainBuf tb, const float *w_batch, hipStream_t s)
+{
+    hipLaunchKernelGGL(wsum_kernel, dim3(1), dim3(256), 0, s, w_batch, B, tb.wsum);
+    hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.X, NF, P + OFF_W1,
+                       P + OFF_B1, NH, B, tb.H1);
+    hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.H1, NH, P + OFF_W2,
+                       P + OFF_B2, NH, B, tb.H2);
+    hipLaunchKernelGGL(output_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, P, B, tb, w_batch);
+    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NH * NO + NO, 256)), dim3(256), 0, s, tb.H2, NH, tb.dO,
+                       NO, B, tb.G, OFF_W3, OFF_B3);
+    hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dO, NO, P + OFF_W3,
+                       tb.H2, NH, B, tb.dH2);
+    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NH * NH + NH, 256)), dim3(256), 0, s, tb.H1, NH,
+                       tb.dH2, NH, B, tb.G, OFF_W2, OFF_B2);
+    hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dH2, NH, P + OFF_W2,
+                       tb.H1, NH, B, tb.dH1);
+    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NF * NH + NH, 256)), dim3(256), 0, s, tb.X, NF,
+                       tb.dH1, NH, B, tb.G, OFF_W1, OFF_B1);
+    return hipGetLastError();
+}
+
+// Scratch of a training session.
+struct Session {
+    std::vector<void *> ptrs;
+    ~Session()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    int alloc(T **p, size_t count)
+    {
+        *p = nullptr;
+        const hipError_t e = hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) {
+            *p = nullptr;
+            return fail(e == hipErrorOutOfMemory ? MLMC_ERR_OUT_OF_MEMORY : MLMC_ERR_HIP,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        ptrs.push_back(*p);
+        return MLMC_OK;
+    }
+    int train_buf(TrainBuf &tb, int B)
+    {
+        int rc;
+        if ((rc = alloc(&tb.X, static_cast<size_t>(B) * NF))) return rc;
+        if ((rc = alloc(&tb.p6, static_cast<size_t>(B) * NS))) return rc;
+        if ((rc = alloc(&tb.H1, static_cast<size_t>(B) * NH))) return rc;
+        if ((rc = alloc(&tb.H2, static_cast<size_t>(B) * NH))) return rc;
+        if ((rc = alloc(&tb.dO, static_cast<size_t>(B) * NO))) return rc;
+        if ((rc = alloc(&tb.dH2, static_cast<size_t>(B) * NH))) return rc;
+        if ((rc = alloc(&tb.dH1, static_cast<size_t>(B) * NH))) return rc;
+        if ((rc = alloc(&tb.G, NPARAM))) return rc;
+        if ((rc = alloc(&tb.lossb, static_cast<size_t>(B)))) return rc;
+        if ((rc = alloc(&tb.wsum, 1))) return rc;
+        if ((rc = alloc(&tb.slot, static_cast<size_t>(B)))) return rc;
+        if ((rc = alloc(&tb.valid, static_cast<size_t>(B) * NS))) return rc;
+        return MLMC_OK;
+    }
+};
+
+FeatureArgs feature_args(const mlmc_plan *p, int level, const double *xhat, const double *xmax)
+{
+    FeatureArgs fa;
+    fa.rec = p->level_rec[level];
+    fa.slots = p->slots;
+    fa.p_slot = p->p_slot;
+    fa.xhat = xhat;
+    fa.xmax = xmax;
+    fa.n = p->n;
+    fa.dt = static_cast<float>(std::ldexp(p->beta, -level));
+    fa.lvl = static_cast<float>(level - p->l0) / 8.0f;
+    return fa;
+}
+
+int check_level(const mlmc_plan *p, int level)
+{
+    if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
+    return MLMC_OK;
+}
+
+template <typename T>
+int plan_alloc(mlmc_plan *p, T **ptr, size_t count)
+{
+    if (*ptr) return MLMC_OK;
+    const hipError_t e = hipMalloc(reinterpret_cast<void **>(ptr), std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(e == hipErrorOutOfMemory ? MLMC_ERR_OUT_OF_MEMORY : MLMC_ERR_HIP,
+                    std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    p->bytes += static_cast<int64_t>(std::max<size_t>(count, 1) * sizeof(T));
+    return MLMC_OK;
+}
+
+// Device buffers every proposal call reads: the plain law per slot and the parameters.
+int ensure_proposal_buffers(mlmc_plan *p, hipStream_t s)
+{
+    const bool fresh = p->p_slot == nullptr;
+    int rc;
+    if ((rc = plan_alloc(p, &p->p_slot, p->p_slot_host.size())) || (rc = plan_alloc(p, &p->prop_P, NPARAM)) ||
+        (rc = plan_alloc(p, &p->prop_frag, NFRAG)) || (rc = plan_alloc(p, &p->prop_xhat, static_cast<size_t>(p->n))) ||
+        (rc = plan_alloc(p, &p->prop_xmax, 1)))
+        return rc;
+    if (fresh)
+        MLMC_HIP_TRY(hipMemcpyAsync(p->p_slot, p->p_slot_host.data(), p->p_slot_host.size() * sizeof(float),
+                                    hipMemcpyHostToDevice, s));
+    return MLMC_OK;
+}
+
+// Build (and optionally export) the proposal tables of one level.
+int build_tables(mlmc_plan *p, int level, SlotRecIS *out, uint32_t *x_thr, int32_t *x_alias, float *x_ratio,
+                 float *x_q, hipStream_t s)
+{
+    TableArgs ta;
+    ta.fa = feature_args(p, level, p->prop_xhat, p->prop_xmax);
+    ta.frag = p->prop_frag;
+    ta.P = p->prop_P;
+    ta.out = out;
+    ta.x_thr = x_thr;
+    ta.x_alias = x_alias;
+    ta.x_ratio = x_ratio;
+    ta.x_q = x_q;
+    ta.identity = p->prop_identity;
+    const uint64_t tiles = (static_cast<uint64_t>(p->n) + 15) / 16;
+    if (tiles == 0) return MLMC_OK;
+    hipLaunchKernelGGL(tables_kernel, dim3(nblk(tiles, 4)), dim3(256), 0, s, ta);
+    MLMC_HIP_TRY(hipGetLastError());
+    return MLMC_OK;
+}
+
+// Copy the parameters and the pilot estimate in, and build the tables of the levels.
+int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_levels, hipStream_t s)
+{
+    int rc;
+    if ((rc = ensure_proposal_buffers(p, s))) return rc;
+    p->prop_identity = params == nullptr;
+    if (params) {
+        MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(fragments_kernel, dim3(nblk(NFRAG, 256)), dim3(256), 0, s, p->prop_P, p->prop_frag);
+        MLMC_HIP_TRY(hipGetLastError());
+    }
+    if (p->n > 0) {
+        if (xhat) {
+            if (xhat != p->prop_xhat)
+                MLMC_HIP_TRY(hipMemcpyAsync(p->prop_xhat, xhat, p->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+            MLMC_HIP_TRY(hipMemsetAsync(p->prop_xhat, 0, p->n * sizeof(double), s));
+        }
+    }
+    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, p->prop_xhat, p->n, p->prop_xmax);
+    MLMC_HIP_TRY(hipGetLastError());
+    if (p->is_slots.size() < static_cast<size_t>(kMaxLevel + 1)) p->is_slots.resize(kMaxLevel + 1, nullptr);
+    for (int q = 0; q < num_levels; ++q) {
+        const int level = p->l0 + q;
+        if ((rc = upload_level(p, level, s))) return rc;
+        if ((rc = plan_alloc(p, &p->is_slots[level], static_cast<size_t>(p->n_slots)))) return rc;
+        if ((rc = build_tables(p, level, p->is_slots[level], nullptr, nullptr, nullptr, nullptr, s))) return rc;
+    }
+    // levels past the new range walk with the plain tables
+    for (int level = p->l0 + num_levels; level <= kMaxLevel; ++level)
+        if (p->is_slots[level]) {
+            (void)hipFree(p->is_slots[level]);
+            p->bytes -= static_cast<int64_t>(std::max<int64_t>(p->n_slots, 1) * sizeof(SlotRecIS));
+            p->is_slots[level] = nullptr;
+        }
+    p->prop_levels = num_levels;
+    p->proposal_on = true;
+    return MLMC_OK;
+}
+
+}  // namespace
+}  // namespace mlmc
+
+using namespace mlmc;
+
+extern "C" {
+
+int mlmc_expv_proposal_set(mlmc_plan_t *p, const float *params, const double *xhat, int32_t num_levels,
+                           void *stream)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    if (num_levels < 1 || p->l0 + num_levels - 1 > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "num_levels out of range");
+    return set_proposal(p, params, xhat, num_levels, static_cast<hipStream_t>(stream));
+}
+
+int mlmc_expv_proposal_enable(mlmc_plan_t *p, int32_t on)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    if (on && p->prop_levels == 0) return fail(MLMC_ERR_INVALID_ARG, "no proposal has been set");
+    p->proposal_on = on != 0;
+    return MLMC_OK;
+}
+
+int mlmc_expv_proposal_tables(mlmc_plan_t *p, int32_t level, uint32_t *thr, int32_t *alias_slot, float *ratio,
+                              float *q, void *stream)
+{
+    if (!p || !thr || !alias_slot || !ratio || !q) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (p->prop_levels == 0) return fail(MLMC_ERR_INVALID_ARG, "no proposal has been set");
+    int rc = check_level(p, level);
+    if (rc) return rc;
+    if (level >= p->l0 + p->prop_levels) return fail(MLMC_ERR_INVALID_ARG, "level has no proposal table");
+    return build_tables(p, level, p->is_slots[level], thr, alias_slot, ratio, q, static_cast<hipStream_t>(stream));
+}
+
+int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const double *xhat, int32_t level,
+                                 int32_t count, const int64_t *rows, const int32_t *slots, const float *weights,
+                                 float *grad, double *loss, void *stream)
+{
+    if (!p || !params || !rows || !slots || !weights || !grad || !loss) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (count < 1 || count > (1 << 20)) return fail(MLMC_ERR_INVALID_ARG, "count must be in [1, 2^20]");
+    int rc = check_level(p, level);
+    if (rc) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = upload_level(p, level, s)) || (rc = ensure_proposal_buffers(p, s))) return rc;
+    for (int32_t b = 0; b < count; ++b) {
+        if (rows[b] < 0 || rows[b] >= p->n) return fail(MLMC_ERR_INVALID_ARG, "transition row out of range");
+        if (slots[b] < -1 || slots[b] >= NS) return fail(MLMC_ERR_INVALID_ARG, "transition slot out of range [-1, 6)");
+        if (!(weights[b] >= 0.0f) || !std::isfinite(weights[b])) return fail(MLMC_ERR_INVALID_ARG, "weights must be finite and >= 0");
+    }
+    Session ss;
+    float *dP = nullptr, *F = nullptr, *wb = nullptr, *d_w = nullptr;
+    int64_t *d_rows = nullptr;
+    int32_t *d_slots = nullptr;
+    double *xmax = nullptr;
+    TrainBuf tb{};
+    if ((rc = ss.alloc(&dP, NPARAM)) || (rc = ss.alloc(&F, static_cast<size_t>(p->n) * NF)) ||
+        (rc = ss.alloc(&wb, count)) || (rc = ss.alloc(&xmax, 1)) || (rc = ss.train_buf(tb, count)) ||
+        (rc = ss.alloc(&d_rows, count)) || (rc = ss.alloc(&d_slots, count)) || (rc = ss.alloc(&d_w, count)))
+        return rc;
+    MLMC_HIP_TRY(hipMemcpyAsync(dP, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(d_rows, rows, count * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(d_slots, slots, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(d_w, weights, count * sizeof(float), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, xhat, p->n, xmax);
+    const FeatureArgs fa = feature_args(p, level, xhat, xmax);
+    if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
+    hipLaunchKernelGGL(batch_from_arrays_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, F, fa, d_rows, d_slots, d_w,
+                       count, tb, wb);
+    MLMC_HIP_TRY(train_pass(dP, count, tb, wb, s));
+    std::vector<float> lb(count);
+    MLMC_HIP_TRY(hipMemcpyAsync(grad, tb.G, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, count * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
+    double L = 0.0;
+    for (float v : lb) L += v;
+    *loss = L;
+    return MLMC_OK;
+}
+
+int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, const mlmc_train_opts_t *o,
+                             float *params_out, mlmc_train_stats_t *st, void *stream)
+{
+    if (!p || !u || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (u_dtype != MLMC_DTYPE_F32) return fail(MLMC_ERR_UNSUPPORTED, "training reads an FP32 right-hand side");
+    if (!o->init_params) return fail(MLMC_ERR_INVALID_ARG, "init_params is null");
+    if (o->pilot_walks < 1 || o->pilot_walks > 0xFFFFFFFFll || o->capture_walks < 1 || o->steps < 0 ||
+        o->batch < 1 || o->batch > (1 << 20) || o->num_levels < 1 || p->l0 + o->num_levels - 1 > kMaxLevel ||
+        o->sample_stride < 1 || !(o->lr > 0.0))
+        return fail(MLMC_ERR_INVALID_ARG, "training options out of range");
+    if (p->n_rows != p->n) return fail(MLMC_ERR_UNSUPPORTED, "training needs a plan over all rows");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc;
+    const int level = p->l0;
+    if ((rc = upload_level(p, level, s)) || (rc = ensure_proposal_buffers(p, s))) return rc;
+    hipEvent_t e0, e1;
+    MLMC_HIP_TRY(hipEventCreate(&e0));
+    MLMC_HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    MLMC_HIP_TRY(hipEventRecord(e0, s));
+    Session ss;
+    // 1. pilot estimate xhat: the level-l0 mean of plain walks (an independent stream family)
+    const bool was_on = p->proposal_on;
+    p->proposal_on = false;
+    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1))) return rc;
+    rc = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0x9E3779B97F4A7C15ull, 4095, level, 0,
+                              static_cast<uint32_t>(o->pilot_walks), s1, s2, nullptr, nullptr, stream);
+    p->proposal_on = was_on;
+    if (rc) return rc;
+    CombineArgs ca{};
+    ca.levels = 1;
+    ca.s1[0] = s1;
+    ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
+    MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
+    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, p->prop_xhat, p->n, xmax);
+    // 2. transitions of plain walks from every sample_stride-th row
+    const uint32_t n_sample = static_cast<uint32_t>((p->n + o->sample_stride - 1) / o->sample_stride);
+    const uint64_t walks_cap = static_cast<uint64_t>(n_sample) * static_cast<uint64_t>(o->capture_walks);
+    const uint64_t T = walks_cap * kCaptureJumps;
+    if (T > (uint64_t(1) << 31)) return fail(MLMC_ERR_INVALID_ARG, "capture too large (rows x walks x 8 > 2^31)");
+    uint32_t *t_row = nullptr;
+    int32_t *t_slot = nullptr;
+    float *t_w = nullptr, *F = nullptr;
+    if ((rc = ss.alloc(&t_row, T)) || (rc = ss.alloc(&t_slot, T)) || (rc = ss.alloc(&t_w, T)) ||
+        (rc = ss.alloc(&F, static_cast<size_t>(p->n) * NF)))
+        return rc;
+    LevelArgs L = level_args(p, level, o->seed, 4094);
+    L.is_slots = nullptr;
+    const FeatureArgs fa = feature_args(p, level, p->prop_xhat, xmax);
+    if (walks_cap > 0) {
+        hipLaunchKernelGGL(capture_kernel, dim3(nblk(walks_cap, 256)), dim3(256), 0, s, L,
+                           static_cast<const float *>(u), static_cast<uint32_t>(o->sample_stride), n_sample,
+                           static_cast<uint32_t>(o->capture_walks), t_row, t_slot, t_w);
+        MLMC_HIP_TRY(hipGetLastError());
+    }
+    if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
+    // keep the recorded transitions (weight > 0) in their original order
+    std::vector<uint32_t> h_row(T);
+    std::vector<int32_t> h_slot(T);
+    std::vector<float> h_w(T);
+    MLMC_HIP_TRY(hipMemcpyAsync(h_row.data(), t_row, T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(h_slot.data(), t_slot, T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(h_w.data(), t_w, T * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
+    uint64_t kept = 0;
+    for (uint64_t i = 0; i < T; ++i)
+        if (h_w[i] > 0.0f && std::isfinite(h_w[i]) && h_slot[i] >= 0) {
+            h_row[kept] = h_row[i];
+            h_slot[kept] = h_slot[i];
+            h_w[kept] = h_w[i];
+            ++kept;
+        }
+    // 3. Adam on minibatches taken by a fixed stride (coprime with the count) through the
+    //    transitions, so that each batch spreads over all sampled rows
+    std::vector<float> P(o->init_params, o->init_params + NPARAM);
+    float *m = nullptr, *v = nullptr, *wbat = nullptr;
+    TrainBuf tb{};
+    const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(kept, 1)));
+    if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&wbat, B)) ||
+        (rc = ss.train_buf(tb, B)))
+        return rc;
+    MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
+    MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
+    std::vector<double> losses;
+    if (kept > 0 && o->steps > 0) {
+        MLMC_HIP_TRY(hipMemcpyAsync(t_row, h_row.data(), kept * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, h_slot.data(), kept * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_w, h_w.data(), kept * sizeof(float), hipMemcpyHostToDevice, s));
+        auto gcd = [](uint64_t a, uint64_t b) {
+            while (b) {
+                const uint64_t t = a % b;
+                a = b;
+                b = t;
+            }
+            return a;
+        };
+        uint64_t mult = kept == 1 ? 1 : 2654435761ull % kept;
+        while (kept > 1 && (mult == 0 || gcd(mult, kept) != 1)) mult = (mult + 1) % kept;
+        const float b1 = 0.9f, b2 = 0.999f;
+        std::vector<float> lb(B);
+        for (int step = 0; step < o->steps; ++step) {
+            hipLaunchKernelGGL(gather_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w, kept,
+                               static_cast<uint64_t>(step) * B, mult, B, tb, wbat);
+            MLMC_HIP_TRY(train_pass(p->prop_P, B, tb, wbat, s));
+            const float c1 = 1.0f - std::pow(b1, static_cast<float>(step + 1));
+            const float c2 = 1.0f - std::pow(b2, static_cast<float>(step + 1));
+            hipLaunchKernelGGL(adam_kernel, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, p->prop_P, tb.G, m, v,
+                               static_cast<float>(o->lr), b1, b2, 1e-8f, c1, c2);
+            MLMC_HIP_TRY(hipGetLastError());
+            if (step == 0 || step == o->steps - 1 || (step + 1) % 16 == 0) {
+                MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
+                MLMC_HIP_TRY(hipStreamSynchronize(s));
+                double Ls = 0.0;
+                for (float x : lb) Ls += x;
+                losses.push_back(Ls);
+            }
+        }
+    }
+    MLMC_HIP_TRY(hipMemcpyAsync(P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
+    // 4. the levels' tables from the trained parameters and the pilot estimate
+    if ((rc = set_proposal(p, P.data(), p->prop_xhat, o->num_levels, s))) return rc;
+    MLMC_HIP_TRY(hipEventRecord(e1, s));
+    MLMC_HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    MLMC_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (params_out) std::memcpy(params_out, P.data(), NPARAM * sizeof(float));
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->transitions = static_cast<int64_t>(kept);
+        st->steps = o->steps;
+        st->train_ms = ms;
+        const int nl = static_cast<int>(std::min<size_t>(losses.size(), 64));
+        st->n_losses = nl;
+        for (int i = 0; i < nl; ++i) st->losses[i] = losses[losses.size() - nl + i];
+        st->first_loss = losses.empty() ? 0.0 : losses.front();
+        st->last_loss = losses.empty() ? 0.0 : losses.back();
+    }
+    return MLMC_OK;
+}
+
+}  // extern "C"

@@ -55,7 +55,24 @@ struct WalkOut {
     uint32_t jumps;
     uint64_t hash;
     R ef2, ec2, ed2;  // 2/dt times E_f, E_c, E_f - E_c
+    R wr;             // product of the likelihood ratios p/q (1 without a proposal)
 };
+
+// The jump from the alias table of the current row: returns the packed column | sign, and
+// under a proposal multiplies wr by the likelihood ratio of the slot taken.
+template <typename R, bool kIS>
+__device__ __forceinline__ uint32_t jump_pick(const LevelArgs &L, uint32_t slot_index,
+                                              uint32_t coin, R &wr)
+{
+    if (kIS) {
+        const SlotRecIS sr = L.is_slots[slot_index];
+        const bool own = coin < sr.thr;
+        wr *= static_cast<R>(own ? sr.ratio_own : sr.ratio_alias);
+        return own ? sr.own : sr.alias;
+    }
+    const SlotRec sr = L.slots[slot_index];
+    return (coin < sr.thr) ? sr.own : sr.alias;
+}
 
 // Add the grid points a..b (held at one state with weight d) to the three sums.
 template <typename R>
@@ -71,13 +88,20 @@ __device__ __forceinline__ void add_run(R d, uint32_t a, uint32_t b, uint32_t N,
     ed2 += d * static_cast<R>(f2 - c2);
 }
 
-template <typename R, bool kHash>
-__device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row, uint32_t walk)
+// Observer of the jumps of run_walk: called with the state left, its record and the packed
+// column | sign jumped to. NoObs compiles away.
+struct NoObs {
+    __device__ __forceinline__ void jump(uint32_t, const RowRec &, uint32_t) {}
+};
+
+template <typename R, bool kHash, bool kIS, typename Obs = NoObs>
+__device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row, uint32_t walk,
+                                               Obs *obs = nullptr)
 {
     RowRec cur = L.rec[row];
     uint32_t k = row, neg = 0, J = 0, run_start = 0;
     uint64_t h = kFnvOffset;
-    R ef2 = 0, ec2 = 0, ed2 = 0;
+    R ef2 = 0, ec2 = 0, ed2 = 0, wr = 1;
     const uint32_t nblk = (L.N + 3) >> 2;
     for (uint32_t q = 0; q < nblk; ++q) {
         Word4 w = philox10(Word4{q, walk, row, L.c3_step}, L.k0, L.k1);
@@ -98,8 +122,8 @@ __device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row,
             do {
                 const Word4 jw = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
                 const uint32_t slot = mulhi32(jw.x, cur.deg);
-                const SlotRec s = L.slots[cur.slot_begin + slot];
-                const uint32_t cs = (jw.y < s.thr) ? s.own : s.alias;
+                const uint32_t cs = jump_pick<R, kIS>(L, cur.slot_begin + slot, jw.y, wr);
+                if (obs) obs->jump(k, cur, cs);
                 k = cs & kColMask;
                 neg ^= cs >> 31;
                 cur = L.rec[k];
@@ -122,6 +146,7 @@ __device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row,
     o.ef2 = ef2;
     o.ec2 = ec2;
     o.ed2 = ed2;
+    o.wr = wr;
     return o;
 }
 
@@ -130,7 +155,7 @@ __device__ __forceinline__ WalkOut<R> run_walk(const LevelArgs &L, uint32_t row,
 template <typename R>
 __device__ __forceinline__ R weight_of(const WalkOut<R> &o, int base, R hd)
 {
-    R v = base ? expR(o.ef2 * hd) : expR(o.ec2 * hd) * expm1R(o.ed2 * hd);
+    R v = (base ? expR(o.ef2 * hd) : expR(o.ec2 * hd) * expm1R(o.ed2 * hd)) * o.wr;
     return o.neg ? -v : v;
 }
 
@@ -219,6 +244,7 @@ struct Walker {
     float tau_h = 0.0f, tau_e = 0.0f;
     uint32_t chain_k = 0, chain_J = 0, chain_word = 0;
     R ef2 = 0, ec2 = 0, ed2 = 0;
+    R wr = 1;                             // likelihood ratio of the path under a proposal
     uint64_t hash = kFnvOffset;
 };
 
@@ -234,6 +260,7 @@ struct Finished {
 // Holding time of the current step's chain in the exact FP64 sequence: the step's word at
 // the chain's first state, then the next-holding-time word of each jump J0 .. J1 - 1 at
 // the state that jump reached (the jumps are replayed from their blocks).
+template <bool kIS>
 __device__ __forceinline__ double chain_tau_exact(const LevelArgs &L, uint32_t row, uint32_t walk,
                                                   uint32_t k0, uint32_t J0, uint32_t J1,
                                                   uint32_t word)
@@ -243,8 +270,8 @@ __device__ __forceinline__ double chain_tau_exact(const LevelArgs &L, uint32_t r
     for (uint32_t J = J0; J < J1; ++J) {
         const Word4 ph = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
         const uint32_t slot = mulhi32(ph.x, rk.deg);
-        const SlotRec sr = L.slots[rk.slot_begin + slot];
-        const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
+        float unused = 1.0f;
+        const uint32_t cs = jump_pick<float, kIS>(L, rk.slot_begin + slot, ph.y, unused);
         rk = L.rec[cs & kColMask];
         tau = tau + neg_log_uniform(ph.z) * rk.inv_r;
     }
@@ -264,7 +291,7 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
     s.chain_word = word;
 }
 
-template <typename R, bool kHash, typename Sink>
+template <typename R, bool kHash, bool kIS, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
                                            uint64_t wb, uint64_t we, Sink &sink)
 {
@@ -291,6 +318,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 s.jumping = 0;
                 s.bq = 0xFFFFFFFFu;
                 s.ef2 = s.ec2 = s.ed2 = 0;
+                s.wr = 1;
                 if (kHash) s.hash = kFnvOffset;
             }
             pool += __popcll(idle);
@@ -311,8 +339,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
         if (jumping) {
             // jump from k by the alias table of row k: slot, coin, then the new state's record
             const uint32_t slot = mulhi32(ph.x, s.cur.deg);
-            const SlotRec sr = L.slots[s.cur.slot_begin + slot];
-            const uint32_t cs = (ph.y < sr.thr) ? sr.own : sr.alias;
+            const uint32_t cs = jump_pick<R, kIS>(L, s.cur.slot_begin + slot, ph.y, s.wr);
             s.k = cs & kColMask;
             s.neg ^= cs >> 31;
             s.cur = L.rec[s.k];
@@ -334,8 +361,8 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 const double lo = static_cast<double>(s.tau_h) - static_cast<double>(s.tau_e);
                 if (hi < L.dt) chain_over = false;
                 else if (lo >= L.dt) chain_over = true;
-                else chain_over = !(chain_tau_exact(L, row, s.w, s.chain_k, s.chain_J, s.J,
-                                                    s.chain_word) < L.dt);
+                else chain_over = !(chain_tau_exact<kIS>(L, row, s.w, s.chain_k, s.chain_J, s.J,
+                                                         s.chain_word) < L.dt);
             }
         } else if (scanning) {
             if (s.bq != q) {
@@ -378,7 +405,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
         Finished<R> f{0u, 0u, static_cast<R>(0), 0ull};
         if (finish) {
             add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
-            R v = L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd);
+            R v = (L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd)) * s.wr;
             f.k = s.k;
             f.jumps = s.J;
             f.W = s.neg ? -v : v;

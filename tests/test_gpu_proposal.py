@@ -1,0 +1,298 @@
+"""The learned proposal on the GPU, through the C-ABI:
+  - BF16 matrix-core inference against an FP32 emulation of the same arithmetic (the MFMA
+    operand layout) and against the oracle's FP64 network;
+  - the alias tables and likelihood ratios built on the device are exactly the ones the
+    oracle builds from the same proposal law;
+  - walks under the proposal follow the oracle's paths bit-exactly, and their level sums
+    agree with the oracle's within the plain method's bars;
+  - the identity proposal reproduces the plain walks bit for bit;
+  - the FP32 training gradients match the oracle's analytic FP64 gradients;
+  - training on the GPU lowers the estimator variance without moving its mean.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlmc as orc
+from oracle import proposal as prop
+from paper_1904_12754_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1904_12754_amd import api as _api
+    return _api
+
+
+def _convdiff(m, seed=3):
+    A = inputs.convection_diffusion_3d(m, seed)
+    return A, 4.0 / A.norm1(), inputs.rhs_gaussian_bump(m)
+
+
+def _mixed(n=400, seed=5):
+    """Rows of degree 1..12, so that some rows are past the six proposal slots."""
+    return inputs.erdos_renyi(n, 5.0, seed)
+
+
+def _params(seed, scale3=20.0, alpha_logit=1.5):
+    P = prop.init_params(seed)
+    P["W3"] = P["W3"] * scale3
+    P["b3"][prop.NS] = alpha_logit
+    return P
+
+
+def _bf16(x):
+    return torch.as_tensor(np.asarray(x, np.float32)).bfloat16().float()
+
+
+def _kernel_features(t, xhat, beta, level, l0):
+    """The network inputs exactly as the device forms them (FP32 arithmetic)."""
+    n = t.n
+    deg = np.asarray(t.deg)
+    sb = np.asarray(t.slot_begin)
+    p32 = t.slot_probs().astype(np.float32)
+    xabs = np.abs(np.asarray(xhat, np.float64))
+    xmax = float(xabs.max()) if xabs.max() > 0 else 1.0
+    inv = np.float32(1.0 / xmax)
+    dt = np.float32(beta / 2.0 ** level)
+    F = np.zeros((n, prop.NF), np.float32)
+    elig = (deg >= 1) & (deg <= prop.NS)
+    col = np.asarray(t.slot_col)
+    for s in range(prop.NS):
+        ok = elig & (deg > s)
+        idx = sb[:-1][ok] + s
+        F[ok, s] = p32[idx]
+        F[ok, prop.NS + s] = xabs[col[idx]].astype(np.float32) * inv
+    r = np.asarray(t.r)
+    with np.errstate(divide="ignore"):
+        F[:, 12] = np.where(r > 0, (1.0 / (1.0 / r)).astype(np.float32) * dt, 0.0)
+    F[:, 13] = np.asarray(t.d).astype(np.float32) * dt
+    F[:, 14] = xabs.astype(np.float32) * inv
+    F[:, 15] = np.float32(level - l0) / np.float32(8.0)
+    return F
+
+
+def _emulated_q(t, P, xhat, beta, level, l0):
+    """q per slot from BF16 inputs, weights and hidden activations with FP32 sums."""
+    F = _kernel_features(t, xhat, beta, level, l0)
+    W = {k: torch.as_tensor(np.asarray(v, np.float32)) for k, v in P.items()}
+    h1 = torch.relu(_bf16(F) @ _bf16(W["W1"]) + W["b1"])
+    h2 = torch.relu(_bf16(h1) @ _bf16(W["W2"]) + W["b2"])
+    o = (_bf16(h2) @ _bf16(W["W3"]) + W["b3"]).numpy()
+    deg = np.asarray(t.deg)
+    sb = np.asarray(t.slot_begin)
+    p32 = t.slot_probs().astype(np.float32)
+    q = p32.copy()
+    for i in np.nonzero((deg >= 1) & (deg <= prop.NS))[0]:
+        k = deg[i]
+        z = o[i, :k]
+        e = np.exp(z - z.max()).astype(np.float32)
+        soft = e / e.sum(dtype=np.float32)
+        alpha = np.float32(prop.ALPHA_MAX) / (np.float32(1.0) + np.exp(-o[i, prop.NS]))
+        q[sb[i]:sb[i] + k] = alpha * soft + (np.float32(1.0) - alpha) * p32[sb[i]:sb[i] + k]
+    return q
+
+
+def _set(plan, P, xhat, nlev):
+    plan.set_proposal(prop.flatten(P).astype(np.float32), xhat, num_levels=nlev)
+
+
+@pytest.mark.parametrize("case", ["convdiff", "mixed"])
+def test_inference_and_tables(api, case):
+    if case == "convdiff":
+        A, beta, _ = _convdiff(9)
+    else:
+        A = _mixed()
+        beta = 0.3
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    rng = np.random.default_rng(17)
+    xhat = np.abs(rng.normal(size=A.n)) * (rng.random(A.n) < 0.7)
+    P = _params(4)
+    plan = api.Plan(A, beta, precision="fp32")
+    l0 = plan.l0
+    _set(plan, P, xhat, 3)
+    deg = np.asarray(t.deg)
+    sb = np.asarray(t.slot_begin)
+    ns = int(sb[-1])
+    slot_row = np.repeat(np.arange(A.n), deg)
+    elig_slot = (deg[slot_row] <= prop.NS)
+    plain_thr, plain_alias = t.slot_thr[:ns], t.slot_alias[:ns]
+    for lev in (l0, l0 + 2):
+        thr, alias, ratio, q = plan.proposal_tables(lev)
+        # (1) against the FP32 emulation of the BF16 arithmetic: the operand layout
+        qe = _emulated_q(t, P, xhat, beta, lev, l0)
+        d_emul = np.abs(q - qe)
+        # (2) against the oracle's FP64 network
+        qo = prop.proposal_tables(t, P, xhat, beta, lev, l0)[0]
+        d_orc = np.abs(q - qo)
+        _say(f"{case} level {lev}: |q - emulated| max {d_emul.max():.2e} "
+             f"p99 {np.quantile(d_emul, 0.99):.2e}; |q - fp64| max {d_orc.max():.2e}; "
+             f"|q - p| max {np.abs(qo - t.slot_probs()).max():.2f}")
+        assert np.quantile(d_emul, 0.99) <= 1e-5
+        assert d_emul.max() <= 2e-3
+        assert d_orc.max() <= 0.01
+        assert np.abs(qo - t.slot_probs()).max() > 0.1      # a law well away from p
+        # rows past six slots keep the plain law and tables
+        assert np.array_equal(q[~elig_slot], t.slot_probs()[~elig_slot].astype(np.float32))
+        assert np.array_equal(thr[~elig_slot], plain_thr[~elig_slot])
+        assert np.array_equal(alias[~elig_slot], plain_alias[~elig_slot])
+        # alias tables of the device's q: exactly the oracle's construction
+        othr, oal = orc.alias_tables(t, q.astype(np.float64))
+        assert np.array_equal(thr[elig_slot], othr[:ns][elig_slot])
+        assert np.array_equal(alias[elig_slot], oal[:ns][elig_slot])
+        # ratios p/q in FP32
+        r32 = t.slot_probs().astype(np.float32) / q
+        assert np.array_equal(ratio[elig_slot], r32[elig_slot])
+        assert np.all(ratio <= np.float32(1.0 / (1.0 - prop.ALPHA_MAX)) * 1.0001)
+        # every row's law sums to one
+        sums = np.add.reduceat(q.astype(np.float64), sb[:-1][deg > 0])
+        assert np.max(np.abs(sums - 1.0)) < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_walks_under_proposal_match_oracle(api, precision):
+    A, beta, v = _convdiff(8)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    rng = np.random.default_rng(23)
+    xhat = np.abs(rng.normal(size=A.n))
+    P = _params(9)
+    plan = api.Plan(A, beta, precision=precision)
+    l0 = plan.l0
+    _set(plan, P, xhat, 3)
+    u = np.ascontiguousarray(v)
+    ut = torch.as_tensor(u, device="cuda")
+    for lev in range(l0, l0 + 3):
+        thr, alias, ratio, q = plan.proposal_tables(lev)
+        ti = t.with_proposal(thr, alias, ratio.astype(np.float64))
+        # individual paths
+        M = 1500
+        rows = rng.integers(0, A.n, size=M)
+        walks = (np.arange(M, dtype=np.uint64) * 104729 % (2 ** 32)).astype(np.uint32)
+        _say(f"IS trace prec={precision} level={lev}")
+        g = plan.trace(lev, rows, walks, seed=71)
+        o = orc.walk_trace(ti, beta, lev, 71, rows, walks)
+        assert np.array_equal(g["final_state"].cpu().numpy(), o.final_state)
+        assert np.array_equal(g["sign"].cpu().numpy(), o.sign)
+        assert np.array_equal(g["jumps"].cpu().numpy(), o.jumps)
+        assert np.array_equal(g["hash"].cpu().numpy().view(np.uint64), o.hash)
+        ref = np.log(np.abs(o.eta_fine))
+        lf = g["log_eta_fine"].cpu().numpy()
+        assert np.max(np.abs(lf - ref) / (1.0 + np.abs(ref))) < TOL[precision]
+        assert o.jumps.sum() > 0
+        # and the plain paths are different ones
+        o_plain = orc.walk_trace(t, beta, lev, 71, rows, walks)
+        assert not np.array_equal(o_plain.hash, o.hash)
+        # level sums of the production kernel
+        _say(f"IS level sums prec={precision} level={lev}")
+        s1, s2, jumps, hs = plan.level_sums(ut, lev, 0, 700, seed=13, hashes=True)
+        ol = orc.level_sums(ti, beta, lev, l0, 13, u, None, 0, 700)
+        assert jumps == int(ol.jumps.sum())
+        assert np.array_equal(hs.cpu().numpy().view(np.uint64), ol.hash_sum)
+        assert np.all(np.abs(s1.cpu().numpy() - ol.sum1) <= TOL[precision] * (ol.mass + 1e-300))
+        assert np.all(np.abs(s2.cpu().numpy() - ol.sum2) <= 4 * TOL[precision] * (ol.mass2 + 1e-300))
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_identity_proposal_is_the_plain_method(api, precision):
+    A, beta, v = _convdiff(8)
+    plan = api.Plan(A, beta, precision=precision)
+    ut = torch.as_tensor(v, device="cuda")
+    l0 = plan.l0
+    plain = [plan.level_sums(ut, lev, 0, 900, seed=3, hashes=True) for lev in range(l0, l0 + 3)]
+    plan.set_proposal(None, None, num_levels=3)
+    ident = [plan.level_sums(ut, lev, 0, 900, seed=3, hashes=True) for lev in range(l0, l0 + 3)]
+    for a, b in zip(plain, ident):
+        assert a[2] == b[2]
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[3], b[3])
+    thr, alias, ratio, q = plan.proposal_tables(l0)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    ns = int(t.slot_begin[-1])
+    assert np.array_equal(thr, t.slot_thr[:ns]) and np.array_equal(alias, t.slot_alias[:ns])
+    assert np.all(ratio == 1.0)
+    # switching a learned proposal off gives the plain walks again
+    _set(plan, _params(2), np.abs(v), 3)
+    learned = plan.level_sums(ut, l0 + 1, 0, 900, seed=3, hashes=True)
+    assert not torch.equal(learned[3], plain[1][3])
+    plan.enable_proposal(False)
+    off = plan.level_sums(ut, l0 + 1, 0, 900, seed=3, hashes=True)
+    assert torch.equal(off[0], plain[1][0]) and torch.equal(off[3], plain[1][3])
+    plan.close()
+
+
+def test_training_gradients_match_oracle(api):
+    A, beta, v = _convdiff(7)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    plan = api.Plan(A, beta, precision="fp32")
+    rng = np.random.default_rng(31)
+    xhat = np.abs(rng.normal(size=A.n))
+    P = _params(6, scale3=5.0, alpha_logit=0.3)
+    P = prop.unflatten(prop.flatten(P).astype(np.float32).astype(np.float64))
+    B = 3000
+    deg = np.asarray(t.deg)
+    rows = rng.integers(0, A.n, size=B)
+    slots = np.array([rng.integers(0, d) if d <= prop.NS and d > 0 else -1 for d in deg[rows]],
+                     dtype=np.int32)
+    slots[:7] = -1                                    # transitions that carry nothing
+    w = rng.exponential(size=B).astype(np.float32)
+    lev = plan.l0 + 1
+    g, loss = plan.proposal_loss_grad(prop.flatten(P).astype(np.float32), xhat, lev, rows, slots, w)
+    # oracle: FP64 network on the FP32 features the device forms
+    F = _kernel_features(t, xhat, beta, lev, plan.l0).astype(np.float64)
+    _, p6, valid, _ = prop.features(t, xhat, beta, lev, plan.l0)
+    keep = slots >= 0
+    G, L = prop.grads(P, F[rows[keep]], p6.astype(np.float32).astype(np.float64)[rows[keep]],
+                      valid[rows[keep]], slots[keep], w[keep].astype(np.float64))
+    # the oracle normalises by the weights of the kept transitions; the device by all
+    L *= w[keep].sum(dtype=np.float64) / w.sum(dtype=np.float64)
+    Gf = prop.flatten(G) * (w[keep].sum(dtype=np.float64) / w.sum(dtype=np.float64))
+    err = np.abs(g - Gf)
+    _say(f"loss gpu {loss:.8f} oracle {L:.8f}; grad max err {err.max():.2e} of max {np.abs(Gf).max():.2e}")
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    assert err.max() <= 1e-4 * np.abs(Gf).max()
+    off = 0
+    for k in prop.ORDER:
+        n = P[k].size
+        assert np.abs(g[off:off + n] - Gf[off:off + n]).max() <= 1e-4 * np.abs(Gf[off:off + n]).max() + 1e-9, k
+        off += n
+    plan.close()
+
+
+def test_training_lowers_variance_and_keeps_the_mean(api):
+    A, beta, v = _convdiff(12)
+    u = torch.as_tensor(np.asarray(v, np.float32), device="cuda")
+    plan = api.Plan(A, beta, precision="fp32")
+    nlev = 3
+    walks = [2048, 512, 128]
+    x0, st0 = plan.run(u, walks=walks, seed=101)
+    P0 = prop.flatten(prop.init_params(0)).astype(np.float32)
+    params, tst = plan.train_proposal(u, P0, seed=5, pilot_walks=256, capture_walks=64,
+                                      steps=300, batch=4096, lr=2e-3, num_levels=nlev)
+    _say(f"training: {tst['transitions']} transitions, loss {tst['first_loss']:.4f} -> "
+         f"{tst['last_loss']:.4f}, {tst['train_ms']:.1f} ms")
+    x1, st1 = plan.run(u, walks=walks, seed=202)
+    v0 = np.array(st0["level_var"][:nlev])
+    v1 = np.array(st1["level_var"][:nlev])
+    _say(f"level variances plain {v0} learned {v1}; est var {st0['est_variance']:.3e} -> "
+         f"{st1['est_variance']:.3e}")
+    assert tst["last_loss"] < tst["first_loss"]
+    assert st1["est_variance"] < st0["est_variance"]
+    # same finite-level estimator, independent samples: the difference is noise
+    d = (x1 - x0).cpu().numpy()[:, 0]
+    se = np.sqrt((st0["est_variance"] + st1["est_variance"]) / 1.0)
+    _say(f"mean |x_learned - x_plain| {np.abs(d).mean():.3e}, pooled se {se:.3e}")
+    assert abs(d.mean()) < 5 * se / np.sqrt(A.n) + 1e-12
+    plan.close()
