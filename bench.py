@@ -70,7 +70,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=512)
-    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc"], default="bench",
+    ap.add_argument("--cd-grid", type=int, default=128)
+    ap.add_argument("--cd-pilot", type=int, default=32)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc", "learned"],
+                    default="bench",
                     help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
                          "--walks per row), for counter runs; copy: a plain device copy of "
                          "--bytes, the calibration for the traffic counters")
@@ -203,6 +207,97 @@ def tc_bench(args):
     plan.close()
 
 
+def learned_bench(args):
+    """Time to a target RMSE with the learned proposal against the plain jump law, on the 3D
+    7-point convection-diffusion operator (m^3 cells, lognormal(0, 0.5) diffusivity,
+    uniform(-1, 1) velocity per cell, ||tA||_1 = 4, v = exp(-|x|^2)), FP32 weights,
+    Algorithm 1 with the same pilot in both cases, at the target eps, eps / 10 and eps / 30. The
+    proposal is trained once (pilot estimate, transition capture, Adam, table build: the
+    whole call is timed) and then used for both targets."""
+    import numpy as np
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    t0 = time.perf_counter()
+    A, t, v = inputs.workload_convdiff3d(args.cd_grid)
+    t_gen = time.perf_counter() - t0
+    u = torch.as_tensor(v.astype(np.float32), device="cuda")
+    t0 = time.perf_counter()
+    plan = api.Plan(A, t, precision="fp32")
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def solve(eps, seed):
+        return timed(lambda: plan.run(u, eps=eps, seed=seed, pilot_walks=args.cd_pilot,
+                                      max_levels=12))
+
+    def summary(st, el):
+        nl = st["num_levels"]
+        return {"time_to_rmse_s": el, "steps": st["steps"], "jumps": st["total_jumps"],
+                "walks": st["walks"][:nl], "level_var": st["level_var"][:nl],
+                "est_rmse": math.sqrt(st["est_variance"] + st["est_bias"] ** 2),
+                "steps_per_s": st["steps"] / el}
+
+    solve(args.eps, 1)                                # warm-up: level tables, scratch
+    rng = np.random.default_rng(0)
+    P0 = _init_params(rng)
+    train_opts = dict(seed=3, pilot_walks=32, capture_walks=16,
+                      sample_stride=max(1, A.n // 65536), steps=800, batch=4096, lr=1e-2,
+                      shrink=10.0, num_levels=6, judge_walks=8)
+    (params, tst), t_train = timed(lambda: plan.train_proposal(u, P0, **train_opts))
+    out = {
+        "workload": f"3D 7-point convection-diffusion {args.cd_grid}^3 (n={A.n}, nonsymmetric), "
+                    f"lognormal(0,0.5) diffusivity, U(-1,1) velocity, ||tA||_1=4, "
+                    f"v=exp(-|x|^2); Algorithm 1 (pilot {args.cd_pilot} walks per row on "
+                    f"l0..l0+4); FP32 weights",
+        "train_s": t_train,
+        "training": {k: tst[k] for k in ("transitions", "held_out", "steps", "best_step",
+                                         "train_ms", "first_val_loss", "best_val_loss",
+                                         "judge_var_plain", "judge_var_learned", "accepted")},
+        "train_options": train_opts,
+        "targets": [],
+        "host_s": {"generate": t_gen, "plan": t_plan},
+    }
+    for k, eps in enumerate((args.eps, args.eps / 10, args.eps / 30)):
+        plan.enable_proposal(False)
+        (xp, stp), tp = solve(eps, 100 + k)
+        plan.enable_proposal(True)
+        (xl, stl), tl = solve(eps, 200 + k)
+        d = (xl - xp).cpu().numpy()[:, 0]
+        out["targets"].append({
+            "eps": eps, "plain": summary(stp, tp), "learned": summary(stl, tl),
+            "speedup_solve": tp / tl, "speedup_incl_training": tp / (tl + t_train),
+            "variance_ratio_l0": stp["level_var"][0] / max(stl["level_var"][0], 1e-300),
+            "rms_learned_minus_plain": float(np.sqrt(np.mean(d * d))),
+        })
+    plan.close()
+    return out
+
+
+def _init_params(rng):
+    """Initial weights of the 16-64-64-7 proposal network (flat, FP32): He-scaled hidden
+    layers, a zero output layer (no correction to the value-ratio prior) and the mixing
+    output at alpha = 0.9 sigmoid(-2) = 0.11, so that the untrained proposal is close to
+    the plain law and the gain comes from training."""
+    import numpy as np
+
+    W1 = rng.normal(size=(16, 64)) * math.sqrt(2.0 / 16)
+    W2 = rng.normal(size=(64, 64)) * math.sqrt(2.0 / 64)
+    W3 = np.zeros((64, 7))
+    b3 = np.zeros(7)
+    b3[6] = -2.0
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(),
+                           b3]).astype(np.float32)
+
+
 def copy_only(args):
     """A plain device-to-device copy of a known size (the traffic-counter calibration)."""
     import torch
@@ -265,6 +360,9 @@ def main():
         return batch_bench(args)
     if args.mode == "tc":
         return tc_bench(args)
+    if args.mode == "learned":
+        print(json.dumps(learned_bench(args)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "
                                    "measured at one GPU's share of the work (--gpus 1)"}))
@@ -349,10 +447,12 @@ def main():
         },
         "roofline": roofline,
     }
+    plan.close()
+    if not args.no_learned:
+        line["learned_proposal"] = learned_bench(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, t, v, last["l0"], last["walks"], args.cpu_seconds)
     print(json.dumps(line), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -241,10 +241,14 @@ void mlmc_expv_batch_destroy(mlmc_batch_t *batch);
  * section 3, with the path's functional multiplied by p/q of every jump taken. Any q with
  * the support of p leaves each level's expectation, and so the estimator of section 2.2,
  * unchanged; a q close to |Y| p lowers the variance. q is a small network of row features:
- *   features of row k (16): p_s and |xhat(col_s)| / max|xhat| for slots s = 0..5, r_k dt,
- *     d_k dt, |xhat_k| / max|xhat|, (l - l0) / 8   (xhat: a pilot estimate of x)
+ *   features of row k (16): max(log p_s, -20) and clip(log((|xhat(col_s)| + delta) /
+ *     (|xhat_k| + delta)), -8, 8) for slots s = 0..5, r_k dt, d_k dt, |xhat_k| / max|xhat|,
+ *     (l - l0) / 8   (xhat: a pilot estimate of x, delta = 1e-6 max|xhat|; slot features
+ *     are 0 past the row's slots)
  *   16 -> 64 (ReLU) -> 64 (ReLU) -> 7;  q_s = alpha softmax(z)_s + (1 - alpha) p_s over
- *     the row's slots, z = outputs 0..5, alpha = 0.9 sigmoid(output 6)
+ *     the row's slots, z_s = feature s + feature 6 + s + output s (a log-ratio prior whose
+ *     softmax is p_s (|xhat(col_s)| + delta) normalised, plus the network's correction),
+ *     alpha = 0.9 sigmoid(output 6)
  * Rows with more than 6 off-diagonal entries keep q = p. The defensive mixture bounds the
  * ratio p/q by 10. Tables are built on the device (BF16 matrix-core inference, FP32
  * accumulation), one alias table per level. Walks of levels with tables use them while the
@@ -272,16 +276,17 @@ int mlmc_expv_proposal_tables(mlmc_plan_t *plan, int32_t level, uint32_t *thr,
                               int32_t *alias_slot, float *ratio, float *q, void *stream);
 
 /* Training loss and its gradient for given parameters, in FP32 on the device:
- *   L = - sum_b w_b log q_{slot_b}(row_b) / sum_b w_b
- * (the cross-entropy method; its minimiser over all laws is q ~ |Y| p). Transitions with
- * slot -1, or a slot past the row's entries, contribute nothing.
+ *   L = ( - sum_b w_b log q_{slot_b}(row_b) + shrink sum_b w_b sum_s c_{b,s}^2 ) / sum_b w_b
+ * (the cross-entropy method, whose minimiser over all laws is q ~ |Y| p, plus a shrinkage of
+ * the network's corrections c = outputs 0..5 over the row's slots towards the prior).
+ * Transitions with slot -1, or a slot past the row's entries, contribute nothing.
  *   params: HOST; xhat: DEVICE n FP64 or NULL; rows, slots, weights: HOST, count entries
  *   (rows in [0, n), slots in [-1, 6), weights finite >= 0); grad: HOST
  *   MLMC_PROPOSAL_PARAMS floats; loss: HOST. Waits for the stream. */
 int mlmc_expv_proposal_loss_grad(mlmc_plan_t *plan, const float *params, const double *xhat,
                                  int32_t level, int32_t count, const int64_t *rows,
-                                 const int32_t *slots, const float *weights, float *grad,
-                                 double *loss, void *stream);
+                                 const int32_t *slots, const float *weights, double shrink,
+                                 float *grad, double *loss, void *stream);
 
 typedef struct {
     uint64_t seed;              /* Philox key of the pilot and capture walks (instances 4095
@@ -294,21 +299,34 @@ typedef struct {
     int32_t steps;              /* Adam steps */
     int32_t batch;              /* transitions per step, <= 2^20 */
     double lr;                  /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+    double shrink;              /* weight of the shrinkage term of the loss, >= 0 */
     int32_t num_levels;         /* levels that get tables, as in mlmc_expv_proposal_set */
-    int32_t pad;
+    int32_t judge_walks;        /* 0 or 2..65536: level-l0 walks per row of the variance
+                                   judge (instance 4093); 0 skips it */
 } mlmc_train_opts_t;
 
 typedef struct {
     int64_t transitions;        /* recorded transitions with a nonzero weight */
+    int64_t held_out;           /* of these, held out for validation (every 8th, <= 65536) */
     int32_t steps, n_losses;
+    int32_t best_step, pad;     /* Adam steps of the kept parameters (0: the initial ones) */
     double train_ms;            /* device time of the whole call */
-    double first_loss, last_loss;
+    double first_loss, last_loss;            /* minibatch losses */
+    double first_val_loss, best_val_loss;    /* held-out losses */
+    double judge_var_plain;     /* variance judge: mean per-walk variance at l0 under the */
+    double judge_var_learned;   /*   plain law and under the trained proposal */
+    int32_t accepted, pad2;     /* 1: the proposal is enabled (judge skipped, or it won) */
     double losses[64];          /* the last n_losses minibatch losses, every 16 steps */
 } mlmc_train_stats_t;
 
 /* Train the proposal and set it (as mlmc_expv_proposal_set with the trained parameters and
  * the pilot estimate): pilot estimate of x from plain level-l0 walks, capture of their
- * jumps with |Y| weights, minibatch Adam on the loss of mlmc_expv_proposal_loss_grad.
+ * jumps with |Y| weights, minibatch Adam on the loss of mlmc_expv_proposal_loss_grad over
+ * all but every 8th transition, and early stopping: the held-out loss is evaluated every 16
+ * steps and the parameters with the lowest one (the initial parameters included) are kept.
+ * Then, if judge_walks > 0, fresh level-l0 walks measure the per-walk variance under the
+ * plain law and under the proposal, and the proposal is left enabled only if it is lower
+ * (otherwise it is set but disabled, and runs use the plain law).
  * Needs a plan over all rows and an FP32 right-hand side (u: DEVICE, n entries).
  * params_out: HOST, nullable. Waits for the stream. */
 int mlmc_expv_proposal_train(mlmc_plan_t *plan, const void *u, int32_t u_dtype,

@@ -127,19 +127,29 @@ class TrainOpts(ctypes.Structure):
                 ("pilot_walks", ctypes.c_int64), ("capture_walks", ctypes.c_int32),
                 ("sample_stride", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
-                ("num_levels", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("shrink", ctypes.c_double), ("num_levels", ctypes.c_int32),
+                ("judge_walks", ctypes.c_int32)]
 
 
 class TrainStats(ctypes.Structure):
-    _fields_ = [("transitions", ctypes.c_int64), ("steps", ctypes.c_int32),
-                ("n_losses", ctypes.c_int32), ("train_ms", ctypes.c_double),
+    _fields_ = [("transitions", ctypes.c_int64), ("held_out", ctypes.c_int64),
+                ("steps", ctypes.c_int32), ("n_losses", ctypes.c_int32),
+                ("best_step", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("train_ms", ctypes.c_double),
                 ("first_loss", ctypes.c_double), ("last_loss", ctypes.c_double),
+                ("first_val_loss", ctypes.c_double), ("best_val_loss", ctypes.c_double),
+                ("judge_var_plain", ctypes.c_double), ("judge_var_learned", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("pad2", ctypes.c_int32),
                 ("losses", ctypes.c_double * 64)]
 
     def to_dict(self) -> dict:
-        return {"transitions": self.transitions, "steps": self.steps,
-                "train_ms": self.train_ms, "first_loss": self.first_loss,
-                "last_loss": self.last_loss, "losses": list(self.losses[:self.n_losses])}
+        return {"transitions": self.transitions, "held_out": self.held_out,
+                "steps": self.steps, "best_step": self.best_step, "train_ms": self.train_ms,
+                "first_loss": self.first_loss, "last_loss": self.last_loss,
+                "first_val_loss": self.first_val_loss, "best_val_loss": self.best_val_loss,
+                "judge_var_plain": self.judge_var_plain,
+                "judge_var_learned": self.judge_var_learned, "accepted": bool(self.accepted),
+                "losses": list(self.losses[:self.n_losses])}
 
 
 _lib = None
@@ -190,7 +200,7 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_proposal_tables.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.mlmc_expv_proposal_tables.restype = ctypes.c_int
     L.mlmc_expv_proposal_loss_grad.argtypes = [vp, fp, vp, i32, i32, ctypes.POINTER(i64),
-                                               ctypes.POINTER(i32), fp, fp,
+                                               ctypes.POINTER(i32), fp, f64, fp,
                                                ctypes.POINTER(f64), vp]
     L.mlmc_expv_proposal_loss_grad.restype = ctypes.c_int
     L.mlmc_expv_proposal_train.argtypes = [vp, vp, i32, ctypes.POINTER(TrainOpts), fp,

@@ -186,7 +186,8 @@ class Plan:
         return (thr.cpu().numpy().view(np.uint32)[:k], al.cpu().numpy()[:k],
                 ratio.cpu().numpy()[:k], q.cpu().numpy()[:k])
 
-    def proposal_loss_grad(self, params, xhat, level: int, rows, slots, weights, stream=None):
+    def proposal_loss_grad(self, params, xhat, level: int, rows, slots, weights,
+                           shrink: float = 0.0, stream=None):
         """(flat FP32 gradient, loss) of the cross-entropy training loss on given transitions."""
         P, pp = self._params(params)
         x, xp = self._xhat(xhat)
@@ -199,7 +200,7 @@ class Plan:
             self._handle, pp, xp, int(level), int(rows.size),
             rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
             slots.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-            weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), float(shrink),
             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss),
             _stream_ptr(stream)))
         del P, x
@@ -208,7 +209,8 @@ class Plan:
     def train_proposal(self, u: torch.Tensor, init_params, seed: int = 0,
                        pilot_walks: int = 256, capture_walks: int = 64, sample_stride: int = 1,
                        steps: int = 200, batch: int = 4096, lr: float = 1e-3,
-                       num_levels: int = 1, stream=None):
+                       shrink: float = 1.0, num_levels: int = 1, judge_walks: int = 8,
+                       stream=None):
         """Train the proposal on the device and set it; returns (params, stats)."""
         u, R, dt = _u_args(u, self.n)
         if R != 1:
@@ -217,7 +219,7 @@ class Plan:
         out = np.zeros(_abi.MLMC_PROPOSAL_PARAMS, np.float32)
         opts = _abi.TrainOpts(int(seed), pp, int(pilot_walks), int(capture_walks),
                               int(sample_stride), int(steps), int(batch), float(lr),
-                              int(num_levels), 0)
+                              float(shrink), int(num_levels), int(judge_walks))
         st = _abi.TrainStats()
         check(self._lib.mlmc_expv_proposal_train(
             self._handle, _dev_ptr(u), dt, ctypes.byref(opts),

@@ -5,10 +5,15 @@
 // multiplying the path's functional by p/q of the slot taken keeps every level's
 // expectation, so the estimator stays unbiased. q comes from a small MLP of row features:
 //
-//   features (16): p_s and |xhat(col_s)| / max|xhat| for six slots, r_k dt, d_k dt,
-//                  |xhat_k| / max|xhat|, (l - l0) / 8      (xhat: a pilot estimate of x)
+//   features (16): max(log p_s, -20) and clip(log((|xhat(col_s)| + delta) / (|xhat_k| +
+//                  delta)), -8, 8) for six slots, r_k dt, d_k dt, |xhat_k| / max|xhat|,
+//                  (l - l0) / 8   (xhat: a pilot estimate of x, delta = 1e-6 max|xhat|)
+//   The log features make the variance-optimal law q_s ~ p_s |x(col_s)| linear in the
+//   inputs.
 //   16 -> 64 (ReLU) -> 64 (ReLU) -> 7;  q_s = alpha softmax_s(z) + (1 - alpha) p_s over the
-//   valid slots, z = outputs 0..5, alpha = 0.9 sigmoid(output 6)
+//   valid slots, z_s = feature s + feature 6 + s + output s (the log-ratio prior, whose
+//   softmax is p_s (|xhat(col_s)| + delta) normalised, plus the network's correction),
+//   alpha = 0.9 sigmoid(output 6)
 //
 // Rows with more than six slots keep q = p. Inference runs on the matrix cores: every wave
 // evaluates 16 rows with v_mfma_f32_16x16x16_bf16 in the transposed form H^T = W^T X^T, so
@@ -36,7 +41,11 @@ constexpr int NF = 16, NH = 64, NO = 7, NS = 6;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NO, NPARAM = OFF_B3 + NO;
 constexpr float kAlphaMax = 0.9f;
+constexpr double kLogPMin = -20.0;        // floor of the log p_s features
+constexpr double kLogRatioMax = 8.0;      // clip of the log value-ratio features
 constexpr int kCaptureJumps = 8;   // transitions recorded per captured walk
+constexpr int kMaxHeldOut = 1 << 16;  // held-out transitions of a training call
+constexpr int kEvalEvery = 16;        // Adam steps between held-out evaluations
 
 static_assert(NPARAM == MLMC_PROPOSAL_PARAMS, "parameter layout");
 
@@ -61,21 +70,27 @@ struct FeatureArgs {
     float dt, lvl;            // dt of the level, (l - l0) / 8
 };
 
-// Feature f (0..15) of row `row`; eligible rows only for the slot features.
+// Feature f (0..15) of row `row`, formed in FP64 and rounded once to FP32. Slot features are
+// 0 past the row's slots and for rows with more than NS slots.
 __device__ __forceinline__ float feature(const FeatureArgs &a, const RowRec &rr, uint32_t row,
-                                         int f, float inv_xmax)
+                                         int f, double xmax)
 {
     const bool elig = rr.deg >= 1 && rr.deg <= NS;
-    if (f < NS) return (elig && f < static_cast<int>(rr.deg)) ? a.p_slot[rr.slot_begin + f] : 0.0f;
+    if (f < NS) {
+        if (!elig || f >= static_cast<int>(rr.deg)) return 0.0f;
+        return static_cast<float>(fmax(log(static_cast<double>(a.p_slot[rr.slot_begin + f])), kLogPMin));
+    }
     if (f < 2 * NS) {
         const int s = f - NS;
-        if (!elig || s >= static_cast<int>(rr.deg) || !a.xhat) return 0.0f;
+        if (!elig || s >= static_cast<int>(rr.deg)) return 0.0f;
         const uint32_t c = a.slots[rr.slot_begin + s].own & kColMask;
-        return static_cast<float>(fabs(a.xhat[c])) * inv_xmax;
+        const double delta = 1e-6 * xmax;
+        const double lr = log((fabs(a.xhat[c]) + delta) / (fabs(a.xhat[row]) + delta));
+        return static_cast<float>(fmin(fmax(lr, -kLogRatioMax), kLogRatioMax));
     }
     if (f == 12) return (rr.inv_r < INFINITY) ? static_cast<float>(1.0 / rr.inv_r) * a.dt : 0.0f;
     if (f == 13) return rr.d32 * a.dt;
-    if (f == 14) return a.xhat ? static_cast<float>(fabs(a.xhat[row])) * inv_xmax : 0.0f;
+    if (f == 14) return static_cast<float>(fabs(a.xhat[row]) / xmax);
     return a.lvl;
 }
 
@@ -84,9 +99,9 @@ __global__ void features_kernel(FeatureArgs a, float *F)
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const RowRec rr = a.rec[i];
-    const float inv_xmax = static_cast<float>(1.0 / *a.xmax);
+    const double xmax = *a.xmax;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) F[i * NF + f] = feature(a, rr, static_cast<uint32_t>(i), f, inv_xmax);
+    for (int f = 0; f < NF; ++f) F[i * NF + f] = feature(a, rr, static_cast<uint32_t>(i), f, xmax);
 }
 
 __global__ void absmax_kernel(const double *x, int64_t n, double *out)
@@ -247,12 +262,12 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a)
         if (g == 0 && inrow) build_row(a, rr, nullptr);
         return;
     }
-    const float inv_xmax = static_cast<float>(1.0 / *a.fa.xmax);
+    const double xmax = *a.fa.xmax;
     float4_t xf;
-    xf.x = inrow ? feature(a.fa, rr, row, 4 * g + 0, inv_xmax) : 0.0f;
-    xf.y = inrow ? feature(a.fa, rr, row, 4 * g + 1, inv_xmax) : 0.0f;
-    xf.z = inrow ? feature(a.fa, rr, row, 4 * g + 2, inv_xmax) : 0.0f;
-    xf.w = inrow ? feature(a.fa, rr, row, 4 * g + 3, inv_xmax) : 0.0f;
+    xf.x = inrow ? feature(a.fa, rr, row, 4 * g + 0, xmax) : 0.0f;
+    xf.y = inrow ? feature(a.fa, rr, row, 4 * g + 1, xmax) : 0.0f;
+    xf.z = inrow ? feature(a.fa, rr, row, 4 * g + 2, xmax) : 0.0f;
+    xf.w = inrow ? feature(a.fa, rr, row, 4 * g + 3, xmax) : 0.0f;
     const short4_t x = pack4(xf);
     const short4_t *fr = reinterpret_cast<const short4_t *>(a.frag);
     // layer 1: H1^T (64 x 16) in four 16-row tiles
@@ -298,11 +313,17 @@ __global__ __launch_bounds__(256) void tables_kernel(TableArgs a)
     float q[NS] = {0, 0, 0, 0, 0, 0};
     const uint32_t k = rr.deg;
     if (k >= 1 && k <= NS) {
+        // logits: the log-ratio prior (features s and NS + s, FP32) plus the correction
+        float z[NS];
         float zmax = -INFINITY;
-        for (uint32_t s = 0; s < k; ++s) zmax = fmaxf(zmax, out[s]);
+        for (uint32_t s = 0; s < k; ++s) {
+            const int si = static_cast<int>(s);
+            z[s] = out[s] + (feature(a.fa, rr, row, si, xmax) + feature(a.fa, rr, row, NS + si, xmax));
+            zmax = fmaxf(zmax, z[s]);
+        }
         float den = 0.0f, e[NS];
         for (uint32_t s = 0; s < k; ++s) {
-            e[s] = expf(out[s] - zmax);
+            e[s] = expf(z[s] - zmax);
             den += e[s];
         }
         const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
@@ -362,7 +383,7 @@ __global__ void capture_kernel(LevelArgs L, const float *__restrict__ u, uint32_
 // Training: FP32 forward / backward on a batch of B transitions (fixed summation order).
 // ------------------------------------------------------------------------------------
 struct TrainBuf {
-    float *X, *p6, *H1, *H2, *dO, *dH2, *dH1, *G, *lossb, *wsum;
+    float *X, *p6, *H1, *H2, *dO, *dH2, *dH1, *G, *lossb, *wsum, *part;
     int32_t *slot;
     uint8_t *valid;
 };
@@ -432,7 +453,7 @@ __global__ void wsum_kernel(const float *w, int B, float *out)
 }
 
 // Output layer, loss and its gradient with respect to the 7 outputs, per transition.
-__global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w_batch)
+__global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w_batch, float shrink)
 {
     const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
     if (b >= B) return;
@@ -447,12 +468,15 @@ __global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w
     float dO[NO] = {0, 0, 0, 0, 0, 0, 0};
     float lb = 0.0f;
     if (s >= 0 && W > 0.0f && tb.valid[b * NS + s]) {
+        float z[NS];
         float zmax = -INFINITY;
-        for (int t = 0; t < NS; ++t)
-            if (tb.valid[b * NS + t]) zmax = fmaxf(zmax, o[t]);
+        for (int t = 0; t < NS; ++t) {
+            z[t] = o[t] + (tb.X[b * NF + t] + tb.X[b * NF + NS + t]);
+            if (tb.valid[b * NS + t]) zmax = fmaxf(zmax, z[t]);
+        }
         float e[NS], den = 0.0f;
         for (int t = 0; t < NS; ++t) {
-            e[t] = tb.valid[b * NS + t] ? expf(o[t] - zmax) : 0.0f;
+            e[t] = tb.valid[b * NS + t] ? expf(z[t] - zmax) : 0.0f;
             den += e[t];
         }
         float soft[NS];
@@ -462,10 +486,15 @@ __global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w
         const float ps = tb.p6[b * NS + s];
         const float qs = alpha * soft[s] + (1.0f - alpha) * ps;
         const float wb = w_batch[b];
-        lb = -wb * logf(qs) / W;
+        float pen = 0.0f;
+        for (int t = 0; t < NS; ++t)
+            if (tb.valid[b * NS + t]) pen += o[t] * o[t];
+        lb = (-wb * logf(qs) + shrink * wb * pen) / W;
         const float coef = -(wb / W) / qs;
         for (int t = 0; t < NS; ++t)
-            dO[t] = tb.valid[b * NS + t] ? coef * alpha * soft[s] * ((t == s ? 1.0f : 0.0f) - soft[t]) : 0.0f;
+            dO[t] = tb.valid[b * NS + t]
+                        ? coef * alpha * soft[s] * ((t == s ? 1.0f : 0.0f) - soft[t]) + 2.0f * shrink * (wb / W) * o[t]
+                        : 0.0f;
         dO[NS] = coef * (soft[s] - ps) * kAlphaMax * sg * (1.0f - sg);
     }
     for (int j = 0; j < NO; ++j) tb.dO[b * NO + j] = dO[j];
@@ -484,22 +513,63 @@ __global__ void back_act_kernel(const float *dOut, int nout, const float *W, con
     dIn[t] = act[t] > 0.0f ? acc : 0.0f;
 }
 
-// dW[i][j] = sum_b in[b][i] d[b][j] (into G + offW), db[j] = sum_b d[b][j] (into G + offb)
-__global__ void weight_grad_kernel(const float *in, int nin, const float *d, int nout, int B, float *G,
-                                   int offW, int offb)
+// Weight gradients dW[i][j] = sum_b in[b][i] d[b][j] and db[j] = sum_b d[b][j], split over
+// the batch: block s takes the 64-row chunks s, s + S, ... staged in LDS and writes its
+// partial sums; weight_grad_reduce adds the S partials in a fixed order (deterministic).
+constexpr int kGradChunk = 64;
+constexpr int kGradSplits = 1024;
+constexpr int kGradTotalMax = NH * NH + NH;
+
+__global__ __launch_bounds__(256) void weight_grad_partial(const float *in, int nin, const float *d, int nout,
+                                                           int B, float *partial)
+{
+    __shared__ float s_in[kGradChunk * NH];
+    __shared__ float s_d[kGradChunk * NH];
+    const int total = nin * nout + nout;
+    float acc[(kGradTotalMax + 255) / 256];
+#pragma unroll
+    for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) acc[q] = 0.0f;
+    const int chunks = (B + kGradChunk - 1) / kGradChunk;
+    for (int c = static_cast<int>(blockIdx.x); c < chunks; c += static_cast<int>(gridDim.x)) {
+        const int b0 = c * kGradChunk;
+        const int nb = min(kGradChunk, B - b0);
+        __syncthreads();
+        for (int e = static_cast<int>(threadIdx.x); e < nb * nin; e += 256) s_in[e] = in[b0 * nin + e];
+        for (int e = static_cast<int>(threadIdx.x); e < nb * nout; e += 256) s_d[e] = d[b0 * nout + e];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) {
+            const int t = static_cast<int>(threadIdx.x) + 256 * q;
+            if (t < nin * nout) {
+                const int i = t / nout, j = t % nout;
+                float a = 0.0f;
+                for (int b = 0; b < nb; ++b) a += s_in[b * nin + i] * s_d[b * nout + j];
+                acc[q] += a;
+            } else if (t < total) {
+                const int j = t - nin * nout;
+                float a = 0.0f;
+                for (int b = 0; b < nb; ++b) a += s_d[b * nout + j];
+                acc[q] += a;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) {
+        const int t = static_cast<int>(threadIdx.x) + 256 * q;
+        if (t < total) partial[static_cast<size_t>(blockIdx.x) * total + t] = acc[q];
+    }
+}
+
+__global__ void weight_grad_reduce(const float *partial, int splits, int nin, int nout, float *G, int offW,
+                                   int offb)
 {
     const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t < nin * nout) {
-        const int i = t / nout, j = t % nout;
-        float acc = 0.0f;
-        for (int b = 0; b < B; ++b) acc += in[b * nin + i] * d[b * nout + j];
-        G[offW + t] = acc;
-    } else if (t < nin * nout + nout) {
-        const int j = t - nin * nout;
-        float acc = 0.0f;
-        for (int b = 0; b < B; ++b) acc += d[b * nout + j];
-        G[offb + j] = acc;
-    }
+    const int total = nin * nout + nout;
+    if (t >= total) return;
+    float a = 0.0f;
+    for (int s = 0; s < splits; ++s) a += partial[static_cast<size_t>(s) * total + t];
+    if (t < nin * nout) G[offW + t] = a;
+    else G[offb + (t - nin * nout)] = a;
 }
 
 __global__ void adam_kernel(float *P, const float *G, float *m, float *v, float lr, float b1, float b2,
@@ -515,25 +585,31 @@ __global__ void adam_kernel(float *P, const float *G, float *m, float *v, float 
 
 uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
+void weight_grad(const float *in, int nin, const float *d, int nout, int B, TrainBuf tb, int offW, int offb,
+                 hipStream_t s)
+{
+    const int splits = std::min(kGradSplits, (B + kGradChunk - 1) / kGradChunk);
+    hipLaunchKernelGGL(weight_grad_partial, dim3(splits), dim3(256), 0, s, in, nin, d, nout, B, tb.part);
+    hipLaunchKernelGGL(weight_grad_reduce, dim3(nblk(nin * nout + nout, 256)), dim3(256), 0, s, tb.part, splits,
+                       nin, nout, tb.G, offW, offb);
+}
+
 // One forward/backward pass: G = dL/dP, lossb[b] = the terms of L.
-hipError_t train_pass(const float *P, int B, TrainBuf tb, const float *w_batch, hipStream_t s)
+hipError_t train_pass(const float *P, int B, TrainBuf tb, const float *w_batch, float shrink, hipStream_t s)
 {
     hipLaunchKernelGGL(wsum_kernel, dim3(1), dim3(256), 0, s, w_batch, B, tb.wsum);
     hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.X, NF, P + OFF_W1,
                        P + OFF_B1, NH, B, tb.H1);
     hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.H1, NH, P + OFF_W2,
                        P + OFF_B2, NH, B, tb.H2);
-    hipLaunchKernelGGL(output_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, P, B, tb, w_batch);
-    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NH * NO + NO, 256)), dim3(256), 0, s, tb.H2, NH, tb.dO,
-                       NO, B, tb.G, OFF_W3, OFF_B3);
+    hipLaunchKernelGGL(output_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, P, B, tb, w_batch, shrink);
+    weight_grad(tb.H2, NH, tb.dO, NO, B, tb, OFF_W3, OFF_B3, s);
     hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dO, NO, P + OFF_W3,
                        tb.H2, NH, B, tb.dH2);
-    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NH * NH + NH, 256)), dim3(256), 0, s, tb.H1, NH,
-                       tb.dH2, NH, B, tb.G, OFF_W2, OFF_B2);
+    weight_grad(tb.H1, NH, tb.dH2, NH, B, tb, OFF_W2, OFF_B2, s);
     hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dH2, NH, P + OFF_W2,
                        tb.H1, NH, B, tb.dH1);
-    hipLaunchKernelGGL(weight_grad_kernel, dim3(nblk(NF * NH + NH, 256)), dim3(256), 0, s, tb.X, NF,
-                       tb.dH1, NH, B, tb.G, OFF_W1, OFF_B1);
+    weight_grad(tb.X, NF, tb.dH1, NH, B, tb, OFF_W1, OFF_B1, s);
     return hipGetLastError();
 }
 
@@ -570,6 +646,7 @@ struct Session {
         if ((rc = alloc(&tb.G, NPARAM))) return rc;
         if ((rc = alloc(&tb.lossb, static_cast<size_t>(B)))) return rc;
         if ((rc = alloc(&tb.wsum, 1))) return rc;
+        if ((rc = alloc(&tb.part, static_cast<size_t>(kGradSplits) * kGradTotalMax))) return rc;
         if ((rc = alloc(&tb.slot, static_cast<size_t>(B)))) return rc;
         if ((rc = alloc(&tb.valid, static_cast<size_t>(B) * NS))) return rc;
         return MLMC_OK;
@@ -722,8 +799,9 @@ int mlmc_expv_proposal_tables(mlmc_plan_t *p, int32_t level, uint32_t *thr, int3
 
 int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const double *xhat, int32_t level,
                                  int32_t count, const int64_t *rows, const int32_t *slots, const float *weights,
-                                 float *grad, double *loss, void *stream)
+                                 double shrink, float *grad, double *loss, void *stream)
 {
+    if (!(shrink >= 0.0) || !std::isfinite(shrink)) return fail(MLMC_ERR_INVALID_ARG, "shrink must be finite and >= 0");
     if (!p || !params || !rows || !slots || !weights || !grad || !loss) return fail(MLMC_ERR_INVALID_ARG, "null argument");
     if (count < 1 || count > (1 << 20)) return fail(MLMC_ERR_INVALID_ARG, "count must be in [1, 2^20]");
     int rc = check_level(p, level);
@@ -754,7 +832,7 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
     if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
     hipLaunchKernelGGL(batch_from_arrays_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, F, fa, d_rows, d_slots, d_w,
                        count, tb, wb);
-    MLMC_HIP_TRY(train_pass(dP, count, tb, wb, s));
+    MLMC_HIP_TRY(train_pass(dP, count, tb, wb, static_cast<float>(shrink), s));
     std::vector<float> lb(count);
     MLMC_HIP_TRY(hipMemcpyAsync(grad, tb.G, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, count * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -773,7 +851,8 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     if (!o->init_params) return fail(MLMC_ERR_INVALID_ARG, "init_params is null");
     if (o->pilot_walks < 1 || o->pilot_walks > 0xFFFFFFFFll || o->capture_walks < 1 || o->steps < 0 ||
         o->batch < 1 || o->batch > (1 << 20) || o->num_levels < 1 || p->l0 + o->num_levels - 1 > kMaxLevel ||
-        o->sample_stride < 1 || !(o->lr > 0.0))
+        o->sample_stride < 1 || !(o->lr > 0.0) || !(o->shrink >= 0.0) || !std::isfinite(o->shrink) ||
+        o->judge_walks < 0 || o->judge_walks == 1 || o->judge_walks > 65536)
         return fail(MLMC_ERR_INVALID_ARG, "training options out of range");
     if (p->n_rows != p->n) return fail(MLMC_ERR_UNSUPPORTED, "training needs a plan over all rows");
     const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -845,23 +924,66 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
             h_w[kept] = h_w[i];
             ++kept;
         }
-    // 3. Adam on minibatches taken by a fixed stride (coprime with the count) through the
-    //    transitions, so that each batch spreads over all sampled rows
+    // 3. every 8th transition is held out (at most kMaxHeldOut of them); Adam on minibatches
+    //    of the rest, taken by a fixed stride (coprime with the count) so that each batch
+    //    spreads over all sampled rows; the parameters with the lowest held-out loss (the
+    //    initial ones included) are kept
+    uint64_t n_train = 0, n_val = 0;
+    std::vector<uint32_t> v_row_h;
+    std::vector<int32_t> v_slot_h;
+    std::vector<float> v_w_h;
+    for (uint64_t i = 0; i < kept; ++i) {
+        if (i % 8 == 7 && n_val < static_cast<uint64_t>(kMaxHeldOut)) {
+            v_row_h.push_back(h_row[i]);
+            v_slot_h.push_back(h_slot[i]);
+            v_w_h.push_back(h_w[i]);
+            ++n_val;
+        } else {
+            h_row[n_train] = h_row[i];
+            h_slot[n_train] = h_slot[i];
+            h_w[n_train] = h_w[i];
+            ++n_train;
+        }
+    }
     std::vector<float> P(o->init_params, o->init_params + NPARAM);
-    float *m = nullptr, *v = nullptr, *wbat = nullptr;
-    TrainBuf tb{};
-    const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(kept, 1)));
+    float *m = nullptr, *v = nullptr, *wbat = nullptr, *best = nullptr, *wval = nullptr;
+    TrainBuf tb{}, tbv{};
+    const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
+    const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
     if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&wbat, B)) ||
-        (rc = ss.train_buf(tb, B)))
+        (rc = ss.train_buf(tb, B)) || (rc = ss.alloc(&best, NPARAM)) || (rc = ss.alloc(&wval, V)) ||
+        (rc = ss.train_buf(tbv, V)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
     MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
     std::vector<double> losses;
-    if (kept > 0 && o->steps > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(t_row, h_row.data(), kept * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, h_slot.data(), kept * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_w, h_w.data(), kept * sizeof(float), hipMemcpyHostToDevice, s));
+    std::vector<float> lbv(V);
+    auto val_loss = [&](double &out) -> int {
+        MLMC_HIP_TRY(train_pass(p->prop_P, static_cast<int>(n_val), tbv, wval, static_cast<float>(o->shrink), s));
+        MLMC_HIP_TRY(hipMemcpyAsync(lbv.data(), tbv.lossb, n_val * sizeof(float), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (uint64_t i = 0; i < n_val; ++i) acc += lbv[i];
+        out = acc;
+        return MLMC_OK;
+    };
+    double first_val = 0.0, best_val = 0.0;
+    int best_step = 0;
+    if (n_val > 0) {
+        MLMC_HIP_TRY(hipMemcpyAsync(t_row, v_row_h.data(), n_val * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, v_slot_h.data(), n_val * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_w, v_w_h.data(), n_val * sizeof(float), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(gather_kernel, dim3(nblk(n_val, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w,
+                           n_val, uint64_t(0), uint64_t(1), static_cast<int>(n_val), tbv, wval);
+        if ((rc = val_loss(first_val))) return rc;
+        best_val = first_val;
+    }
+    if (n_train > 0 && o->steps > 0) {
+        MLMC_HIP_TRY(hipMemcpyAsync(t_row, h_row.data(), n_train * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, h_slot.data(), n_train * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(t_w, h_w.data(), n_train * sizeof(float), hipMemcpyHostToDevice, s));
         auto gcd = [](uint64_t a, uint64_t b) {
             while (b) {
                 const uint64_t t = a % b;
@@ -870,32 +992,66 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
             }
             return a;
         };
-        uint64_t mult = kept == 1 ? 1 : 2654435761ull % kept;
-        while (kept > 1 && (mult == 0 || gcd(mult, kept) != 1)) mult = (mult + 1) % kept;
+        uint64_t mult = n_train == 1 ? 1 : 2654435761ull % n_train;
+        while (n_train > 1 && (mult == 0 || gcd(mult, n_train) != 1)) mult = (mult + 1) % n_train;
         const float b1 = 0.9f, b2 = 0.999f;
         std::vector<float> lb(B);
         for (int step = 0; step < o->steps; ++step) {
-            hipLaunchKernelGGL(gather_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w, kept,
+            hipLaunchKernelGGL(gather_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w, n_train,
                                static_cast<uint64_t>(step) * B, mult, B, tb, wbat);
-            MLMC_HIP_TRY(train_pass(p->prop_P, B, tb, wbat, s));
+            MLMC_HIP_TRY(train_pass(p->prop_P, B, tb, wbat, static_cast<float>(o->shrink), s));
             const float c1 = 1.0f - std::pow(b1, static_cast<float>(step + 1));
             const float c2 = 1.0f - std::pow(b2, static_cast<float>(step + 1));
             hipLaunchKernelGGL(adam_kernel, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, p->prop_P, tb.G, m, v,
                                static_cast<float>(o->lr), b1, b2, 1e-8f, c1, c2);
             MLMC_HIP_TRY(hipGetLastError());
-            if (step == 0 || step == o->steps - 1 || (step + 1) % 16 == 0) {
+            if (step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0) {
                 MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
                 MLMC_HIP_TRY(hipStreamSynchronize(s));
                 double Ls = 0.0;
                 for (float x : lb) Ls += x;
                 losses.push_back(Ls);
+                if (n_val > 0 && step > 0) {
+                    double vl = 0.0;
+                    if ((rc = val_loss(vl))) return rc;
+                    if (vl < best_val) {
+                        best_val = vl;
+                        best_step = step + 1;
+                        MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
+                    }
+                }
             }
         }
+        if (n_val > 0) MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, best, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     MLMC_HIP_TRY(hipMemcpyAsync(P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     // 4. the levels' tables from the trained parameters and the pilot estimate
     if ((rc = set_proposal(p, P.data(), p->prop_xhat, o->num_levels, s))) return rc;
+    // 5. the plain law judges: the per-walk variance at l0 (mean over rows) of fresh walks
+    //    under the plain law and under the proposal; the proposal stays enabled only if it
+    //    is lower
+    double judge_plain = 0.0, judge_learned = 0.0;
+    bool accepted = true;
+    if (o->judge_walks > 0) {
+        auto level_var = [&](bool on, double &out) -> int {
+            p->proposal_on = on;
+            int r2 = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0xD1B54A32D192ED03ull, 4093, level,
+                                          0, static_cast<uint32_t>(o->judge_walks), s1, s2, nullptr, nullptr,
+                                          stream);
+            if (r2) return r2;
+            MLMC_HIP_TRY(launch_level_moments(s1, s2, p->n, static_cast<double>(o->judge_walks), p->moments,
+                                              p->moment_scratch, s));
+            double h[3];
+            MLMC_HIP_TRY(hipMemcpyAsync(h, p->moments, sizeof h, hipMemcpyDeviceToHost, s));
+            MLMC_HIP_TRY(hipStreamSynchronize(s));
+            out = h[2] / static_cast<double>(std::max<int64_t>(p->n, 1));
+            return MLMC_OK;
+        };
+        if ((rc = level_var(false, judge_plain)) || (rc = level_var(true, judge_learned))) return rc;
+        accepted = judge_learned < judge_plain;
+        p->proposal_on = accepted;
+    }
     MLMC_HIP_TRY(hipEventRecord(e1, s));
     MLMC_HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -904,7 +1060,14 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     if (st) {
         std::memset(st, 0, sizeof *st);
         st->transitions = static_cast<int64_t>(kept);
+        st->held_out = static_cast<int64_t>(n_val);
         st->steps = o->steps;
+        st->best_step = best_step;
+        st->first_val_loss = first_val;
+        st->best_val_loss = best_val;
+        st->judge_var_plain = judge_plain;
+        st->judge_var_learned = judge_learned;
+        st->accepted = accepted ? 1 : 0;
         st->train_ms = ms;
         const int nl = static_cast<int>(std::min<size_t>(losses.size(), 64));
         st->n_losses = nl;

@@ -65,7 +65,7 @@ def _kernel_features(t, xhat, beta, level, l0):
     p32 = t.slot_probs().astype(np.float32)
     xabs = np.abs(np.asarray(xhat, np.float64))
     xmax = float(xabs.max()) if xabs.max() > 0 else 1.0
-    inv = np.float32(1.0 / xmax)
+    delta = 1e-6 * xmax
     dt = np.float32(beta / 2.0 ** level)
     F = np.zeros((n, prop.NF), np.float32)
     elig = (deg >= 1) & (deg <= prop.NS)
@@ -73,13 +73,14 @@ def _kernel_features(t, xhat, beta, level, l0):
     for s in range(prop.NS):
         ok = elig & (deg > s)
         idx = sb[:-1][ok] + s
-        F[ok, s] = p32[idx]
-        F[ok, prop.NS + s] = xabs[col[idx]].astype(np.float32) * inv
+        F[ok, s] = np.maximum(np.log(p32[idx].astype(np.float64)), prop.LOG_P_MIN)
+        lr = np.log((xabs[col[idx]] + delta) / (xabs[ok] + delta))
+        F[ok, prop.NS + s] = np.clip(lr, -prop.LOG_RATIO_MAX, prop.LOG_RATIO_MAX)
     r = np.asarray(t.r)
     with np.errstate(divide="ignore"):
         F[:, 12] = np.where(r > 0, (1.0 / (1.0 / r)).astype(np.float32) * dt, 0.0)
     F[:, 13] = np.asarray(t.d).astype(np.float32) * dt
-    F[:, 14] = xabs.astype(np.float32) * inv
+    F[:, 14] = xabs / xmax
     F[:, 15] = np.float32(level - l0) / np.float32(8.0)
     return F
 
@@ -97,7 +98,7 @@ def _emulated_q(t, P, xhat, beta, level, l0):
     q = p32.copy()
     for i in np.nonzero((deg >= 1) & (deg <= prop.NS))[0]:
         k = deg[i]
-        z = o[i, :k]
+        z = o[i, :k] + (F[i, :k] + F[i, prop.NS:prop.NS + k])
         e = np.exp(z - z.max()).astype(np.float32)
         soft = e / e.sum(dtype=np.float32)
         alpha = np.float32(prop.ALPHA_MAX) / (np.float32(1.0) + np.exp(-o[i, prop.NS]))
@@ -119,7 +120,7 @@ def test_inference_and_tables(api, case):
     t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
     rng = np.random.default_rng(17)
     xhat = np.abs(rng.normal(size=A.n)) * (rng.random(A.n) < 0.7)
-    P = _params(4)
+    P = _params(4, scale3=5.0)
     plan = api.Plan(A, beta, precision="fp32")
     l0 = plan.l0
     _set(plan, P, xhat, 3)
@@ -142,7 +143,8 @@ def test_inference_and_tables(api, case):
              f"|q - p| max {np.abs(qo - t.slot_probs()).max():.2f}")
         assert np.quantile(d_emul, 0.99) <= 1e-5
         assert d_emul.max() <= 2e-3
-        assert d_orc.max() <= 0.01
+        # BF16 inputs, weights and activations (relative rounding 2^-9 each, three layers)
+        assert d_orc.max() <= 0.02
         assert np.abs(qo - t.slot_probs()).max() > 0.1      # a law well away from p
         # rows past six slots keep the plain law and tables
         assert np.array_equal(q[~elig_slot], t.slot_probs()[~elig_slot].astype(np.float32))
@@ -249,13 +251,15 @@ def test_training_gradients_match_oracle(api):
     slots[:7] = -1                                    # transitions that carry nothing
     w = rng.exponential(size=B).astype(np.float32)
     lev = plan.l0 + 1
-    g, loss = plan.proposal_loss_grad(prop.flatten(P).astype(np.float32), xhat, lev, rows, slots, w)
+    shrink = 0.5
+    g, loss = plan.proposal_loss_grad(prop.flatten(P).astype(np.float32), xhat, lev, rows, slots, w,
+                                      shrink=shrink)
     # oracle: FP64 network on the FP32 features the device forms
     F = _kernel_features(t, xhat, beta, lev, plan.l0).astype(np.float64)
     _, p6, valid, _ = prop.features(t, xhat, beta, lev, plan.l0)
     keep = slots >= 0
     G, L = prop.grads(P, F[rows[keep]], p6.astype(np.float32).astype(np.float64)[rows[keep]],
-                      valid[rows[keep]], slots[keep], w[keep].astype(np.float64))
+                      valid[rows[keep]], slots[keep], w[keep].astype(np.float64), shrink)
     # the oracle normalises by the weights of the kept transitions; the device by all
     L *= w[keep].sum(dtype=np.float64) / w.sum(dtype=np.float64)
     Gf = prop.flatten(G) * (w[keep].sum(dtype=np.float64) / w.sum(dtype=np.float64))
@@ -278,18 +282,33 @@ def test_training_lowers_variance_and_keeps_the_mean(api):
     nlev = 3
     walks = [2048, 512, 128]
     x0, st0 = plan.run(u, walks=walks, seed=101)
-    P0 = prop.flatten(prop.init_params(0)).astype(np.float32)
+    P = prop.init_params(0)
+    P["W3"][:] = 0.0                  # no correction to the value-ratio prior, and ...
+    P["b3"][:] = 0.0
+    P["b3"][prop.NS] = -2.0           # ... alpha = 0.11: close to the plain law
+    P0 = prop.flatten(P).astype(np.float32)
+    # the untrained proposal, for comparison
+    _, t0st = plan.train_proposal(u, P0, seed=5, pilot_walks=256, capture_walks=64, steps=0,
+                                  judge_walks=0, num_levels=nlev)
+    xi, sti = plan.run(u, walks=walks, seed=303)
     params, tst = plan.train_proposal(u, P0, seed=5, pilot_walks=256, capture_walks=64,
-                                      steps=300, batch=4096, lr=2e-3, num_levels=nlev)
-    _say(f"training: {tst['transitions']} transitions, loss {tst['first_loss']:.4f} -> "
-         f"{tst['last_loss']:.4f}, {tst['train_ms']:.1f} ms")
+                                      steps=400, batch=4096, lr=1e-2, shrink=10.0,
+                                      num_levels=nlev, judge_walks=16)
+    _say(f"training: {tst['transitions']} transitions ({tst['held_out']} held out), held-out "
+         f"loss {tst['first_val_loss']:.5f} -> {tst['best_val_loss']:.5f} at step "
+         f"{tst['best_step']}, {tst['train_ms']:.1f} ms")
     x1, st1 = plan.run(u, walks=walks, seed=202)
     v0 = np.array(st0["level_var"][:nlev])
     v1 = np.array(st1["level_var"][:nlev])
     _say(f"level variances plain {v0} learned {v1}; est var {st0['est_variance']:.3e} -> "
-         f"{st1['est_variance']:.3e}")
-    assert tst["last_loss"] < tst["first_loss"]
-    assert st1["est_variance"] < st0["est_variance"]
+         f"{st1['est_variance']:.3e} (untrained {sti['est_variance']:.3e}); judge "
+         f"{tst['judge_var_plain']:.3e} -> {tst['judge_var_learned']:.3e}")
+    assert tst["best_val_loss"] <= tst["first_val_loss"]
+    assert tst["held_out"] > 1000
+    assert tst["accepted"] and tst["judge_var_learned"] < tst["judge_var_plain"]
+    # training, not the initialisation, makes the gain
+    assert st1["est_variance"] < 0.5 * sti["est_variance"]
+    assert st1["est_variance"] < 0.5 * st0["est_variance"]
     # same finite-level estimator, independent samples: the difference is noise
     d = (x1 - x0).cpu().numpy()[:, 0]
     se = np.sqrt((st0["est_variance"] + st1["est_variance"]) / 1.0)

@@ -30,12 +30,14 @@ def _batch(seed, B=40):
     return X, p6, valid, slot, w
 
 
-def test_gradients_match_finite_differences():
+@pytest.mark.parametrize("shrink", [0.0, 0.7])
+def test_gradients_match_finite_differences(shrink):
     P = proposal.init_params(3)
     P["b3"][proposal.NS] = 0.3        # away from the tiny-alpha corner
+    P["W3"] *= 10.0                   # corrections of order one
     X, p6, valid, slot, w = _batch(4)
-    G, L0 = proposal.grads(P, X, p6, valid, slot, w)
-    assert abs(L0 - proposal.loss(P, X, p6, valid, slot, w)) < 1e-14
+    G, L0 = proposal.grads(P, X, p6, valid, slot, w, shrink)
+    assert abs(L0 - proposal.loss(P, X, p6, valid, slot, w, shrink)) < 1e-14
     rng = np.random.default_rng(5)
     for key in proposal.ORDER:
         for _ in range(6):
@@ -45,8 +47,8 @@ def test_gradients_match_finite_differences():
             Pm = {k: v.copy() for k, v in P.items()}
             Pp[key][idx] += h
             Pm[key][idx] -= h
-            fd = (proposal.loss(Pp, X, p6, valid, slot, w) -
-                  proposal.loss(Pm, X, p6, valid, slot, w)) / (2 * h)
+            fd = (proposal.loss(Pp, X, p6, valid, slot, w, shrink) -
+                  proposal.loss(Pm, X, p6, valid, slot, w, shrink)) / (2 * h)
             assert abs(fd - G[key][idx]) <= 1e-6 * max(1.0, abs(fd)), (key, idx, fd, G[key][idx])
 
 
@@ -105,3 +107,43 @@ def test_importance_sampled_levels_are_unbiased(seed):
     z = np.concatenate(z)
     assert np.max(np.abs(z)) < 5.0
     assert 0.4 < np.mean(z * z) < 1.8
+
+
+def test_zero_correction_gives_the_value_ratio_prior():
+    """With the network's outputs 0..5 at zero, softmax(z) is p_s times the value ratio
+    (|xhat_j| + delta) / (|xhat_k| + delta), clipped to [e^-8, e^8], normalised over the
+    row (without the clip the row's denominator cancels), and alpha = 0.9 sigmoid(b3[6])."""
+    a = _sparse_signed(14, 6, per_row=5)
+    C = inputs.from_dense(a)
+    t = mlmc.decompose(C.n, C.row_ptr, C.col_idx, C.values)
+    P = proposal.init_params(1)
+    P["W3"][:] = 0.0
+    P["b3"][:] = 0.0
+    P["b3"][proposal.NS] = 1.3
+    xhat = np.random.default_rng(2).normal(size=14)
+    xhat[3] = 0.0
+    q = proposal.proposal_tables(t, P, xhat, 0.2, 3, 1)[0]
+    alpha = proposal.ALPHA_MAX / (1.0 + np.exp(-1.3))
+    delta = 1e-6 * np.abs(xhat).max()
+    p = t.slot_probs()
+    for i in range(14):
+        b, e = t.slot_begin[i], t.slot_begin[i + 1]
+        ratio = (np.abs(xhat[t.slot_col[b:e]]) + delta) / (abs(xhat[i]) + delta)
+        w = p[b:e] * np.clip(ratio, np.exp(-8.0), np.exp(8.0))
+        expect = alpha * w / w.sum() + (1.0 - alpha) * p[b:e]
+        assert np.allclose(q[b:e], expect, rtol=1e-12, atol=1e-15)
+
+
+def test_shrinkage_is_the_weighted_square_of_the_corrections():
+    """The penalty term alone, for a network whose corrections are known: with W1 = W2 = 0
+    and b1 = b2 = 0 the hidden layers are zero, so output s is b3[s] for every row."""
+    P = proposal.init_params(9)
+    for k in ("W1", "b1", "W2", "b2", "W3"):
+        P[k][:] = 0.0
+    P["b3"][:] = [0.5, -1.0, 0.25, 2.0, 0.0, 1.5, 0.3]
+    X, p6, valid, slot, w = _batch(12, B=30)
+    base = proposal.loss(P, X, p6, valid, slot, w, 0.0)
+    with_pen = proposal.loss(P, X, p6, valid, slot, w, 0.4)
+    per_row = np.array([sum(P["b3"][s] ** 2 for s in range(proposal.NS) if valid[b, s])
+                        for b in range(len(w))])
+    assert abs((with_pen - base) - 0.4 * (w * per_row).sum() / w.sum()) < 1e-13
