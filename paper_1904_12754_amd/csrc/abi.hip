@@ -201,6 +201,7 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
     const int64_t per_row_items = std::max<int64_t>(1, (kTargetItems + p->n_rows - 1) / p->n_rows);
     uint64_t chunk = (M + per_row_items - 1) / per_row_items;
     chunk = std::min<uint64_t>(std::max<uint64_t>((chunk + 63) / 64 * 64, 64), 64 * 64);
+    if (M < 64) chunk = M;   // one item per row; the kernel packs several rows into a wave
     // bound the scratch: sub-launches over walk ranges
     const uint64_t bytes_per_item = static_cast<uint64_t>(nrhs) * 2 * sizeof(double);
     uint64_t max_items = std::max<uint64_t>(1, kPartialCapBytes / bytes_per_item);

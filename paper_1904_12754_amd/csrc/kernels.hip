@@ -11,36 +11,45 @@
 namespace mlmc {
 namespace {
 
+// Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
+// per group of lpr lanes (lpr a power of two, 1..64).
 template <typename R, typename U, bool kHash, bool kIS>
 __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
                                                          uint32_t M, uint32_t chunk,
-                                                         uint32_t chunks, double *partial,
+                                                         uint32_t chunks, uint32_t lpr,
+                                                         double *partial,
                                                          unsigned long long *counters,
                                                          unsigned long long *hash_sums)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
-    if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
-    const uint32_t q = static_cast<uint32_t>(item / chunks);
-    const uint32_t c = static_cast<uint32_t>(item % chunks);
+    const uint32_t per_wave = kWave / lpr;
+    const uint64_t total = static_cast<uint64_t>(n_rows) * chunks;
+    const uint64_t wave = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    if (wave * per_wave >= total) return;
+    const uint64_t item = wave * per_wave + lane / lpr;
+    const bool has = item < total;
+    const uint32_t q = has ? static_cast<uint32_t>(item / chunks) : 0u;
+    const uint32_t c = has ? static_cast<uint32_t>(item % chunks) : 0u;
     const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
-    const uint64_t wb = static_cast<uint64_t>(c) * chunk;
-    const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
+    const uint64_t wb = has ? static_cast<uint64_t>(c) * chunk : 0ull;
+    const uint64_t we = has ? min(wb + chunk, static_cast<uint64_t>(M)) : 0ull;
     SinkR1<R, U> sink{u};
-    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink);
-    const double a = wave_sum(sink.s1.value());
-    const double b = wave_sum(sink.s2.value());
+    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink, lpr);
+    const double a = group_sum(sink.s1.value(), lpr);
+    const double b = group_sum(sink.s2.value(), lpr);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
-    const unsigned long long hsum = wave_sum_u(sink.hash);
-    if (lane == 0) {
+    const unsigned long long hsum = group_sum_u(sink.hash, lpr);
+    if (has && (lane & (lpr - 1)) == 0) {
         partial[item * 2 + 0] = a;
         partial[item * 2 + 1] = b;
+        if (kHash) atomicAdd(&hash_sums[q], hsum);
+    }
+    if (lane == 0) {
         atomicAdd(&counters[0], jumps);
         if (nonfinite) atomicAdd(&counters[1], nonfinite);
-        if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
 }
 
@@ -269,7 +278,13 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
 {
     const uint64_t items = static_cast<uint64_t>(n_rows) * chunks;
     if (items == 0) return hipSuccess;
-    const dim3 grid(static_cast<uint32_t>((items + kWavesPerBlock - 1) / kWavesPerBlock));
+    // single right-hand side: groups of lpr lanes (the power of two >= the walks of an item,
+    // at most 64) so that items of few walks still fill the wave
+    uint32_t lpr = kWave;
+    if (nrhs == 1)
+        while (lpr > 1 && lpr / 2 >= chunk) lpr /= 2;
+    const uint64_t waves = nrhs == 1 ? (items + kWave / lpr - 1) / (kWave / lpr) : items;
+    const dim3 grid(static_cast<uint32_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock));
     const dim3 block(kBlock);
     const uint32_t nr = static_cast<uint32_t>(n_rows);
 #define MLMC_LAUNCH_WALKS(R, U, H, IS)                                                        \
@@ -277,7 +292,7 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
         if (nrhs == 1)                                                                        \
             hipLaunchKernelGGL((level_walks_r1<R, U, H, IS>), grid, block, 0, s, L,           \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
-                               partial, counters, hash_sums);                                 \
+                               lpr, partial, counters, hash_sums);                            \
         else                                                                                  \
             hipLaunchKernelGGL((level_walks_rhs<R, U, H, IS>), grid, block, 0, s, L,          \
                                static_cast<const U *>(u), nrhs, rows, nr, walk0, M, chunk,    \

@@ -104,19 +104,43 @@ __global__ void features_kernel(FeatureArgs a, float *F)
     for (int f = 0; f < NF; ++f) F[i * NF + f] = feature(a, rr, static_cast<uint32_t>(i), f, xmax);
 }
 
-__global__ void absmax_kernel(const double *x, int64_t n, double *out)
+// max |x| in two stages: kAbsmaxBlocks partial maxima, then the final one (1 when x is
+// null or zero). Maxima do not depend on the order of evaluation.
+constexpr int kAbsmaxBlocks = 256;
+
+__global__ void absmax_partial(const double *x, int64_t n, double *part)
 {
     __shared__ double sh[256];
     double m = 0.0;
     if (x)
-        for (int64_t i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(x[i]));
+        for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += kAbsmaxBlocks * 256)
+            m = fmax(m, fabs(x[i]));
     sh[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (static_cast<int>(threadIdx.x) < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void absmax_final(const double *part, double *out)
+{
+    __shared__ double sh[kAbsmaxBlocks];
+    sh[threadIdx.x] = part[threadIdx.x];
+    __syncthreads();
+    for (int o = kAbsmaxBlocks / 2; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) *out = sh[0] > 0.0 ? sh[0] : 1.0;
+}
+
+// out[0] = max |x| (1 when zero); out[1 .. kAbsmaxBlocks] is scratch.
+void absmax(const double *x, int64_t n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(absmax_partial, dim3(kAbsmaxBlocks), dim3(256), 0, s, x, n, out + 1);
+    hipLaunchKernelGGL(absmax_final, dim3(1), dim3(kAbsmaxBlocks), 0, s, out + 1, out);
 }
 
 // ------------------------------------------------------------------------------------
@@ -380,204 +404,297 @@ __global__ void capture_kernel(LevelArgs L, const float *__restrict__ u, uint32_
 }
 
 // ------------------------------------------------------------------------------------
-// Training: FP32 forward / backward on a batch of B transitions (fixed summation order).
+// Training: FP32 forward / backward, one workgroup per chunk of kTC transitions of the batch,
+// activations in LDS; every workgroup writes its own partial gradient and the partials are
+// added in a fixed order (deterministic).
 // ------------------------------------------------------------------------------------
-struct TrainBuf {
-    float *X, *p6, *H1, *H2, *dO, *dH2, *dH1, *G, *lossb, *wsum, *part;
-    int32_t *slot;
-    uint8_t *valid;
+constexpr int kTC = 16;               // transitions per chunk
+constexpr int kMaxTrainBlocks = 1024; // workgroups of a training pass (they loop over chunks)
+
+// The transitions of a batch: element b is transition ((begin + b) * mult) % T of the arrays.
+struct BatchSrc {
+    const uint32_t *row;
+    const int32_t *slot;
+    const float *w;
+    uint64_t T, begin, mult;
+    __device__ __forceinline__ uint64_t at(int b) const
+    {
+        return ((begin + static_cast<uint64_t>(b)) * mult) % T;
+    }
 };
 
-// Gather the batch: features, plain law and valid mask of the transition's row.
-__global__ void gather_kernel(const float *__restrict__ F, FeatureArgs fa, const uint32_t *t_row,
-                              const int32_t *t_slot, const float *t_w, uint64_t T, uint64_t begin,
-                              uint64_t mult, int B, TrainBuf tb, float *w_batch)
+__device__ __forceinline__ float block_sum_256(float v, float *sh)
 {
-    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (b >= B) return;
-    const uint64_t src = ((begin + static_cast<uint64_t>(b)) * mult) % T;
-    const uint32_t row = t_row[src];
-    const RowRec rr = fa.rec[row];
-    for (int f = 0; f < NF; ++f) tb.X[b * NF + f] = F[static_cast<uint64_t>(row) * NF + f];
-    for (int s = 0; s < NS; ++s) {
-        const bool ok = s < static_cast<int>(rr.deg) && rr.deg <= NS;
-        tb.p6[b * NS + s] = ok ? fa.p_slot[rr.slot_begin + s] : 0.0f;
-        tb.valid[b * NS + s] = ok ? 1 : 0;
-    }
-    tb.slot[b] = t_slot[src];
-    w_batch[b] = t_w[src];
-}
-
-__global__ void batch_from_arrays_kernel(const float *__restrict__ F, FeatureArgs fa,
-                                         const int64_t *rows, const int32_t *slots, const float *w,
-                                         int B, TrainBuf tb, float *w_batch)
-{
-    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (b >= B) return;
-    const uint32_t row = static_cast<uint32_t>(rows[b]);
-    const RowRec rr = fa.rec[row];
-    for (int f = 0; f < NF; ++f) tb.X[b * NF + f] = F[static_cast<uint64_t>(row) * NF + f];
-    for (int s = 0; s < NS; ++s) {
-        const bool ok = s < static_cast<int>(rr.deg) && rr.deg <= NS;
-        tb.p6[b * NS + s] = ok ? fa.p_slot[rr.slot_begin + s] : 0.0f;
-        tb.valid[b * NS + s] = ok ? 1 : 0;
-    }
-    tb.slot[b] = slots[b];
-    w_batch[b] = w[b];
-}
-
-// out[b][j] = relu(sum_i in[b][i] W[i][j] + bias[j])
-__global__ void dense_relu_kernel(const float *in, int nin, const float *W, const float *bias,
-                                  int nout, int B, float *out)
-{
-    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t >= B * nout) return;
-    const int b = t / nout, j = t % nout;
-    float acc = bias[j];
-    for (int i = 0; i < nin; ++i) acc += in[b * nin + i] * W[i * nout + j];
-    out[t] = fmaxf(acc, 0.0f);
-}
-
-__global__ void wsum_kernel(const float *w, int B, float *out)
-{
-    __shared__ float sh[256];
-    float s = 0.0f;
-    for (int b = threadIdx.x; b < B; b += 256) s += w[b];
-    sh[threadIdx.x] = s;
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (static_cast<int>(threadIdx.x) < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    const float r = sh[0];
+    __syncthreads();
+    return r;
 }
 
-// Output layer, loss and its gradient with respect to the 7 outputs, per transition.
-__global__ void output_kernel(const float *P, int B, TrainBuf tb, const float *w_batch, float shrink)
-{
-    const int b = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (b >= B) return;
-    float o[NO];
-    for (int j = 0; j < NO; ++j) {
-        float acc = P[OFF_B3 + j];
-        for (int i = 0; i < NH; ++i) acc += tb.H2[b * NH + i] * P[OFF_W3 + i * NO + j];
-        o[j] = acc;
-    }
-    const int s = tb.slot[b];
-    const float W = *tb.wsum;
-    float dO[NO] = {0, 0, 0, 0, 0, 0, 0};
-    float lb = 0.0f;
-    if (s >= 0 && W > 0.0f && tb.valid[b * NS + s]) {
-        float z[NS];
-        float zmax = -INFINITY;
-        for (int t = 0; t < NS; ++t) {
-            z[t] = o[t] + (tb.X[b * NF + t] + tb.X[b * NF + NS + t]);
-            if (tb.valid[b * NS + t]) zmax = fmaxf(zmax, z[t]);
-        }
-        float e[NS], den = 0.0f;
-        for (int t = 0; t < NS; ++t) {
-            e[t] = tb.valid[b * NS + t] ? expf(z[t] - zmax) : 0.0f;
-            den += e[t];
-        }
-        float soft[NS];
-        for (int t = 0; t < NS; ++t) soft[t] = e[t] / den;
-        const float sg = 1.0f / (1.0f + expf(-o[NS]));
-        const float alpha = kAlphaMax * sg;
-        const float ps = tb.p6[b * NS + s];
-        const float qs = alpha * soft[s] + (1.0f - alpha) * ps;
-        const float wb = w_batch[b];
-        float pen = 0.0f;
-        for (int t = 0; t < NS; ++t)
-            if (tb.valid[b * NS + t]) pen += o[t] * o[t];
-        lb = (-wb * logf(qs) + shrink * wb * pen) / W;
-        const float coef = -(wb / W) / qs;
-        for (int t = 0; t < NS; ++t)
-            dO[t] = tb.valid[b * NS + t]
-                        ? coef * alpha * soft[s] * ((t == s ? 1.0f : 0.0f) - soft[t]) + 2.0f * shrink * (wb / W) * o[t]
-                        : 0.0f;
-        dO[NS] = coef * (soft[s] - ps) * kAlphaMax * sg * (1.0f - sg);
-    }
-    for (int j = 0; j < NO; ++j) tb.dO[b * NO + j] = dO[j];
-    tb.lossb[b] = lb;
-}
+// Loss terms of the batch (lossb[b]) and, with kBackward, the workgroup's partial gradient
+// partial[blockIdx.x][NPARAM] summed over the chunks it takes. Thread t works on hidden unit
+// j = t % 64 for the rows (or inputs) of group g = t / 64, with independent accumulators;
+// W2 sits in LDS with a padded row stride so that reads along either index are free of bank
+// conflicts.
+constexpr int kRG = kTC / 4;          // rows per thread group
+constexpr int kW2S = NH + 1;          // padded LDS row stride of W2
 
-// dIn[b][i] = (sum_j dOut[b][j] W[i][j]) * [act[b][i] > 0]
-__global__ void back_act_kernel(const float *dOut, int nout, const float *W, const float *act, int nin,
-                                int B, float *dIn)
+template <bool kBackward>
+__global__ __launch_bounds__(256) void train_kernel(const float *__restrict__ P, const float *__restrict__ F,
+                                                    const float *__restrict__ p_slot,
+                                                    const RowRec *__restrict__ rec, BatchSrc src, int B,
+                                                    float shrink, float *__restrict__ partial,
+                                                    float *__restrict__ lossb)
 {
-    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t >= B * nin) return;
-    const int b = t / nin, i = t % nin;
+    __shared__ float sW1[NF * NH], sW2[NH * kW2S], sW3[NH * NO], sB1[NH], sB2[NH], sB3[8];
+    __shared__ float sX[kTC * NF], sH1[kTC * NH], sH2[kTC * NH], sD2[kTC * NH];
+    __shared__ float sdO[kTC * 8], sP6[kTC * NS], sW[kTC];
+    __shared__ int sSlot[kTC];
+    __shared__ int sValid[kTC];           // bit s: slot s is one of the row's entries
+    __shared__ uint32_t sRow[kTC];
+    __shared__ float sRed[256];
+    const int tid = static_cast<int>(threadIdx.x);
+    const int j = tid & (NH - 1), g = tid >> 6;
+    for (int e = tid; e < NF * NH; e += 256) sW1[e] = P[OFF_W1 + e];
+    for (int e = tid; e < NH * NH; e += 256) sW2[(e / NH) * kW2S + (e % NH)] = P[OFF_W2 + e];
+    for (int e = tid; e < NH * NO; e += 256) sW3[e] = P[OFF_W3 + e];
+    if (tid < NH) {
+        sB1[tid] = P[OFF_B1 + tid];
+        sB2[tid] = P[OFF_B2 + tid];
+    }
+    if (tid < NO) sB3[tid] = P[OFF_B3 + tid];
+    // total weight of the batch, in the same order in every workgroup; element b + 256 of
+    // the batch is 256 mult (mod T) past element b
     float acc = 0.0f;
-    for (int j = 0; j < nout; ++j) acc += dOut[b * nout + j] * W[i * nout + j];
-    dIn[t] = act[t] > 0.0f ? acc : 0.0f;
-}
-
-// Weight gradients dW[i][j] = sum_b in[b][i] d[b][j] and db[j] = sum_b d[b][j], split over
-// the batch: block s takes the 64-row chunks s, s + S, ... staged in LDS and writes its
-// partial sums; weight_grad_reduce adds the S partials in a fixed order (deterministic).
-constexpr int kGradChunk = 64;
-constexpr int kGradSplits = 1024;
-constexpr int kGradTotalMax = NH * NH + NH;
-
-__global__ __launch_bounds__(256) void weight_grad_partial(const float *in, int nin, const float *d, int nout,
-                                                           int B, float *partial)
-{
-    __shared__ float s_in[kGradChunk * NH];
-    __shared__ float s_d[kGradChunk * NH];
-    const int total = nin * nout + nout;
-    float acc[(kGradTotalMax + 255) / 256];
-#pragma unroll
-    for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) acc[q] = 0.0f;
-    const int chunks = (B + kGradChunk - 1) / kGradChunk;
+    if (tid < B) {
+        uint64_t idx = src.at(tid);
+        const uint64_t stride = (256ull * (src.mult % src.T)) % src.T;
+        for (int b = tid; b < B; b += 256) {
+            acc += src.w[idx];
+            idx += stride;
+            if (idx >= src.T) idx -= src.T;
+        }
+    }
+    const float Wsum = block_sum_256(acc, sRed);
+    float *G = partial + static_cast<size_t>(blockIdx.x) * NPARAM;
+    const int chunks = (B + kTC - 1) / kTC;
+    bool first = true;
     for (int c = static_cast<int>(blockIdx.x); c < chunks; c += static_cast<int>(gridDim.x)) {
-        const int b0 = c * kGradChunk;
-        const int nb = min(kGradChunk, B - b0);
+        const int b0 = c * kTC;
+        const int nb = min(kTC, B - b0);
         __syncthreads();
-        for (int e = static_cast<int>(threadIdx.x); e < nb * nin; e += 256) s_in[e] = in[b0 * nin + e];
-        for (int e = static_cast<int>(threadIdx.x); e < nb * nout; e += 256) s_d[e] = d[b0 * nout + e];
+        if (tid < kTC) {
+            int slot = -1, valid = 0;
+            float w = 0.0f;
+            uint32_t row = 0;
+            if (tid < nb) {
+                const uint64_t t = src.at(b0 + tid);
+                row = src.row[t];
+                const RowRec rr = rec[row];
+                slot = src.slot[t];
+                w = src.w[t];
+                const bool elig = rr.deg >= 1 && rr.deg <= NS;
+                for (int q = 0; q < NS; ++q) {
+                    const bool ok = elig && q < static_cast<int>(rr.deg);
+                    sP6[tid * NS + q] = ok ? p_slot[rr.slot_begin + q] : 0.0f;
+                    valid |= ok ? (1 << q) : 0;
+                }
+            } else {
+                for (int q = 0; q < NS; ++q) sP6[tid * NS + q] = 0.0f;
+            }
+            sSlot[tid] = slot;
+            sValid[tid] = valid;
+            sW[tid] = w;
+            sRow[tid] = row;
+        }
         __syncthreads();
+        for (int e = tid; e < kTC * NF; e += 256) {
+            const int b = e / NF;
+            sX[e] = b < nb ? F[static_cast<size_t>(sRow[b]) * NF + (e % NF)] : 0.0f;
+        }
+        __syncthreads();
+        // forward: unit j of rows g kRG .. g kRG + kRG - 1
+        {
+            float a[kRG];
 #pragma unroll
-        for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) {
-            const int t = static_cast<int>(threadIdx.x) + 256 * q;
-            if (t < nin * nout) {
-                const int i = t / nout, j = t % nout;
-                float a = 0.0f;
-                for (int b = 0; b < nb; ++b) a += s_in[b * nin + i] * s_d[b * nout + j];
-                acc[q] += a;
-            } else if (t < total) {
-                const int j = t - nin * nout;
-                float a = 0.0f;
-                for (int b = 0; b < nb; ++b) a += s_d[b * nout + j];
-                acc[q] += a;
+            for (int r = 0; r < kRG; ++r) a[r] = sB1[j];
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const float w = sW1[i * NH + j];
+#pragma unroll
+                for (int r = 0; r < kRG; ++r) a[r] += sX[(g * kRG + r) * NF + i] * w;
+            }
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) sH1[(g * kRG + r) * NH + j] = fmaxf(a[r], 0.0f);
+        }
+        __syncthreads();
+        {
+            float a[kRG];
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) a[r] = sB2[j];
+#pragma unroll 8
+            for (int i = 0; i < NH; ++i) {
+                const float w = sW2[i * kW2S + j];
+#pragma unroll
+                for (int r = 0; r < kRG; ++r) a[r] += sH1[(g * kRG + r) * NH + i] * w;
+            }
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) sH2[(g * kRG + r) * NH + j] = fmaxf(a[r], 0.0f);
+        }
+        __syncthreads();
+        // outputs: one thread per (row, output)
+        if (tid < kTC * NO) {
+            const int b = tid / NO, q = tid % NO;
+            float a = sB3[q];
+#pragma unroll 8
+            for (int i = 0; i < NH; ++i) a += sH2[b * NH + i] * sW3[i * NO + q];
+            sdO[b * 8 + q] = a;
+        }
+        __syncthreads();
+        // loss and output gradient: one thread per transition (sdO holds the outputs on entry)
+        if (tid < kTC) {
+            const int b = tid;
+            float o[NO];
+            for (int q = 0; q < NO; ++q) o[q] = sdO[b * 8 + q];
+            const int sl = sSlot[b];
+            const int valid = sValid[b];
+            float dO[NO] = {0, 0, 0, 0, 0, 0, 0};
+            float lb = 0.0f;
+            if (b < nb && sl >= 0 && sl < NS && Wsum > 0.0f && ((valid >> sl) & 1)) {
+                float z[NS];
+                float zmax = -INFINITY;
+                for (int t = 0; t < NS; ++t) {
+                    z[t] = o[t] + (sX[b * NF + t] + sX[b * NF + NS + t]);
+                    if ((valid >> t) & 1) zmax = fmaxf(zmax, z[t]);
+                }
+                float e[NS], den = 0.0f;
+                for (int t = 0; t < NS; ++t) {
+                    e[t] = ((valid >> t) & 1) ? expf(z[t] - zmax) : 0.0f;
+                    den += e[t];
+                }
+                float soft[NS];
+                for (int t = 0; t < NS; ++t) soft[t] = e[t] / den;
+                const float sg = 1.0f / (1.0f + expf(-o[NS]));
+                const float alpha = kAlphaMax * sg;
+                const float ps = sP6[b * NS + sl];
+                const float qs = alpha * soft[sl] + (1.0f - alpha) * ps;
+                const float wb = sW[b];
+                float pen = 0.0f;
+                for (int t = 0; t < NS; ++t)
+                    if ((valid >> t) & 1) pen += o[t] * o[t];
+                lb = (-wb * logf(qs) + shrink * wb * pen) / Wsum;
+                const float coef = -(wb / Wsum) / qs;
+                for (int t = 0; t < NS; ++t)
+                    dO[t] = ((valid >> t) & 1) ? coef * alpha * soft[sl] * ((t == sl ? 1.0f : 0.0f) - soft[t]) +
+                                                     2.0f * shrink * (wb / Wsum) * o[t]
+                                               : 0.0f;
+                dO[NS] = coef * (soft[sl] - ps) * kAlphaMax * sg * (1.0f - sg);
+            }
+            for (int q = 0; q < NO; ++q) sdO[b * 8 + q] = dO[q];
+            if (b < nb) lossb[b0 + b] = lb;
+        }
+        __syncthreads();
+        if (!kBackward) continue;
+        // dH2 = (dO W3^T) [H2 > 0]: unit j of the group's rows
+#pragma unroll
+        for (int r = 0; r < kRG; ++r) {
+            const int b = g * kRG + r;
+            float a = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NO; ++q) a += sdO[b * 8 + q] * sW3[j * NO + q];
+            sD2[b * NH + j] = sH2[b * NH + j] > 0.0f ? a : 0.0f;
+        }
+        __syncthreads();
+        // output layer gradients: one thread per weight
+        for (int t = tid; t < NH * NO + NO; t += 256) {
+            float a = 0.0f;
+            if (t < NH * NO) {
+                const int i = t / NO, q = t % NO;
+                for (int b = 0; b < nb; ++b) a += sH2[b * NH + i] * sdO[b * 8 + q];
+                G[OFF_W3 + t] = (first ? 0.0f : G[OFF_W3 + t]) + a;
+            } else {
+                const int q = t - NH * NO;
+                for (int b = 0; b < nb; ++b) a += sdO[b * 8 + q];
+                G[OFF_B3 + q] = (first ? 0.0f : G[OFF_B3 + q]) + a;
             }
         }
-    }
+        // second layer: dW2[i][j] for i = 16 g .. 16 g + 15
+        {
+            float a[16];
 #pragma unroll
-    for (int q = 0; q < (kGradTotalMax + 255) / 256; ++q) {
-        const int t = static_cast<int>(threadIdx.x) + 256 * q;
-        if (t < total) partial[static_cast<size_t>(blockIdx.x) * total + t] = acc[q];
+            for (int ii = 0; ii < 16; ++ii) a[ii] = 0.0f;
+            float bsum = 0.0f;
+            for (int b = 0; b < nb; ++b) {
+                const float d = sD2[b * NH + j];
+                bsum += d;
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) a[ii] += sH1[b * NH + g * 16 + ii] * d;
+            }
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) {
+                const int t = (g * 16 + ii) * NH + j;
+                G[OFF_W2 + t] = (first ? 0.0f : G[OFF_W2 + t]) + a[ii];
+            }
+            if (g == 0) G[OFF_B2 + j] = (first ? 0.0f : G[OFF_B2 + j]) + bsum;
+        }
+        __syncthreads();
+        // dH1 = (dH2 W2^T) [H1 > 0] into sH2 (no longer needed): unit j of the group's rows
+        {
+            float a[kRG];
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) a[r] = 0.0f;
+#pragma unroll 8
+            for (int q = 0; q < NH; ++q) {
+                const float w = sW2[j * kW2S + q];
+#pragma unroll
+                for (int r = 0; r < kRG; ++r) a[r] += sD2[(g * kRG + r) * NH + q] * w;
+            }
+#pragma unroll
+            for (int r = 0; r < kRG; ++r) {
+                const int e = (g * kRG + r) * NH + j;
+                sH2[e] = sH1[e] > 0.0f ? a[r] : 0.0f;
+            }
+        }
+        __syncthreads();
+        // first layer: dW1[i][j] for i = 4 g .. 4 g + 3
+        {
+            float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float bsum = 0.0f;
+            for (int b = 0; b < nb; ++b) {
+                const float d = sH2[b * NH + j];
+                bsum += d;
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) a[ii] += sX[b * NF + g * 4 + ii] * d;
+            }
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                const int t = (g * 4 + ii) * NH + j;
+                G[OFF_W1 + t] = (first ? 0.0f : G[OFF_W1 + t]) + a[ii];
+            }
+            if (g == 0) G[OFF_B1 + j] = (first ? 0.0f : G[OFF_B1 + j]) + bsum;
+        }
+        first = false;
     }
 }
 
-__global__ void weight_grad_reduce(const float *partial, int splits, int nin, int nout, float *G, int offW,
-                                   int offb)
-{
-    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    const int total = nin * nout + nout;
-    if (t >= total) return;
-    float a = 0.0f;
-    for (int s = 0; s < splits; ++s) a += partial[static_cast<size_t>(s) * total + t];
-    if (t < nin * nout) G[offW + t] = a;
-    else G[offb + (t - nin * nout)] = a;
-}
-
-__global__ void adam_kernel(float *P, const float *G, float *m, float *v, float lr, float b1, float b2,
-                            float eps, float c1, float c2)
+// G = sum of the partial gradients (fixed order); with kAdam, one Adam step on P instead.
+template <bool kAdam>
+__global__ void grad_sum_kernel(const float *__restrict__ partial, int blocks, float *out, float *P, float *m,
+                                float *v, float lr, float b1, float b2, float eps, float c1, float c2)
 {
     const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
     if (t >= NPARAM) return;
-    const float g = G[t];
+    float g = 0.0f;
+    for (int q = 0; q < blocks; ++q) g += partial[static_cast<size_t>(q) * NPARAM + t];
+    if (!kAdam) {
+        out[t] = g;
+        return;
+    }
     m[t] = b1 * m[t] + (1.0f - b1) * g;
     v[t] = b2 * v[t] + (1.0f - b2) * g * g;
     P[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
@@ -585,31 +702,19 @@ __global__ void adam_kernel(float *P, const float *G, float *m, float *v, float 
 
 uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
-void weight_grad(const float *in, int nin, const float *d, int nout, int B, TrainBuf tb, int offW, int offb,
-                 hipStream_t s)
-{
-    const int splits = std::min(kGradSplits, (B + kGradChunk - 1) / kGradChunk);
-    hipLaunchKernelGGL(weight_grad_partial, dim3(splits), dim3(256), 0, s, in, nin, d, nout, B, tb.part);
-    hipLaunchKernelGGL(weight_grad_reduce, dim3(nblk(nin * nout + nout, 256)), dim3(256), 0, s, tb.part, splits,
-                       nin, nout, tb.G, offW, offb);
-}
+int train_blocks(int B) { return std::min(kMaxTrainBlocks, (B + kTC - 1) / kTC); }
 
-// One forward/backward pass: G = dL/dP, lossb[b] = the terms of L.
-hipError_t train_pass(const float *P, int B, TrainBuf tb, const float *w_batch, float shrink, hipStream_t s)
+// Loss terms (and, with backward, the partial gradients) of a batch.
+hipError_t train_pass(bool backward, const float *P, const float *F, const mlmc_plan *p, int level,
+                      const BatchSrc &src, int B, float shrink, float *partial, float *lossb, hipStream_t s)
 {
-    hipLaunchKernelGGL(wsum_kernel, dim3(1), dim3(256), 0, s, w_batch, B, tb.wsum);
-    hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.X, NF, P + OFF_W1,
-                       P + OFF_B1, NH, B, tb.H1);
-    hipLaunchKernelGGL(dense_relu_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.H1, NH, P + OFF_W2,
-                       P + OFF_B2, NH, B, tb.H2);
-    hipLaunchKernelGGL(output_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, P, B, tb, w_batch, shrink);
-    weight_grad(tb.H2, NH, tb.dO, NO, B, tb, OFF_W3, OFF_B3, s);
-    hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dO, NO, P + OFF_W3,
-                       tb.H2, NH, B, tb.dH2);
-    weight_grad(tb.H1, NH, tb.dH2, NH, B, tb, OFF_W2, OFF_B2, s);
-    hipLaunchKernelGGL(back_act_kernel, dim3(nblk(B * NH, 256)), dim3(256), 0, s, tb.dH2, NH, P + OFF_W2,
-                       tb.H1, NH, B, tb.dH1);
-    weight_grad(tb.X, NF, tb.dH1, NH, B, tb, OFF_W1, OFF_B1, s);
+    const int blocks = train_blocks(B);
+    if (backward)
+        hipLaunchKernelGGL(train_kernel<true>, dim3(blocks), dim3(256), 0, s, P, F, p->p_slot, p->level_rec[level],
+                           src, B, shrink, partial, lossb);
+    else
+        hipLaunchKernelGGL(train_kernel<false>, dim3(blocks), dim3(256), 0, s, P, F, p->p_slot, p->level_rec[level],
+                           src, B, shrink, partial, lossb);
     return hipGetLastError();
 }
 
@@ -631,24 +736,6 @@ struct Session {
                         std::string("hipMalloc: ") + hipGetErrorString(e));
         }
         ptrs.push_back(*p);
-        return MLMC_OK;
-    }
-    int train_buf(TrainBuf &tb, int B)
-    {
-        int rc;
-        if ((rc = alloc(&tb.X, static_cast<size_t>(B) * NF))) return rc;
-        if ((rc = alloc(&tb.p6, static_cast<size_t>(B) * NS))) return rc;
-        if ((rc = alloc(&tb.H1, static_cast<size_t>(B) * NH))) return rc;
-        if ((rc = alloc(&tb.H2, static_cast<size_t>(B) * NH))) return rc;
-        if ((rc = alloc(&tb.dO, static_cast<size_t>(B) * NO))) return rc;
-        if ((rc = alloc(&tb.dH2, static_cast<size_t>(B) * NH))) return rc;
-        if ((rc = alloc(&tb.dH1, static_cast<size_t>(B) * NH))) return rc;
-        if ((rc = alloc(&tb.G, NPARAM))) return rc;
-        if ((rc = alloc(&tb.lossb, static_cast<size_t>(B)))) return rc;
-        if ((rc = alloc(&tb.wsum, 1))) return rc;
-        if ((rc = alloc(&tb.part, static_cast<size_t>(kGradSplits) * kGradTotalMax))) return rc;
-        if ((rc = alloc(&tb.slot, static_cast<size_t>(B)))) return rc;
-        if ((rc = alloc(&tb.valid, static_cast<size_t>(B) * NS))) return rc;
         return MLMC_OK;
     }
 };
@@ -694,7 +781,7 @@ int ensure_proposal_buffers(mlmc_plan *p, hipStream_t s)
     int rc;
     if ((rc = plan_alloc(p, &p->p_slot, p->p_slot_host.size())) || (rc = plan_alloc(p, &p->prop_P, NPARAM)) ||
         (rc = plan_alloc(p, &p->prop_frag, NFRAG)) || (rc = plan_alloc(p, &p->prop_xhat, static_cast<size_t>(p->n))) ||
-        (rc = plan_alloc(p, &p->prop_xmax, 1)))
+        (rc = plan_alloc(p, &p->prop_xmax, 1 + kAbsmaxBlocks)))
         return rc;
     if (fresh)
         MLMC_HIP_TRY(hipMemcpyAsync(p->p_slot, p->p_slot_host.data(), p->p_slot_host.size() * sizeof(float),
@@ -742,7 +829,7 @@ int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_
             MLMC_HIP_TRY(hipMemsetAsync(p->prop_xhat, 0, p->n * sizeof(double), s));
         }
     }
-    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, p->prop_xhat, p->n, p->prop_xmax);
+    absmax(p->prop_xhat, p->n, p->prop_xmax, s);
     MLMC_HIP_TRY(hipGetLastError());
     if (p->is_slots.size() < static_cast<size_t>(kMaxLevel + 1)) p->is_slots.resize(kMaxLevel + 1, nullptr);
     for (int q = 0; q < num_levels; ++q) {
@@ -813,29 +900,34 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
         if (slots[b] < -1 || slots[b] >= NS) return fail(MLMC_ERR_INVALID_ARG, "transition slot out of range [-1, 6)");
         if (!(weights[b] >= 0.0f) || !std::isfinite(weights[b])) return fail(MLMC_ERR_INVALID_ARG, "weights must be finite and >= 0");
     }
+    std::vector<uint32_t> rows32(count);
+    for (int32_t b = 0; b < count; ++b) rows32[b] = static_cast<uint32_t>(rows[b]);
     Session ss;
-    float *dP = nullptr, *F = nullptr, *wb = nullptr, *d_w = nullptr;
-    int64_t *d_rows = nullptr;
+    float *dP = nullptr, *F = nullptr, *d_w = nullptr, *part = nullptr, *G = nullptr, *lossb = nullptr;
+    uint32_t *d_rows = nullptr;
     int32_t *d_slots = nullptr;
     double *xmax = nullptr;
-    TrainBuf tb{};
+    const int blocks = train_blocks(count);
     if ((rc = ss.alloc(&dP, NPARAM)) || (rc = ss.alloc(&F, static_cast<size_t>(p->n) * NF)) ||
-        (rc = ss.alloc(&wb, count)) || (rc = ss.alloc(&xmax, 1)) || (rc = ss.train_buf(tb, count)) ||
-        (rc = ss.alloc(&d_rows, count)) || (rc = ss.alloc(&d_slots, count)) || (rc = ss.alloc(&d_w, count)))
+        (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks)) || (rc = ss.alloc(&d_rows, count)) || (rc = ss.alloc(&d_slots, count)) ||
+        (rc = ss.alloc(&d_w, count)) || (rc = ss.alloc(&part, static_cast<size_t>(blocks) * NPARAM)) ||
+        (rc = ss.alloc(&G, NPARAM)) || (rc = ss.alloc(&lossb, count)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(dP, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(d_rows, rows, count * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(d_rows, rows32.data(), count * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(d_slots, slots, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(d_w, weights, count * sizeof(float), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, xhat, p->n, xmax);
+    absmax(xhat, p->n, xmax, s);
     const FeatureArgs fa = feature_args(p, level, xhat, xmax);
     if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
-    hipLaunchKernelGGL(batch_from_arrays_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, F, fa, d_rows, d_slots, d_w,
-                       count, tb, wb);
-    MLMC_HIP_TRY(train_pass(dP, count, tb, wb, static_cast<float>(shrink), s));
+    const BatchSrc src{d_rows, d_slots, d_w, static_cast<uint64_t>(count), 0, 1};
+    MLMC_HIP_TRY(train_pass(true, dP, F, p, level, src, count, static_cast<float>(shrink), part, lossb, s));
+    hipLaunchKernelGGL(grad_sum_kernel<false>, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, part, blocks, G, nullptr,
+                       nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f);
+    MLMC_HIP_TRY(hipGetLastError());
     std::vector<float> lb(count);
-    MLMC_HIP_TRY(hipMemcpyAsync(grad, tb.G, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, count * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(grad, G, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), lossb, count * sizeof(float), hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     double L = 0.0;
     for (float v : lb) L += v;
@@ -876,7 +968,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     const bool was_on = p->proposal_on;
     p->proposal_on = false;
     double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
-    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1))) return rc;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
     rc = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0x9E3779B97F4A7C15ull, 4095, level, 0,
                               static_cast<uint32_t>(o->pilot_walks), s1, s2, nullptr, nullptr, stream);
     p->proposal_on = was_on;
@@ -886,7 +978,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     ca.s1[0] = s1;
     ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
     MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
-    hipLaunchKernelGGL(absmax_kernel, dim3(1), dim3(256), 0, s, p->prop_xhat, p->n, xmax);
+    absmax(p->prop_xhat, p->n, xmax, s);
     // 2. transitions of plain walks from every sample_stride-th row
     const uint32_t n_sample = static_cast<uint32_t>((p->n + o->sample_stride - 1) / o->sample_stride);
     const uint64_t walks_cap = static_cast<uint64_t>(n_sample) * static_cast<uint64_t>(o->capture_walks);
@@ -946,13 +1038,16 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         }
     }
     std::vector<float> P(o->init_params, o->init_params + NPARAM);
-    float *m = nullptr, *v = nullptr, *wbat = nullptr, *best = nullptr, *wval = nullptr;
-    TrainBuf tb{}, tbv{};
+    float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
+    uint32_t *v_row = nullptr;
+    int32_t *v_slot = nullptr;
+    float *v_w = nullptr;
     const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
     const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
-    if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&wbat, B)) ||
-        (rc = ss.train_buf(tb, B)) || (rc = ss.alloc(&best, NPARAM)) || (rc = ss.alloc(&wval, V)) ||
-        (rc = ss.train_buf(tbv, V)))
+    if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&best, NPARAM)) ||
+        (rc = ss.alloc(&part, static_cast<size_t>(train_blocks(B)) * NPARAM)) || (rc = ss.alloc(&lossb, B)) ||
+        (rc = ss.alloc(&lossv, V)) || (rc = ss.alloc(&v_row, V)) || (rc = ss.alloc(&v_slot, V)) ||
+        (rc = ss.alloc(&v_w, V)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -960,9 +1055,11 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
     std::vector<double> losses;
     std::vector<float> lbv(V);
+    const BatchSrc vsrc{v_row, v_slot, v_w, std::max<uint64_t>(n_val, 1), 0, 1};
+    const float shrink = static_cast<float>(o->shrink);
     auto val_loss = [&](double &out) -> int {
-        MLMC_HIP_TRY(train_pass(p->prop_P, static_cast<int>(n_val), tbv, wval, static_cast<float>(o->shrink), s));
-        MLMC_HIP_TRY(hipMemcpyAsync(lbv.data(), tbv.lossb, n_val * sizeof(float), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(train_pass(false, p->prop_P, F, p, level, vsrc, static_cast<int>(n_val), shrink, part, lossv, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(lbv.data(), lossv, n_val * sizeof(float), hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
         double acc = 0.0;
         for (uint64_t i = 0; i < n_val; ++i) acc += lbv[i];
@@ -972,11 +1069,9 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     double first_val = 0.0, best_val = 0.0;
     int best_step = 0;
     if (n_val > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(t_row, v_row_h.data(), n_val * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, v_slot_h.data(), n_val * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_w, v_w_h.data(), n_val * sizeof(float), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(gather_kernel, dim3(nblk(n_val, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w,
-                           n_val, uint64_t(0), uint64_t(1), static_cast<int>(n_val), tbv, wval);
+        MLMC_HIP_TRY(hipMemcpyAsync(v_row, v_row_h.data(), n_val * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(v_slot, v_slot_h.data(), n_val * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(v_w, v_w_h.data(), n_val * sizeof(float), hipMemcpyHostToDevice, s));
         if ((rc = val_loss(first_val))) return rc;
         best_val = first_val;
     }
@@ -995,18 +1090,18 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         uint64_t mult = n_train == 1 ? 1 : 2654435761ull % n_train;
         while (n_train > 1 && (mult == 0 || gcd(mult, n_train) != 1)) mult = (mult + 1) % n_train;
         const float b1 = 0.9f, b2 = 0.999f;
+        const int blocks = train_blocks(B);
         std::vector<float> lb(B);
         for (int step = 0; step < o->steps; ++step) {
-            hipLaunchKernelGGL(gather_kernel, dim3(nblk(B, 256)), dim3(256), 0, s, F, fa, t_row, t_slot, t_w, n_train,
-                               static_cast<uint64_t>(step) * B, mult, B, tb, wbat);
-            MLMC_HIP_TRY(train_pass(p->prop_P, B, tb, wbat, static_cast<float>(o->shrink), s));
+            const BatchSrc src{t_row, t_slot, t_w, n_train, static_cast<uint64_t>(step) * B, mult};
+            MLMC_HIP_TRY(train_pass(true, p->prop_P, F, p, level, src, B, shrink, part, lossb, s));
             const float c1 = 1.0f - std::pow(b1, static_cast<float>(step + 1));
             const float c2 = 1.0f - std::pow(b2, static_cast<float>(step + 1));
-            hipLaunchKernelGGL(adam_kernel, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, p->prop_P, tb.G, m, v,
-                               static_cast<float>(o->lr), b1, b2, 1e-8f, c1, c2);
+            hipLaunchKernelGGL(grad_sum_kernel<true>, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, part, blocks,
+                               nullptr, p->prop_P, m, v, static_cast<float>(o->lr), b1, b2, 1e-8f, c1, c2);
             MLMC_HIP_TRY(hipGetLastError());
             if (step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0) {
-                MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), tb.lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
+                MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
                 MLMC_HIP_TRY(hipStreamSynchronize(s));
                 double Ls = 0.0;
                 for (float x : lb) Ls += x;

@@ -189,6 +189,19 @@ __device__ __forceinline__ unsigned long long wave_sum_u(unsigned long long v)
     return v;
 }
 
+// Sum over each aligned group of lpr lanes (lpr a power of two <= 64), in a fixed order.
+__device__ __forceinline__ double group_sum(double v, uint32_t lpr)
+{
+    for (uint32_t o = lpr / 2; o > 0; o >>= 1) v += __shfl_xor(v, static_cast<int>(o), kWave);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long group_sum_u(unsigned long long v, uint32_t lpr)
+{
+    for (uint32_t o = lpr / 2; o > 0; o >>= 1) v += __shfl_xor(v, static_cast<int>(o), kWave);
+    return v;
+}
+
 template <typename U>
 __device__ __forceinline__ double load_u(const U *u, uint64_t idx)
 {
@@ -196,8 +209,9 @@ __device__ __forceinline__ double load_u(const U *u, uint64_t idx)
 }
 
 // ------------------------------------------------------------------------------------
-// Lane-refilling walk engine. A wave owns the walks [wb, we) of one row; each lane runs
-// one walk at a time and takes the next unassigned walk as soon as its walk ends. Every
+// Lane-refilling walk engine. A wave (or a group of its lanes) owns the walks [wb, we) of
+// one row; each lane runs one walk at a time and takes the next unassigned walk as soon as
+// its walk ends. Every
 // iteration gives every busy lane exactly one Philox block: the next step block while
 // it scans for the next jump, or the jump block (slot, alias coin, next holding time)
 // while it jumps. The divergent work between the blocks (threshold tests, one alias
@@ -291,19 +305,25 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
     s.chain_word = word;
 }
 
+// The wave's lanes form groups of lpr lanes (lpr a power of two, 1..64); the lanes of a group
+// run the walks [wb, we) of the group's row (row, wb and we are the same within a group).
+// Groups of fewer than 64 lanes serve rows with few walks, so that a wave still has 64
+// walks in flight.
 template <typename R, bool kHash, bool kIS, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
-                                           uint64_t wb, uint64_t we, Sink &sink)
+                                           uint64_t wb, uint64_t we, Sink &sink,
+                                           uint32_t lpr = kWave)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes below
+    const uint64_t group = lpr >= kWave ? ~0ull : ((1ull << lpr) - 1ull) << (lane & ~(lpr - 1u));
     const RowRec start = L.rec[row];
     const R hd = static_cast<R>(L.half_dt);
     Walker<R, kHash> s;
-    uint64_t pool = wb;                    // next unassigned walk (wave-uniform)
+    uint64_t pool = wb;                    // next unassigned walk of the group
     for (;;) {
-        // ---- refill idle lanes with the next walks of the range
-        const uint64_t idle = __ballot(!s.active);
+        // ---- refill idle lanes with the next walks of the group's range
+        const uint64_t idle = __ballot(!s.active) & group;
         if (idle) {
             const uint64_t mine = pool + __popcll(idle & lower);
             if (!s.active && mine < we) {

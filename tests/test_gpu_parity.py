@@ -155,6 +155,17 @@ def test_level_sums_multi_rhs(api, R):
                       values_dtype=np.float32)
 
 
+@pytest.mark.parametrize("precision,M", [("fp64", 1), ("fp32", 5), ("fp64", 8), ("fp32", 17),
+                                         ("fp32", 32), ("fp64", 40), ("fp32", 63)])
+def test_level_sums_few_walks_per_row(api, precision, M):
+    """Items of fewer than 64 walks share a wave (groups of 1..32 lanes per row): sums,
+    jumps and path hashes per row as the oracle's, on rows that do and do not fill a wave."""
+    a = _signed(150, 21, density=0.05, scale=2.0)
+    A = inputs.from_dense(a)
+    u = np.random.default_rng(5).normal(size=150)
+    _check_level_sums(api, A, 0.5, u, precision, 3, M, seed=19, walk0=M * 3)
+
+
 def test_level_sums_full_size_laplace2d_sampled_rows(api):
     """The 256 x 256 workload at its full size, in the launch configuration of the
     benchmark, on 384 sampled rows (FP32 weights, levels 2..7)."""
