@@ -73,7 +73,8 @@ def parse():
     ap.add_argument("--cd-grid", type=int, default=128)
     ap.add_argument("--cd-pilot", type=int, default=32)
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc", "learned"],
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc", "learned",
+                                       "classical"],
                     default="bench",
                     help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
                          "--walks per row), for counter runs; copy: a plain device copy of "
@@ -282,6 +283,64 @@ def learned_bench(args):
     return out
 
 
+def classical_bench(args):
+    """MLMC against classical (single-level) Monte Carlo at the same accuracy, on workload 2
+    restricted to 4096 sampled rows: for each eps, Algorithm 1 gives the finest level L
+    whose bias passes its test; classical MC samples the base estimator at that level alone
+    (a plan with l0 = L) with M = 2 V_L / eps^2 walks per row (the same variance budget
+    eps^2 / 2), V_L from a 1024-walk pilot that is timed with it. Section 4 predicts costs
+    of order eps^-2 for MLMC and eps^-5/2 for classical MC."""
+    import numpy as np
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    A, t, v = inputs.workload_laplace2d(args.grid)
+    rows = np.sort(np.random.default_rng(11).choice(A.n, size=4096, replace=False))
+    u = torch.as_tensor(v.astype(np.float32), device="cuda")
+    ml = api.Plan(A, t, precision="fp32", rows=rows)
+    ml.run(u, eps=1e-2, seed=1, pilot_walks=1024)
+    torch.cuda.synchronize()
+    out = {"workload": f"2D 5-point Laplacian {args.grid}x{args.grid}, 4096 sampled rows, "
+                       f"t=h^2/2, FP32 weights", "targets": []}
+    mc_plans = {}
+    for k, eps in enumerate((1e-2, 3e-3, 1e-3)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x_ml, st = ml.run(u, eps=eps, seed=100 + k, pilot_walks=1024, max_levels=12)
+        torch.cuda.synchronize()
+        t_ml = time.perf_counter() - t0
+        L = st["l0"] + st["num_levels"] - 1
+        if L not in mc_plans:
+            mc_plans[L] = api.Plan(A, t, precision="fp32", rows=rows, l0=L)
+            mc_plans[L].run(u, walks=[64], seed=1)
+        mc = mc_plans[L]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, pst = mc.run(u, walks=[1024], seed=200 + k)
+        M = int(math.ceil(2.0 * pst["level_var"][0] / eps ** 2))
+        x_mc, mst = mc.run(u, walks=[M], seed=300 + k)
+        torch.cuda.synchronize()
+        t_mc = time.perf_counter() - t0
+        d = (x_ml - x_mc).cpu().numpy()[:, 0]
+        out["targets"].append({
+            "eps": eps, "finest_level": L,
+            "mlmc": {"time_s": t_ml, "steps": st["steps"], "walks": st["walks"][:st["num_levels"]],
+                     "est_rmse": math.sqrt(st["est_variance"] + st["est_bias"] ** 2)},
+            "classical": {"time_s": t_mc, "steps": pst["steps"] + mst["steps"], "walks": M,
+                          "est_rmse": math.sqrt(mst["est_variance"])},
+            "classical_over_mlmc_time": t_mc / t_ml,
+            "rms_mlmc_minus_classical": float(np.sqrt(np.mean(d * d))),
+        })
+    ts = out["targets"]
+    le = np.log([t_["eps"] for t_ in ts])
+    for key in ("mlmc", "classical"):
+        out[f"{key}_cost_slope_vs_eps"] = float(np.polyfit(le, np.log([t_[key]["steps"] for t_ in ts]), 1)[0])
+    for p in list(mc_plans.values()) + [ml]:
+        p.close()
+    return out
+
+
 def _init_params(rng):
     """Initial weights of the 16-64-64-7 proposal network (flat, FP32): He-scaled hidden
     layers, a zero output layer (no correction to the value-ratio prior) and the mixing
@@ -362,6 +421,9 @@ def main():
         return tc_bench(args)
     if args.mode == "learned":
         print(json.dumps(learned_bench(args)), flush=True)
+        return
+    if args.mode == "classical":
+        print(json.dumps(classical_bench(args)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "

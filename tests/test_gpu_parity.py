@@ -230,3 +230,36 @@ def test_adaptive_run_reaches_target(api):
     _say(f"adaptive eps={eps}: rmse={rmse:.3e} levels={st['num_levels']} walks={st['walks']}")
     assert rmse < 3 * eps
     plan.close()
+
+
+def test_classical_single_level_mc_estimates_the_finest_strang_product(api):
+    """Classical Monte Carlo is the base estimator at one fine level L: a plan with l0 = L
+    and one level. Its expectation is the Strang product x^L, the same as that of MLMC on
+    l0..L (section 2.2's telescoping sum), checked here against the dense product row by row
+    and against an MLMC run with independent streams."""
+    a = _signed(40, 33, density=0.2, scale=0.5)
+    A = inputs.from_dense(a)
+    beta = 0.6
+    u = np.random.default_rng(8).normal(size=40)
+    ut = torch.as_tensor(u, device="cuda")
+    mlmc_plan = api.Plan(A, beta, precision="fp64")
+    L = mlmc_plan.l0 + 3
+    mc_plan = api.Plan(A, beta, precision="fp64", l0=L)
+    assert mc_plan.l0 == L
+    M = 200_000
+    x_mc, st_mc = mc_plan.run(ut, walks=[M], seed=3)
+    s1, s2, _ = mc_plan.level_sums(ut, L, 0, M, seed=3)
+    mean = s1.cpu().numpy()[:, 0] / M
+    assert np.allclose(mean, x_mc.cpu().numpy()[:, 0], rtol=1e-13, atol=1e-300)
+    se = np.sqrt(np.maximum(s2.cpu().numpy()[:, 0] / M - mean ** 2, 0.0) / M)
+    exact_L = reference.strang_level(a, u, beta, L)
+    z = (mean - exact_L) / se
+    x_ml, st_ml = mlmc_plan.run(ut, walks=[M, M // 4, M // 16, M // 64], seed=4)
+    _say(f"classical MC at level {L}: max |z| {np.abs(z).max():.2f}, mean z^2 {np.mean(z * z):.2f}, "
+         f"steps {st_mc['steps']:.3e}; MLMC steps {st_ml['steps']:.3e}")
+    assert np.abs(z).max() < 5.0 and 0.3 < np.mean(z * z) < 2.0
+    d = mean - x_ml.cpu().numpy()[:, 0]
+    assert np.sqrt(np.mean(d ** 2)) < 5 * np.sqrt(st_mc["est_variance"] + st_ml["est_variance"])
+    assert st_mc["steps"] == M * 40 * (1 << L)
+    mc_plan.close()
+    mlmc_plan.close()
