@@ -67,7 +67,7 @@ def _declare(L):
     L.orc_walk_trace.restype = None
     L.orc_level_sums.argtypes = tables + [ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_uint64, ctypes.c_uint32, _p(ctypes.c_double),
-                                          ctypes.c_int32, ctypes.c_int64, _p(ctypes.c_int64),
+                                          _p(ctypes.c_double), ctypes.c_int32, ctypes.c_int64, _p(ctypes.c_int64),
                                           ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
                                           _p(ctypes.c_double), _p(ctypes.c_double),
                                           _p(ctypes.c_double), _p(ctypes.c_int64),
@@ -274,12 +274,20 @@ class LevelSums:
 
 
 def level_sums(t: Tables, beta: float, level: int, l0: int, seed: int, u, rows=None,
-               walk0: int = 0, M: int = 1, instance: int = 0, threads: int = 0) -> LevelSums:
+               walk0: int = 0, M: int = 1, instance: int = 0, threads: int = 0,
+               F=None) -> LevelSums:
+    """Algorithm 2's per-row sums at one level; with a source vector F (one right-hand side,
+    level >= 1, and levels above l0 need l0 >= 1), Algorithm 3's samples, which add the
+    Simpson sums of the source term to each sample."""
     u = np.asarray(u, dtype=np.float64)
     if u.ndim == 1:
         u = u[:, None]
     u = np.ascontiguousarray(u)
     R = u.shape[1]
+    if F is not None:
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        if R != 1 or F.shape != (t.n,) or level < 1 or (level > l0 and l0 < 1):
+            raise ValueError("source term: one right-hand side, n entries, level >= 1, l0 >= 1")
     rows = np.arange(t.n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
     nr = rows.size
     s1 = np.zeros((nr, R), np.float64)
@@ -289,7 +297,9 @@ def level_sums(t: Tables, beta: float, level: int, l0: int, seed: int, u, rows=N
     jp = np.zeros(nr, np.int64)
     hs = np.zeros(nr, np.uint64)
     lib().orc_level_sums(*t.args(), float(beta), int(level), int(l0), int(seed), int(instance),
-                         _ptr(u, ctypes.c_double), R, nr, _ptr(rows, ctypes.c_int64),
+                         _ptr(u, ctypes.c_double),
+                         ctypes.cast(None, _p(ctypes.c_double)) if F is None else _ptr(F, ctypes.c_double),
+                         R, nr, _ptr(rows, ctypes.c_int64),
                          int(walk0), int(M), _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
                          _ptr(ms, ctypes.c_double), _ptr(ms2, ctypes.c_double),
                          _ptr(jp, ctypes.c_int64), _ptr(hs, ctypes.c_uint64), int(threads))
@@ -333,8 +343,9 @@ class Result:
 
 
 def mlmc_fixed(t: Tables, beta: float, u, l0: int, L: int, M, seed: int, rows=None,
-               instance: int = 0, threads: int = 0) -> Result:
-    """x^L estimate with M[l - l0] walks per row at level l, l = l0..L."""
+               instance: int = 0, threads: int = 0, F=None) -> Result:
+    """x^L estimate with M[l - l0] walks per row at level l, l = l0..L (with a source vector
+    F: Algorithm 3's estimate of exp(beta A) u + int_0^beta exp(sA) F ds)."""
     levels = []
     x = None
     mass = None
@@ -342,7 +353,7 @@ def mlmc_fixed(t: Tables, beta: float, u, l0: int, L: int, M, seed: int, rows=No
     jumps = 0
     for q, lev in enumerate(range(l0, L + 1)):
         Ml = int(M[q]) if np.ndim(M) else int(M)
-        ls = level_sums(t, beta, lev, l0, seed, u, rows, 0, Ml, instance, threads)
+        ls = level_sums(t, beta, lev, l0, seed, u, rows, 0, Ml, instance, threads, F=F)
         st = LevelStats(lev, Ml, ls.sum1, ls.sum2, ls.mass, int(ls.jumps.sum()))
         levels.append(st)
         x = st.mean if x is None else x + st.mean

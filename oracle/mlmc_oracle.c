@@ -246,19 +246,46 @@ typedef struct {
     int64_t jumps;
     uint64_t hash;           /* FNV-1a over (state, step) of every jump */
     double eta_fine, eta_coarse;
+    /* with a source term F (Algorithm 3): the Simpson sums of the fine and coarse
+     * functionals times F along the path, and their absolute magnitude */
+    double integ_fine, integ_coarse, integ_mag;
 } orc_walk_out;
+
+/* Composite Simpson weight of grid point n of an even number K of intervals: 1 at both
+ * ends, 4 at odd points, 2 at even interior points. */
+static double simpson_weight(int64_t n, int64_t K)
+{
+    if (n == 0 || n == K) return 1.0;
+    return (n % 2 != 0) ? 4.0 : 2.0;
+}
 
 #define ORC_FNV_OFFSET 14695981039346656037ull
 #define ORC_FNV_PRIME 1099511628211ull
 
+/* One sample of Algorithm 2 (Algorithm 3 when F is given: the source term's integral
+ * int_0^beta exp(sA) F ds at the walk's row, by the composite Simpson rule on the fine grid
+ * (step dt, N intervals) and, for the coarse functional, on the coarse grid (step 2 dt,
+ * its N/2 intervals at the even fine points); F is read at the path's state at each grid
+ * time). */
 static void orc_one_walk(const orc_tables *t, double beta, int level, const uint32_t key[2],
-                         uint32_t inst, int64_t row, uint32_t walk, orc_walk_out *o)
+                         uint32_t inst, int64_t row, uint32_t walk, const double *F,
+                         orc_walk_out *o)
 {
     const int64_t N = (int64_t)1 << level;
     const double dt = ldexp(beta, -level);
     double eta2 = 1.0, eta1 = 1.0;   /* fine and coarse functionals */
     int64_t j = row, jumps = 0;
     uint64_t h = ORC_FNV_OFFSET;
+    double integ2 = 0.0, integ1 = 0.0, imag2 = 0.0, imag1 = 0.0;
+    if (F) {
+        /* grid point 0: no time elapsed, both functionals are 1 */
+        integ2 += simpson_weight(0, N) * eta2 * F[j];
+        imag2 += simpson_weight(0, N) * fabs(eta2 * F[j]);
+        if (N >= 2) {
+            integ1 += simpson_weight(0, N / 2) * eta1 * F[j];
+            imag1 += simpson_weight(0, N / 2) * fabs(eta1 * F[j]);
+        }
+    }
     for (int64_t n = 1; n <= N; ++n) {
         eta2 = eta2 * exp(t->d[j] * dt / 2.0);
         if (n % 2 != 0) eta1 = eta1 * exp(t->d[j] * dt);
@@ -297,6 +324,15 @@ static void orc_one_walk(const orc_tables *t, double beta, int level, const uint
         }
         eta2 = eta2 * exp(t->d[j] * dt / 2.0);
         if (n % 2 == 0) eta1 = eta1 * exp(t->d[j] * dt);
+        if (F) {
+            /* eta2 is now the fine weight of time n dt, eta1 (at even n) the coarse one */
+            integ2 += simpson_weight(n, N) * eta2 * F[j];
+            imag2 += simpson_weight(n, N) * fabs(eta2 * F[j]);
+            if (n % 2 == 0) {
+                integ1 += simpson_weight(n / 2, N / 2) * eta1 * F[j];
+                imag1 += simpson_weight(n / 2, N / 2) * fabs(eta1 * F[j]);
+            }
+        }
     }
     o->final_state = j;
     o->sign = (eta2 < 0.0) ? -1 : 1;
@@ -304,6 +340,9 @@ static void orc_one_walk(const orc_tables *t, double beta, int level, const uint
     o->hash = h;
     o->eta_fine = eta2;
     o->eta_coarse = eta1;
+    o->integ_fine = dt / 3.0 * integ2;
+    o->integ_coarse = 2.0 * dt / 3.0 * integ1;
+    o->integ_mag = dt / 3.0 * imag2 + 2.0 * dt / 3.0 * imag1;
 }
 
 /* Trace of individual walks: for each (row[q], walk[q]) the final state, sign, jump
@@ -323,7 +362,7 @@ void orc_walk_trace(const double *d, const double *inv_r, const int64_t *slot_be
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t q = 0; q < count; ++q) {
         orc_walk_out o;
-        orc_one_walk(&t, beta, level, key, instance, rows[q], walks[q], &o);
+        orc_one_walk(&t, beta, level, key, instance, rows[q], walks[q], NULL, &o);
         final_state[q] = o.final_state;
         sign[q] = o.sign;
         jumps[q] = o.jumps;
@@ -359,7 +398,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                     const uint32_t *slot_thr, const int32_t *slot_alias, const uint32_t *q_thr,
                     const int32_t *q_alias, const double *q_ratio, double beta,
                     int level, int l0, uint64_t seed, uint32_t instance, const double *u,
-                    int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
+                    const double *F, int32_t R, int64_t n_rows, const int64_t *rows, uint32_t walk0,
                     uint32_t M, double *sum1, double *sum2, double *mass, double *mass2,
                     int64_t *jumps, uint64_t *hash_sum, int32_t nthreads)
 {
@@ -388,7 +427,7 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
             memset(am2, 0, sizeof(orc_sum) * (size_t)R);
             for (uint32_t w = 0; w < M; ++w) {
                 orc_walk_out o;
-                orc_one_walk(&t, beta, level, key, instance, i, walk0 + w, &o);
+                orc_one_walk(&t, beta, level, key, instance, i, walk0 + w, F, &o);
                 nj += o.jumps;
                 hs += o.hash;
                 for (int32_t rr = 0; rr < R; ++rr) {
@@ -400,6 +439,11 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
                     } else {
                         y = uj * o.eta_fine;
                         m = fabs(uj) * fabs(o.eta_fine);
+                    }
+                    if (F) {
+                        /* Algorithm 3: the source term's Simpson sums join the sample */
+                        y += (level > l0) ? o.integ_fine - o.integ_coarse : o.integ_fine;
+                        m += o.integ_mag;
                     }
                     orc_add(&a1[rr], y);
                     orc_add(&a2[rr], y * y);

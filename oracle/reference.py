@@ -51,6 +51,48 @@ def strang_level(a: np.ndarray, u: np.ndarray, beta: float, level: int) -> np.nd
     return strang_operator(a, beta, level) @ np.asarray(u, np.float64)
 
 
+def simpson_weights(K: int) -> np.ndarray:
+    """Composite Simpson weights of the K + 1 points of K (even) intervals: 1, 4, 2, ..., 4, 1."""
+    w = np.where(np.arange(K + 1) % 2 == 1, 4.0, 2.0)
+    w[0] = w[-1] = 1.0
+    return w
+
+
+def source_level(a: np.ndarray, u: np.ndarray, F: np.ndarray, beta: float, level: int) -> np.ndarray:
+    """Expectation of Algorithm 3's fine sample at one level: S^N u + (dt/3) sum_n w_n S^n F,
+    S the Strang step at dt = beta / N (the n-step product is the expectation of the fine
+    functional at time n dt times F at the state then)."""
+    D, T = decomposition(a)
+    N = 1 << level
+    dt = beta / N
+    half = np.diag(np.exp(np.diag(D) * dt / 2.0))
+    S = half @ scipy.linalg.expm(-dt * T) @ half
+    w = simpson_weights(N)
+    acc = np.zeros(len(u))
+    v = np.asarray(F, np.float64).copy()
+    for n in range(N + 1):
+        acc += w[n] * v
+        v = S @ v
+    return np.linalg.matrix_power(S, N) @ np.asarray(u, np.float64) + dt / 3.0 * acc
+
+
+def source_level_means(a, u, F, beta: float, l0: int, L: int):
+    """Exact expectations of Algorithm 3's MLMC terms at levels l0..L."""
+    xs = [source_level(a, u, F, beta, l) for l in range(l0, L + 1)]
+    return [xs[0]] + [xs[q] - xs[q - 1] for q in range(1, len(xs))]
+
+
+def inhomogeneous_exact(a: np.ndarray, u: np.ndarray, F: np.ndarray, beta: float) -> np.ndarray:
+    """exp(beta A) u + int_0^beta exp(sA) F ds, by the augmented-matrix exponential
+    [[A, F], [0, 0]] (Van Loan), no inverse of A needed."""
+    n = a.shape[0]
+    big = np.zeros((n + 1, n + 1))
+    big[:n, :n] = a
+    big[:n, n] = F
+    E = scipy.linalg.expm(beta * big)
+    return E[:n, :n] @ np.asarray(u, np.float64) + E[:n, n]
+
+
 def level_means(a: np.ndarray, u: np.ndarray, beta: float, l0: int, L: int):
     """Exact expectations of the MLMC terms: [x^{l0}, x^{l0+1} - x^{l0}, ...]."""
     xs = [strang_level(a, u, beta, l) for l in range(l0, L + 1)]
