@@ -181,6 +181,23 @@ int mlmc_expv_trace(mlmc_plan_t *plan, uint64_t seed, int32_t instance, int32_t 
                     int64_t *final_state, int32_t *sign, int64_t *jumps, uint64_t *hash,
                     double *log_eta_fine, double *log_eta_coarse, void *stream);
 
+/* Algorithm 3 (section 5): the solution of x' = A x + F, x(0) = u, with F constant in time,
+ *   x(beta) = exp(beta A) u + int_0^beta exp(sA) F ds,
+ * where each walk also carries the composite Simpson sum of the source term over its grid
+ * times (weights 1, 4, 2, ..., 4, 1 times dt/3; F read at the path's state at each grid
+ * time; the coarse functional uses the coarse rule on the even points, so the levels still
+ * telescope). One right-hand side; F: DEVICE, n entries of u_dtype; the plan's l0 must be
+ * >= 1. Otherwise as mlmc_expv_run and mlmc_expv_level_sums (whose sums then hold the
+ * combined samples). */
+int mlmc_expv_run_source(mlmc_plan_t *plan, const void *u, const void *F, int32_t u_dtype,
+                         const mlmc_run_opts_t *opts, double *x, mlmc_stats_t *stats,
+                         void *stream);
+
+int mlmc_expv_level_sums_source(mlmc_plan_t *plan, const void *u, const void *F,
+                                int32_t u_dtype, uint64_t seed, int32_t instance, int32_t level,
+                                uint32_t walk0, uint32_t walks, double *sum1, double *sum2,
+                                int64_t *jumps, uint64_t *hash_sums, void *stream);
+
 void mlmc_expv_destroy(mlmc_plan_t *plan);
 
 /* ---- batched runs ------------------------------------------------------------------

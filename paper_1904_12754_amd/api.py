@@ -70,13 +70,24 @@ class Plan:
         self.info = {f: getattr(info, f) for f, _ in _abi.PlanInfo._fields_}
 
     # ------------------------------------------------------------------------------
+    def _source(self, source, u):
+        if source is None:
+            return None
+        if not source.is_cuda or source.dtype != u.dtype or source.numel() != self.n:
+            raise ValueError("source must be a device vector of n entries with u's dtype")
+        if u.shape[1] != 1:
+            raise ValueError("a source term takes one right-hand side")
+        return source.contiguous()
+
     def run(self, u: torch.Tensor, walks=None, eps: float | None = None, seed: int = 0,
             instance: int = 0, pilot_walks: int = 1024, max_levels: int = 20,
             max_walks: int = 0, out: torch.Tensor | None = None, stream=None,
-            want_stats: bool = True, allow=()):
-        """x = exp(beta A) u at the plan's rows. Fixed schedule: walks[q] walks per row at
+            want_stats: bool = True, allow=(), source: torch.Tensor | None = None):
+        """x = exp(beta A) u at the plan's rows (with a source vector F: Algorithm 3's
+        exp(beta A) u + int_0^beta exp(sA) F ds). Fixed schedule: walks[q] walks per row at
         level l0 + q. Adaptive (Algorithm 1): eps > 0."""
         u, R, dt = _u_args(u, self.n)
+        F = self._source(source, u)
         x = out if out is not None else torch.empty((self.n_rows, R), dtype=torch.float64,
                                                     device=u.device)
         if eps is not None and eps > 0:
@@ -89,27 +100,42 @@ class Plan:
                                 walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0,
                                 0, 0, 0)
         stats = _abi.Stats() if want_stats else None
-        code = self._lib.mlmc_expv_run(self._handle, _dev_ptr(u), R, dt, ctypes.byref(opts),
-                                       _dev_ptr(x), ctypes.byref(stats) if stats else None,
-                                       _stream_ptr(stream))
+        if F is None:
+            code = self._lib.mlmc_expv_run(self._handle, _dev_ptr(u), R, dt, ctypes.byref(opts),
+                                           _dev_ptr(x), ctypes.byref(stats) if stats else None,
+                                           _stream_ptr(stream))
+        else:
+            code = self._lib.mlmc_expv_run_source(self._handle, _dev_ptr(u), _dev_ptr(F), dt,
+                                                  ctypes.byref(opts), _dev_ptr(x),
+                                                  ctypes.byref(stats) if stats else None,
+                                                  _stream_ptr(stream))
         check(code, allow)
         del walks_arr
         return x, (stats.to_dict() if stats else None)
 
     def level_sums(self, u: torch.Tensor, level: int, walk0: int, walks: int, seed: int = 0,
-                   instance: int = 0, stream=None, hashes: bool = False):
-        """Algorithm 2's accumulators at one level: (sum Y, sum Y^2) per (row, rhs), jumps,
-        and with hashes=True the per-row sum (mod 2^64) of the path hashes."""
+                   instance: int = 0, stream=None, hashes: bool = False,
+                   source: torch.Tensor | None = None):
+        """Algorithm 2's accumulators at one level (Algorithm 3's with a source vector):
+        (sum Y, sum Y^2) per (row, rhs), jumps, and with hashes=True the per-row sum
+        (mod 2^64) of the path hashes."""
         u, R, dt = _u_args(u, self.n)
+        F = self._source(source, u)
         s1 = torch.empty((self.n_rows, R), dtype=torch.float64, device=u.device)
         s2 = torch.empty_like(s1)
         hs = torch.empty(self.n_rows, dtype=torch.int64, device=u.device) if hashes else None
         jumps = ctypes.c_int64()
-        check(self._lib.mlmc_expv_level_sums(self._handle, _dev_ptr(u), R, dt, seed, instance,
-                                             level, walk0, walks, _dev_ptr(s1), _dev_ptr(s2),
-                                             ctypes.byref(jumps),
-                                             _dev_ptr(hs) if hashes else None,
-                                             _stream_ptr(stream)))
+        if F is None:
+            check(self._lib.mlmc_expv_level_sums(self._handle, _dev_ptr(u), R, dt, seed, instance,
+                                                 level, walk0, walks, _dev_ptr(s1), _dev_ptr(s2),
+                                                 ctypes.byref(jumps),
+                                                 _dev_ptr(hs) if hashes else None,
+                                                 _stream_ptr(stream)))
+        else:
+            check(self._lib.mlmc_expv_level_sums_source(
+                self._handle, _dev_ptr(u), _dev_ptr(F), dt, seed, instance, level, walk0, walks,
+                _dev_ptr(s1), _dev_ptr(s2), ctypes.byref(jumps),
+                _dev_ptr(hs) if hashes else None, _stream_ptr(stream)))
         if hashes:
             return s1, s2, int(jumps.value), hs
         return s1, s2, int(jumps.value)

@@ -145,6 +145,7 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
     LevelArgs L;
     L.rec = p->level_rec[level];
     L.slots = p->slots;
+    L.src = p->cur_src;
     L.is_slots = (p->proposal_on && level < static_cast<int>(p->is_slots.size())) ? p->is_slots[level]
                                                                                    : nullptr;
     L.n = p->n;
@@ -655,6 +656,49 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     }
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
     return MLMC_OK;
+}
+
+
+// Algorithm 3: the same calls with a source vector F (x' = A x + F, F constant in time).
+namespace {
+
+struct SourceScope {
+    mlmc_plan *p;
+    SourceScope(mlmc_plan *q, const void *F) : p(q) { p->cur_src = F; }
+    ~SourceScope() { p->cur_src = nullptr; }
+};
+
+int check_source(const mlmc_plan *p, const void *F)
+{
+    if (!F && p->n > 0) return fail(MLMC_ERR_INVALID_ARG, "F is null");
+    if (p->l0 < 1)
+        return fail(MLMC_ERR_INVALID_ARG, "a source term needs l0 >= 1 (Simpson's rule needs two intervals on every grid)");
+    return MLMC_OK;
+}
+
+}  // namespace
+
+int mlmc_expv_run_source(mlmc_plan_t *p, const void *u, const void *F, int32_t u_dtype,
+                         const mlmc_run_opts_t *opts, double *x, mlmc_stats_t *stats, void *stream)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    int rc = check_source(p, F);
+    if (rc) return rc;
+    SourceScope scope(p, F);
+    return mlmc_expv_run(p, u, 1, u_dtype, opts, x, stats, stream);
+}
+
+int mlmc_expv_level_sums_source(mlmc_plan_t *p, const void *u, const void *F, int32_t u_dtype,
+                                uint64_t seed, int32_t instance, int32_t level, uint32_t walk0,
+                                uint32_t walks, double *sum1, double *sum2, int64_t *jumps,
+                                uint64_t *hash_sums, void *stream)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    int rc = check_source(p, F);
+    if (rc) return rc;
+    SourceScope scope(p, F);
+    return mlmc_expv_level_sums(p, u, 1, u_dtype, seed, instance, level, walk0, walks, sum1, sum2, jumps,
+                                hash_sums, stream);
 }
 
 }  // extern "C"

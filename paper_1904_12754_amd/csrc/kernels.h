@@ -10,6 +10,7 @@ struct LevelArgs {
     const RowRec *rec;       // the level's row records
     const SlotRec *slots;    // alias tables of all rows
     const SlotRecIS *is_slots;  // the level's proposal tables (used by the proposal kernels)
+    const void *src;         // source vector F of Algorithm 3 (element type of u), or null
     int64_t n;               // rows of A
     uint32_t N;              // steps, 2^level
     int32_t level;

@@ -13,7 +13,7 @@ namespace {
 
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
-template <typename R, typename U, bool kHash, bool kIS>
+template <typename R, typename U, bool kHash, bool kIS, bool kSrc>
 __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
     const uint64_t wb = has ? static_cast<uint64_t>(c) * chunk : 0ull;
     const uint64_t we = has ? min(wb + chunk, static_cast<uint64_t>(M)) : 0ull;
-    SinkR1<R, U> sink{u};
-    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink, lpr);
+    SinkR1<R, U> sink{u, static_cast<const U *>(L.src)};
+    walk_range<R, kHash, kIS, kSrc>(L, row, walk0, wb, we, sink, lpr);
     const double a = group_sum(sink.s1.value(), lpr);
     const double b = group_sum(sink.s2.value(), lpr);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
@@ -289,8 +289,12 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
     const uint32_t nr = static_cast<uint32_t>(n_rows);
 #define MLMC_LAUNCH_WALKS(R, U, H, IS)                                                        \
     do {                                                                                      \
-        if (nrhs == 1)                                                                        \
-            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS>), grid, block, 0, s, L,           \
+        if (nrhs == 1 && L.src)                                                               \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, true>), grid, block, 0, s, L,     \
+                               static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
+                               lpr, partial, counters, hash_sums);                            \
+        else if (nrhs == 1)                                                                   \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false>), grid, block, 0, s, L,    \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
                                lpr, partial, counters, hash_sums);                            \
         else                                                                                  \

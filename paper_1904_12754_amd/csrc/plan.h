@@ -57,6 +57,8 @@ struct mlmc_plan {
     double *prop_xmax = nullptr;             // max |xhat| (1 when zero)
     int32_t prop_levels = 0;                 // levels l0 .. l0 + prop_levels - 1 carry tables
     int32_t prop_identity = 0;               // 1: the tables are the plain ones (ratio 1)
+    // source vector of the current Algorithm 3 call (device, element type of u), else null
+    const void *cur_src = nullptr;
     int64_t bytes = 0;
 };
 

@@ -259,6 +259,7 @@ struct Walker {
     uint32_t chain_k = 0, chain_J = 0, chain_word = 0;
     R ef2 = 0, ec2 = 0, ed2 = 0;
     R wr = 1;                             // likelihood ratio of the path under a proposal
+    R jf = 0, jc = 0;                     // source term: fine and coarse Simpson sums
     uint64_t hash = kFnvOffset;
 };
 
@@ -269,7 +270,55 @@ struct Finished {
     uint32_t jumps;
     R W;               // the sample without its u factor (sign included)
     uint64_t hash;
+    R src;             // the source term's part of the sample (0 without a source)
 };
+
+// ------------------------------------------------------------------------------------
+// Source term (Algorithm 3): int_0^beta exp(sA) F ds by the composite Simpson rule over
+// the walk's grid times, the fine functional on the N intervals of the level and the coarse
+// one on the N/2 intervals of the even points. Within a holding run of grid points a..b at
+// state k the functionals grow by q = e^{d_k dt} per fine step, so a run adds
+//   sign * F_k * eta(a) * sum_n w_n q^{n - a}
+// with w_n = 2 + 2 [n odd] - [n = 0] - [n = N]: geometric series, O(1) per run.
+// ------------------------------------------------------------------------------------
+// sum_{j < L} e^{j x}
+template <typename R>
+__device__ __forceinline__ R geo_sum(uint32_t L, R x)
+{
+    if (L == 0) return static_cast<R>(0);
+    if (x == static_cast<R>(0)) return static_cast<R>(L);
+    return expm1R(static_cast<R>(L) * x) / expm1R(x);
+}
+
+// sum_{n = a}^{b} w_n e^{(n - a) x} for the Simpson weights of K intervals (a <= b <= K)
+template <typename R>
+__device__ __forceinline__ R simpson_run(uint32_t a, uint32_t b, uint32_t K, R x)
+{
+    R s = static_cast<R>(2) * geo_sum<R>(b - a + 1, x);
+    const uint32_t o = a | 1u;                       // first odd point >= a
+    if (o <= b) s += static_cast<R>(2) * ((a & 1u) ? static_cast<R>(1) : expR(x)) *
+                     geo_sum<R>((b - o) / 2 + 1, static_cast<R>(2) * x);
+    if (a == 0) s -= static_cast<R>(1);
+    if (b == K) s -= expR(static_cast<R>(K - a) * x);
+    return s;
+}
+
+// The run a..b at the walker's state: add its fine and coarse Simpson sums. Called before
+// add_run, while ef2 and ec2 hold the exponents of the points before a.
+template <typename R, typename W>
+__device__ __forceinline__ void source_run(W &s, R d, R hd, uint32_t a, uint32_t b, uint32_t N,
+                                           R Fk)
+{
+    const R x = d * (hd + hd);                        // d dt
+    const R sgn = (s.neg ? -s.wr : s.wr) * Fk;
+    const R ea = (a == 0) ? static_cast<R>(1) : expR(hd * (s.ef2 + d));
+    s.jf += sgn * ea * simpson_run<R>(a, b, N, x);
+    const uint32_t e0 = a + (a & 1u), e1 = b - (b & 1u);
+    if (N >= 2 && e0 <= e1) {
+        const R ec = (e0 == 0) ? static_cast<R>(1) : expR(hd * (s.ec2 + d + d));
+        s.jc += sgn * ec * simpson_run<R>(e0 / 2, e1 / 2, N / 2, x + x);
+    }
+}
 
 // Holding time of the current step's chain in the exact FP64 sequence: the step's word at
 // the chain's first state, then the next-holding-time word of each jump J0 .. J1 - 1 at
@@ -309,7 +358,7 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
 // run the walks [wb, we) of the group's row (row, wb and we are the same within a group).
 // Groups of fewer than 64 lanes serve rows with few walks, so that a wave still has 64
 // walks in flight.
-template <typename R, bool kHash, bool kIS, typename Sink>
+template <typename R, bool kHash, bool kIS, bool kSrc = false, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
                                            uint64_t wb, uint64_t we, Sink &sink,
                                            uint32_t lpr = kWave)
@@ -339,6 +388,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 s.bq = 0xFFFFFFFFu;
                 s.ef2 = s.ec2 = s.ed2 = 0;
                 s.wr = 1;
+                s.jf = s.jc = 0;
                 if (kHash) s.hash = kFnvOffset;
             }
             pool += __popcll(idle);
@@ -396,6 +446,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
             if (so.jump) {
                 // the step's holding time at k is below dt: a chain of jumps starts
+                if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, s.n, L.N, sink.source(s.k));
                 add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
                 chain_start(s, so.word);
                 s.jumping = 1;
@@ -413,6 +464,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             if (!finish && (s.n >> 2) == s.bq) {
                 const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
                 if (so.jump) {
+                    if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, s.n, L.N, sink.source(s.k));
                     add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
                     chain_start(s, so.word);
                     s.jumping = 1;
@@ -422,14 +474,20 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             }
         }
 
-        Finished<R> f{0u, 0u, static_cast<R>(0), 0ull};
+        Finished<R> f{0u, 0u, static_cast<R>(0), 0ull, static_cast<R>(0)};
         if (finish) {
+            if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, L.N, L.N, sink.source(s.k));
             add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
             R v = (L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd)) * s.wr;
             f.k = s.k;
             f.jumps = s.J;
             f.W = s.neg ? -v : v;
             f.hash = s.hash;
+            if constexpr (kSrc) {
+                // dt/3 times the fine sum, minus 2 dt/3 times the coarse sum above l0
+                const R third = (hd + hd) / static_cast<R>(3);
+                f.src = L.base ? third * s.jf : third * s.jf - (third + third) * s.jc;
+            }
             s.active = false;
         }
         sink.take(finish, f);
@@ -440,12 +498,14 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
 template <typename R, typename U>
 struct SinkR1 {
     const U *u;
+    const U *F;       // source vector (Algorithm 3), or null
     Kahan<R> s1, s2;
     unsigned long long jumps = 0, nonfinite = 0, hash = 0;
+    __device__ __forceinline__ R source(uint32_t k) const { return static_cast<R>(F[k]); }
     __device__ __forceinline__ void take(bool done, const Finished<R> &f)
     {
         if (!done) return;
-        const R y = f.W * static_cast<R>(u[f.k]);
+        const R y = f.W * static_cast<R>(u[f.k]) + f.src;
         jumps += f.jumps;
         hash += f.hash;
         nonfinite += !isfinite(y);

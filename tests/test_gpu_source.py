@@ -1,0 +1,110 @@
+"""Algorithm 3 on the GPU (the source term of x' = A x + F by Simpson's rule over the walk's
+grid times), through the C-ABI, against the oracle's step-by-step evaluation: the same paths
+(jump counts and path hashes bit-exact) and per-row sums within the plain method's bars; the
+kernel sums each holding run's Simpson terms in closed form. Also: the adaptive solve reaches
+its target against the exact solution, and plans with l0 = 0 are refused."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlmc as orc
+from oracle import reference
+from paper_1904_12754_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_1904_12754_amd import api as _api
+    return _api
+
+
+def _signed(n, seed, density=0.3, scale=1.0):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(n, n)) * (rng.random((n, n)) < density) * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_level_sums_with_source_match_oracle(api, precision):
+    a = _signed(70, 5, density=0.1)
+    A = inputs.from_dense(a)
+    beta = 0.4
+    rng = np.random.default_rng(6)
+    dt = np.float64 if precision == "fp64" else np.float32
+    u = rng.normal(size=70).astype(dt)
+    F = (rng.normal(size=70) + 0.5).astype(dt)
+    plan = api.Plan(A, beta, precision=precision, l0=1)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    ut = torch.as_tensor(u, device="cuda")
+    Ft = torch.as_tensor(F, device="cuda")
+    for lev in range(1, 5):
+        M = 1200 + 37 * lev
+        _say(f"source level sums prec={precision} level={lev} M={M}")
+        s1, s2, jumps, hs = plan.level_sums(ut, lev, 5, M, seed=77, hashes=True, source=Ft)
+        o = orc.level_sums(t, beta, lev, 1, 77, u.astype(np.float64), None, 5, M,
+                           F=F.astype(np.float64))
+        assert jumps == int(o.jumps.sum())
+        assert np.array_equal(hs.cpu().numpy().view(np.uint64), o.hash_sum)
+        g1 = s1.cpu().numpy()
+        assert np.all(np.abs(g1 - o.sum1) <= TOL[precision] * (o.mass + 1e-300))
+        assert np.all(np.abs(s2.cpu().numpy() - o.sum2) <= 4 * TOL[precision] * (o.mass2 + 1e-300))
+        # the source term changes the sums (it is not silently ignored)
+        p1, _, _ = plan.level_sums(ut, lev, 5, M, seed=77)
+        assert not torch.equal(p1, s1)
+    plan.close()
+
+
+def test_fixed_run_with_source_matches_oracle(api):
+    A, t, v = inputs.workload_laplace1d()
+    F = np.cos(np.arange(A.n) / 7.0)
+    plan = api.Plan(A, t, precision="fp64")
+    assert plan.l0 >= 1
+    walks = [6000, 3000, 1500, 800]
+    x, st = plan.run(torch.as_tensor(v, device="cuda"), walks=walks, seed=21,
+                     source=torch.as_tensor(F, device="cuda"))
+    tt = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    res = orc.mlmc_fixed(tt, t, v, plan.l0, plan.l0 + 3, walks, seed=21, F=F)
+    assert st["total_jumps"] == res.jumps
+    xg = x.cpu().numpy()[:, 0]
+    assert np.all(np.abs(xg - res.x[:, 0]) <= 1e-12 * res.mass[:, 0])
+    plan.close()
+
+
+def test_adaptive_run_with_source_reaches_the_exact_solution(api):
+    """exp(tA) v + int_0^t exp(sA) F ds on the 1D Laplacian (t scaled so that the source
+    term matters), Algorithm 1 to eps, against the augmented-matrix exponential."""
+    A, _, v = inputs.workload_laplace1d()
+    t = 2.0 / A.norm1()
+    F = 0.5 / t * (1.0 + np.sin(np.pi * np.arange(1, A.n + 1) / (A.n + 1)))
+    exact = reference.inhomogeneous_exact(A.to_dense(), v, F, t)
+    plan = api.Plan(A, t, precision="fp32")
+    eps = 2e-3
+    x, st = plan.run(torch.as_tensor(v, dtype=torch.float32, device="cuda"), eps=eps, seed=9,
+                     pilot_walks=2048, source=torch.as_tensor(F, dtype=torch.float32, device="cuda"))
+    rmse = float(np.sqrt(np.mean((x.cpu().numpy()[:, 0] - exact) ** 2)))
+    src_part = reference.inhomogeneous_exact(A.to_dense(), np.zeros(A.n), F, t)
+    _say(f"source run: levels {st['num_levels']}, walks {st['walks'][:st['num_levels']]}, "
+         f"rmse {rmse:.2e} (eps {eps}), |source part| {np.abs(src_part).max():.3f}")
+    assert np.abs(src_part).max() > 0.5
+    assert rmse < 2.0 * eps
+    plan.close()
+
+
+def test_source_needs_l0_of_at_least_one(api):
+    A = inputs.from_dense(np.diag([-1.0, 0.5]))
+    plan = api.Plan(A, 0.2, precision="fp64", l0=0)
+    u = torch.ones(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception, match="l0 >= 1"):
+        plan.run(u, walks=[8, 8], seed=1, source=u)
+    plan.close()
