@@ -73,6 +73,12 @@ def _declare(L):
                                           _p(ctypes.c_double), _p(ctypes.c_int64),
                                           _p(ctypes.c_uint64), ctypes.c_int32]
     L.orc_level_sums.restype = None
+    L.orc_functional_sums.argtypes = tables[:8] + [
+        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+        ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_int32), _p(ctypes.c_uint8),
+        _p(ctypes.c_double), ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
+        _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_uint64)]
+    L.orc_functional_sums.restype = None
     L.orc_log_array.argtypes = [ctypes.c_int64, _p(ctypes.c_double), _p(ctypes.c_double)]
     L.orc_log_array.restype = None
     L.orc_philox_array.argtypes = [ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_uint32),
@@ -456,3 +462,60 @@ def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | No
     res = Result(x, levels, l0, mass, steps, sum(st.jumps for st in levels))
     res.converged = converged
     return res
+
+
+# ----------------------------------------------------------------------------------
+# scalar functional (w, exp(beta A) u) by walks from random start rows
+# ----------------------------------------------------------------------------------
+def start_tables(u):
+    """Alias table over rows for the start law |u_l| / U (the construction of the slot
+    tables, on one 'row' of n entries), the sign of u per row, and U."""
+    u = np.asarray(u, np.float64)
+    n = u.size
+    U = float(np.abs(u).sum())
+    one = Tables(1, None, None, None, np.array([0, n], np.int64), np.array([n], np.int32),
+                 None, None, None, None)
+    thr, alias = alias_tables(one, np.abs(u) / U)
+    return thr, alias, (u < 0).astype(np.uint8), U
+
+
+@dataclass
+class FunctionalSums:
+    sum1: float
+    sum2: float
+    jumps: int
+    hash_sum: int
+    walks: int
+    U: float
+
+
+def functional_sums(tT: Tables, beta: float, level: int, l0: int, seed: int, u, w,
+                    walk0: int = 0, M: int = 1, instance: int = 0) -> FunctionalSums:
+    """Sums of the samples sign(u_l) w_j (eta_f - eta_c) over walks walk0..walk0+M-1 on the
+    tables tT of A^T; the functional's level term is U sum1 / M."""
+    thr, alias, neg, U = start_tables(u)
+    w = np.ascontiguousarray(w, np.float64)
+    s1 = np.zeros(1)
+    s2 = np.zeros(1)
+    jp = np.zeros(1, np.int64)
+    hs = np.zeros(1, np.uint64)
+    lib().orc_functional_sums(*tT.args()[:8], float(beta), int(level), int(l0), int(seed),
+                              int(instance), int(tT.n), _ptr(thr, ctypes.c_uint32),
+                              _ptr(alias, ctypes.c_int32), _ptr(neg, ctypes.c_uint8),
+                              _ptr(w, ctypes.c_double), int(walk0), int(M),
+                              _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
+                              _ptr(jp, ctypes.c_int64), _ptr(hs, ctypes.c_uint64))
+    return FunctionalSums(float(s1[0]), float(s2[0]), int(jp[0]), int(hs[0]), int(M), U)
+
+
+def functional_fixed(tT: Tables, beta: float, u, w, l0: int, L: int, M, seed: int,
+                     instance: int = 0):
+    """(w, exp(beta A) u) with M[q] walks at level l0 + q: (estimate, variance of it)."""
+    est = var = 0.0
+    for q, lev in enumerate(range(l0, L + 1)):
+        fs = functional_sums(tT, beta, lev, l0, seed, u, w, 0, int(M[q]), instance)
+        m = fs.sum1 / fs.walks
+        v = max(fs.sum2 / fs.walks - m * m, 0.0)
+        est += fs.U * m
+        var += fs.U ** 2 * v / fs.walks
+    return est, var

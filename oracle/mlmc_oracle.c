@@ -464,6 +464,52 @@ void orc_level_sums(const double *d, const double *inv_r, const int64_t *slot_be
     }
 }
 
+/* ------------------------------------------------------------------------------ */
+/* Scalar functional (w, exp(beta A) u) by walks started at random rows (the        */
+/* full-vector representation of section 2.1, summed against w): walk m draws its    */
+/* start row l with probability |u_l| / U (U = sum |u_l|) from the alias table over   */
+/* rows (start_thr, start_alias) with the words of the block (0, m, 0, stream 2),     */
+/* then runs as the walk m of row l on the tables of A^T (jump law of column l of A); */
+/* its sample is sign(u_l) w_j eta (eta_fine - eta_coarse above l0), times U outside. */
+/* Outputs: the sums of the samples and of their squares (Neumaier), jumps, and the   */
+/* sum (mod 2^64) of the path hashes.                                                */
+/* ------------------------------------------------------------------------------ */
+void orc_functional_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
+                         const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
+                         const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                         int level, int l0, uint64_t seed, uint32_t instance, int64_t n,
+                         const uint32_t *start_thr, const int32_t *start_alias,
+                         const uint8_t *start_neg, const double *w, uint32_t walk0, uint32_t M,
+                         double *sum1, double *sum2, int64_t *jumps, uint64_t *hash_sum)
+{
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr,
+                    NULL, NULL, NULL};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_sum a1 = {0, 0}, a2 = {0, 0};
+    int64_t nj = 0;
+    uint64_t hs = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        const uint32_t walk = walk0 + m;
+        uint32_t ctr[4] = {0u, walk, 0u, c3_of(level, instance, 2)};
+        uint32_t out[4];
+        orc_philox4x32_10(ctr, key, out);
+        uint32_t slot = (uint32_t)(((uint64_t)out[0] * (uint64_t)n) >> 32);
+        uint32_t l = (out[1] < start_thr[slot]) ? slot : (uint32_t)start_alias[slot];
+        orc_walk_out o;
+        orc_one_walk(&t, beta, level, key, instance, (int64_t)l, walk, NULL, &o);
+        double y = w[o.final_state] * ((level > l0) ? (o.eta_fine - o.eta_coarse) : o.eta_fine);
+        if (start_neg[l]) y = -y;
+        orc_add(&a1, y);
+        orc_add(&a2, y * y);
+        nj += o.jumps;
+        hs += o.hash;
+    }
+    *sum1 = a1.s + a1.c;
+    *sum2 = a2.s + a2.c;
+    *jumps = nj;
+    *hash_sum = hs;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP
