@@ -198,6 +198,34 @@ int mlmc_expv_level_sums_source(mlmc_plan_t *plan, const void *u, const void *F,
                                 uint32_t walk0, uint32_t walks, double *sum1, double *sum2,
                                 int64_t *jumps, uint64_t *hash_sums, void *stream);
 
+/* Scalar functional (w, exp(beta A) u) by walks from random start rows (the full-vector
+ * representation of section 2.1, summed against w). Walk m starts at row l with probability
+ * |u_l| / U (U = sum of |u_l| in row order; the start row is drawn from an alias table over
+ * rows, built like the slot tables, with the words of the Philox block (0, m, 0, stream 2))
+ * and runs as walk m of row l on the plan's tables; its sample is
+ *   U sign(u_l) w_j eta_fine                  at l0,
+ *   U sign(u_l) w_j (eta_fine - eta_coarse)   above l0        (j the final state).
+ * The plan must be built on A^T (the transposed generator); for a symmetric A, such as a
+ * network's adjacency matrix, the plan of A serves, and u = w = 1 gives the total
+ * communicability (1, exp(beta A) 1). u, w: DEVICE, n entries of dtype.
+ * mlmc_expv_functional: fixed schedule (opts->walks[q] = total walks at level l0 + q) or
+ *   Algorithm 1 on the scalar's variance (opts->eps > 0; pilot_walks total walks per level).
+ *   result, variance: HOST (variance nullable: the estimator's variance). stats: per level
+ *   the total walks, jumps, |level mean|, per-walk variance of U * sample, cost.
+ * mlmc_expv_functional_level_sums: walks walk0 .. walk0 + walks - 1 of one level; HOST
+ *   outputs: the sums of sign(u_l) w_j (eta_f - eta_c) (without U) and of their squares,
+ *   jumps and the sum (mod 2^64) of the path hashes (nullable), and U (nullable).
+ * Both wait for the stream. */
+int mlmc_expv_functional(mlmc_plan_t *plan, const void *u, const void *w, int32_t dtype,
+                         const mlmc_run_opts_t *opts, double *result, double *variance,
+                         mlmc_stats_t *stats, void *stream);
+
+int mlmc_expv_functional_level_sums(mlmc_plan_t *plan, const void *u, const void *w,
+                                    int32_t dtype, uint64_t seed, int32_t instance,
+                                    int32_t level, uint32_t walk0, uint32_t walks, double *sum1,
+                                    double *sum2, int64_t *jumps, uint64_t *hash_sum, double *U,
+                                    void *stream);
+
 void mlmc_expv_destroy(mlmc_plan_t *plan);
 
 /* ---- batched runs ------------------------------------------------------------------

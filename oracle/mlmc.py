@@ -472,7 +472,7 @@ def start_tables(u):
     tables, on one 'row' of n entries), the sign of u per row, and U."""
     u = np.asarray(u, np.float64)
     n = u.size
-    U = float(np.abs(u).sum())
+    U = float(np.cumsum(np.abs(u))[-1]) if n else 0.0      # summed in row order
     one = Tables(1, None, None, None, np.array([0, n], np.int64), np.array([n], np.int32),
                  None, None, None, None)
     thr, alias = alias_tables(one, np.abs(u) / U)

@@ -28,7 +28,8 @@ MLMC_MAX_LEVELS = 40
 
 # every symbol the header declares
 EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_level_sums",
-           "mlmc_expv_run_source", "mlmc_expv_level_sums_source",
+           "mlmc_expv_run_source", "mlmc_expv_level_sums_source", "mlmc_expv_functional",
+           "mlmc_expv_functional_level_sums",
            "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_expv_batch_create",
            "mlmc_expv_batch_launch", "mlmc_expv_batch_stats", "mlmc_expv_batch_info",
            "mlmc_expv_batch_destroy", "mlmc_expv_proposal_set", "mlmc_expv_proposal_enable",
@@ -185,6 +186,15 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_level_sums_source.argtypes = [vp, vp, vp, i32, u64, i32, i32, u32, u32, vp, vp,
                                               ctypes.POINTER(i64), vp, vp]
     L.mlmc_expv_level_sums_source.restype = ctypes.c_int
+    L.mlmc_expv_functional.argtypes = [vp, vp, vp, i32, ctypes.POINTER(RunOpts),
+                                        ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                        ctypes.POINTER(Stats), vp]
+    L.mlmc_expv_functional.restype = ctypes.c_int
+    L.mlmc_expv_functional_level_sums.argtypes = [vp, vp, vp, i32, u64, i32, i32, u32, u32,
+                                                   ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                                   ctypes.POINTER(i64), ctypes.POINTER(u64),
+                                                   ctypes.POINTER(f64), vp]
+    L.mlmc_expv_functional_level_sums.restype = ctypes.c_int
     L.mlmc_expv_trace.argtypes = [vp, u64, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.mlmc_expv_trace.restype = ctypes.c_int
     L.mlmc_expv_destroy.argtypes = [vp]

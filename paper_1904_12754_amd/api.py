@@ -166,6 +166,53 @@ class Plan:
                                         _stream_ptr(stream)))
         return out
 
+    # ---- scalar functional (w, exp(beta A) u) by walks from random start rows ----------
+    def _uw(self, u, w):
+        if not (u.is_cuda and w.is_cuda) or u.dtype != w.dtype or u.dtype not in (torch.float32, torch.float64):
+            raise ValueError("u and w must be device vectors of one float dtype")
+        if u.numel() != self.n or w.numel() != self.n:
+            raise ValueError("u and w must have n entries")
+        dt = _abi.MLMC_DTYPE_F64 if u.dtype == torch.float64 else _abi.MLMC_DTYPE_F32
+        return u.contiguous(), w.contiguous(), dt
+
+    def functional(self, u: torch.Tensor, w: torch.Tensor, walks=None, eps: float | None = None,
+                   seed: int = 0, instance: int = 0, pilot_walks: int = 1 << 16,
+                   max_levels: int = 20, max_walks: int = 0, stream=None, allow=()):
+        """(w, exp(beta A) u) with the plan built on A^T (on A when A is symmetric): walks[q]
+        total walks at level l0 + q, or Algorithm 1 to eps. Returns (value, variance, stats)."""
+        u, w, dt = self._uw(u, w)
+        if eps is not None and eps > 0:
+            opts = _abi.RunOpts(seed, instance, 0, None, float(eps), int(pilot_walks),
+                                int(max_levels), int(max_walks))
+            walks_arr = None
+        else:
+            walks_arr = np.ascontiguousarray(walks, dtype=np.int64)
+            opts = _abi.RunOpts(seed, instance, int(walks_arr.size),
+                                walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0,
+                                0, 0, 0)
+        res = ctypes.c_double()
+        var = ctypes.c_double()
+        st = _abi.Stats()
+        check(self._lib.mlmc_expv_functional(self._handle, _dev_ptr(u), _dev_ptr(w), dt,
+                                             ctypes.byref(opts), ctypes.byref(res),
+                                             ctypes.byref(var), ctypes.byref(st),
+                                             _stream_ptr(stream)), allow)
+        del walks_arr
+        return float(res.value), float(var.value), st.to_dict()
+
+    def functional_level_sums(self, u: torch.Tensor, w: torch.Tensor, level: int, walk0: int,
+                              walks: int, seed: int = 0, instance: int = 0, stream=None):
+        """(sum of samples without U, sum of squares, jumps, hash sum, U) of one level."""
+        u, w, dt = self._uw(u, w)
+        s1, s2, U = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        j = ctypes.c_int64()
+        h = ctypes.c_uint64()
+        check(self._lib.mlmc_expv_functional_level_sums(
+            self._handle, _dev_ptr(u), _dev_ptr(w), dt, seed, instance, level, walk0, walks,
+            ctypes.byref(s1), ctypes.byref(s2), ctypes.byref(j), ctypes.byref(h), ctypes.byref(U),
+            _stream_ptr(stream)))
+        return float(s1.value), float(s2.value), int(j.value), int(h.value), float(U.value)
+
     # ---- learned proposal (importance sampling of the jump law) -----------------------
     @staticmethod
     def _params(params):

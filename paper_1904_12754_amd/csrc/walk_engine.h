@@ -248,6 +248,7 @@ struct Walker {
     // per-lane state of the current walk
     bool active = false;
     uint32_t w = 0, k = 0, neg = 0, J = 0, run_start = 0, n = 0;
+    uint32_t row0 = 0;                    // the walk's start row (its counters' row)
     uint32_t jumping = 0;                 // 1 while a jump of step n is pending
     uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
     uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
@@ -358,15 +359,60 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
 // run the walks [wb, we) of the group's row (row, wb and we are the same within a group).
 // Groups of fewer than 64 lanes serve rows with few walks, so that a wave still has 64
 // walks in flight.
+// Start of a walk: every walk of the range starts at one row (the backward representation
+// of a single entry) ...
+struct FixedStart {
+    uint32_t row;
+    RowRec rec;
+    __device__ __forceinline__ void pick(const LevelArgs &, uint32_t, uint32_t &r, RowRec &rr,
+                                         uint32_t &neg) const
+    {
+        r = row;
+        rr = rec;
+        neg = 0;
+    }
+};
+
+// ... or walk m starts at row l with probability |u_l| / U, drawn from the alias table over
+// rows with the words of the block (0, m, 0, stream 2); the walk then carries sign(u_l).
+struct AliasStart {
+    const uint32_t *thr;
+    const int32_t *alias;
+    const uint8_t *neg;
+    uint32_t n;
+    uint32_t c3;                         // stream word of the start draws
+    __device__ __forceinline__ void pick(const LevelArgs &L, uint32_t walk, uint32_t &r,
+                                         RowRec &rr, uint32_t &ng) const
+    {
+        const Word4 ph = philox10(Word4{0u, walk, 0u, c3}, L.k0, L.k1);
+        const uint32_t slot = mulhi32(ph.x, n);
+        r = (ph.y < thr[slot]) ? slot : static_cast<uint32_t>(alias[slot]);
+        rr = L.rec[r];
+        ng = neg[r];
+    }
+};
+
+template <typename R, bool kHash, bool kIS, bool kSrc, typename Sink, typename Start>
+__device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
+                                                uint64_t wb, uint64_t we, Sink &sink,
+                                                uint32_t lpr = kWave);
+
 template <typename R, bool kHash, bool kIS, bool kSrc = false, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
                                            uint64_t wb, uint64_t we, Sink &sink,
                                            uint32_t lpr = kWave)
 {
+    const FixedStart st{row, L.rec[row]};
+    walk_range_from<R, kHash, kIS, kSrc>(L, st, walk0, wb, we, sink, lpr);
+}
+
+template <typename R, bool kHash, bool kIS, bool kSrc, typename Sink, typename Start>
+__device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
+                                                uint64_t wb, uint64_t we, Sink &sink, uint32_t lpr)
+{
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes below
     const uint64_t group = lpr >= kWave ? ~0ull : ((1ull << lpr) - 1ull) << (lane & ~(lpr - 1u));
-    const RowRec start = L.rec[row];
     const R hd = static_cast<R>(L.half_dt);
     Walker<R, kHash> s;
     uint64_t pool = wb;                    // next unassigned walk of the group
@@ -378,9 +424,11 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
             if (!s.active && mine < we) {
                 s.active = true;
                 s.w = walk0 + static_cast<uint32_t>(mine);
-                s.k = row;
-                s.cur = start;
-                s.neg = 0;
+                uint32_t r0 = 0, ng = 0;
+                st.pick(L, s.w, r0, s.cur, ng);
+                s.row0 = r0;
+                s.k = r0;
+                s.neg = ng;
                 s.J = 0;
                 s.run_start = 0;
                 s.n = 0;
@@ -401,7 +449,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
         const uint32_t q = s.n >> 2;
         Word4 ph{0u, 0u, 0u, 0u};
         if (jumping || (scanning && s.bq != q))
-            ph = philox10(Word4{jumping ? s.J : q, s.w, row, jumping ? L.c3_jump : L.c3_step},
+            ph = philox10(Word4{jumping ? s.J : q, s.w, s.row0, jumping ? L.c3_jump : L.c3_step},
                           L.k0, L.k1);
 
         bool finish = false;
@@ -431,7 +479,7 @@ __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uin
                 const double lo = static_cast<double>(s.tau_h) - static_cast<double>(s.tau_e);
                 if (hi < L.dt) chain_over = false;
                 else if (lo >= L.dt) chain_over = true;
-                else chain_over = !(chain_tau_exact<kIS>(L, row, s.w, s.chain_k, s.chain_J, s.J,
+                else chain_over = !(chain_tau_exact<kIS>(L, s.row0, s.w, s.chain_k, s.chain_J, s.J,
                                                          s.chain_word) < L.dt);
             }
         } else if (scanning) {
