@@ -193,12 +193,27 @@ def tc_bench(args):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
     tc = float(x[:, 0].sum().item())
+    sd_back = math.sqrt(st["est_variance"] * A.n)
+    # the same quantity by the forward scalar representation: walks from uniformly drawn
+    # start rows, Algorithm 1 to the backward run's standard deviation
+    ones = torch.ones(A.n, dtype=torch.float32, device="cuda")
+    plan.functional(ones, ones, walks=[1 << 16] * 5, seed=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tc_f, var_f, st_f = plan.functional(ones, ones, eps=sd_back, seed=3, pilot_walks=1 << 16)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
     print(json.dumps({
         "metric": "walk steps/s", "value": st["steps"] / el, "unit": "steps/s",
         "ms_per_run": el * 1e3, "walk_kernel_ms": st["walk_kernel_ms"],
         "rhs_samples_per_s": st["steps"] * u.shape[1] / el,
         "jumps": st["total_jumps"], "steps": st["steps"],
         "total_communicability_estimate": tc,
+        "total_communicability_sd": sd_back,
+        "forward_scalar": {"estimate": tc_f, "sd": math.sqrt(var_f), "seconds": t_f,
+                           "walks": st_f["walks"][:st_f["num_levels"]],
+                           "steps": st_f["steps"],
+                           "note": "Algorithm 1 on the scalar to the backward run's sd"},
         "config": {"workload": f"Barabasi-Albert n={A.n} m=5, beta=1/d_max={beta:.3e}, "
                                f"{u.shape[1]} right-hand sides (ones + Rademacher), "
                                f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level",
