@@ -274,6 +274,45 @@ struct Finished {
     R src;             // the source term's part of the sample (0 without a source)
 };
 
+// A finished walk waiting for its evaluation: the final state, the sign, the exponents of
+// the sample (2 E_f / dt at the base level, 2 E_c / dt and 2 (E_f - E_c) / dt above), the
+// likelihood ratio, and what the counters need.
+constexpr int kFlushAt = 48;
+
+template <typename R, bool kSrc>
+struct Pending {
+    bool valid = false;
+    uint32_t k = 0, neg = 0, jumps = 0;
+    R e1 = 0, e2 = 0, wr = 1;
+    R src = 0;                            // the source term's part (Algorithm 3)
+    uint64_t hash = 0;
+    template <typename W>
+    __device__ __forceinline__ void hold(const W &s, int base, R hd)
+    {
+        valid = true;
+        k = s.k;
+        neg = s.neg;
+        jumps = s.J;
+        wr = s.wr;
+        hash = s.hash;
+        e1 = base ? s.ef2 : s.ec2;
+        e2 = s.ed2;
+        if constexpr (kSrc) {
+            // dt/3 times the fine sum, minus 2 dt/3 times the coarse sum above l0
+            const R third = (hd + hd) / static_cast<R>(3);
+            src = base ? third * s.jf : third * s.jf - (third + third) * s.jc;
+        }
+    }
+    __device__ __forceinline__ Finished<R> finished(int base, R hd) const
+    {
+        Finished<R> f{k, jumps, static_cast<R>(0), hash, static_cast<R>(0)};
+        const R v = (base ? expR(e1 * hd) : expR(e1 * hd) * expm1R(e2 * hd)) * wr;
+        f.W = neg ? -v : v;
+        if constexpr (kSrc) f.src = src;
+        return f;
+    }
+};
+
 // ------------------------------------------------------------------------------------
 // Source term (Algorithm 3): int_0^beta exp(sA) F ds by the composite Simpson rule over
 // the walk's grid times, the fine functional on the N intervals of the level and the coarse
@@ -415,6 +454,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
     const uint64_t group = lpr >= kWave ? ~0ull : ((1ull << lpr) - 1ull) << (lane & ~(lpr - 1u));
     const R hd = static_cast<R>(L.half_dt);
     Walker<R, kHash> s;
+    Pending<R, kSrc> pend;
     uint64_t pool = wb;                    // next unassigned walk of the group
     for (;;) {
         // ---- refill idle lanes with the next walks of the group's range
@@ -453,7 +493,6 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                           L.k0, L.k1);
 
         bool finish = false;
-        bool chain_over = false;
         if (jumping) {
             // jump from k by the alias table of row k: slot, coin, then the new state's record
             const uint32_t slot = mulhi32(ph.x, s.cur.deg);
@@ -469,6 +508,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
             // add the holding time at the new state; the chain goes on while the total is
             // below dt (an absorbing state holds forever)
             const float ir = static_cast<float>(s.cur.inv_r);
+            bool chain_over;
             if (!(ir < INFINITY)) {
                 chain_over = true;
             } else {
@@ -482,15 +522,25 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 else chain_over = !(chain_tau_exact<kIS>(L, s.row0, s.w, s.chain_k, s.chain_J, s.J,
                                                          s.chain_word) < L.dt);
             }
-        } else if (scanning) {
-            if (s.bq != q) {
-                const bool short_walk = L.N < 4;   // levels 0, 1: words past step N never jump
-                s.b0 = ph.x;
-                s.b1 = (short_walk && L.N < 2) ? 0u : ph.y;
-                s.b2 = short_walk ? 0u : ph.z;
-                s.b3 = short_walk ? 0u : ph.w;
-                s.bq = q;
+            if (chain_over) {
+                // the chain of step n ends: the walk scans on from step n + 1 (below, in
+                // this iteration when that step is in the cached block)
+                s.jumping = 0;
+                s.n = s.n + 1;
+                s.run_start = s.n;
+                finish = s.n == L.N;
             }
+        } else if (scanning && s.bq != q) {
+            const bool short_walk = L.N < 4;   // levels 0, 1: words past step N never jump
+            s.b0 = ph.x;
+            s.b1 = (short_walk && L.N < 2) ? 0u : ph.y;
+            s.b2 = short_walk ? 0u : ph.z;
+            s.b3 = short_walk ? 0u : ph.w;
+            s.bq = q;
+        }
+        // scan the cached block: the lanes that were scanning, and the lanes whose chain
+        // just ended inside the cached block (one code path for both)
+        if (s.active && !s.jumping && !finish && (s.n >> 2) == s.bq) {
             const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
             if (so.jump) {
                 // the step's holding time at k is below dt: a chain of jumps starts
@@ -503,43 +553,21 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
             }
         }
 
-        if (chain_over) {
-            // the chain of step n ends: scan on from step n + 1 in the cached block
-            s.jumping = 0;
-            s.n = s.n + 1;
-            s.run_start = s.n;
-            finish = s.n == L.N;
-            if (!finish && (s.n >> 2) == s.bq) {
-                const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
-                if (so.jump) {
-                    if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, s.n, L.N, sink.source(s.k));
-                    add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                    chain_start(s, so.word);
-                    s.jumping = 1;
-                } else {
-                    finish = s.n == L.N;
-                }
-            }
+        // ---- the end of a walk: its exponents wait in the lane's slot, and the slots are
+        // evaluated together (exp, expm1, the sink) when kFlushAt lanes hold one, when a
+        // lane ends a walk while its slot is full, or after the last walk
+        if (__ballot(finish && pend.valid) != 0 || __popcll(__ballot(pend.valid)) >= kFlushAt) {
+            sink.take(pend.valid, pend.finished(L.base, hd));
+            pend.valid = false;
         }
-
-        Finished<R> f{0u, 0u, static_cast<R>(0), 0ull, static_cast<R>(0)};
         if (finish) {
             if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, L.N, L.N, sink.source(s.k));
             add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
-            R v = (L.base ? expR(s.ef2 * hd) : expR(s.ec2 * hd) * expm1R(s.ed2 * hd)) * s.wr;
-            f.k = s.k;
-            f.jumps = s.J;
-            f.W = s.neg ? -v : v;
-            f.hash = s.hash;
-            if constexpr (kSrc) {
-                // dt/3 times the fine sum, minus 2 dt/3 times the coarse sum above l0
-                const R third = (hd + hd) / static_cast<R>(3);
-                f.src = L.base ? third * s.jf : third * s.jf - (third + third) * s.jc;
-            }
+            pend.hold(s, L.base, hd);
             s.active = false;
         }
-        sink.take(finish, f);
     }
+    sink.take(pend.valid, pend.finished(L.base, hd));
 }
 
 // Single right-hand side: each lane adds its own samples to compensated sums.
