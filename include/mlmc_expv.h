@@ -207,7 +207,8 @@ int mlmc_expv_level_sums_source(mlmc_plan_t *plan, const void *u, const void *F,
  *   U sign(u_l) w_j (eta_fine - eta_coarse)   above l0        (j the final state).
  * The plan must be built on A^T (the transposed generator); for a symmetric A, such as a
  * network's adjacency matrix, the plan of A serves, and u = w = 1 gives the total
- * communicability (1, exp(beta A) 1). u, w: DEVICE, n entries of dtype.
+ * communicability (1, exp(beta A) 1). u, w: DEVICE, n entries of dtype. The walks use the
+ * plain jump law (a proposal set on the plan is not used here).
  * mlmc_expv_functional: fixed schedule (opts->walks[q] = total walks at level l0 + q) or
  *   Algorithm 1 on the scalar's variance (opts->eps > 0; pilot_walks total walks per level).
  *   result, variance: HOST (variance nullable: the estimator's variance). stats: per level

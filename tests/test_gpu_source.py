@@ -108,3 +108,37 @@ def test_source_needs_l0_of_at_least_one(api):
     with pytest.raises(Exception, match="l0 >= 1"):
         plan.run(u, walks=[8, 8], seed=1, source=u)
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_source_under_a_proposal_matches_oracle(api, precision):
+    """Algorithm 3 with the jumps drawn from a learned proposal: the likelihood ratios weigh
+    the source term's Simpson sums as they weigh the functionals (oracle fed the device's
+    exported tables; paths bit-exact, sums within the bars)."""
+    from oracle import proposal as prop
+    A = inputs.convection_diffusion_3d(6, 3)
+    beta = 4.0 / A.norm1()
+    rng = np.random.default_rng(14)
+    dt = np.float64 if precision == "fp64" else np.float32
+    u = rng.normal(size=A.n).astype(dt)
+    F = (rng.normal(size=A.n) + 1.0).astype(dt)
+    plan = api.Plan(A, beta, precision=precision)
+    assert plan.l0 >= 1
+    P = prop.init_params(21)
+    P["W3"] *= 20.0
+    P["b3"][prop.NS] = 1.0
+    xhat = np.abs(rng.normal(size=A.n))
+    plan.set_proposal(prop.flatten(P).astype(np.float32), xhat, num_levels=3)
+    t = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    ut = torch.as_tensor(u, device="cuda")
+    Ft = torch.as_tensor(F, device="cuda")
+    for lev in range(plan.l0, plan.l0 + 3):
+        thr, alias, ratio, q = plan.proposal_tables(lev)
+        ti = t.with_proposal(thr, alias, ratio.astype(np.float64))
+        s1, s2, jumps, hs = plan.level_sums(ut, lev, 0, 900, seed=5, hashes=True, source=Ft)
+        o = orc.level_sums(ti, beta, lev, plan.l0, 5, u.astype(np.float64), None, 0, 900,
+                           F=F.astype(np.float64))
+        assert jumps == int(o.jumps.sum())
+        assert np.array_equal(hs.cpu().numpy().view(np.uint64), o.hash_sum)
+        assert np.all(np.abs(s1.cpu().numpy() - o.sum1) <= TOL[precision] * (o.mass + 1e-300))
+    plan.close()
