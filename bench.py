@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--cd-pilot", type=int, default=32)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc", "learned",
-                                       "classical"],
+                                       "classical", "config1"],
                     default="bench",
                     help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
                          "--walks per row), for counter runs; copy: a plain device copy of "
@@ -424,8 +424,46 @@ def cpu_baseline(A, t, v, l0, walks, target_s):
                       f"{steps:.3e} steps in {el:.1f} s"}
 
 
+def config1_bench(args):
+    """The FP64 1D Dirichlet Laplacian (n = 100, t = 1e-4, v = sin(pi i h) + U(0, 0.1)),
+    full vector, 1e4 walks per row at the finest of four levels (coarser levels by the ratio
+    2^{1.5}), FP64 weights; error against the dense FP64 matrix exponential."""
+    import numpy as np
+    import scipy.linalg
+    import torch
+
+    from paper_1904_12754_amd import api, inputs
+
+    A, t, v = inputs.workload_laplace1d()
+    exact = scipy.linalg.expm(t * A.to_dense()) @ v
+    plan = api.Plan(A, t, precision="fp64")
+    u = torch.as_tensor(v, device="cuda")
+    walks = [int(round(1e4 * 2 ** (1.5 * (3 - q)))) for q in range(4)]
+    plan.run(u, walks=walks, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = plan.run(u, walks=walks, seed=2)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    err = x.cpu().numpy()[:, 0] - exact
+    plan.close()
+    return {"workload": "1D Dirichlet Laplacian n=100, t=1e-4, FP64, levels "
+                        f"{st['l0']}..{st['l0'] + 3}, walks per row {walks}",
+            "seconds": el, "steps": st["steps"], "steps_per_s": st["steps"] / el,
+            "rmse_vs_dense_expm": float(np.sqrt(np.mean(err ** 2))),
+            "max_abs_error": float(np.abs(err).max()),
+            "est_rmse": math.sqrt(st["est_variance"])}
+
+
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "
+                                   "measured at one GPU's share of the work (--gpus 1)"}))
+        sys.exit(2)
+    if args.mode == "config1":
+        print(json.dumps(config1_bench(args)), flush=True)
+        return
     if args.mode == "kernel":
         return kernel_only(args)
     if args.mode == "copy":
@@ -440,10 +478,6 @@ def main():
     if args.mode == "classical":
         print(json.dumps(classical_bench(args)), flush=True)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the walk kernel is "
-                                   "measured at one GPU's share of the work (--gpus 1)"}))
-        sys.exit(2)
     import numpy as np
     import torch
 
