@@ -210,13 +210,15 @@ __device__ __forceinline__ double load_u(const U *u, uint64_t idx)
 
 // ------------------------------------------------------------------------------------
 // Lane-refilling walk engine. A wave (or a group of its lanes) owns the walks [wb, we) of
-// one row; each lane runs one walk at a time and takes the next unassigned walk as soon as
-// its walk ends. Every
-// iteration gives every busy lane exactly one Philox block: the next step block while
-// it scans for the next jump, or the jump block (slot, alias coin, next holding time)
-// while it jumps. The divergent work between the blocks (threshold tests, one alias
-// gather, one logarithm, the end of a walk) is short, so the wave stays busy on the
-// generator instead of waiting on its slowest lane.
+// one row (or, with a random start, walks of many rows); each lane runs one walk at a time
+// and takes the next unassigned walk as soon as its walk ends. In an iteration a busy lane
+// draws at most one Philox block: the next step block when it has scanned past its cached
+// one, or the jump block (slot, alias coin, next holding time) while it jumps. A chain of
+// jumps that ends inside the cached step block is followed by the scan in the same
+// iteration, on the same code path as the other scanning lanes. The end of a walk only
+// stores its exponents; the expensive evaluation (exp, expm1, the sink) runs for many
+// lanes at once. The divergent work between the blocks is therefore short, and the wave
+// stays busy on the generator instead of waiting on its slowest lane.
 // ------------------------------------------------------------------------------------
 struct ScanOut {
     bool jump;       // a step of the block jumps
@@ -483,7 +485,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         }
         if (__ballot(s.active) == 0) break;
 
-        // ---- one Philox block per busy lane
+        // ---- at most one Philox block per busy lane
         const bool jumping = s.active && s.jumping;
         const bool scanning = s.active && !s.jumping;
         const uint32_t q = s.n >> 2;
