@@ -39,19 +39,28 @@ BYTES_PER_JUMP = 48
 # HBM traffic of the walk kernel from the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
 # plain copy), recorded with the hash of the kernel source it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1904_12754_amd", "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1904_12754_amd", "csrc", f)
+                  for f in ("kernels.hip", "walk_engine.h", "common.h", "kernels.h")]
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the sources the walk kernel is compiled from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def kernel_traffic(launches_walks):
     """Calibrated HBM bytes per walk-kernel launch, or None when the counters were taken on
-    another version of the kernel source."""
-    import hashlib
-
+    another version of the kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_sources_sha256()
     except OSError:
         return None
     if rec.get("kernel_sha256") != sha:
