@@ -77,6 +77,7 @@ void free_plan(mlmc_plan *p)
     hipFree(p->req_rows);
     hipFree(p->partial);
     hipFree(p->counters);
+    hipFree(p->counter_sums);
     hipFree(p->bad);
     hipFree(p->moments);
     hipFree(p->moment_scratch);
@@ -180,7 +181,7 @@ int ensure_partial(mlmc_plan *p, size_t bytes)
 
 // Walks [walk0, walk0 + M) of every requested row at `level`: per-(row, rhs) sums of Y and
 // Y^2 into out1/out2 (overwritten, or added to when accumulate). Jump and non-finite
-// counts are added to counters[0..1].
+// counts are added to the counter set `counters`.
 int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void *u, int u_f64,
                int32_t nrhs, uint32_t walk0, uint64_t M, double *out1, double *out2, int accumulate,
                unsigned long long *counters, unsigned long long *hash_sums, hipStream_t s)
@@ -400,7 +401,8 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     int rc;
     if ((rc = dev_alloc(p, &p->slots, slots.size()))) return rc;
     if ((rc = dev_alloc(p, &p->rows_base, rows.size()))) return rc;
-    if ((rc = dev_alloc(p, &p->counters, 2 * (kMaxLevel + 1)))) return rc;
+    if ((rc = dev_alloc(p, &p->counters, kCounterSetU64 * (kMaxLevel + 1)))) return rc;
+    if ((rc = dev_alloc(p, &p->counter_sums, 2 * (kMaxLevel + 1)))) return rc;
     if ((rc = dev_alloc(p, &p->bad, 1))) return rc;
     if ((rc = dev_alloc(p, &p->moments, 3 * (kMaxLevel + 1)))) return rc;
     if ((rc = dev_alloc(p, &p->moment_scratch, 3 * kMomentBlocks))) return rc;
@@ -451,7 +453,7 @@ int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_
     if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
     if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long), s));
+    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, kCounterSetU64 * sizeof(unsigned long long), s));
     if (hash_sums && p->n_rows > 0)
         MLMC_HIP_TRY(hipMemsetAsync(hash_sums, 0, sizeof(uint64_t) * p->n_rows, s));
     rc = level_sums(p, level, seed, instance, u, u_dtype == MLMC_DTYPE_F64, nrhs, walk0, walks, sum1,
@@ -459,7 +461,8 @@ int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_
     if (rc) return rc;
     if (jumps) {
         unsigned long long c[2];
-        MLMC_HIP_TRY(hipMemcpyAsync(c, p->counters, sizeof c, hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(launch_counter_sum(p->counters, 1, p->counter_sums, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(c, p->counter_sums, sizeof c, hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
         *jumps = static_cast<int64_t>(c[0]);
         if (c[1]) return fail(MLMC_ERR_NONFINITE, std::to_string(c[1]) + " non-finite samples");
@@ -521,14 +524,14 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
     p->timing = stats != nullptr;
     p->tev_used = 0;
-    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, 2 * sizeof(unsigned long long) * (kMaxLevel + 1), s));
+    MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, kCounterSetU64 * sizeof(unsigned long long) * max_levels, s));
     MLMC_HIP_TRY(hipEventRecord(p->ev0, s));
     // add `extra` walks at level index qq
     auto add_walks = [&](int qq, int64_t extra) -> int {
         const int level = p->l0 + qq;
         const int r2 = level_sums(p, level, o->seed, o->instance, u, u_f64, nrhs,
                                   static_cast<uint32_t>(M[qq]), static_cast<uint64_t>(extra), s1_of(qq),
-                                  s2_of(qq), M[qq] > 0 ? 1 : 0, p->counters + 2 * qq, nullptr, s);
+                                  s2_of(qq), M[qq] > 0 ? 1 : 0, p->counters + kCounterSetU64 * qq, nullptr, s);
         if (r2) return r2;
         M[qq] += extra;
         return MLMC_OK;
@@ -542,7 +545,8 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
                                               p->moments + 3 * qq, p->moment_scratch, s));
         std::vector<double> h(3 * static_cast<size_t>(levels));
         MLMC_HIP_TRY(hipMemcpyAsync(h.data(), p->moments, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), p->counters, sizeof(unsigned long long) * ctr.size(),
+        MLMC_HIP_TRY(launch_counter_sum(p->counters, levels, p->counter_sums, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), p->counter_sums, sizeof(unsigned long long) * 2 * levels,
                                     hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
         for (int qq = 0; qq < levels; ++qq) mom[qq] = Mom{h[3 * qq], h[3 * qq + 1], h[3 * qq + 2]};

@@ -37,13 +37,18 @@ struct Segment {
     const int64_t *rows;              // requested rows of the plan, nullptr = all
     double *partial;                  // items x nrhs x 2
     double *acc;                      // [sum Y: n_rows x nrhs][sum Y^2: n_rows x nrhs]
-    unsigned long long *counters;     // jumps, non-finite samples
+    unsigned long long *counters;     // a counter set of kSegSlots slots (jumps, non-finite)
     uint64_t item_begin;              // first global item of the segment
     uint64_t pair_begin;              // first global (row, rhs) pair of the segment
     double inv_M;
     uint32_t n_rows, M, chunk, chunks;
     int32_t nrhs, pad;
 };
+
+// Each segment's counters are spread over kSegSlots 64-byte slots (the wave's index picks the
+// slot), so that the items of a segment do not all add to one address.
+constexpr int kSegSlots = 32;
+constexpr size_t kSegSetU64 = static_cast<size_t>(kSegSlots) * kCounterStride;
 
 struct InstanceOut {
     double *x;
@@ -129,8 +134,9 @@ __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict_
             }
         }
         if (lane == 0) {
-            atomicAdd(&sg.counters[0], jumps);
-            if (nonfinite) atomicAdd(&sg.counters[1], nonfinite);
+            unsigned long long *c = sg.counters + (wave_id % kSegSlots) * kCounterStride;
+            atomicAdd(&c[0], jumps);
+            if (nonfinite) atomicAdd(&c[1], nonfinite);
         }
     }
 }
@@ -229,6 +235,7 @@ struct mlmc_batch {
     InstanceOut *d_outs = nullptr;
     BatchParams *d_prm = nullptr;
     unsigned long long *d_counters = nullptr;
+    unsigned long long *d_counter_sums = nullptr;
     double *d_partial = nullptr;
     double *d_acc = nullptr;
     double *d_moments = nullptr;
@@ -258,6 +265,7 @@ void free_batch(mlmc_batch *b)
     hipFree(b->d_outs);
     hipFree(b->d_prm);
     hipFree(b->d_counters);
+    hipFree(b->d_counter_sums);
     hipFree(b->d_partial);
     hipFree(b->d_acc);
     hipFree(b->d_moments);
@@ -356,7 +364,8 @@ int build_tables(mlmc_batch *b, hipStream_t s)
     int rc;
     if ((rc = balloc(b, &b->d_partial, partial_doubles))) return rc;
     if ((rc = balloc(b, &b->d_acc, 2 * b->total_pairs))) return rc;
-    if ((rc = balloc(b, &b->d_counters, 2 * b->h_segs.size()))) return rc;
+    if ((rc = balloc(b, &b->d_counters, kSegSetU64 * b->h_segs.size()))) return rc;
+    if ((rc = balloc(b, &b->d_counter_sums, 2 * b->h_segs.size()))) return rc;
     if ((rc = balloc(b, &b->d_moments, 3 * b->h_segs.size()))) return rc;
     if ((rc = balloc(b, &b->d_moment_scratch, 3 * kMomentBlocks))) return rc;
     uint64_t acc_off = 0;
@@ -365,7 +374,7 @@ int build_tables(mlmc_batch *b, hipStream_t s)
         sg.partial = b->d_partial + reinterpret_cast<uintptr_t>(sg.partial);
         sg.acc = b->d_acc + acc_off;
         acc_off += 2ull * sg.n_rows * sg.nrhs;
-        sg.counters = b->d_counters + 2 * g;
+        sg.counters = b->d_counters + kSegSetU64 * g;
     }
     for (int i = 0; i < b->count; ++i) b->h_outs[i].x = nullptr;   // filled by create
     if ((rc = balloc(b, &b->d_segs, b->h_segs.size()))) return rc;
@@ -420,22 +429,22 @@ int autotune(mlmc_batch *b, hipStream_t s)
         unsigned long long *ctr = nullptr;
         Segment *dseg = nullptr;
         if (hipMalloc(&part, std::max<uint64_t>(pdoubles, 1) * sizeof(double)) != hipSuccess ||
-            hipMalloc(&ctr, 2 * segs.size() * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc(&ctr, kSegSetU64 * segs.size() * sizeof(unsigned long long)) != hipSuccess ||
             hipMalloc(&dseg, segs.size() * sizeof(Segment)) != hipSuccess) {
             rc = fail(MLMC_ERR_OUT_OF_MEMORY, "autotune scratch");
         } else {
             for (size_t g = 0; g < segs.size(); ++g) {
                 segs[g].partial = part + reinterpret_cast<uintptr_t>(segs[g].partial);
                 segs[g].acc = nullptr;
-                segs[g].counters = ctr + 2 * g;
+                segs[g].counters = ctr + kSegSetU64 * g;
             }
             double ms_sum = 0.0;
             if (hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(),
                                hipMemcpyHostToDevice, s) != hipSuccess)
                 rc = fail(MLMC_ERR_HIP, "autotune upload");
             for (int rep = 0; rep < 2 && rc == MLMC_OK; ++rep) {
-                hipLaunchKernelGGL(batch_reset, dim3(blocks_of(2 * segs.size(), 256)), dim3(256), 0, s,
-                                   b->d_prm, ctr, static_cast<int32_t>(2 * segs.size()));
+                hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * segs.size(), 256)), dim3(256), 0, s,
+                                   b->d_prm, ctr, static_cast<int32_t>(kSegSetU64 * segs.size()));
                 hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, 0x5EEDu, rep + 1u);
                 hipEventRecord(e0, s);
                 if (launch_walks(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s) !=
@@ -527,8 +536,8 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     MLMC_HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     MLMC_HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
     const int32_t nseg = static_cast<int32_t>(b->h_segs.size());
-    hipLaunchKernelGGL(batch_reset, dim3(blocks_of(2 * nseg, 256)), dim3(256), 0, b->cap_stream,
-                       b->d_prm, b->d_counters, 2 * nseg);
+    hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * nseg, 256)), dim3(256), 0, b->cap_stream,
+                       b->d_prm, b->d_counters, static_cast<int32_t>(kSegSetU64 * nseg));
     hipError_t le = launch_walks(b, b->shape, b->d_segs, nseg, b->total_items, b->cap_stream);
     if (b->total_pairs)
         hipLaunchKernelGGL(batch_finalize, dim3(blocks_of(b->total_pairs, 256)), dim3(256), 0,
@@ -575,8 +584,9 @@ int mlmc_expv_batch_stats(mlmc_batch_t *b, mlmc_stats_t *per_instance, void *str
     }
     std::vector<double> mom(3 * nseg);
     std::vector<unsigned long long> ctr(2 * nseg);
+    MLMC_HIP_TRY(launch_counter_sum(b->d_counters, static_cast<int>(nseg), b->d_counter_sums, s, kSegSlots));
     MLMC_HIP_TRY(hipMemcpyAsync(mom.data(), b->d_moments, sizeof(double) * mom.size(), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), b->d_counters, sizeof(unsigned long long) * ctr.size(),
+    MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), b->d_counter_sums, sizeof(unsigned long long) * ctr.size(),
                                 hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     float ms = 0.0f;

@@ -45,8 +45,9 @@ __global__ __launch_bounds__(kBlock) void functional_walks(LevelArgs L, AliasSta
     if (lane == 0) {
         partial[static_cast<size_t>(item) * 2 + 0] = a;
         partial[static_cast<size_t>(item) * 2 + 1] = b;
-        atomicAdd(&counters[0], jumps);
-        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+        unsigned long long *c = counter_slot(counters, item);
+        atomicAdd(&c[0], jumps);
+        if (nonfinite) atomicAdd(&c[1], nonfinite);
         if (kHash) atomicAdd(hash_sum, hsum);
     }
 }
@@ -84,7 +85,7 @@ struct FuncCall {
     double *partial = nullptr;
     size_t partial_items = 0;
     double *total = nullptr;           // 2 doubles
-    unsigned long long *ctr = nullptr; // jumps, non-finite, hash
+    unsigned long long *ctr = nullptr; // a counter set, then its two sums and the hash sum
     double U = 0.0;
     ~FuncCall()
     {
@@ -154,7 +155,7 @@ int prepare(FuncCall &fc, const mlmc_plan *p, const void *u, int u_f64, hipStrea
     }
     int rc;
     if ((rc = dalloc(&fc.thr, n)) || (rc = dalloc(&fc.alias, n)) || (rc = dalloc(&fc.neg, n)) ||
-        (rc = dalloc(&fc.total, 2)) || (rc = dalloc(&fc.ctr, 3)))
+        (rc = dalloc(&fc.total, 2)) || (rc = dalloc(&fc.ctr, kCounterSetU64 + 3)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(fc.thr, thr.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(fc.alias, alias.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -190,7 +191,7 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
         if ((rc = dalloc(&fc.partial, 2 * static_cast<size_t>(items)))) return rc;
         fc.partial_items = items;
     }
-    MLMC_HIP_TRY(hipMemsetAsync(fc.ctr, 0, 3 * sizeof(unsigned long long), s));
+    MLMC_HIP_TRY(hipMemsetAsync(fc.ctr, 0, (kCounterSetU64 + 3) * sizeof(unsigned long long), s));
     hipEvent_t e0, e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
@@ -199,7 +200,8 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     const uint32_t Mu = static_cast<uint32_t>(M);
 #define MLMC_FUNC(R, U, H)                                                                      \
     hipLaunchKernelGGL((functional_walks<R, U, H>), grid, block, 0, s, L, st,                  \
-                       static_cast<const U *>(w), walk0, Mu, items, fc.partial, fc.ctr, fc.ctr + 2)
+                       static_cast<const U *>(w), walk0, Mu, items, fc.partial, fc.ctr,                 \
+                       fc.ctr + kCounterSetU64 + 2)
     if (p->precision == MLMC_PRECISION_FP64) {
         if (u_f64) { if (hash) MLMC_FUNC(double, double, true); else MLMC_FUNC(double, double, false); }
         else { if (hash) MLMC_FUNC(double, float, true); else MLMC_FUNC(double, float, false); }
@@ -212,10 +214,11 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     MLMC_HIP_TRY(hipEventRecord(e1, s));
     hipLaunchKernelGGL(functional_total, dim3(1), dim3(256), 0, s, fc.partial, items, fc.total);
     MLMC_HIP_TRY(hipGetLastError());
+    MLMC_HIP_TRY(launch_counter_sum(fc.ctr, 1, fc.ctr + kCounterSetU64, s));
     double tot[2];
     unsigned long long c[3];
     MLMC_HIP_TRY(hipMemcpyAsync(tot, fc.total, sizeof tot, hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr, sizeof c, hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     (void)hipEventElapsedTime(&out.ms, e0, e1);
     (void)hipEventDestroy(e0);

@@ -23,14 +23,33 @@ struct LevelArgs {
 
 enum class Prec { FP64, FP32 };
 
+// A counter set: kCounterSlots slots of kCounterStride u64 (one 64-byte line each), [0] the
+// jumps and [1] the non-finite samples. Wave w adds its totals to slot w mod kCounterSlots,
+// so that no single address takes an atomic from every wave (atomics on one address
+// serialise across the XCDs); launch_counter_sum adds the slots up (integer sums, so the
+// order does not matter).
+constexpr int kCounterSlots = 256;
+constexpr int kCounterStride = 8;
+constexpr size_t kCounterSetU64 = static_cast<size_t>(kCounterSlots) * kCounterStride;
+
+__device__ __forceinline__ unsigned long long *counter_slot(unsigned long long *set, uint64_t wave)
+{
+    return set + (wave % kCounterSlots) * kCounterStride;
+}
+
+// out[2 i + j] = sum over the slots of counter j of set i, for sets 0 .. nsets - 1 of
+// `slots` slots each (kCounterSlots for the single-level path).
+hipError_t launch_counter_sum(const unsigned long long *sets, int nsets, unsigned long long *out,
+                              hipStream_t s, int slots = kCounterSlots);
+
 // Fill rec[i].thr for one level: the largest word w with -ln U(w) / r_i >= dt (no jump).
 // Sets *bad if some row jumps at every word (r_i dt too large for 32-bit words).
 hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *bad,
                              hipStream_t s);
 
 // Per-(row, chunk) partial sums of Y and Y^2 for walks [walk0, walk0 + M) of each
-// requested row. partial: n_rows * chunks * nrhs * 2 doubles. counters[0] += jumps,
-// counters[1] += non-finite samples; hash_sums (nullable) [q] += the path hashes of row
+// requested row. partial: n_rows * chunks * nrhs * 2 doubles. counters: a counter set
+// (jumps, non-finite samples); hash_sums (nullable) [q] += the path hashes of row
 // q's walks (mod 2^64).
 hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
                               int32_t nrhs, const int64_t *rows, int64_t n_rows,

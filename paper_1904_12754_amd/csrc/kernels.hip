@@ -48,8 +48,9 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
         if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
     if (lane == 0) {
-        atomicAdd(&counters[0], jumps);
-        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+        unsigned long long *c = counter_slot(counters, wave);
+        atomicAdd(&c[0], jumps);
+        if (nonfinite) atomicAdd(&c[1], nonfinite);
     }
 }
 
@@ -100,8 +101,9 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
         }
     }
     if (lane == 0) {
-        atomicAdd(&counters[0], jumps);
-        if (nonfinite) atomicAdd(&counters[1], nonfinite);
+        unsigned long long *c = counter_slot(counters, item);
+        atomicAdd(&c[0], jumps);
+        if (nonfinite) atomicAdd(&c[1], nonfinite);
         if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
 }
@@ -261,7 +263,41 @@ uint32_t blocks_for(int64_t n, int threads)
     return static_cast<uint32_t>((n + threads - 1) / threads);
 }
 
+__global__ void counter_sum_kernel(const unsigned long long *sets, int slots, unsigned long long *out)
+{
+    // one block per set, thread t adds the slots t, t + 256, ... of both counters
+    __shared__ unsigned long long sh[2][256];
+    const unsigned long long *set = sets + static_cast<size_t>(blockIdx.x) * slots * kCounterStride;
+    unsigned long long a = 0, b = 0;
+    for (int slot = threadIdx.x; slot < slots; slot += 256) {
+        a += set[slot * kCounterStride + 0];
+        b += set[slot * kCounterStride + 1];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x + 0] = sh[0][0];
+        out[2 * blockIdx.x + 1] = sh[1][0];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_counter_sum(const unsigned long long *sets, int nsets, unsigned long long *out,
+                              hipStream_t s, int slots)
+{
+    if (nsets <= 0) return hipSuccess;
+    hipLaunchKernelGGL(counter_sum_kernel, dim3(nsets), dim3(256), 0, s, sets, slots, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *bad, hipStream_t s)
 {

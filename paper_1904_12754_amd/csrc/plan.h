@@ -34,7 +34,8 @@ struct mlmc_plan {
     int64_t *req_rows = nullptr;             // device; null = all rows
     double *partial = nullptr;
     size_t partial_bytes = 0;
-    unsigned long long *counters = nullptr;  // 2 per level
+    unsigned long long *counters = nullptr;  // one counter set per level
+    unsigned long long *counter_sums = nullptr;  // 2 per level: jumps, non-finite samples
     unsigned int *bad = nullptr;
     double *moments = nullptr;               // 3 per level
     double *moment_scratch = nullptr;        // 3 * kMomentBlocks
