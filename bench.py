@@ -118,20 +118,15 @@ def kernel_only(args):
     plan.close()
 
 
-def batch_bench(args):
-    """The uneven batch: 512 instances (1D/2D Laplacians and Erdos-Renyi graphs, n
-    log-uniform in [1e3, 1e5], ||tA||_1 log-uniform in [0.5, 8], v ~ N(0, 1)), four levels
-    from each instance's l0 with 64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32
-    weights, in one graph-captured persistent launch. Also times the same work as one
-    fixed-schedule run per instance."""
+def _batch_vs_runs(insts, steps):
+    """Times one graph replay of the batch of `insts` (four levels from each instance's l0,
+    64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32 weights) and the same work as
+    one fixed-schedule run per instance."""
     import numpy as np
     import torch
 
-    from paper_1904_12754_amd import api, inputs
+    from paper_1904_12754_amd import api
 
-    t0 = time.perf_counter()
-    insts = inputs.workload_uneven_batch(args.instances)
-    t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     plans = [api.Plan(A, t, precision="fp32") for A, t, v in insts]
     us = [torch.as_tensor(v.astype(np.float32), device="cuda") for A, t, v in insts]
@@ -145,35 +140,54 @@ def batch_bench(args):
     batch.launch(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         batch.launch(100 + k)
     torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / args.steps
+    el = (time.perf_counter() - t0) / steps
     st = batch.stats()
-    steps = sum(x["steps"] for x in st)
+    total_steps = sum(x["steps"] for x in st)
     jumps = sum(x["total_jumps"] for x in st)
     # the same work, one fixed-schedule run per instance
+    for b, p in enumerate(plans[:8]):
+        p.run(us[b], walks=walks[b], seed=99, instance=b, want_stats=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b, p in enumerate(plans):
         p.run(us[b], walks=walks[b], seed=100, instance=b, want_stats=False)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t0
-    print(json.dumps({
-        "metric": "walk steps/s", "value": steps / el, "unit": "steps/s",
-        "ms_per_launch": el * 1e3, "steps_per_launch": steps, "jumps_per_launch": jumps,
-        "one_run_per_instance_ms": el_seq * 1e3, "speedup_vs_one_run_per_instance": el_seq / el,
-        "config": {"workload": f"{len(insts)} uneven instances (1D/2D Laplacian, ER mean degree 8), "
-                               "4 levels, FP32 weights, one graph-captured persistent launch",
-                   "rows_total": int(sum(A.n for A, _, _ in insts)),
-                   "walks_per_row_per_level": walks[0].tolist(),
-                   "batch": batch.info,
-                   "host_s": {"generate": t_gen, "plans": t_plan, "create_with_autotune": t_create}},
-    }), flush=True)
+    out = {"steps_per_s": total_steps / el, "ms_per_launch": el * 1e3,
+           "steps_per_launch": total_steps, "jumps_per_launch": jumps,
+           "one_run_per_instance_ms": el_seq * 1e3, "speedup_vs_one_run_per_instance": el_seq / el,
+           "rows_total": int(sum(A.n for A, _, _ in insts)),
+           "walks_per_row_per_level": walks[0].tolist(), "batch": batch.info,
+           "host_s": {"plans": t_plan, "create_with_autotune": t_create}}
     batch.close()
     for p in plans:
         p.close()
+    return out
 
+
+def batch_bench(args):
+    """The uneven batch: 512 instances (1D/2D Laplacians and Erdos-Renyi graphs, n
+    log-uniform in [1e3, 1e5], ||tA||_1 log-uniform in [0.5, 8], v ~ N(0, 1)), four levels
+    per instance, in one graph replay; and a batch of 2048 small instances (n log-uniform in
+    [100, 2000]) where one run per instance is dominated by launch and host costs."""
+    from paper_1904_12754_amd import inputs
+
+    t0 = time.perf_counter()
+    insts = inputs.workload_uneven_batch(args.instances)
+    t_gen = time.perf_counter() - t0
+    big = _batch_vs_runs(insts, args.steps)
+    del insts
+    small = _batch_vs_runs(inputs.workload_uneven_batch(2048, nmin=100, nmax=2000), args.steps)
+    big["host_s"]["generate"] = t_gen
+    print(json.dumps({
+        "metric": "walk steps/s", "value": big.pop("steps_per_s"), "unit": "steps/s", **big,
+        "config": {"workload": f"{args.instances} uneven instances (1D/2D Laplacian, ER mean degree 8, "
+                               "n in [1e3, 1e5]), 4 levels, FP32 weights, one graph replay"},
+        "small_instances": {"workload": "2048 uneven instances, n in [100, 2000], same schedule", **small},
+    }), flush=True)
 
 def tc_bench(args):
     """Total communicability with many right-hand sides: exp(beta A) [1, r_1..r_63] on a

@@ -252,18 +252,22 @@ typedef struct {
     double *const *x;                 /* count DEVICE outputs, n_rows_b x nrhs_b FP64 */
     int32_t num_levels;               /* levels l0_b .. l0_b + num_levels - 1 of each plan */
     const int64_t *walks;             /* HOST, count x num_levels walks per row (row major) */
-    int32_t autotune;                 /* 1: time candidate launch shapes on this batch (sample
-                                         sizes cut by 8) and keep the fastest; the choice is
-                                         cached per class of batch for the process */
+    int32_t autotune;                 /* 1: time 8, 16 and 32 resident waves per CU on this
+                                         batch (sample sizes cut by 8) and keep the fastest;
+                                         the choice is cached per class of batch for the
+                                         process. 0: 16. The walks per item always follow
+                                         from the total walk count (64 .. 4096). */
 } mlmc_batch_desc_t;
 
 typedef struct {
-    int32_t count, segments, walks_per_item, waves_per_cu, graph_nodes, pad;
+    int32_t count, segments, walks_per_item, waves_per_cu, graph_nodes;
+    int32_t phases;                   /* walk launches in the graph (phases of consecutive
+                                         items) */
     int64_t items;                    /* (row, walk chunk) items per launch */
     int64_t device_bytes;
-    double tune_ms[9];                /* autotuner timings of the candidate shapes (ms), in the
-                                         order (walks per item, waves per CU) = (256, 8),
-                                         (256, 16), (256, 32), (1024, 8), ..., (4096, 32) */
+    double tune_ms[3];                /* autotuner timings (ms) of 8, 16 and 32 waves per CU
+                                         (zero when the choice came from the cache or
+                                         autotune was off) */
 } mlmc_batch_info_t;
 
 /* Validate, upload the levels' tables, optionally autotune, lay out the work, and capture

@@ -119,9 +119,9 @@ class BatchDesc(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("segments", ctypes.c_int32),
                 ("walks_per_item", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
-                ("graph_nodes", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("graph_nodes", ctypes.c_int32), ("phases", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("tune_ms", ctypes.c_double * 9)]
+                ("tune_ms", ctypes.c_double * 3)]
 
 
 class TrainOpts(ctypes.Structure):

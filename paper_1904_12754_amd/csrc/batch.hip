@@ -1,13 +1,14 @@
 // Batched runs: many plans (matrices, right-hand sides, times) with fixed level schedules in
-// one persistent launch, captured once in a hipGraph and replayed.
+// a few persistent launches, captured once in a hipGraph and replayed.
 //
 // The batch is a list of segments, one per (instance, level). A segment's work is split into
 // items of `chunk` walks of one requested row; a persistent grid of waves deals the items
 // round robin, so instances of very different sizes and levels of very different walk
 // lengths share the chip without a launch per segment. The graph is: reset the counters ->
-// persistent walks -> per-row chunk sums -> per-instance FP64
-// combine of the levels (the estimator of section 2.2). The launch shape (walks per item,
-// resident waves per CU) comes from a small autotuner that times candidates on the batch
+// persistent walks (in phases of consecutive items) -> per-row chunk sums -> per-instance
+// FP64 combine of the levels (the estimator of section 2.2). The walks per item follow from the
+// batch's total walk count (the largest items that still give every wave many of them); the
+// resident waves per CU come from a small autotuner that times candidates on the batch
 // itself with reduced sample sizes and caches the winner per class of batch.
 #include <algorithm>
 #include <cmath>
@@ -30,6 +31,12 @@ namespace mlmc {
 namespace {
 
 constexpr int kCUs = 256;
+constexpr uint32_t kXcds = 8;
+// Items per wave in one phase of the walk launches.
+constexpr uint64_t kItemsPerWavePhase = 64;
+// Items per launch the walks-per-item rule aims for: about 128 per wave of a 32-waves-per-CU
+// grid, so that the end of the launch is short against its length.
+constexpr double kBatchTargetItems = 1 << 20;
 
 struct Segment {
     LevelArgs L;                      // tables of the instance at this level (key set per launch)
@@ -61,21 +68,27 @@ struct BatchParams {
     uint32_t k0, k1;                  // Philox key of the current launch
 };
 
+// Items [item_lo, item_hi) of the batch (one phase of the launch sequence).
 template <typename R, typename U, bool kMulti>
 __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
-                                                      uint64_t total_items, BatchParams *prm)
+                                                      uint64_t item_lo, uint64_t item_hi,
+                                                      BatchParams *prm)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t k0 = prm->k0, k1 = prm->k1;
-    // Items are dealt to the resident waves round robin (wave v takes v, v + W, v + 2W, ...):
+    // Items are dealt to the waves round robin (wave v takes v, v + W, v + 2W, ...):
     // consecutive items belong to the same (instance, level), so every wave gets a mix of all
-    // segments. The wave index is read with readfirstlane so the loop is wave-uniform in the
-    // compiled control flow. (A shared atomic work counter was measured to serialise at about
-    // one returning atomic per microsecond across the XCDs.)
+    // segments. Workgroups go to the XCDs in turn (workgroup b to XCD b mod 8), so the wave
+    // index is renumbered to give each XCD a contiguous eighth of every round of W items:
+    // walks that start on neighbouring rows then share one XCD's L2. The index is read with
+    // readfirstlane so the loop is wave-uniform in the compiled control flow. (A shared
+    // atomic work counter was measured to serialise at about one returning atomic per
+    // microsecond across the XCDs.) The grid is a multiple of kXcds workgroups.
     const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWavesPerBlock;
+    const uint32_t xcd_block = (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
     const uint64_t wave_id = __builtin_amdgcn_readfirstlane(
-        blockIdx.x * kWavesPerBlock + threadIdx.x / kWave);
-    for (uint64_t item = wave_id; item < total_items; item += waves) {
+        xcd_block * kWavesPerBlock + threadIdx.x / kWave);
+    for (uint64_t item = item_lo + wave_id; item < item_hi; item += waves) {
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -215,7 +228,7 @@ struct Shape {
 };
 
 std::mutex g_tune_mutex;
-std::map<std::string, Shape> g_tune_cache;
+std::map<std::string, int32_t> g_tune_cache;   // waves per CU per class of batch
 
 }  // namespace
 }  // namespace mlmc
@@ -241,13 +254,14 @@ struct mlmc_batch {
     double *d_moments = nullptr;
     double *d_moment_scratch = nullptr;
     uint64_t total_items = 0, total_pairs = 0, total_out_pairs = 0;
+    int32_t phases = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     size_t graph_nodes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool launched = false;
-    double tune_ms[9] = {};
+    double tune_ms[3] = {};
     int64_t bytes = 0;
 };
 
@@ -331,12 +345,13 @@ void layout(const mlmc_batch *b, const Shape &sh, const std::vector<int64_t> &wa
 }
 
 hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
-                        uint64_t total_items, hipStream_t s)
+                        uint64_t item_lo, uint64_t item_hi, hipStream_t s)
 {
     const dim3 grid(static_cast<uint32_t>(kCUs * sh.waves_per_cu / kWavesPerBlock));
+    if (grid.x % kXcds != 0) return hipErrorInvalidConfiguration;
     const dim3 block(kBlock);
 #define MLMC_BATCH(R, U, MULTI)                                                               \
-    hipLaunchKernelGGL((batch_walks<R, U, MULTI>), grid, block, 0, s, d_segs, nseg, total_items, \
+    hipLaunchKernelGGL((batch_walks<R, U, MULTI>), grid, block, 0, s, d_segs, nseg, item_lo, item_hi, \
                        b->d_prm)
     if (b->precision == MLMC_PRECISION_FP64) {
         if (b->u_f64) {
@@ -353,6 +368,24 @@ hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_s
     }
 #undef MLMC_BATCH
     return hipGetLastError();
+}
+
+// The walks of items [0, total_items) as a sequence of launches (phases) of consecutive
+// items. Within a launch the waves drift apart (their items differ in cost) and the chip
+// ends up working on many instances at once, whose tables then compete for the L2; the end
+// of each launch brings the waves back together. On the 512-instance batch this halves the
+// L2 misses of one long launch.
+hipError_t launch_phases(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
+                         uint64_t total_items, hipStream_t s, int32_t *phases)
+{
+    const uint64_t per_phase = static_cast<uint64_t>(kCUs) * sh.waves_per_cu * kItemsPerWavePhase;
+    *phases = 0;
+    for (uint64_t lo = 0; lo < total_items; lo += per_phase) {
+        const hipError_t e = launch_walks(b, sh, d_segs, nseg, lo, std::min(total_items, lo + per_phase), s);
+        if (e != hipSuccess) return e;
+        ++*phases;
+    }
+    return hipSuccess;
 }
 
 // Device buffers and segment table for the final shape.
@@ -383,7 +416,23 @@ int build_tables(mlmc_batch *b, hipStream_t s)
     return MLMC_OK;
 }
 
-// Time the candidate shapes on the batch with sample sizes cut by 8 (at least 64 walks).
+// Walks per item: the total walk count over kBatchTargetItems, rounded up to a multiple of
+// 64, within [64, 4096]. Long items keep the lanes busy (a lane that ends a walk takes the
+// item's next one; only the last walks of an item leave lanes idle), so items are only cut
+// shorter when the batch would otherwise give the waves too few of them.
+uint32_t items_chunk(const mlmc_batch *b)
+{
+    double total = 0.0;
+    for (int i = 0; i < b->count; ++i)
+        for (int q = 0; q < b->levels; ++q)
+            total += static_cast<double>(b->walks[static_cast<size_t>(i) * b->levels + q]) *
+                     static_cast<double>(b->plans[i]->n_rows);
+    const double c = std::ceil(total / kBatchTargetItems / 64.0) * 64.0;
+    return static_cast<uint32_t>(std::min(4096.0, std::max(64.0, c)));
+}
+
+// Time the candidate waves per CU on the batch with sample sizes cut by 8 (at least 64
+// walks) and the batch's walks per item.
 int autotune(mlmc_batch *b, hipStream_t s)
 {
     std::string key = std::to_string(b->precision) + "/" + std::to_string(b->multi) + "/" +
@@ -406,21 +455,20 @@ int autotune(mlmc_batch *b, hipStream_t s)
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            b->shape = it->second;
+            b->shape.waves_per_cu = it->second;
             return MLMC_OK;
         }
     }
     std::vector<int64_t> small(b->walks.size());
     for (size_t i = 0; i < small.size(); ++i) small[i] = std::max<int64_t>(64, b->walks[i] / 8);
-    const Shape cands[9] = {{256, 8}, {256, 16}, {256, 32}, {1024, 8}, {1024, 16},
-                            {1024, 32}, {4096, 8}, {4096, 16}, {4096, 32}};
+    const Shape cands[3] = {{b->shape.chunk, 8}, {b->shape.chunk, 16}, {b->shape.chunk, 32}};
     double best = 1e300;
     Shape pick = b->shape;
     hipEvent_t e0, e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     int rc = MLMC_OK;
-    for (int ci = 0; ci < 9 && rc == MLMC_OK; ++ci) {
+    for (int ci = 0; ci < 3 && rc == MLMC_OK; ++ci) {
         std::vector<Segment> segs;
         std::vector<InstanceOut> outs;
         uint64_t items, pairs, opairs, pdoubles;
@@ -447,8 +495,9 @@ int autotune(mlmc_batch *b, hipStream_t s)
                                    b->d_prm, ctr, static_cast<int32_t>(kSegSetU64 * segs.size()));
                 hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, 0x5EEDu, rep + 1u);
                 hipEventRecord(e0, s);
-                if (launch_walks(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s) !=
-                    hipSuccess)
+                int32_t phases = 0;
+                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s,
+                                  &phases) != hipSuccess)
                     rc = fail(MLMC_ERR_HIP, "autotune launch");
                 hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune sync");
@@ -471,7 +520,7 @@ int autotune(mlmc_batch *b, hipStream_t s)
     if (rc) return rc;
     b->shape = pick;
     std::lock_guard<std::mutex> lk(g_tune_mutex);
-    g_tune_cache[key] = pick;
+    g_tune_cache[key] = pick.waves_per_cu;
     return MLMC_OK;
 }
 
@@ -525,6 +574,7 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     if ((rc = balloc(b, &b->d_prm, 1))) return rc;
     MLMC_HIP_TRY(hipEventCreate(&b->ev0));
     MLMC_HIP_TRY(hipEventCreate(&b->ev1));
+    b->shape.chunk = items_chunk(b);
     if (d->autotune && (rc = autotune(b, s))) return rc;
     if ((rc = build_tables(b, s))) return rc;
     for (int i = 0; i < b->count; ++i) b->h_outs[i].x = d->x[i];
@@ -538,7 +588,8 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     const int32_t nseg = static_cast<int32_t>(b->h_segs.size());
     hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * nseg, 256)), dim3(256), 0, b->cap_stream,
                        b->d_prm, b->d_counters, static_cast<int32_t>(kSegSetU64 * nseg));
-    hipError_t le = launch_walks(b, b->shape, b->d_segs, nseg, b->total_items, b->cap_stream);
+    hipError_t le = launch_phases(b, b->shape, b->d_segs, nseg, b->total_items, b->cap_stream,
+                                  &b->phases);
     if (b->total_pairs)
         hipLaunchKernelGGL(batch_finalize, dim3(blocks_of(b->total_pairs, 256)), dim3(256), 0,
                            b->cap_stream, b->d_segs, nseg, b->total_pairs);
@@ -635,8 +686,9 @@ int mlmc_expv_batch_info(const mlmc_batch_t *b, mlmc_batch_info_t *info)
     info->walks_per_item = static_cast<int32_t>(b->shape.chunk);
     info->waves_per_cu = b->shape.waves_per_cu;
     info->graph_nodes = static_cast<int32_t>(b->graph_nodes);
+    info->phases = b->phases;
     info->device_bytes = b->bytes;
-    for (int i = 0; i < 9; ++i) info->tune_ms[i] = b->tune_ms[i];
+    for (int i = 0; i < 3; ++i) info->tune_ms[i] = b->tune_ms[i];
     return MLMC_OK;
 }
 
