@@ -97,3 +97,38 @@ def test_batch_matches_oracle_and_graph_replays_are_exact(api, R):
     batch.close()
     for p in plans:
         p.close()
+
+
+def test_batch_in_several_phases_matches_oracle(api):
+    """A batch large enough in items (rows x levels) to be split into several walk launches
+    (phases of consecutive items): every instance against the oracle, and a replay with
+    another key set in between reproduces the result exactly."""
+    insts = [(inputs.laplacian_1d(120_000), None, None),
+             (inputs.laplacian_2d(300), None, None),
+             (inputs.erdos_renyi(50_000, 8.0, 5), None, None)]
+    rng = np.random.default_rng(17)
+    insts = [(A, c / A.norm1(), rng.normal(size=A.n)) for (A, _, _), c in zip(insts, (0.7, 3.0, 1.5))]
+    walks = np.array([[3, 2, 1, 1]] * len(insts), dtype=np.int64)
+    plans = [api.Plan(A, t, precision="fp32") for A, t, _ in insts]
+    us = [torch.as_tensor(v.astype(np.float32), device="cuda") for _, _, v in insts]
+    batch = api.Batch(plans, us, walks, autotune=False)
+    _say(f"phased batch info {batch.info}")
+    assert batch.info["phases"] >= 2
+    seed = 4242
+    xs = [x.clone() for x in batch.launch(seed)]
+    st = batch.stats()
+    for b, ((A, t, _), p) in enumerate(zip(insts, plans)):
+        _say(f"  oracle instance {b}: n={A.n} l0={p.l0}")
+        u = us[b].double().cpu().numpy()
+        res = _oracle_x(A, t, u, p.l0, walks[b], seed, instance=b)
+        assert st[b]["total_jumps"] == res.jumps, b
+        assert st[b]["steps"] == res.steps, b
+        assert np.all(np.abs(xs[b].cpu().numpy() - res.x) <= TOL32 * res.mass + 1e-300), b
+    batch.launch(seed + 1)
+    again = batch.launch(seed)
+    torch.cuda.synchronize()
+    for b in range(len(insts)):
+        assert torch.equal(again[b], xs[b]), b
+    batch.close()
+    for p in plans:
+        p.close()
