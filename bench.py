@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--cd-grid", type=int, default=128)
-    ap.add_argument("--cd-pilot", type=int, default=32)
+    ap.add_argument("--cd-pilot", type=int, default=2)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-loose", action="store_true",
                     help="skip the solves to RMSE 1e-2 after the timed region")
@@ -291,8 +291,8 @@ def learned_bench(args):
     rng = np.random.default_rng(0)
     P0 = _init_params(rng)
     train_opts = dict(seed=3, pilot_walks=32, capture_walks=16,
-                      sample_stride=max(1, A.n // 65536), steps=800, batch=4096, lr=1e-2,
-                      shrink=10.0, num_levels=6, judge_walks=8)
+                      sample_stride=max(1, A.n // 65536), steps=200, batch=4096, lr=1e-2,
+                      shrink=10.0, num_levels=1, judge_walks=8)
     (params, tst), t_train = timed(lambda: plan.train_proposal(u, P0, **train_opts))
     out = {
         "workload": f"3D 7-point convection-diffusion {args.cd_grid}^3 (n={A.n}, nonsymmetric), "

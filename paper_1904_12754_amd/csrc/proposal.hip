@@ -404,6 +404,103 @@ __global__ void capture_kernel(LevelArgs L, const float *__restrict__ u, uint32_
 }
 
 // ------------------------------------------------------------------------------------
+// The recorded transitions that carry a sample (weight > 0 and finite, a slot taken) are kept
+// in their recorded order. Kept transition r (its rank in that order) is held out when
+// r mod 8 = 7 and r / 8 < kMaxHeldOut (as held-out transition r / 8); the others train, as
+// training transition r - min(r / 8, kMaxHeldOut). Three passes: per-block counts, one
+// workgroup scans the counts, and every block scatters its kept transitions.
+// ------------------------------------------------------------------------------------
+constexpr int kKeepPer = 4;                    // transitions per thread
+constexpr int kKeepBlock = 256 * kKeepPer;     // transitions per block
+
+__device__ __forceinline__ bool kept_transition(float w, int32_t slot)
+{
+    return w > 0.0f && isfinite(w) && slot >= 0;
+}
+
+// Exclusive scan of v over the 256 threads of the block (sh: 256 entries); returns the
+// thread's offset, and the block total in *total.
+__device__ __forceinline__ uint32_t block_scan_256(uint32_t v, uint32_t *sh, uint32_t *total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t add = t >= o ? sh[t - o] : 0u;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = sh[t];
+    *total = sh[255];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void keep_count_kernel(const int32_t *__restrict__ slot, const float *__restrict__ w,
+                                  uint64_t T, uint32_t *counts)
+{
+    __shared__ uint32_t sh[256];
+    const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kKeepBlock + threadIdx.x * kKeepPer;
+    uint32_t c = 0;
+    for (int k = 0; k < kKeepPer; ++k)
+        if (i0 + k < T && kept_transition(w[i0 + k], slot[i0 + k])) ++c;
+    uint32_t total;
+    block_scan_256(c, sh, &total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// counts[0..nb) -> exclusive offsets in place; offsets[nb] = the total. One workgroup.
+__global__ void keep_scan_kernel(uint32_t *counts, uint32_t nb)
+{
+    __shared__ uint32_t sh[256];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += 256) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? counts[b] : 0u;
+        uint32_t total;
+        const uint32_t off = block_scan_256(v, sh, &total);
+        if (b < nb) counts[b] = carry + off;
+        carry += total;
+    }
+    if (threadIdx.x == 0) counts[nb] = carry;
+}
+
+__global__ void keep_scatter_kernel(const uint32_t *__restrict__ row, const int32_t *__restrict__ slot,
+                                    const float *__restrict__ w, uint64_t T,
+                                    const uint32_t *__restrict__ offsets, uint32_t *tr_row,
+                                    int32_t *tr_slot, float *tr_w, uint32_t *va_row, int32_t *va_slot,
+                                    float *va_w)
+{
+    __shared__ uint32_t sh[256];
+    const uint64_t i0 = static_cast<uint64_t>(blockIdx.x) * kKeepBlock + threadIdx.x * kKeepPer;
+    bool keep[kKeepPer];
+    uint32_t c = 0;
+    for (int k = 0; k < kKeepPer; ++k) {
+        keep[k] = i0 + k < T && kept_transition(w[i0 + k], slot[i0 + k]);
+        c += keep[k] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint64_t r = offsets[blockIdx.x] + block_scan_256(c, sh, &total);
+    for (int k = 0; k < kKeepPer; ++k) {
+        if (!keep[k]) continue;
+        const uint64_t i = i0 + k;
+        const uint64_t q = r / 8;
+        if ((r & 7u) == 7u && q < static_cast<uint64_t>(kMaxHeldOut)) {
+            va_row[q] = row[i];
+            va_slot[q] = slot[i];
+            va_w[q] = w[i];
+        } else {
+            const uint64_t t = r - min(q, static_cast<uint64_t>(kMaxHeldOut));
+            tr_row[t] = row[i];
+            tr_slot[t] = slot[i];
+            tr_w[t] = w[i];
+        }
+        ++r;
+    }
+}
+
+// ------------------------------------------------------------------------------------
 // Training: FP32 forward / backward, one workgroup per chunk of kTC transitions of the batch,
 // activations in LDS; every workgroup writes its own partial gradient and the partials are
 // added in a fixed order (deterministic).
@@ -682,21 +779,36 @@ __global__ __launch_bounds__(256) void train_kernel(const float *__restrict__ P,
     }
 }
 
-// G = sum of the partial gradients (fixed order); with kAdam, one Adam step on P instead.
+// G = sum of the partial gradients in a fixed order; with kAdam, one Adam step on P instead.
+// A workgroup serves kGradParams parameters with kGradGroups threads each: thread group g
+// adds the partials g, g + kGradGroups, ... in turn, and the group sums are added in the
+// order g = 0, 1, ... (deterministic).
+constexpr int kGradParams = 32;
+constexpr int kGradGroups = 8;
+
 template <bool kAdam>
-__global__ void grad_sum_kernel(const float *__restrict__ partial, int blocks, float *out, float *P, float *m,
-                                float *v, float lr, float b1, float b2, float eps, float c1, float c2)
+__global__ __launch_bounds__(kGradParams * kGradGroups) void grad_sum_kernel(
+    const float *__restrict__ partial, int blocks, float *out, float *P, float *m, float *v, float lr,
+    float b1, float b2, float eps, float c1, float c2)
 {
-    const int t = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
-    if (t >= NPARAM) return;
-    float g = 0.0f;
-    for (int q = 0; q < blocks; ++q) g += partial[static_cast<size_t>(q) * NPARAM + t];
+    __shared__ float sh[kGradGroups][kGradParams];
+    const int jj = static_cast<int>(threadIdx.x) % kGradParams;
+    const int g = static_cast<int>(threadIdx.x) / kGradParams;
+    const int t = static_cast<int>(blockIdx.x) * kGradParams + jj;
+    float acc = 0.0f;
+    if (t < NPARAM)
+        for (int q = g; q < blocks; q += kGradGroups) acc += partial[static_cast<size_t>(q) * NPARAM + t];
+    sh[g][jj] = acc;
+    __syncthreads();
+    if (g != 0 || t >= NPARAM) return;
+    float gs = sh[0][jj];
+    for (int k = 1; k < kGradGroups; ++k) gs += sh[k][jj];
     if (!kAdam) {
-        out[t] = g;
+        out[t] = gs;
         return;
     }
-    m[t] = b1 * m[t] + (1.0f - b1) * g;
-    v[t] = b2 * v[t] + (1.0f - b2) * g * g;
+    m[t] = b1 * m[t] + (1.0f - b1) * gs;
+    v[t] = b2 * v[t] + (1.0f - b2) * gs * gs;
     P[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
 }
 
@@ -922,8 +1034,8 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
     if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
     const BatchSrc src{d_rows, d_slots, d_w, static_cast<uint64_t>(count), 0, 1};
     MLMC_HIP_TRY(train_pass(true, dP, F, p, level, src, count, static_cast<float>(shrink), part, lossb, s));
-    hipLaunchKernelGGL(grad_sum_kernel<false>, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, part, blocks, G, nullptr,
-                       nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f);
+    hipLaunchKernelGGL(grad_sum_kernel<false>, dim3(nblk(NPARAM, kGradParams)), dim3(kGradParams * kGradGroups), 0,
+                       s, part, blocks, G, nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f);
     MLMC_HIP_TRY(hipGetLastError());
     std::vector<float> lb(count);
     MLMC_HIP_TRY(hipMemcpyAsync(grad, G, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1000,54 +1112,42 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         MLMC_HIP_TRY(hipGetLastError());
     }
     if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
-    // keep the recorded transitions (weight > 0) in their original order
-    std::vector<uint32_t> h_row(T);
-    std::vector<int32_t> h_slot(T);
-    std::vector<float> h_w(T);
-    MLMC_HIP_TRY(hipMemcpyAsync(h_row.data(), t_row, T * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(h_slot.data(), t_slot, T * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(h_w.data(), t_w, T * sizeof(float), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipStreamSynchronize(s));
-    uint64_t kept = 0;
-    for (uint64_t i = 0; i < T; ++i)
-        if (h_w[i] > 0.0f && std::isfinite(h_w[i]) && h_slot[i] >= 0) {
-            h_row[kept] = h_row[i];
-            h_slot[kept] = h_slot[i];
-            h_w[kept] = h_w[i];
-            ++kept;
-        }
-    // 3. every 8th transition is held out (at most kMaxHeldOut of them); Adam on minibatches
-    //    of the rest, taken by a fixed stride (coprime with the count) so that each batch
-    //    spreads over all sampled rows; the parameters with the lowest held-out loss (the
-    //    initial ones included) are kept
-    uint64_t n_train = 0, n_val = 0;
-    std::vector<uint32_t> v_row_h;
-    std::vector<int32_t> v_slot_h;
-    std::vector<float> v_w_h;
-    for (uint64_t i = 0; i < kept; ++i) {
-        if (i % 8 == 7 && n_val < static_cast<uint64_t>(kMaxHeldOut)) {
-            v_row_h.push_back(h_row[i]);
-            v_slot_h.push_back(h_slot[i]);
-            v_w_h.push_back(h_w[i]);
-            ++n_val;
-        } else {
-            h_row[n_train] = h_row[i];
-            h_slot[n_train] = h_slot[i];
-            h_w[n_train] = h_w[i];
-            ++n_train;
-        }
+    // 3. the transitions that carry a sample, in their recorded order: every 8th is held out
+    //    (at most kMaxHeldOut of them), the rest train (compacted on the device). Adam on
+    //    minibatches of the training transitions, taken by a fixed stride (coprime with the
+    //    count) so that each batch spreads over all sampled rows; the parameters with the
+    //    lowest held-out loss (the initial ones included) are kept
+    const uint64_t nb_keep = (T + kKeepBlock - 1) / kKeepBlock;
+    const uint64_t val_cap = std::min<uint64_t>(T / 8, static_cast<uint64_t>(kMaxHeldOut));
+    uint32_t *keep_off = nullptr, *tr_row = nullptr, *v_row = nullptr;
+    int32_t *tr_slot = nullptr, *v_slot = nullptr;
+    float *tr_w = nullptr, *v_w = nullptr;
+    if ((rc = ss.alloc(&keep_off, nb_keep + 1)) || (rc = ss.alloc(&tr_row, T)) || (rc = ss.alloc(&tr_slot, T)) ||
+        (rc = ss.alloc(&tr_w, T)) || (rc = ss.alloc(&v_row, val_cap)) || (rc = ss.alloc(&v_slot, val_cap)) ||
+        (rc = ss.alloc(&v_w, val_cap)))
+        return rc;
+    if (nb_keep > 0xFFFFFFFFull) return fail(MLMC_ERR_INVALID_ARG, "capture too large");
+    uint32_t kept32 = 0;
+    if (T > 0) {
+        hipLaunchKernelGGL(keep_count_kernel, dim3(static_cast<uint32_t>(nb_keep)), dim3(256), 0, s, t_slot, t_w, T,
+                           keep_off);
+        hipLaunchKernelGGL(keep_scan_kernel, dim3(1), dim3(256), 0, s, keep_off, static_cast<uint32_t>(nb_keep));
+        hipLaunchKernelGGL(keep_scatter_kernel, dim3(static_cast<uint32_t>(nb_keep)), dim3(256), 0, s, t_row, t_slot,
+                           t_w, T, keep_off, tr_row, tr_slot, tr_w, v_row, v_slot, v_w);
+        MLMC_HIP_TRY(hipGetLastError());
+        MLMC_HIP_TRY(hipMemcpyAsync(&kept32, keep_off + nb_keep, sizeof kept32, hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
     }
+    const uint64_t kept = kept32;
+    const uint64_t n_val = std::min<uint64_t>(kept / 8, static_cast<uint64_t>(kMaxHeldOut));
+    const uint64_t n_train = kept - n_val;
     std::vector<float> P(o->init_params, o->init_params + NPARAM);
     float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
-    uint32_t *v_row = nullptr;
-    int32_t *v_slot = nullptr;
-    float *v_w = nullptr;
     const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
     const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
     if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&best, NPARAM)) ||
         (rc = ss.alloc(&part, static_cast<size_t>(train_blocks(B)) * NPARAM)) || (rc = ss.alloc(&lossb, B)) ||
-        (rc = ss.alloc(&lossv, V)) || (rc = ss.alloc(&v_row, V)) || (rc = ss.alloc(&v_slot, V)) ||
-        (rc = ss.alloc(&v_w, V)))
+        (rc = ss.alloc(&lossv, V)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1069,16 +1169,10 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     double first_val = 0.0, best_val = 0.0;
     int best_step = 0;
     if (n_val > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(v_row, v_row_h.data(), n_val * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(v_slot, v_slot_h.data(), n_val * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(v_w, v_w_h.data(), n_val * sizeof(float), hipMemcpyHostToDevice, s));
         if ((rc = val_loss(first_val))) return rc;
         best_val = first_val;
     }
     if (n_train > 0 && o->steps > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(t_row, h_row.data(), n_train * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_slot, h_slot.data(), n_train * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(t_w, h_w.data(), n_train * sizeof(float), hipMemcpyHostToDevice, s));
         auto gcd = [](uint64_t a, uint64_t b) {
             while (b) {
                 const uint64_t t = a % b;
@@ -1093,12 +1187,13 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         const int blocks = train_blocks(B);
         std::vector<float> lb(B);
         for (int step = 0; step < o->steps; ++step) {
-            const BatchSrc src{t_row, t_slot, t_w, n_train, static_cast<uint64_t>(step) * B, mult};
+            const BatchSrc src{tr_row, tr_slot, tr_w, n_train, static_cast<uint64_t>(step) * B, mult};
             MLMC_HIP_TRY(train_pass(true, p->prop_P, F, p, level, src, B, shrink, part, lossb, s));
             const float c1 = 1.0f - std::pow(b1, static_cast<float>(step + 1));
             const float c2 = 1.0f - std::pow(b2, static_cast<float>(step + 1));
-            hipLaunchKernelGGL(grad_sum_kernel<true>, dim3(nblk(NPARAM, 256)), dim3(256), 0, s, part, blocks,
-                               nullptr, p->prop_P, m, v, static_cast<float>(o->lr), b1, b2, 1e-8f, c1, c2);
+            hipLaunchKernelGGL(grad_sum_kernel<true>, dim3(nblk(NPARAM, kGradParams)), dim3(kGradParams * kGradGroups),
+                               0, s, part, blocks, nullptr, p->prop_P, m, v, static_cast<float>(o->lr), b1, b2,
+                               1e-8f, c1, c2);
             MLMC_HIP_TRY(hipGetLastError());
             if (step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0) {
                 MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
