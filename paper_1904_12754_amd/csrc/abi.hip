@@ -74,6 +74,8 @@ void free_plan(mlmc_plan *p)
     hipFree(p->prop_frag);
     hipFree(p->prop_xhat);
     hipFree(p->prop_xmax);
+    for (auto &b : p->train_pool) hipFree(b.first);
+    for (auto &b : p->grad_pool) hipFree(b.first);
     hipFree(p->req_rows);
     hipFree(p->partial);
     hipFree(p->counters);

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mlmc_expv.h"
@@ -58,6 +59,8 @@ struct mlmc_plan {
     double *prop_xmax = nullptr;             // max |xhat| (1 when zero)
     int32_t prop_levels = 0;                 // levels l0 .. l0 + prop_levels - 1 carry tables
     int32_t prop_identity = 0;               // 1: the tables are the plain ones (ratio 1)
+    // scratch buffers kept between proposal training calls and between gradient calls
+    std::vector<std::pair<void *, size_t>> train_pool, grad_pool;
     // source vector of the current Algorithm 3 call (device, element type of u), else null
     const void *cur_src = nullptr;
     int64_t bytes = 0;

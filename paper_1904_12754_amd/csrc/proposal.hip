@@ -830,24 +830,39 @@ hipError_t train_pass(bool backward, const float *P, const float *F, const mlmc_
     return hipGetLastError();
 }
 
-// Scratch of a training session.
+// Scratch of a training call, kept by the plan between calls: the k-th buffer a call asks
+// for is the plan's k-th pooled buffer, reallocated only when it is too small (the calls ask
+// in the same order every time). The call's stream is synchronised when the session ends, so
+// that no kernel of this call still uses the buffers when the next call (on any stream)
+// takes them.
 struct Session {
-    std::vector<void *> ptrs;
-    ~Session()
-    {
-        for (void *p : ptrs) (void)hipFree(p);
-    }
+    mlmc_plan *plan;
+    std::vector<std::pair<void *, size_t>> &pool;
+    hipStream_t stream;
+    size_t next = 0;
+    Session(mlmc_plan *p, std::vector<std::pair<void *, size_t>> &pl, hipStream_t s) : plan(p), pool(pl), stream(s) {}
+    ~Session() { (void)hipStreamSynchronize(stream); }
     template <typename T>
     int alloc(T **p, size_t count)
     {
         *p = nullptr;
-        const hipError_t e = hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(count, 1) * sizeof(T));
-        if (e != hipSuccess) {
-            *p = nullptr;
-            return fail(e == hipErrorOutOfMemory ? MLMC_ERR_OUT_OF_MEMORY : MLMC_ERR_HIP,
-                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (next == pool.size()) pool.emplace_back(nullptr, 0);
+        auto &b = pool[next++];
+        if (b.second < bytes) {
+            (void)hipStreamSynchronize(stream);
+            if (b.first) (void)hipFree(b.first);
+            plan->bytes -= static_cast<int64_t>(b.second);
+            b = {nullptr, 0};
+            void *q = nullptr;
+            const hipError_t e = hipMalloc(&q, bytes);
+            if (e != hipSuccess)
+                return fail(e == hipErrorOutOfMemory ? MLMC_ERR_OUT_OF_MEMORY : MLMC_ERR_HIP,
+                            std::string("hipMalloc: ") + hipGetErrorString(e));
+            b = {q, bytes};
+            plan->bytes += static_cast<int64_t>(bytes);
         }
-        ptrs.push_back(*p);
+        *p = static_cast<T *>(b.first);
         return MLMC_OK;
     }
 };
@@ -1014,7 +1029,7 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
     }
     std::vector<uint32_t> rows32(count);
     for (int32_t b = 0; b < count; ++b) rows32[b] = static_cast<uint32_t>(rows[b]);
-    Session ss;
+    Session ss(p, p->grad_pool, s);
     float *dP = nullptr, *F = nullptr, *d_w = nullptr, *part = nullptr, *G = nullptr, *lossb = nullptr;
     uint32_t *d_rows = nullptr;
     int32_t *d_slots = nullptr;
@@ -1075,7 +1090,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         }
     } ev{e0, e1};
     MLMC_HIP_TRY(hipEventRecord(e0, s));
-    Session ss;
+    Session ss(p, p->train_pool, s);
     // 1. pilot estimate xhat: the level-l0 mean of plain walks (an independent stream family)
     const bool was_on = p->proposal_on;
     p->proposal_on = false;
