@@ -251,7 +251,8 @@ struct Walker {
     bool active = false;
     uint32_t w = 0, k = 0, neg = 0, J = 0, run_start = 0, n = 0;
     uint32_t row0 = 0;                    // the walk's start row (its counters' row)
-    uint32_t jumping = 0;                 // 1 while a jump of step n is pending
+    uint32_t jumping = 0;                 // 1 while a jump of step n is pending; 2 once the
+                                          // walk has ended and waits for a free slot
     uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
     uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
     RowRec cur;
@@ -279,7 +280,8 @@ struct Finished {
 // A finished walk waiting for its evaluation: the final state, the sign, the exponents of
 // the sample (2 E_f / dt at the base level, 2 E_c / dt and 2 (E_f - E_c) / dt above), the
 // likelihood ratio, and what the counters need.
-constexpr int kFlushAt = 48;
+constexpr int kFlushAt = 40;
+constexpr int kMaxWaiting = 4;
 
 template <typename R, bool kSrc>
 struct Pending {
@@ -486,8 +488,8 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         if (__ballot(s.active) == 0) break;
 
         // ---- at most one Philox block per busy lane
-        const bool jumping = s.active && s.jumping;
-        const bool scanning = s.active && !s.jumping;
+        const bool jumping = s.active && s.jumping == 1u;
+        const bool scanning = s.active && s.jumping == 0u;
         const uint32_t q = s.n >> 2;
         Word4 ph{0u, 0u, 0u, 0u};
         if (jumping || (scanning && s.bq != q))
@@ -556,17 +558,30 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         }
 
         // ---- the end of a walk: its exponents wait in the lane's slot, and the slots are
-        // evaluated together (exp, expm1, the sink) when kFlushAt lanes hold one, when a
-        // lane ends a walk while its slot is full, or after the last walk
-        if (__ballot(finish && pend.valid) != 0 || __popcll(__ballot(pend.valid)) >= kFlushAt) {
-            sink.take(pend.valid, pend.finished(L.base, hd));
-            pend.valid = false;
-        }
+        // evaluated together (exp, expm1, the sink) when kFlushAt lanes hold one, when
+        // kMaxWaiting lanes have ended a walk while their slot was full (they wait, without
+        // a new walk, for the evaluation), when no lane is still walking, or after the last
+        // walk
         if (finish) {
             if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, L.N, L.N, sink.source(s.k));
             add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
-            pend.hold(s, L.base, hd);
-            s.active = false;
+            if (!pend.valid) {
+                pend.hold(s, L.base, hd);
+                s.active = false;
+            } else {
+                s.jumping = 2u;
+            }
+        }
+        const uint64_t waiting = __ballot(s.active && s.jumping == 2u);
+        if (__popcll(__ballot(pend.valid)) >= kFlushAt ||
+            (waiting != 0 && (__popcll(waiting) >= kMaxWaiting ||
+                              __ballot(s.active && s.jumping != 2u) == 0))) {
+            sink.take(pend.valid, pend.finished(L.base, hd));
+            pend.valid = false;
+            if (s.active && s.jumping == 2u) {
+                pend.hold(s, L.base, hd);
+                s.active = false;
+            }
         }
     }
     sink.take(pend.valid, pend.finished(L.base, hd));
