@@ -74,16 +74,18 @@ __device__ __forceinline__ uint32_t jump_pick(const LevelArgs &L, uint32_t slot_
     return (coin < sr.thr) ? sr.own : sr.alias;
 }
 
-// Add the grid points a..b (held at one state with weight d) to the three sums.
+// Add the grid points a..b (held at one state with weight d) to the three sums; at the
+// coarsest level (fine_only) the sample needs the fine sum alone.
 template <typename R>
 __device__ __forceinline__ void add_run(R d, uint32_t a, uint32_t b, uint32_t N, R &ef2, R &ec2,
-                                        R &ed2)
+                                        R &ed2, bool fine_only = false)
 {
     const int a0 = (a == 0), bN = (b == N);
     const int f2 = 2 * static_cast<int>(b - a + 1) - a0 - bN;                 // 2 sum w_f
+    ef2 += d * static_cast<R>(f2);
+    if (fine_only) return;
     const int even = static_cast<int>(b >> 1) - static_cast<int>((a + 1) >> 1) + 1;
     const int c2 = 4 * even - 2 * a0 - 2 * bN;                                 // 2 sum w_c
-    ef2 += d * static_cast<R>(f2);
     ec2 += d * static_cast<R>(c2);
     ed2 += d * static_cast<R>(f2 - c2);
 }
@@ -544,17 +546,25 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         }
         // scan the cached block: the lanes that were scanning, and the lanes whose chain
         // just ended inside the cached block (one code path for both)
+        bool chain = false;
+        uint32_t chain_word = 0;
         if (s.active && !s.jumping && !finish && (s.n >> 2) == s.bq) {
             const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
-            if (so.jump) {
-                // the step's holding time at k is below dt: a chain of jumps starts
-                if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, s.n, L.N, sink.source(s.k));
-                add_run<R>(d_of<R>(s.cur), s.run_start, s.n, L.N, s.ef2, s.ec2, s.ed2);
-                chain_start(s, so.word);
-                s.jumping = 1;
-            } else {
-                finish = s.n == L.N;
-            }
+            // the step's holding time at k is below dt: a chain of jumps starts
+            chain = so.jump;
+            chain_word = so.word;
+            finish = !so.jump && s.n == L.N;
+        }
+        // the holding run at k ends: at the step that starts a chain, or at the end of the
+        // walk (one code path for both)
+        if (chain || finish) {
+            const uint32_t run_end = chain ? s.n : L.N;
+            if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, run_end, L.N, sink.source(s.k));
+            add_run<R>(d_of<R>(s.cur), s.run_start, run_end, L.N, s.ef2, s.ec2, s.ed2, L.base != 0);
+        }
+        if (chain) {
+            chain_start(s, chain_word);
+            s.jumping = 1;
         }
 
         // ---- the end of a walk: its exponents wait in the lane's slot, and the slots are
@@ -563,8 +573,6 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         // a new walk, for the evaluation), when no lane is still walking, or after the last
         // walk
         if (finish) {
-            if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, L.N, L.N, sink.source(s.k));
-            add_run<R>(d_of<R>(s.cur), s.run_start, L.N, L.N, s.ef2, s.ec2, s.ed2);
             if (!pend.valid) {
                 pend.hold(s, L.base, hd);
                 s.active = false;
