@@ -11,6 +11,13 @@
 namespace mlmc {
 namespace {
 
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
 template <typename R, typename U, bool kHash, bool kIS, bool kSrc>
@@ -36,7 +43,20 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     const uint64_t wb = has ? static_cast<uint64_t>(c) * chunk : 0ull;
     const uint64_t we = has ? min(wb + chunk, static_cast<uint64_t>(M)) : 0ull;
     SinkR1<R, U> sink{u, static_cast<const U *>(L.src)};
-    walk_range<R, kHash, kIS, kSrc>(L, row, walk0, wb, we, sink, lpr);
+    bool done = false;
+    if constexpr (!kIS && !kSrc) {
+        // one item per wave: its row and walk range are wave-uniform, so the engine's group
+        // bookkeeping and the start row's record stay in scalar registers (the walks under
+        // a proposal or with a source term keep the general path: a second copy of the
+        // engine would cost them a wave per SIMD)
+        if (lpr == kWave) {
+            const uint32_t urow = __builtin_amdgcn_readfirstlane(row);
+            const uint64_t uwb = uniform64(wb), uwe = uniform64(we);
+            walk_range<R, kHash, kIS, kSrc>(L, urow, walk0, uwb, uwe, sink);
+            done = true;
+        }
+    }
+    if (!done) walk_range<R, kHash, kIS, kSrc>(L, row, walk0, wb, we, sink, lpr);
     const double a = group_sum(sink.s1.value(), lpr);
     const double b = group_sum(sink.s2.value(), lpr);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
