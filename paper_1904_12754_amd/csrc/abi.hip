@@ -383,7 +383,11 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     int l0 = o->l0;
     if (l0 < 0) {
         l0 = 0;
-        if (r_max > 0.0) l0 = std::max(0, static_cast<int>(std::ceil(std::log2(2.0 * o->beta * r_max))));
+        if (r_max > 0.0) {
+            // clamp before the conversion: 2 beta r_max may overflow to infinity
+            const double e = std::ceil(std::log2(2.0 * o->beta * r_max));
+            l0 = e > static_cast<double>(kMaxLevel) ? kMaxLevel + 1 : std::max(0, static_cast<int>(e));
+        }
     }
     if (l0 > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "coarsest level from the l0 rule exceeds 28");
     // ---- upload

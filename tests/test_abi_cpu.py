@@ -68,6 +68,8 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert _plan_status(A, precision=7)[0] == _abi.MLMC_ERR_INVALID_ARG
     assert _plan_status(A, rows=[0, 10])[0] == _abi.MLMC_ERR_INVALID_ARG
     assert _plan_status(A, l0=99)[0] == _abi.MLMC_ERR_INVALID_ARG
+    # the l0 rule with 2 beta r_max beyond the double range: refused, not a wrapped level
+    assert _plan_status(A, beta=1e308)[0] == _abi.MLMC_ERR_INVALID_ARG
     lib = _lib()
     assert lib.mlmc_expv_plan(None, None, None, None) == _abi.MLMC_ERR_INVALID_ARG
 
