@@ -592,9 +592,13 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
                 C[qq] = level_cost(qq);
                 tot += std::sqrt(V[qq] * C[qq]);
             }
-            bool added = false;
+            bool added = false, nan_size = false;
             for (int qq = 0; qq < levels; ++qq) {
                 const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(V[qq] / C[qq]) * tot);
+                if (std::isnan(Mopt)) {   // non-finite samples: stop here and write what there is
+                    nan_size = true;
+                    break;
+                }
                 int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
                 if (target > M[qq]) {
                     if ((rc = add_walks(qq, target - M[qq]))) return rc;
@@ -602,6 +606,7 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
                 }
             }
             if (added && (rc = read_moments(levels))) return rc;
+            if (nan_size) break;
             double var = 0.0;
             for (int qq = 0; qq < levels; ++qq) var += level_var(qq) / static_cast<double>(M[qq]);
             bias = std::max(level_rms(levels - 1), level_rms(levels - 2) / 4.0) / 3.0;

@@ -355,11 +355,17 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
             ++iterations;
             double tot = 0.0;
             for (int q = 0; q < levels; ++q) tot += std::sqrt(std::max(var_of(q), 1e-300) * cost_of(q));
+            bool nan_size = false;
             for (int q = 0; q < levels; ++q) {
                 const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(std::max(var_of(q), 1e-300) / cost_of(q)) * tot);
+                if (std::isnan(Mopt)) {   // non-finite samples: stop here and report them
+                    nan_size = true;
+                    break;
+                }
                 const int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
                 if (target > M[q] && (rc = add(q, target - M[q]))) return rc;
             }
+            if (nan_size) break;
             double var = 0.0;
             for (int q = 0; q < levels; ++q) var += var_of(q) / static_cast<double>(M[q]);
             bias = std::max(std::fabs(mean_of(levels - 1)), std::fabs(mean_of(levels - 2)) / 4.0) / 3.0;
