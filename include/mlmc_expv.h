@@ -252,12 +252,16 @@ typedef struct {
     double *const *x;                 /* count DEVICE outputs, n_rows_b x nrhs_b FP64 */
     int32_t num_levels;               /* levels l0_b .. l0_b + num_levels - 1 of each plan */
     const int64_t *walks;             /* HOST, count x num_levels walks per row (row major) */
-    int32_t autotune;                 /* 1: time 8, 16 and 32 resident waves per CU on this
-                                         batch (sample sizes cut by 8) and keep the fastest;
-                                         the choice is cached per class of batch for the
-                                         process. 0: 16. The walks per item always follow
-                                         from the total walk count (64 .. 4096). */
+    int32_t autotune;                 /* 1: time candidate launch shapes (walks per item 256,
+                                         1024, 4096 and the size rule's choice x 8, 16, 32
+                                         resident waves per CU) on every 8th instance at full
+                                         sample sizes and keep the fastest; the choice is
+                                         cached per class of batch for the process.
+                                         0: walks per item from the total walk count
+                                         (64 .. 4096), 16 waves per CU. */
 } mlmc_batch_desc_t;
+
+#define MLMC_BATCH_TUNE_MAX 12   /* autotuner candidates reported in mlmc_batch_info_t */
 
 typedef struct {
     int32_t count, segments, walks_per_item, waves_per_cu, graph_nodes;
@@ -265,9 +269,12 @@ typedef struct {
                                          items) */
     int64_t items;                    /* (row, walk chunk) items per launch */
     int64_t device_bytes;
-    double tune_ms[3];                /* autotuner timings (ms) of 8, 16 and 32 waves per CU
-                                         (zero when the choice came from the cache or
-                                         autotune was off) */
+    int32_t tune_count;               /* candidates the autotuner timed (0 when the choice
+                                         came from the cache or autotune was off) */
+    int32_t tune_walks_per_item[MLMC_BATCH_TUNE_MAX];
+    int32_t tune_waves_per_cu[MLMC_BATCH_TUNE_MAX];
+    int32_t pad;
+    double tune_ms[MLMC_BATCH_TUNE_MAX];  /* their times on the instance subset (ms) */
 } mlmc_batch_info_t;
 
 /* Validate, upload the levels' tables, optionally autotune, lay out the work, and capture

@@ -37,6 +37,7 @@ EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_
            "mlmc_expv_proposal_train", "mlmc_status_string", "mlmc_last_error")
 
 MLMC_PROPOSAL_PARAMS = 5703
+MLMC_BATCH_TUNE_MAX = 12
 
 
 class CSR(ctypes.Structure):
@@ -121,7 +122,11 @@ class BatchInfo(ctypes.Structure):
                 ("walks_per_item", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
                 ("graph_nodes", ctypes.c_int32), ("phases", ctypes.c_int32),
                 ("items", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("tune_ms", ctypes.c_double * 3)]
+                ("tune_count", ctypes.c_int32),
+                ("tune_walks_per_item", ctypes.c_int32 * MLMC_BATCH_TUNE_MAX),
+                ("tune_waves_per_cu", ctypes.c_int32 * MLMC_BATCH_TUNE_MAX),
+                ("pad", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double * MLMC_BATCH_TUNE_MAX)]
 
 
 class TrainOpts(ctypes.Structure):

@@ -361,7 +361,9 @@ class Batch:
                                                _stream_ptr(stream)))
         info = _abi.BatchInfo()
         check(self._lib.mlmc_expv_batch_info(self._handle, ctypes.byref(info)))
-        self.info = {f: (list(getattr(info, f)) if f == "tune_ms" else getattr(info, f))
+        n = int(info.tune_count)
+        self.info = {f: (list(getattr(info, f))[:n] if f.startswith("tune_") and f != "tune_count"
+                         else getattr(info, f))
                      for f, _ in _abi.BatchInfo._fields_ if f != "pad"}
 
     def launch(self, seed: int = 0, stream=None):

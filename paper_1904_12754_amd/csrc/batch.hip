@@ -6,10 +6,10 @@
 // round robin, so instances of very different sizes and levels of very different walk
 // lengths share the chip without a launch per segment. The graph is: reset the counters ->
 // persistent walks (in phases of consecutive items) -> per-row chunk sums -> per-instance
-// FP64 combine of the levels (the estimator of section 2.2). The walks per item follow from the
-// batch's total walk count (the largest items that still give every wave many of them); the
-// resident waves per CU come from a small autotuner that times candidates on the batch
-// itself with reduced sample sizes and caches the winner per class of batch.
+// FP64 combine of the levels (the estimator of section 2.2). The launch shape (walks per item,
+// resident waves per CU) comes from a small autotuner that times candidates on a subset of
+// the batch's instances at full sample sizes and caches the winner per class of batch;
+// without it, the walks per item follow from the batch's total walk count.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -228,7 +228,7 @@ struct Shape {
 };
 
 std::mutex g_tune_mutex;
-std::map<std::string, int32_t> g_tune_cache;   // waves per CU per class of batch
+std::map<std::string, Shape> g_tune_cache;   // the chosen shape per class of batch
 
 }  // namespace
 }  // namespace mlmc
@@ -261,7 +261,9 @@ struct mlmc_batch {
     size_t graph_nodes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool launched = false;
-    double tune_ms[3] = {};
+    int32_t tune_n = 0;                // candidates timed by the autotuner
+    double tune_ms[MLMC_BATCH_TUNE_MAX] = {};
+    int32_t tune_chunk[MLMC_BATCH_TUNE_MAX] = {}, tune_waves[MLMC_BATCH_TUNE_MAX] = {};
     int64_t bytes = 0;
 };
 
@@ -302,16 +304,17 @@ int balloc(mlmc_batch *b, T **ptr, size_t count)
     return MLMC_OK;
 }
 
-// Segment tables for a shape and sample sizes (walks[b * levels + q]); device buffers are
-// laid out by the caller through the offsets returned in the segments.
+// Segment tables for a shape and sample sizes (walks[b * levels + q]) of every instance, or of
+// every stride-th one; device buffers are laid out by the caller through the offsets returned
+// in the segments.
 void layout(const mlmc_batch *b, const Shape &sh, const std::vector<int64_t> &walks,
             std::vector<Segment> &segs, std::vector<InstanceOut> &outs, uint64_t &items,
-            uint64_t &pairs, uint64_t &out_pairs, uint64_t &partial_doubles)
+            uint64_t &pairs, uint64_t &out_pairs, uint64_t &partial_doubles, int stride = 1)
 {
     segs.clear();
     outs.clear();
     items = pairs = out_pairs = partial_doubles = 0;
-    for (int i = 0; i < b->count; ++i) {
+    for (int i = 0; i < b->count; i += stride) {
         mlmc_plan *p = b->plans[i];
         InstanceOut o{};
         o.pair_begin = out_pairs;
@@ -431,8 +434,12 @@ uint32_t items_chunk(const mlmc_batch *b)
     return static_cast<uint32_t>(std::min(4096.0, std::max(64.0, c)));
 }
 
-// Time the candidate waves per CU on the batch with sample sizes cut by 8 (at least 64
-// walks) and the batch's walks per item.
+// Time candidate shapes (walks per item: 256, 1024, 4096 and the size rule's choice; waves
+// per CU: 8, 16, 32) on every kTuneStride-th instance of the batch at its full sample sizes,
+// with the phases of the real launch, and keep the fastest. The choice is cached per class of
+// batch for the process.
+constexpr int kTuneStride = 8;
+
 int autotune(mlmc_batch *b, hipStream_t s)
 {
     std::string key = std::to_string(b->precision) + "/" + std::to_string(b->multi) + "/" +
@@ -455,30 +462,38 @@ int autotune(mlmc_batch *b, hipStream_t s)
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            b->shape.waves_per_cu = it->second;
+            b->shape = it->second;
             return MLMC_OK;
         }
     }
-    std::vector<int64_t> small(b->walks.size());
-    for (size_t i = 0; i < small.size(); ++i) small[i] = std::max<int64_t>(64, b->walks[i] / 8);
-    const Shape cands[3] = {{b->shape.chunk, 8}, {b->shape.chunk, 16}, {b->shape.chunk, 32}};
+    std::vector<Shape> cands;
+    {
+        std::vector<uint32_t> chunks = {256, 1024, 4096};
+        if (std::find(chunks.begin(), chunks.end(), b->shape.chunk) == chunks.end())
+            chunks.push_back(b->shape.chunk);
+        for (uint32_t c : chunks)
+            for (int w : {8, 16, 32}) cands.push_back(Shape{c, w});
+    }
+    const int stride = b->count >= kTuneStride ? kTuneStride : b->count;
     double best = 1e300;
     Shape pick = b->shape;
     hipEvent_t e0, e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     int rc = MLMC_OK;
-    for (int ci = 0; ci < 3 && rc == MLMC_OK; ++ci) {
+    b->tune_n = 0;
+    for (size_t ci = 0; ci < cands.size() && rc == MLMC_OK; ++ci) {
         std::vector<Segment> segs;
         std::vector<InstanceOut> outs;
         uint64_t items, pairs, opairs, pdoubles;
-        layout(b, cands[ci], small, segs, outs, items, pairs, opairs, pdoubles);
+        layout(b, cands[ci], b->walks, segs, outs, items, pairs, opairs, pdoubles, stride);
         double *part = nullptr;
         unsigned long long *ctr = nullptr;
         Segment *dseg = nullptr;
         if (hipMalloc(&part, std::max<uint64_t>(pdoubles, 1) * sizeof(double)) != hipSuccess ||
-            hipMalloc(&ctr, kSegSetU64 * segs.size() * sizeof(unsigned long long)) != hipSuccess ||
-            hipMalloc(&dseg, segs.size() * sizeof(Segment)) != hipSuccess) {
+            hipMalloc(&ctr, kSegSetU64 * std::max<size_t>(segs.size(), 1) * sizeof(unsigned long long)) !=
+                hipSuccess ||
+            hipMalloc(&dseg, std::max<size_t>(segs.size(), 1) * sizeof(Segment)) != hipSuccess) {
             rc = fail(MLMC_ERR_OUT_OF_MEMORY, "autotune scratch");
         } else {
             for (size_t g = 0; g < segs.size(); ++g) {
@@ -486,28 +501,32 @@ int autotune(mlmc_batch *b, hipStream_t s)
                 segs[g].acc = nullptr;
                 segs[g].counters = ctr + kSegSetU64 * g;
             }
-            double ms_sum = 0.0;
-            if (hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(),
-                               hipMemcpyHostToDevice, s) != hipSuccess)
+            if (hipMemcpyAsync(dseg, segs.data(), sizeof(Segment) * segs.size(), hipMemcpyHostToDevice, s) !=
+                hipSuccess)
                 rc = fail(MLMC_ERR_HIP, "autotune upload");
-            for (int rep = 0; rep < 2 && rc == MLMC_OK; ++rep) {
+            // the first candidate runs twice (the first run warms the tables up), the others once
+            float ms = 0.0f;
+            for (int rep = 0; rep < (ci == 0 ? 2 : 1) && rc == MLMC_OK; ++rep) {
                 hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * segs.size(), 256)), dim3(256), 0, s,
                                    b->d_prm, ctr, static_cast<int32_t>(kSegSetU64 * segs.size()));
                 hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, 0x5EEDu, rep + 1u);
                 hipEventRecord(e0, s);
                 int32_t phases = 0;
-                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s,
-                                  &phases) != hipSuccess)
+                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s, &phases) !=
+                    hipSuccess)
                     rc = fail(MLMC_ERR_HIP, "autotune launch");
                 hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune sync");
-                float ms = 0.0f;
                 hipEventElapsedTime(&ms, e0, e1);
-                if (rep == 1) ms_sum += ms;
             }
-            b->tune_ms[ci] = ms_sum;
-            if (rc == MLMC_OK && ms_sum < best) {
-                best = ms_sum;
+            if (rc == MLMC_OK && b->tune_n < MLMC_BATCH_TUNE_MAX) {
+                b->tune_ms[b->tune_n] = ms;
+                b->tune_chunk[b->tune_n] = static_cast<int32_t>(cands[ci].chunk);
+                b->tune_waves[b->tune_n] = cands[ci].waves_per_cu;
+                ++b->tune_n;
+            }
+            if (rc == MLMC_OK && ms < best) {
+                best = ms;
                 pick = cands[ci];
             }
         }
@@ -520,7 +539,7 @@ int autotune(mlmc_batch *b, hipStream_t s)
     if (rc) return rc;
     b->shape = pick;
     std::lock_guard<std::mutex> lk(g_tune_mutex);
-    g_tune_cache[key] = pick.waves_per_cu;
+    g_tune_cache[key] = pick;
     return MLMC_OK;
 }
 
@@ -688,7 +707,12 @@ int mlmc_expv_batch_info(const mlmc_batch_t *b, mlmc_batch_info_t *info)
     info->graph_nodes = static_cast<int32_t>(b->graph_nodes);
     info->phases = b->phases;
     info->device_bytes = b->bytes;
-    for (int i = 0; i < 3; ++i) info->tune_ms[i] = b->tune_ms[i];
+    info->tune_count = b->tune_n;
+    for (int i = 0; i < b->tune_n; ++i) {
+        info->tune_ms[i] = b->tune_ms[i];
+        info->tune_walks_per_item[i] = b->tune_chunk[i];
+        info->tune_waves_per_cu[i] = b->tune_waves[i];
+    }
     return MLMC_OK;
 }
 
