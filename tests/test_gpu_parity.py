@@ -1,6 +1,7 @@
 """Parity of the HIP path (through the C-ABI) with the oracle, on identical seeded inputs.
 
-Bars (derived in the design doc):
+Bars (from the rounding of the two evaluation orders: the oracle multiplies the per-step
+factors, the kernel sums exponents and evaluates one exp / expm1):
   - paths: final state, sign, jump count and the FNV path hash are bit-exact;
   - FP64 weights: per-row level sums within 1e-12 of the oracle's, relative to the row's
     absolute mass  sum_w |u_j| (|eta_fine| + |eta_coarse|)  (the scale of the rounding of
