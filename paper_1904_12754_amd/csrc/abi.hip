@@ -227,16 +227,20 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
             }
             MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used], s));
         }
+        // one chunk per row: the kernel writes (or adds) the row sums itself
+        const bool direct = nch == 1;
+        const SumsOut lo{p->partial, out1, out2, direct ? ((first && !accumulate) ? 1 : 2) : 0};
         MLMC_HIP_TRY(launch_level_walks(L, prec, u, u_f64, nrhs, p->req_rows, p->n_rows,
                                         walk0 + static_cast<uint32_t>(wb), static_cast<uint32_t>(Msub),
                                         static_cast<uint32_t>(chunk), static_cast<uint32_t>(nch),
-                                        p->partial, counters, hash_sums, s));
+                                        lo, counters, hash_sums, s));
         if (p->timing) {
             MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used + 1], s));
             p->tev_used += 2;
         }
-        MLMC_HIP_TRY(launch_finalize(p->partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
-                                     out2, (first && !accumulate) ? 0 : 1, s));
+        if (!direct)
+            MLMC_HIP_TRY(launch_finalize(p->partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
+                                         out2, (first && !accumulate) ? 0 : 1, s));
         first = false;
     }
     return MLMC_OK;

@@ -47,14 +47,23 @@ hipError_t launch_counter_sum(const unsigned long long *sets, int nsets, unsigne
 hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *bad,
                              hipStream_t s);
 
-// Per-(row, chunk) partial sums of Y and Y^2 for walks [walk0, walk0 + M) of each
-// requested row. partial: n_rows * chunks * nrhs * 2 doubles. counters: a counter set
-// (jumps, non-finite samples); hash_sums (nullable) [q] += the path hashes of row
-// q's walks (mod 2^64).
+// Where the walk kernels put their sums of Y and Y^2: per-(row, chunk) partials
+// (partial[((q * chunks + c) * nrhs + r) * 2 + {0, 1}], reduced by launch_finalize), or,
+// when a row's walks form one chunk, straight into out1/out2[q * nrhs + r] (written, or
+// added to).
+struct SumsOut {
+    double *partial;
+    double *out1, *out2;
+    int32_t direct;          // 0: partials; 1: write out1/out2; 2: add to out1/out2
+};
+
+// Sums of Y and Y^2 for walks [walk0, walk0 + M) of each requested row, into `out`.
+// counters: a counter set (jumps, non-finite samples); hash_sums (nullable) [q] += the path
+// hashes of row q's walks (mod 2^64).
 hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
                               int32_t nrhs, const int64_t *rows, int64_t n_rows,
                               uint32_t walk0, uint32_t M, uint32_t chunk, uint32_t chunks,
-                              double *partial, unsigned long long *counters,
+                              const SumsOut &out, unsigned long long *counters,
                               unsigned long long *hash_sums, hipStream_t s);
 
 // out1/out2[q * nrhs + r] (=, or += when accumulate) the chunk sums of the partials.

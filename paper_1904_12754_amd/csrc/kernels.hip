@@ -11,6 +11,22 @@
 namespace mlmc {
 namespace {
 
+// Sums of item-and-right-hand-side index i (with one chunk per row, i is also the output's
+// (row, rhs) index).
+__device__ __forceinline__ void store_sums(const SumsOut &o, uint64_t i, double a, double b)
+{
+    if (o.direct == 0) {
+        o.partial[i * 2 + 0] = a;
+        o.partial[i * 2 + 1] = b;
+    } else if (o.direct == 1) {
+        o.out1[i] = a;
+        o.out2[i] = b;
+    } else {
+        o.out1[i] += a;
+        o.out2[i] += b;
+    }
+}
+
 __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
@@ -26,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
                                                          uint32_t n_rows, uint32_t walk0,
                                                          uint32_t M, uint32_t chunk,
                                                          uint32_t chunks, uint32_t lpr,
-                                                         double *partial,
+                                                         SumsOut out,
                                                          unsigned long long *counters,
                                                          unsigned long long *hash_sums)
 {
@@ -63,8 +79,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
     const unsigned long long hsum = group_sum_u(sink.hash, lpr);
     if (has && (lane & (lpr - 1)) == 0) {
-        partial[item * 2 + 0] = a;
-        partial[item * 2 + 1] = b;
+        store_sums(out, item, a, b);
         if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
     if (lane == 0) {
@@ -80,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
                                                           const int64_t *__restrict__ rows,
                                                           uint32_t n_rows, uint32_t walk0,
                                                           uint32_t M, uint32_t chunk,
-                                                          uint32_t chunks, double *partial,
+                                                          uint32_t chunks, SumsOut out,
                                                           unsigned long long *counters,
                                                           unsigned long long *hash_sums)
 {
@@ -116,8 +131,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *
                 a += static_cast<double>(nojump) * yr;
                 b += static_cast<double>(nojump) * yr * yr;
             }
-            partial[(item * nrhs + r) * 2 + 0] = a;
-            partial[(item * nrhs + r) * 2 + 1] = b;
+            store_sums(out, item * nrhs + r, a, b);
         }
     }
     if (lane == 0) {
@@ -328,12 +342,13 @@ hipError_t launch_thresholds(RowRec *rec, int64_t n, double dt, unsigned int *ba
 
 hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int u_f64,
                               int32_t nrhs, const int64_t *rows, int64_t n_rows, uint32_t walk0,
-                              uint32_t M, uint32_t chunk, uint32_t chunks, double *partial,
+                              uint32_t M, uint32_t chunk, uint32_t chunks, const SumsOut &out,
                               unsigned long long *counters, unsigned long long *hash_sums,
                               hipStream_t s)
 {
     const uint64_t items = static_cast<uint64_t>(n_rows) * chunks;
     if (items == 0) return hipSuccess;
+    if (out.direct != 0 && chunks != 1) return hipErrorInvalidValue;
     // single right-hand side: groups of lpr lanes (the power of two >= the walks of an item,
     // at most 64) so that items of few walks still fill the wave
     uint32_t lpr = kWave;
@@ -348,15 +363,15 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
         if (nrhs == 1 && L.src)                                                               \
             hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, true>), grid, block, 0, s, L,     \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
-                               lpr, partial, counters, hash_sums);                            \
+                               lpr, out, counters, hash_sums);                                \
         else if (nrhs == 1)                                                                   \
             hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false>), grid, block, 0, s, L,    \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
-                               lpr, partial, counters, hash_sums);                            \
+                               lpr, out, counters, hash_sums);                                \
         else                                                                                  \
             hipLaunchKernelGGL((level_walks_rhs<R, U, H, IS>), grid, block, 0, s, L,          \
                                static_cast<const U *>(u), nrhs, rows, nr, walk0, M, chunk,    \
-                               chunks, partial, counters, hash_sums);                         \
+                               chunks, out, counters, hash_sums);                             \
     } while (0)
 #define MLMC_LAUNCH_WALKS_H(R, U)                                                             \
     do {                                                                                      \
