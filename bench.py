@@ -195,7 +195,9 @@ def tc_bench(args):
     """Total communicability with many right-hand sides: exp(beta A) [1, r_1..r_63] on a
     Barabasi-Albert graph (n = 1e6, m = 5, symmetric 0/1 adjacency stored as FP32),
     beta = 1/d_max, levels l0..l0+4 with 128 walks per row per level, FP32 weights, 64
-    right-hand sides carried by every path."""
+    right-hand sides carried by every path, in one persistent launch (a batch of this one
+    instance replayed from a graph); also timed as five per-level launches of one run, and
+    the forward scalar estimate of the total communicability."""
     import numpy as np
     import torch
 
@@ -228,11 +230,29 @@ def tc_bench(args):
     tc_f, var_f, st_f = plan.functional(ones, ones, eps=sd_back, seed=3, pilot_walks=1 << 16)
     torch.cuda.synchronize()
     t_f = time.perf_counter() - t0
+    # the same five levels as one persistent launch: a batch of this one instance, captured
+    # in a graph and replayed
+    batch = api.Batch([plan], [u], np.array([walks], dtype=np.int64), autotune=True)
+    batch.launch(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        batch.launch(10 + k)
+    torch.cuda.synchronize()
+    el_b = (time.perf_counter() - t0) / args.steps
+    st_b = batch.stats()[0]
+    tc_b = float(batch.xs[0][:, 0].sum().item())
+    info_b = {k: batch.info[k] for k in ("walks_per_item", "waves_per_cu", "phases", "items")}
+    batch.close()
     print(json.dumps({
-        "metric": "walk steps/s", "value": st["steps"] / el, "unit": "steps/s",
-        "ms_per_run": el * 1e3, "walk_kernel_ms": st["walk_kernel_ms"],
-        "rhs_samples_per_s": st["steps"] * u.shape[1] / el,
-        "jumps": st["total_jumps"], "steps": st["steps"],
+        "metric": "walk steps/s", "value": st_b["steps"] / el_b, "unit": "steps/s",
+        "ms_per_launch": el_b * 1e3, "batch": info_b,
+        "rhs_samples_per_s": st_b["steps"] * u.shape[1] / el_b,
+        "jumps": st_b["total_jumps"], "steps": st_b["steps"],
+        "total_communicability_estimate_batch": tc_b,
+        "per_level_runs": {"ms_per_run": el * 1e3, "walk_kernel_ms": st["walk_kernel_ms"],
+                           "steps_per_s": st["steps"] / el,
+                           "note": "the same walks as five launches (one per level) of one run"},
         "total_communicability_estimate": tc,
         "total_communicability_sd": sd_back,
         "forward_scalar": {"estimate": tc_f, "sd": math.sqrt(var_f), "seconds": t_f,
@@ -241,7 +261,8 @@ def tc_bench(args):
                            "note": "Algorithm 1 on the scalar to the backward run's sd"},
         "config": {"workload": f"Barabasi-Albert n={A.n} m=5, beta=1/d_max={beta:.3e}, "
                                f"{u.shape[1]} right-hand sides (ones + Rademacher), "
-                               f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level",
+                               f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level, "
+                               "one persistent launch (graph replay)",
                    "nnz": A.nnz, "d_max": int(round(1 / beta)),
                    "host_s": {"generate": t_gen, "plan": t_plan}},
     }), flush=True)

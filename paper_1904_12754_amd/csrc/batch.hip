@@ -49,7 +49,8 @@ struct Segment {
     uint64_t pair_begin;              // first global (row, rhs) pair of the segment
     double inv_M;
     uint32_t n_rows, M, chunk, chunks;
-    int32_t nrhs, pad;
+    int32_t nrhs;
+    int32_t direct;                   // 1: one chunk per row, the walks write acc themselves
 };
 
 // Each segment's counters are spread over kSegSlots 64-byte slots (the wave's index picks the
@@ -115,8 +116,13 @@ __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict_
             jumps = wave_sum_u(sink.jumps);
             nonfinite = wave_sum_u(sink.nonfinite);
             if (lane == 0) {
-                sg.partial[local * 2 + 0] = a;
-                sg.partial[local * 2 + 1] = b;
+                if (sg.direct) {   // one chunk per row: local is the row
+                    sg.acc[local] = a;
+                    sg.acc[sg.n_rows + local] = b;
+                } else {
+                    sg.partial[local * 2 + 0] = a;
+                    sg.partial[local * 2 + 1] = b;
+                }
             }
         } else {
             const int32_t nrhs = sg.nrhs;
@@ -141,8 +147,14 @@ __global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict_
                         a += static_cast<double>(nojump) * yr;
                         b += static_cast<double>(nojump) * yr * yr;
                     }
-                    sg.partial[(local * nrhs + r) * 2 + 0] = a;
-                    sg.partial[(local * nrhs + r) * 2 + 1] = b;
+                    if (sg.direct) {
+                        const uint64_t count = static_cast<uint64_t>(sg.n_rows) * nrhs;
+                        sg.acc[local * nrhs + r] = a;
+                        sg.acc[count + local * nrhs + r] = b;
+                    } else {
+                        sg.partial[(local * nrhs + r) * 2 + 0] = a;
+                        sg.partial[(local * nrhs + r) * 2 + 1] = b;
+                    }
                 }
             }
         }
@@ -169,7 +181,8 @@ __global__ void batch_set_key(BatchParams *prm, uint32_t k0, uint32_t k1)
     }
 }
 
-// acc of every segment from its chunk partials (fixed order).
+// acc of every segment from its chunk partials (fixed order); segments of one chunk per row
+// were written by the walks.
 __global__ void batch_finalize(const Segment *__restrict__ segs, int32_t nseg, uint64_t total_pairs)
 {
     const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -181,6 +194,7 @@ __global__ void batch_finalize(const Segment *__restrict__ segs, int32_t nseg, u
         else hi = mid - 1;
     }
     const Segment &sg = segs[lo];
+    if (sg.direct) return;
     const uint64_t local = t - sg.pair_begin;
     const uint64_t q = local / sg.nrhs, r = local % sg.nrhs;
     double a = 0.0, b = 0.0;
@@ -409,6 +423,7 @@ int build_tables(mlmc_batch *b, hipStream_t s)
         Segment &sg = b->h_segs[g];
         sg.partial = b->d_partial + reinterpret_cast<uintptr_t>(sg.partial);
         sg.acc = b->d_acc + acc_off;
+        sg.direct = sg.chunks == 1 ? 1 : 0;
         acc_off += 2ull * sg.n_rows * sg.nrhs;
         sg.counters = b->d_counters + kSegSetU64 * g;
     }
