@@ -233,6 +233,31 @@ def test_adaptive_run_reaches_target(api):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adaptive_run_equals_the_oracle_at_its_final_sample_sizes(api, precision):
+    """Algorithm 1 adds walks to levels it already sampled: the added walk ranges are summed
+    into the accumulators (straight from the kernel when a row's new walks form one chunk,
+    through the partials otherwise). Walks are addressed by counters, so the final estimate
+    equals the oracle's fixed-schedule estimate at the final sample sizes: same jumps, sums
+    within the bars. 16384 rows, so each row's walks of a call form a single item."""
+    A, t, v = inputs.workload_laplace2d(128)
+    dt = np.float64 if precision == "fp64" else np.float32
+    u = v.astype(dt)
+    plan = api.Plan(A, t, precision=precision)
+    x, st = plan.run(torch.as_tensor(u, device="cuda"), eps=3e-2, seed=12, pilot_walks=200,
+                     max_levels=8)
+    nl = st["num_levels"]
+    walks = st["walks"][:nl]
+    _say(f"adaptive {precision}: levels {nl}, walks {walks}")
+    assert any(w > 200 for w in walks)          # Algorithm 1 added walks after the pilot
+    tt = _tables(A)
+    res = orc.mlmc_fixed(tt, t, u.astype(np.float64), plan.l0, plan.l0 + nl - 1, walks, seed=12)
+    assert st["total_jumps"] == res.jumps
+    xg = x.cpu().numpy()[:, 0]
+    assert np.all(np.abs(xg - res.x[:, 0]) <= TOL[precision] * res.mass[:, 0] + 1e-300)
+    plan.close()
+
+
 def test_classical_single_level_mc_estimates_the_finest_strang_product(api):
     """Classical Monte Carlo is the base estimator at one fine level L: a plan with l0 = L
     and one level. Its expectation is the Strang product x^L, the same as that of MLMC on
