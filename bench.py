@@ -337,6 +337,8 @@ def learned_bench(args):
         out["targets"].append({
             "eps": eps, "plain": summary(stp, tp), "learned": summary(stl, tl),
             "speedup_solve": tp / tl, "speedup_incl_training": tp / (tl + t_train),
+            # solves with the same trained proposal after which the training has paid off
+            "solves_to_amortize_training": t_train / (tp - tl) if tp > tl else None,
             "variance_ratio_l0": stp["level_var"][0] / max(stl["level_var"][0], 1e-300),
             "rms_learned_minus_plain": float(np.sqrt(np.mean(d * d))),
         })
