@@ -231,11 +231,13 @@ void mlmc_expv_destroy(mlmc_plan_t *plan);
 
 /* ---- batched runs ------------------------------------------------------------------
  * Many plans (different matrices, right-hand sides or times) with fixed level schedules
- * in one persistent launch: every (instance, level) is split into items of whole walks of
- * one row, and the waves of a persistent grid take the items in a fixed interleaved order
- * (wave w takes items w, w + waves, ...), so instances of very different sizes share the
- * chip in a single launch. Plans with an active proposal are rejected. The sequence (reset, walks, per-row
- * sums, per-instance FP64 combine of the levels, section 2.2) is captured once in a
+ * in a few persistent launches: every (instance, level) is split into items of whole walks
+ * of one row, and the waves of a persistent grid take the items in a fixed interleaved
+ * order (wave w takes items w, w + waves, ...), so instances of very different sizes share
+ * the chip without a launch per instance; the item space runs as a sequence of launches
+ * over consecutive item ranges (phases), which keeps the waves on a few instances at a
+ * time. Plans with an active proposal are rejected. The sequence (reset, walk phases,
+ * per-row sums, per-instance FP64 combine of the levels, section 2.2) is captured once in a
  * hipGraph at creation and replayed by mlmc_expv_batch_launch. Instance b draws the
  * random streams of instance number b (the `instance` of a single run), so its estimate
  * follows the same paths as mlmc_expv_run(plans[b], ..., instance = b) with the same seed
