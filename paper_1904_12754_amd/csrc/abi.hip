@@ -157,6 +157,18 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
     L.base = (level == p->l0);
     L.dt = std::ldexp(p->beta, -level);
     L.half_dt = L.dt * 0.5;
+    // FP32 bounds for the walk kernels' certified comparison of a chain's holding time with
+    // dt. A float rounds its value by at most 2^-24 relative, so a bracket whose upper end
+    // sums in FP32 below dt_below (<= dt (1 - 2^-21)(1 + 2^-24)) lies below dt, and one whose
+    // lower end is at or above dt_above lies at or above dt. Outside [2^-100, 2^100] every
+    // decision takes the exact FP64 path.
+    if (L.dt > 0x1p-100 && L.dt < 0x1p+100) {
+        L.dt_below = static_cast<float>(L.dt * (1.0 - 0x1p-21));
+        L.dt_above = static_cast<float>(L.dt * (1.0 + 0x1p-21));
+    } else {
+        L.dt_below = -INFINITY;
+        L.dt_above = INFINITY;
+    }
     L.k0 = static_cast<uint32_t>(seed);
     L.k1 = static_cast<uint32_t>(seed >> 32);
     L.c3_step = stream_word(level, instance, 0);

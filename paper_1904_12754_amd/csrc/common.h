@@ -70,15 +70,26 @@ __host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b)
 #endif
 }
 
+// a ^ b ^ c: one v_bitop3_b32 on gfx950 (truth table 0x96), where the compiler would emit
+// two v_xor_b32
+__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 __host__ __device__ __forceinline__ Word4 philox10(Word4 c, uint32_t k0, uint32_t k1)
 {
-    // the 32x32->64 products map to one v_mad_u64_u32 each on gfx950
+    // a round is two v_mad_u64_u32 (the 32x32->64 products) and two v_bitop3_b32
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c.x;
         const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
-        c = Word4{static_cast<uint32_t>(pb >> 32) ^ c.y ^ k0, static_cast<uint32_t>(pb),
-                  static_cast<uint32_t>(pa >> 32) ^ c.w ^ k1, static_cast<uint32_t>(pa)};
+        c = Word4{xor3(static_cast<uint32_t>(pb >> 32), c.y, k0), static_cast<uint32_t>(pb),
+                  xor3(static_cast<uint32_t>(pa >> 32), c.w, k1), static_cast<uint32_t>(pa)};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

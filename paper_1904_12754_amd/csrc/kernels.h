@@ -17,6 +17,7 @@ struct LevelArgs {
     int32_t base;            // 1 at the coarsest level l0 (sample u eta_fine only)
     double dt;               // beta / 2^level
     double half_dt;
+    float dt_below, dt_above;  // FP32 bounds around dt for the certified holding-time test
     uint32_t k0, k1;         // Philox key (seed)
     uint32_t c3_step, c3_jump;
 };

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *_
     const uint32_t row = rows ? static_cast<uint32_t>(rows[q]) : q;
     const uint64_t wb = has ? static_cast<uint64_t>(c) * chunk : 0ull;
     const uint64_t we = has ? min(wb + chunk, static_cast<uint64_t>(M)) : 0ull;
-    SinkR1<R, U> sink{u, static_cast<const U *>(L.src)};
+    SinkR1<R, U, kSrc> sink{u, static_cast<const U *>(L.src)};
     bool done = false;
     if constexpr (!kIS && !kSrc) {
         // one item per wave: its row and walk range are wave-uniform, so the engine's group

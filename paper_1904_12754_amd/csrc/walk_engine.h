@@ -45,6 +45,14 @@ __device__ __forceinline__ double d_of<double>(const RowRec &r) { return r.d64; 
 
 __device__ __forceinline__ float expR(float x) { return expf(x); }
 __device__ __forceinline__ double expR(double x) { return exp(x); }
+
+// e^{a h} for an exponent sum a and its scale h: in FP32 one v_exp_f32 of a * (h log2 e) (the
+// rounding of the scaled exponent is of the order of that of a h itself), in FP64 exp(a h).
+__device__ __forceinline__ float exp_scaled(float a, float h)
+{
+    return __builtin_amdgcn_exp2f(a * (h * 0x1.715476p+0f));
+}
+__device__ __forceinline__ double exp_scaled(double a, double h) { return exp(a * h); }
 __device__ __forceinline__ float expm1R(float x) { return expm1f(x); }
 __device__ __forceinline__ double expm1R(double x) { return expm1(x); }
 
@@ -247,14 +255,17 @@ __device__ __forceinline__ ScanOut scan_block(uint32_t b0, uint32_t b1, uint32_t
     return o;
 }
 
+// What a lane does: scans the step words of its walk, follows a chain of jumps of step n,
+// waits (its walk has ended while its slot for finished walks was full), or has no walk.
+constexpr uint32_t kScan = 0, kJump = 1, kWait = 2, kIdle = 3;
+
 template <typename R, bool kHash>
 struct Walker {
     // per-lane state of the current walk
-    bool active = false;
+    uint32_t st = kIdle;
     uint32_t w = 0, k = 0, neg = 0, J = 0, run_start = 0, n = 0;
-    uint32_t row0 = 0;                    // the walk's start row (its counters' row)
-    uint32_t jumping = 0;                 // 1 while a jump of step n is pending; 2 once the
-                                          // walk has ended and waits for a free slot
+    uint32_t row0 = 0;                    // the walk's start row (its counters' row), when
+                                          // it differs between walks
     uint32_t bq = 0xFFFFFFFFu;            // index of the cached step block
     uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
     RowRec cur;
@@ -312,7 +323,7 @@ struct Pending {
     __device__ __forceinline__ Finished<R> finished(int base, R hd) const
     {
         Finished<R> f{k, jumps, static_cast<R>(0), hash, static_cast<R>(0)};
-        const R v = (base ? expR(e1 * hd) : expR(e1 * hd) * expm1R(e2 * hd)) * wr;
+        const R v = (base ? exp_scaled(e1, hd) : exp_scaled(e1, hd) * expm1R(e2 * hd)) * wr;
         f.W = neg ? -v : v;
         if constexpr (kSrc) f.src = src;
         return f;
@@ -407,6 +418,7 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
 // Start of a walk: every walk of the range starts at one row (the backward representation
 // of a single entry) ...
 struct FixedStart {
+    static constexpr bool kPerLaneRow = false;   // the counters' row is `row` for every walk
     uint32_t row;
     RowRec rec;
     __device__ __forceinline__ void pick(const LevelArgs &, uint32_t, uint32_t &r, RowRec &rr,
@@ -416,11 +428,13 @@ struct FixedStart {
         rr = rec;
         neg = 0;
     }
+    __device__ __forceinline__ uint32_t start_row() const { return row; }
 };
 
 // ... or walk m starts at row l with probability |u_l| / U, drawn from the alias table over
 // rows with the words of the block (0, m, 0, stream 2); the walk then carries sign(u_l).
 struct AliasStart {
+    static constexpr bool kPerLaneRow = true;
     const uint32_t *thr;
     const int32_t *alias;
     const uint8_t *neg;
@@ -435,6 +449,7 @@ struct AliasStart {
         rr = L.rec[r];
         ng = neg[r];
     }
+    __device__ __forceinline__ uint32_t start_row() const { return 0u; }   // per lane instead
 };
 
 template <typename R, bool kHash, bool kIS, bool kSrc, typename Sink, typename Start>
@@ -456,7 +471,6 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                                                 uint64_t wb, uint64_t we, Sink &sink, uint32_t lpr)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t lower = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));   // lanes below
     const uint64_t group = lpr >= kWave ? ~0ull : ((1ull << lpr) - 1ull) << (lane & ~(lpr - 1u));
     const R hd = static_cast<R>(L.half_dt);
     Walker<R, kHash> s;
@@ -464,21 +478,24 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
     uint64_t pool = wb;                    // next unassigned walk of the group
     for (;;) {
         // ---- refill idle lanes with the next walks of the group's range
-        const uint64_t idle = __ballot(!s.active) & group;
+        const uint64_t idle = __ballot(s.st == kIdle) & group;
         if (idle) {
-            const uint64_t mine = pool + __popcll(idle & lower);
-            if (!s.active && mine < we) {
-                s.active = true;
+            // the idle lanes of the group below this one (v_mbcnt)
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(idle >> 32),
+                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(idle), 0u));
+            const uint64_t mine = pool + below;
+            if (s.st == kIdle && mine < we) {
+                s.st = kScan;
                 s.w = walk0 + static_cast<uint32_t>(mine);
                 uint32_t r0 = 0, ng = 0;
                 st.pick(L, s.w, r0, s.cur, ng);
-                s.row0 = r0;
+                if constexpr (Start::kPerLaneRow) s.row0 = r0;
                 s.k = r0;
                 s.neg = ng;
                 s.J = 0;
                 s.run_start = 0;
                 s.n = 0;
-                s.jumping = 0;
                 s.bq = 0xFFFFFFFFu;
                 s.ef2 = s.ec2 = s.ed2 = 0;
                 s.wr = 1;
@@ -487,16 +504,18 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
             }
             pool += __popcll(idle);
         }
-        if (__ballot(s.active) == 0) break;
+        if (__ballot(s.st != kIdle) == 0) break;
 
-        // ---- at most one Philox block per busy lane
-        const bool jumping = s.active && s.jumping == 1u;
-        const bool scanning = s.active && s.jumping == 0u;
+        // ---- at most one Philox block per busy lane: the block is evaluated for every lane
+        // (the wave issues it whenever one lane needs it) and used by the lanes that jump
+        // or that scanned past their cached block
+        const bool jumping = s.st == kJump;
+        const bool scanning = s.st == kScan;
         const uint32_t q = s.n >> 2;
-        Word4 ph{0u, 0u, 0u, 0u};
-        if (jumping || (scanning && s.bq != q))
-            ph = philox10(Word4{jumping ? s.J : q, s.w, s.row0, jumping ? L.c3_jump : L.c3_step},
-                          L.k0, L.k1);
+        const uint32_t row0 = Start::kPerLaneRow ? s.row0 : st.start_row();
+        const Word4 ph = philox10(Word4{jumping ? s.J : q, s.w, row0,
+                                        jumping ? L.c3_jump : L.c3_step},
+                                  L.k0, L.k1);
 
         bool finish = false;
         if (jumping) {
@@ -521,17 +540,18 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 const float e = neg_log_uniform_fast(ph.z);
                 s.tau_h = s.tau_h + e * ir;
                 s.tau_e = s.tau_e + (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
-                const double hi = static_cast<double>(s.tau_h) + static_cast<double>(s.tau_e);
-                const double lo = static_cast<double>(s.tau_h) - static_cast<double>(s.tau_e);
-                if (hi < L.dt) chain_over = false;
-                else if (lo >= L.dt) chain_over = true;
-                else chain_over = !(chain_tau_exact<kIS>(L, s.row0, s.w, s.chain_k, s.chain_J, s.J,
+                // the ends of the bracket in FP32; dt_below and dt_above absorb their rounding
+                const float hi = s.tau_h + s.tau_e;
+                const float lo = s.tau_h - s.tau_e;
+                if (hi < L.dt_below) chain_over = false;
+                else if (lo >= L.dt_above) chain_over = true;
+                else chain_over = !(chain_tau_exact<kIS>(L, row0, s.w, s.chain_k, s.chain_J, s.J,
                                                          s.chain_word) < L.dt);
             }
             if (chain_over) {
                 // the chain of step n ends: the walk scans on from step n + 1 (below, in
                 // this iteration when that step is in the cached block)
-                s.jumping = 0;
+                s.st = kScan;
                 s.n = s.n + 1;
                 s.run_start = s.n;
                 finish = s.n == L.N;
@@ -548,7 +568,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         // just ended inside the cached block (one code path for both)
         bool chain = false;
         uint32_t chain_word = 0;
-        if (s.active && !s.jumping && !finish && (s.n >> 2) == s.bq) {
+        if (s.st == kScan && !finish && (s.n >> 2) == s.bq) {
             const ScanOut so = scan_block(s.b0, s.b1, s.b2, s.b3, s.cur.thr, s.n, L.N);
             // the step's holding time at k is below dt: a chain of jumps starts
             chain = so.jump;
@@ -564,7 +584,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         }
         if (chain) {
             chain_start(s, chain_word);
-            s.jumping = 1;
+            s.st = kJump;
         }
 
         // ---- the end of a walk: its exponents wait in the lane's slot, and the slots are
@@ -575,38 +595,41 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         if (finish) {
             if (!pend.valid) {
                 pend.hold(s, L.base, hd);
-                s.active = false;
+                s.st = kIdle;
             } else {
-                s.jumping = 2u;
+                s.st = kWait;
             }
         }
-        const uint64_t waiting = __ballot(s.active && s.jumping == 2u);
+        const uint64_t waiting = __ballot(s.st == kWait);
         if (__popcll(__ballot(pend.valid)) >= kFlushAt ||
             (waiting != 0 && (__popcll(waiting) >= kMaxWaiting ||
-                              __ballot(s.active && s.jumping != 2u) == 0))) {
+                              __ballot(s.st < kWait) == 0))) {
             sink.take(pend.valid, pend.finished(L.base, hd));
             pend.valid = false;
-            if (s.active && s.jumping == 2u) {
+            if (s.st == kWait) {
                 pend.hold(s, L.base, hd);
-                s.active = false;
+                s.st = kIdle;
             }
         }
     }
     sink.take(pend.valid, pend.finished(L.base, hd));
 }
 
-// Single right-hand side: each lane adds its own samples to compensated sums.
-template <typename R, typename U>
+// Single right-hand side: each lane adds its own samples to compensated sums (kSrc: the
+// samples carry a source-term part).
+template <typename R, typename U, bool kSrc = false>
 struct SinkR1 {
     const U *u;
     const U *F;       // source vector (Algorithm 3), or null
     Kahan<R> s1, s2;
-    unsigned long long jumps = 0, nonfinite = 0, hash = 0;
+    unsigned long long jumps = 0, hash = 0;
+    uint32_t nonfinite = 0;   // a lane evaluates fewer than 2^32 samples in a launch
     __device__ __forceinline__ R source(uint32_t k) const { return static_cast<R>(F[k]); }
     __device__ __forceinline__ void take(bool done, const Finished<R> &f)
     {
         if (!done) return;
-        const R y = f.W * static_cast<R>(u[f.k]) + f.src;
+        R y = f.W * static_cast<R>(u[f.k]);
+        if constexpr (kSrc) y += f.src;
         jumps += f.jumps;
         hash += f.hash;
         nonfinite += !isfinite(y);
