@@ -24,13 +24,16 @@ if ROOT not in sys.path:
 
 # Algorithmic VALU work of the walk kernel, in lane-instructions of a minimal gfx950
 # sequence: a step consumes a quarter of a Philox4x32-10 block (10 rounds of two
-# v_mad_u64_u32 and four v_xor_b32: 60 per block, 15 per step) and one compare; a jump
-# consumes one block (60), the alias selection and gather addressing (~8), the holding-time
-# bracket (~8) and the run update of the weights (~9); a walk end evaluates exp/expm1 of
-# its weights and adds to the compensated sums (~45).
-OPS_PER_STEP = 16
-OPS_PER_JUMP = 85
-OPS_PER_WALK = 45
+# v_mad_u64_u32 and two v_bitop3_b32 three-input xors: 40 per block, 10 per step) and one
+# compare; a jump consumes one block (40), the alias selection and gather addressing (~8),
+# the holding-time bracket (~8) and the run update of the weights (~9); a walk end scales
+# and exponentiates its exponent and applies the sign (3), gathers u and multiplies (2),
+# adds to the two compensated sums (9) and to the counters (3), plus an expm1 (~23) above
+# the base level.
+OPS_PER_STEP = 11
+OPS_PER_JUMP = 65
+OPS_PER_WALK_BASE = 17
+OPS_PER_WALK_ABOVE = 40
 # MI355X vector ALU: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz (the FP32 vector rate
 # of 157.3 TFLOP/s counts two flops per FMA lane)
 VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
@@ -557,13 +560,15 @@ def main():
     steps = sum(s["steps"] for s in stats)
     jumps = sum(s["total_jumps"] for s in stats)
     walks_total = sum(sum(s["walks"]) * plan.n_rows for s in stats)
+    walks_base = sum(s["walks"][0] * plan.n_rows for s in stats)
     wk_ms = sum(s["walk_kernel_ms"] for s in stats)
     launches = sum(s["walk_launches"] for s in stats)
     last = stats[-1]
     xg = x.cpu().numpy()[:, 0]
     true_rmse = float(np.sqrt(np.mean((xg - x_exact) ** 2)))
 
-    ops = OPS_PER_STEP * steps + OPS_PER_JUMP * jumps + OPS_PER_WALK * walks_total
+    ops = (OPS_PER_STEP * steps + OPS_PER_JUMP * jumps + OPS_PER_WALK_BASE * walks_base +
+           OPS_PER_WALK_ABOVE * (walks_total - walks_base))
     achieved = ops / (wk_ms * 1e-3)
     roofline = {
         "bound": "alu",
@@ -574,7 +579,8 @@ def main():
         "frac": achieved / VALU_PEAK_LANE_OPS,
         "traffic": kernel_traffic(walks_total / max(launches, 1)),
         "per_unit": {"ops_per_step": OPS_PER_STEP, "ops_per_jump": OPS_PER_JUMP,
-                     "ops_per_walk": OPS_PER_WALK},
+                     "ops_per_walk_base": OPS_PER_WALK_BASE,
+                     "ops_per_walk_above": OPS_PER_WALK_ABOVE},
         "launch_avg_ms": wk_ms / max(launches, 1),
         "launches": launches,
         "gathered_GBps": BYTES_PER_JUMP * jumps / (wk_ms * 1e-3) / 1e9,
