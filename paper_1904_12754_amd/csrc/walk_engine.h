@@ -258,6 +258,7 @@ __device__ __forceinline__ ScanOut scan_block(uint32_t b0, uint32_t b1, uint32_t
 // What a lane does: scans the step words of its walk, follows a chain of jumps of step n,
 // waits (its walk has ended while its slot for finished walks was full), or has no walk.
 constexpr uint32_t kScan = 0, kJump = 1, kWait = 2, kIdle = 3;
+static_assert(kScan == 0 && kJump == 1, "the stream word of a lane's block is c3_step + state");
 
 template <typename R, bool kHash>
 struct Walker {
@@ -513,8 +514,9 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         const bool scanning = s.st == kScan;
         const uint32_t q = s.n >> 2;
         const uint32_t row0 = Start::kPerLaneRow ? s.row0 : st.start_row();
-        const Word4 ph = philox10(Word4{jumping ? s.J : q, s.w, row0,
-                                        jumping ? L.c3_jump : L.c3_step},
+        // stream word: c3_step + 1 == c3_jump and kJump == 1, kScan == 0 (the sum is
+        // meaningless for waiting and idle lanes, which do not use the block)
+        const Word4 ph = philox10(Word4{jumping ? s.J : q, s.w, row0, L.c3_step + s.st},
                                   L.k0, L.k1);
 
         bool finish = false;
