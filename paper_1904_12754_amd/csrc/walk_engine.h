@@ -404,7 +404,7 @@ template <typename R, bool kHash>
 __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
 {
     const float e = neg_log_uniform_fast(word);
-    const float ir = static_cast<float>(s.cur.inv_r);      // finite: this state jumps
+    const float ir = static_cast<float>(s.cur.inv_r);      // this state jumps (r > 0)
     s.tau_h = e * ir;
     s.tau_e = (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
     s.chain_k = s.k;
@@ -533,10 +533,12 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 s.hash = (s.hash ^ static_cast<uint64_t>(s.n + 1)) * kFnvPrime;
             }
             // add the holding time at the new state; the chain goes on while the total is
-            // below dt (an absorbing state holds forever)
+            // below dt. An absorbing state (1/r infinite in FP64) holds forever; a rate so
+            // small that only the FP32 copy of 1/r is infinite makes the bracket infinite or
+            // NaN, and every comparison with one sends the decision to the exact path.
             const float ir = static_cast<float>(s.cur.inv_r);
             bool chain_over;
-            if (!(ir < INFINITY)) {
+            if (!(s.cur.inv_r < INFINITY)) {
                 chain_over = true;
             } else {
                 const float e = neg_log_uniform_fast(ph.z);

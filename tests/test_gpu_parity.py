@@ -94,6 +94,29 @@ def test_trace_bit_exact_signed_all_levels(api, precision):
                  instance=9)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("scale", [1e32, 1e-34])
+def test_exact_decisions_at_extreme_time_scales(api, precision, scale):
+    """e^{beta A} is unchanged when A is scaled by s and beta by 1/s. At these scales dt lies
+    outside [2^-100, 2^100], where the kernels' FP32 bounds around dt are switched off and
+    every chain decision takes the exact FP64 path: paths bit-exact at levels 0..4 and level
+    sums within the bars."""
+    a = _signed(40, 3, density=0.3) * scale
+    A = inputs.from_dense(a)
+    beta = 0.3 / scale
+    rng = np.random.default_rng(12)
+    rows = rng.integers(0, A.n, size=2048)
+    walks = rng.integers(0, 2 ** 32, size=2048, dtype=np.uint64).astype(np.uint32)
+    _check_trace(api, A, beta, precision, range(0, 5), rows, walks, seed=4242, l0=0)
+    u = rng.normal(size=A.n)
+    _check_level_sums(api, A, beta, u, precision, 3, 512, seed=31)
+    t = _tables(A)
+    l0 = orc.default_l0(t, beta)
+    for lev in (0, 4, l0, l0 + 2):
+        dt = beta / 2 ** lev
+        assert dt < 2.0 ** -100 or dt > 2.0 ** 100, (lev, dt)
+
+
 def _mass_tol(o_ls, prec):
     return TOL[prec] * (o_ls.mass + 1e-300)
 
