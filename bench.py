@@ -37,6 +37,8 @@ OPS_PER_WALK_ABOVE = 40
 # MI355X vector ALU: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz (the FP32 vector rate
 # of 157.3 TFLOP/s counts two flops per FMA lane)
 VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# MI355X HBM3E peak bandwidth
+HBM_PEAK_BPS = 8.0e12
 # bytes the jumps must gather: one 16-byte alias slot and one 32-byte row record
 BYTES_PER_JUMP = 48
 # HBM traffic of the walk kernel from the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
@@ -584,6 +586,9 @@ def main():
         "launch_avg_ms": wk_ms / max(launches, 1),
         "launches": launches,
         "gathered_GBps": BYTES_PER_JUMP * jumps / (wk_ms * 1e-3) / 1e9,
+        # the same algorithmic gather rate against the HBM peak (the gathers are served by the
+        # caches, so this is the gather-bound roofline, not the kernel's binding limit)
+        "gathered_frac_of_hbm_peak": BYTES_PER_JUMP * jumps / (wk_ms * 1e-3) / HBM_PEAK_BPS,
     }
     line = {
         "metric": "walk steps/s",
