@@ -812,6 +812,41 @@ __global__ __launch_bounds__(kGradParams * kGradGroups) void grad_sum_kernel(
     P[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
 }
 
+// Sum of n floats in FP64 in a fixed order (thread t adds t, t + 256, ...; the 256 partial
+// sums meet in a fixed tree): the loss of a minibatch or of the held-out set, kept on the
+// device so that the training loop does not wait for the host.
+__global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__ x, int n, double *out)
+{
+    __shared__ double sh[256];
+    const int t = static_cast<int>(threadIdx.x);
+    double acc = 0.0;
+    for (int i = t; i < n; i += 256) acc += static_cast<double>(x[i]);
+    sh[t] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) sh[t] += sh[t + o];
+        __syncthreads();
+    }
+    if (t == 0) *out = sh[0];
+}
+
+// The parameters of the lowest held-out loss so far: when *val < *best_val, P is copied to
+// best and the step recorded. One workgroup: every thread reads best_val before the barrier,
+// thread 0 writes it after.
+__global__ __launch_bounds__(256) void keep_best_kernel(const double *__restrict__ val, int step,
+                                                        double *best_val, int *best_step,
+                                                        const float *__restrict__ P, float *best)
+{
+    const bool better = *val < *best_val;
+    __syncthreads();
+    if (!better) return;
+    for (int i = static_cast<int>(threadIdx.x); i < NPARAM; i += 256) best[i] = P[i];
+    if (threadIdx.x == 0) {
+        *best_val = *val;
+        *best_step = step;
+    }
+}
+
 uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
 int train_blocks(int B) { return std::min(kMaxTrainBlocks, (B + kTC - 1) / kTC); }
@@ -1160,34 +1195,43 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
     const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
     const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
+    const bool training = n_train > 0 && o->steps > 0;
+    // the steps after which the minibatch loss is recorded (and, after the first, the
+    // held-out loss evaluated): the first, every kEvalEvery-th and the last
+    auto eval_after = [&](int step) { return step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0; };
+    int n_eval = 0;
+    if (training)
+        for (int step = 0; step < o->steps; ++step) n_eval += eval_after(step) ? 1 : 0;
+    // device records: minibatch losses [n_eval], held-out losses [1 + n_eval] (the initial
+    // parameters first), the best held-out loss and its step
+    double *d_loss = nullptr, *d_val = nullptr, *d_best_val = nullptr;
+    int *d_best_step = nullptr;
     if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&best, NPARAM)) ||
         (rc = ss.alloc(&part, static_cast<size_t>(train_blocks(B)) * NPARAM)) || (rc = ss.alloc(&lossb, B)) ||
-        (rc = ss.alloc(&lossv, V)))
+        (rc = ss.alloc(&lossv, V)) || (rc = ss.alloc(&d_loss, static_cast<size_t>(n_eval))) ||
+        (rc = ss.alloc(&d_val, static_cast<size_t>(n_eval) + 1)) || (rc = ss.alloc(&d_best_val, 1)) ||
+        (rc = ss.alloc(&d_best_step, 1)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
     MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
-    std::vector<double> losses;
-    std::vector<float> lbv(V);
+    MLMC_HIP_TRY(hipMemsetAsync(d_best_step, 0, sizeof(int), s));
     const BatchSrc vsrc{v_row, v_slot, v_w, std::max<uint64_t>(n_val, 1), 0, 1};
     const float shrink = static_cast<float>(o->shrink);
-    auto val_loss = [&](double &out) -> int {
+    // held-out loss of the current parameters into *out (on the device)
+    auto val_loss = [&](double *out) -> int {
         MLMC_HIP_TRY(train_pass(false, p->prop_P, F, p, level, vsrc, static_cast<int>(n_val), shrink, part, lossv, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(lbv.data(), lossv, n_val * sizeof(float), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipStreamSynchronize(s));
-        double acc = 0.0;
-        for (uint64_t i = 0; i < n_val; ++i) acc += lbv[i];
-        out = acc;
+        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, lossv, static_cast<int>(n_val), out);
+        MLMC_HIP_TRY(hipGetLastError());
         return MLMC_OK;
     };
-    double first_val = 0.0, best_val = 0.0;
-    int best_step = 0;
     if (n_val > 0) {
-        if ((rc = val_loss(first_val))) return rc;
-        best_val = first_val;
+        if ((rc = val_loss(d_val))) return rc;
+        MLMC_HIP_TRY(hipMemcpyAsync(d_best_val, d_val, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    if (n_train > 0 && o->steps > 0) {
+    int n_val_evals = 0;
+    if (training) {
         auto gcd = [](uint64_t a, uint64_t b) {
             while (b) {
                 const uint64_t t = a % b;
@@ -1200,7 +1244,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         while (n_train > 1 && (mult == 0 || gcd(mult, n_train) != 1)) mult = (mult + 1) % n_train;
         const float b1 = 0.9f, b2 = 0.999f;
         const int blocks = train_blocks(B);
-        std::vector<float> lb(B);
+        int e = 0;
         for (int step = 0; step < o->steps; ++step) {
             const BatchSrc src{tr_row, tr_slot, tr_w, n_train, static_cast<uint64_t>(step) * B, mult};
             MLMC_HIP_TRY(train_pass(true, p->prop_P, F, p, level, src, B, shrink, part, lossb, s));
@@ -1210,26 +1254,32 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
                                0, s, part, blocks, nullptr, p->prop_P, m, v, static_cast<float>(o->lr), b1, b2,
                                1e-8f, c1, c2);
             MLMC_HIP_TRY(hipGetLastError());
-            if (step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0) {
-                MLMC_HIP_TRY(hipMemcpyAsync(lb.data(), lossb, B * sizeof(float), hipMemcpyDeviceToHost, s));
-                MLMC_HIP_TRY(hipStreamSynchronize(s));
-                double Ls = 0.0;
-                for (float x : lb) Ls += x;
-                losses.push_back(Ls);
+            if (eval_after(step)) {
+                hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, lossb, B, d_loss + e);
+                MLMC_HIP_TRY(hipGetLastError());
+                ++e;
                 if (n_val > 0 && step > 0) {
-                    double vl = 0.0;
-                    if ((rc = val_loss(vl))) return rc;
-                    if (vl < best_val) {
-                        best_val = vl;
-                        best_step = step + 1;
-                        MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
-                    }
+                    ++n_val_evals;
+                    if ((rc = val_loss(d_val + n_val_evals))) return rc;
+                    hipLaunchKernelGGL(keep_best_kernel, dim3(1), dim3(256), 0, s, d_val + n_val_evals, step + 1,
+                                       d_best_val, d_best_step, p->prop_P, best);
+                    MLMC_HIP_TRY(hipGetLastError());
                 }
             }
         }
         if (n_val > 0) MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, best, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
+    std::vector<double> losses(static_cast<size_t>(n_eval));
+    double first_val = 0.0, best_val = 0.0;
+    int best_step = 0;
     MLMC_HIP_TRY(hipMemcpyAsync(P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (n_eval > 0)
+        MLMC_HIP_TRY(hipMemcpyAsync(losses.data(), d_loss, losses.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (n_val > 0) {
+        MLMC_HIP_TRY(hipMemcpyAsync(&first_val, d_val, sizeof(double), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(&best_val, d_best_val, sizeof(double), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(&best_step, d_best_step, sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     // 4. the levels' tables from the trained parameters and the pilot estimate
     if ((rc = set_proposal(p, P.data(), p->prop_xhat, o->num_levels, s))) return rc;
