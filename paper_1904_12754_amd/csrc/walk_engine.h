@@ -596,23 +596,34 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         // kMaxWaiting lanes have ended a walk while their slot was full (they wait, without
         // a new walk, for the evaluation), when no lane is still walking, or after the last
         // walk
+        // At the coarsest level the sample is one exponential, so a sink that adds each
+        // lane's samples on its own lane takes it at once (the lane's samples are added in
+        // the order its walks end either way, so the sums are the same).
+        const bool direct = Sink::kLaneLocal && L.base != 0;
         if (finish) {
-            if (!pend.valid) {
+            if (direct) {
+                Pending<R, kSrc> now;
+                now.hold(s, 1, hd);
+                sink.take(true, now.finished(1, hd));
+                s.st = kIdle;
+            } else if (!pend.valid) {
                 pend.hold(s, L.base, hd);
                 s.st = kIdle;
             } else {
                 s.st = kWait;
             }
         }
-        const uint64_t waiting = __ballot(s.st == kWait);
-        if (__popcll(__ballot(pend.valid)) >= kFlushAt ||
-            (waiting != 0 && (__popcll(waiting) >= kMaxWaiting ||
-                              __ballot(s.st < kWait) == 0))) {
-            sink.take(pend.valid, pend.finished(L.base, hd));
-            pend.valid = false;
-            if (s.st == kWait) {
-                pend.hold(s, L.base, hd);
-                s.st = kIdle;
+        if (!direct) {
+            const uint64_t waiting = __ballot(s.st == kWait);
+            if (__popcll(__ballot(pend.valid)) >= kFlushAt ||
+                (waiting != 0 && (__popcll(waiting) >= kMaxWaiting ||
+                                  __ballot(s.st < kWait) == 0))) {
+                sink.take(pend.valid, pend.finished(L.base, hd));
+                pend.valid = false;
+                if (s.st == kWait) {
+                    pend.hold(s, L.base, hd);
+                    s.st = kIdle;
+                }
             }
         }
     }
@@ -623,6 +634,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
 // samples carry a source-term part).
 template <typename R, typename U, bool kSrc = false>
 struct SinkR1 {
+    static constexpr bool kLaneLocal = true;   // take() touches only the calling lane
     const U *u;
     const U *F;       // source vector (Algorithm 3), or null
     Kahan<R> s1, s2;
@@ -649,6 +661,7 @@ constexpr int kMaxRhsGroups = 4;   // up to 256 right-hand sides
 
 template <typename R, typename U>
 struct SinkRhs {
+    static constexpr bool kLaneLocal = false;  // take() is a wave-wide broadcast
     const U *u;
     int32_t nrhs;
     int groups;
