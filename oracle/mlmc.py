@@ -79,6 +79,12 @@ def _declare(L):
         _p(ctypes.c_double), ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double),
         _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_uint64)]
     L.orc_functional_sums.restype = None
+    L.orc_forward_sums.argtypes = tables[:8] + [
+        ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32,
+        ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_int32), _p(ctypes.c_uint8),
+        ctypes.c_uint32, ctypes.c_uint32, _p(ctypes.c_double), _p(ctypes.c_double),
+        _p(ctypes.c_double), _p(ctypes.c_int64), _p(ctypes.c_int64), _p(ctypes.c_uint64)]
+    L.orc_forward_sums.restype = ctypes.c_int
     L.orc_log_array.argtypes = [ctypes.c_int64, _p(ctypes.c_double), _p(ctypes.c_double)]
     L.orc_log_array.restype = None
     L.orc_philox_array.argtypes = [ctypes.c_int64, _p(ctypes.c_uint32), _p(ctypes.c_uint32),
@@ -506,6 +512,55 @@ def functional_sums(tT: Tables, beta: float, level: int, l0: int, seed: int, u, 
                               _ptr(s1, ctypes.c_double), _ptr(s2, ctypes.c_double),
                               _ptr(jp, ctypes.c_int64), _ptr(hs, ctypes.c_uint64))
     return FunctionalSums(float(s1[0]), float(s2[0]), int(jp[0]), int(hs[0]), int(M), U)
+
+
+@dataclass
+class ForwardSums:
+    sum1: np.ndarray      # per final state j: sum of the deposits sign(u_l)(eta_f - eta_c)
+    sum2: np.ndarray      # and of their squares
+    mass: np.ndarray      # sum of |eta_f| (+ |eta_c|) of the deposits at j
+    count: np.ndarray     # walks that ended at j
+    jumps: int
+    hash_sum: int
+    walks: int
+    U: float
+
+
+def forward_sums(tT: Tables, beta: float, level: int, l0: int, seed: int, u, walk0: int = 0,
+                 M: int = 1, instance: int = 0) -> ForwardSums:
+    """The full vector exp(beta A) u by the walks of `functional_sums` (tables tT of A^T):
+    each walk deposits its sample at its final state; the level term of x is U sum1 / M."""
+    thr, alias, neg, U = start_tables(u)
+    n = tT.n
+    s1 = np.zeros(n)
+    s2 = np.zeros(n)
+    ms = np.zeros(n)
+    ct = np.zeros(n, np.int64)
+    jp = np.zeros(1, np.int64)
+    hs = np.zeros(1, np.uint64)
+    rc = lib().orc_forward_sums(*tT.args()[:8], float(beta), int(level), int(l0), int(seed),
+                                int(instance), int(n), _ptr(thr, ctypes.c_uint32),
+                                _ptr(alias, ctypes.c_int32), _ptr(neg, ctypes.c_uint8),
+                                int(walk0), int(M), _ptr(s1, ctypes.c_double),
+                                _ptr(s2, ctypes.c_double), _ptr(ms, ctypes.c_double),
+                                _ptr(ct, ctypes.c_int64), _ptr(jp, ctypes.c_int64),
+                                _ptr(hs, ctypes.c_uint64))
+    if rc != 0:
+        raise MemoryError("orc_forward_sums")
+    return ForwardSums(s1, s2, ms, ct, int(jp[0]), int(hs[0]), int(M), U)
+
+
+def forward_fixed(tT: Tables, beta: float, u, l0: int, L: int, M, seed: int, instance: int = 0):
+    """exp(beta A) u with M[q] walks at level l0 + q of the forward representation:
+    (estimate, per-entry variance of it)."""
+    est = np.zeros(tT.n)
+    var = np.zeros(tT.n)
+    for q, lev in enumerate(range(l0, L + 1)):
+        fs = forward_sums(tT, beta, lev, l0, seed, u, 0, int(M[q]), instance)
+        m = fs.sum1 / fs.walks
+        est += fs.U * m
+        var += fs.U ** 2 * np.maximum(fs.sum2 / fs.walks - m * m, 0.0) / fs.walks
+    return est, var
 
 
 def functional_fixed(tT: Tables, beta: float, u, w, l0: int, L: int, M, seed: int,

@@ -510,6 +510,70 @@ void orc_functional_sums(const double *d, const double *inv_r, const int64_t *sl
     *hash_sum = hs;
 }
 
+/* ------------------------------------------------------------------------------ */
+/* The full vector exp(beta A) u by the same walks (the forward representation of   */
+/* section 2.1): walk m (start row l drawn as in orc_functional_sums, run on the     */
+/* tables of A^T) deposits its sample sign(u_l) eta (eta_fine - eta_coarse above l0)  */
+/* at its final state j: per state j the sums of the deposits and of their squares   */
+/* (Neumaier, in walk order), the mass |eta_fine| (+ |eta_coarse| above l0) of the   */
+/* deposits, and their count; the level term of x_j is U sum1[j] / M. Also the jumps */
+/* and the sum (mod 2^64) of the path hashes. The arrays of n entries are            */
+/* overwritten.                                                                      */
+/* ------------------------------------------------------------------------------ */
+int orc_forward_sums(const double *d, const double *inv_r, const int64_t *slot_begin,
+                     const int32_t *deg, const int32_t *slot_col, const uint8_t *slot_sign,
+                     const uint32_t *slot_thr, const int32_t *slot_alias, double beta,
+                     int level, int l0, uint64_t seed, uint32_t instance, int64_t n,
+                     const uint32_t *start_thr, const int32_t *start_alias,
+                     const uint8_t *start_neg, uint32_t walk0, uint32_t M,
+                     double *sum1, double *sum2, double *mass, int64_t *count,
+                     int64_t *jumps, uint64_t *hash_sum)
+{
+    orc_tables t = {d, inv_r, slot_begin, deg, slot_col, slot_alias, slot_sign, slot_thr,
+                    NULL, NULL, NULL};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_sum *a1 = (orc_sum *)calloc((size_t)(n > 0 ? n : 1), sizeof(orc_sum));
+    orc_sum *a2 = (orc_sum *)calloc((size_t)(n > 0 ? n : 1), sizeof(orc_sum));
+    if (!a1 || !a2) {
+        free(a1); free(a2);
+        return -1;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        mass[j] = 0.0;
+        count[j] = 0;
+    }
+    int64_t nj = 0;
+    uint64_t hs = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        const uint32_t walk = walk0 + m;
+        uint32_t ctr[4] = {0u, walk, 0u, c3_of(level, instance, 2)};
+        uint32_t out[4];
+        orc_philox4x32_10(ctr, key, out);
+        uint32_t slot = (uint32_t)(((uint64_t)out[0] * (uint64_t)n) >> 32);
+        uint32_t l = (out[1] < start_thr[slot]) ? slot : (uint32_t)start_alias[slot];
+        orc_walk_out o;
+        orc_one_walk(&t, beta, level, key, instance, (int64_t)l, walk, NULL, &o);
+        const int64_t j = o.final_state;
+        double y = (level > l0) ? (o.eta_fine - o.eta_coarse) : o.eta_fine;
+        if (start_neg[l]) y = -y;
+        orc_add(&a1[j], y);
+        orc_add(&a2[j], y * y);
+        mass[j] += fabs(o.eta_fine) + ((level > l0) ? fabs(o.eta_coarse) : 0.0);
+        count[j] += 1;
+        nj += o.jumps;
+        hs += o.hash;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        sum1[j] = a1[j].s + a1[j].c;
+        sum2[j] = a2[j].s + a2[j].c;
+    }
+    free(a1);
+    free(a2);
+    *jumps = nj;
+    *hash_sum = hs;
+    return 0;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

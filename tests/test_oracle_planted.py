@@ -103,16 +103,31 @@ PLANTS = [
      [SOURCE]),
     # the forward representation as a scalar functional
     ("start sign dropped", C,
-     [("        if (start_neg[l]) y = -y;\n", "")],
+     [("        if (start_neg[l]) y = -y;\n        orc_add(&a1, y);", "        orc_add(&a1, y);")],
      [FUNCTIONAL]),
     ("start rows uniform", C,
-     [("uint32_t l = (out[1] < start_thr[slot]) ? slot : (uint32_t)start_alias[slot];",
-       "uint32_t l = slot;")],
+     [("uint32_t l = (out[1] < start_thr[slot]) ? slot : (uint32_t)start_alias[slot];\n"
+       "        orc_walk_out o;\n"
+       "        orc_one_walk(&t, beta, level, key, instance, (int64_t)l, walk, NULL, &o);\n"
+       "        double y = w[",
+       "uint32_t l = slot;\n"
+       "        orc_walk_out o;\n"
+       "        orc_one_walk(&t, beta, level, key, instance, (int64_t)l, walk, NULL, &o);\n"
+       "        double y = w[")],
      [FUNCTIONAL]),
     ("functional without the coarse term", C,
      [("double y = w[o.final_state] * ((level > l0) ? (o.eta_fine - o.eta_coarse) : o.eta_fine);",
        "double y = w[o.final_state] * o.eta_fine;")],
      [FUNCTIONAL]),
+    ("forward deposit at the start row", C,
+     [("        const int64_t j = o.final_state;\n", "        const int64_t j = (int64_t)l;\n")],
+     [FUNCTIONAL + "::test_forward_deposits_give_every_functional",
+      FUNCTIONAL + "::test_forward_level_means_match_dense_strang_products"]),
+    ("forward deposit without the start sign", C,
+     [("        if (start_neg[l]) y = -y;\n        orc_add(&a1[j], y);",
+       "        orc_add(&a1[j], y);")],
+     [FUNCTIONAL + "::test_forward_deposits_give_every_functional",
+      FUNCTIONAL + "::test_forward_level_means_match_dense_strang_products"]),
     # Algorithm 1's sample sizes
     ("optimal M without the factor 2", "mlmc.py",
      [("np.ceil(2.0 * eps ** -2 *", "np.ceil(eps ** -2 *")],
