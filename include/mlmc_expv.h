@@ -227,6 +227,32 @@ int mlmc_expv_functional_level_sums(mlmc_plan_t *plan, const void *u, const void
                                     double *sum2, int64_t *jumps, uint64_t *hash_sum, double *U,
                                     void *stream);
 
+/* The full vector x = exp(beta A) u by the same walks (the forward representation of
+ * section 2.1): walk m (start row l drawn from |u_l| / U as above, run on the plan of A^T)
+ * deposits its sample sign(u_l) eta_fine (l0) or sign(u_l) (eta_fine - eta_coarse) (above
+ * l0) at its final state j, so that the level term of x_j is U sum1[j] / M. At a finite
+ * level this estimates (u, S^N e_j) with S the Strang step of A^T's own splitting; all
+ * levels converge to exp(beta A) u. The deposits are FP64 atomic additions, so the sums
+ * carry rounding that depends on the order of the walks' ends (they are not bit-reproducible
+ * between runs; the paths are). u: DEVICE, n entries of dtype.
+ * mlmc_expv_forward_level_sums: walks walk0 .. walk0 + walks - 1 of one level. sum1, sum2:
+ *   DEVICE, n doubles each, overwritten with the per-state sums of the deposits (without U)
+ *   and of their squares. HOST outputs (nullable): jumps, the sum (mod 2^64) of the path
+ *   hashes, U.
+ * mlmc_expv_forward: fixed schedule only (opts->walks[q] = total walks at level l0 + q,
+ *   opts->num_levels levels; opts->eps must be 0). x: DEVICE, n doubles; variance: DEVICE,
+ *   n doubles or null (the per-entry variance of the estimate). stats (nullable): per level
+ *   the walks, jumps, root mean square of the level term over the entries, mean over the
+ *   entries of the per-walk variance of U times the deposit, cost.
+ * Both wait for the stream. */
+int mlmc_expv_forward(mlmc_plan_t *plan, const void *u, int32_t dtype, const mlmc_run_opts_t *opts,
+                      double *x, double *variance, mlmc_stats_t *stats, void *stream);
+
+int mlmc_expv_forward_level_sums(mlmc_plan_t *plan, const void *u, int32_t dtype, uint64_t seed,
+                                 int32_t instance, int32_t level, uint32_t walk0, uint32_t walks,
+                                 double *sum1, double *sum2, int64_t *jumps, uint64_t *hash_sum,
+                                 double *U, void *stream);
+
 void mlmc_expv_destroy(mlmc_plan_t *plan);
 
 /* ---- batched runs ------------------------------------------------------------------

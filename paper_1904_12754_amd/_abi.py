@@ -29,7 +29,7 @@ MLMC_MAX_LEVELS = 40
 # every symbol the header declares
 EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_level_sums",
            "mlmc_expv_run_source", "mlmc_expv_level_sums_source", "mlmc_expv_functional",
-           "mlmc_expv_functional_level_sums",
+           "mlmc_expv_functional_level_sums", "mlmc_expv_forward", "mlmc_expv_forward_level_sums",
            "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_expv_batch_create",
            "mlmc_expv_batch_launch", "mlmc_expv_batch_stats", "mlmc_expv_batch_info",
            "mlmc_expv_batch_destroy", "mlmc_expv_proposal_set", "mlmc_expv_proposal_enable",
@@ -200,6 +200,13 @@ def load() -> ctypes.CDLL:
                                                    ctypes.POINTER(i64), ctypes.POINTER(u64),
                                                    ctypes.POINTER(f64), vp]
     L.mlmc_expv_functional_level_sums.restype = ctypes.c_int
+    L.mlmc_expv_forward.argtypes = [vp, vp, i32, ctypes.POINTER(RunOpts), vp, vp,
+                                    ctypes.POINTER(Stats), vp]
+    L.mlmc_expv_forward.restype = ctypes.c_int
+    L.mlmc_expv_forward_level_sums.argtypes = [vp, vp, i32, u64, i32, i32, u32, u32, vp, vp,
+                                               ctypes.POINTER(i64), ctypes.POINTER(u64),
+                                               ctypes.POINTER(f64), vp]
+    L.mlmc_expv_forward_level_sums.restype = ctypes.c_int
     L.mlmc_expv_trace.argtypes = [vp, u64, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.mlmc_expv_trace.restype = ctypes.c_int
     L.mlmc_expv_destroy.argtypes = [vp]

@@ -213,6 +213,47 @@ class Plan:
             _stream_ptr(stream)))
         return float(s1.value), float(s2.value), int(j.value), int(h.value), float(U.value)
 
+    # ---- the full vector by the forward representation (same walks, deposited) --------
+    def _u_only(self, u):
+        if not u.is_cuda or u.dtype not in (torch.float32, torch.float64) or u.numel() != self.n:
+            raise ValueError("u must be a device vector of n float32 or float64 entries")
+        dt = _abi.MLMC_DTYPE_F64 if u.dtype == torch.float64 else _abi.MLMC_DTYPE_F32
+        return u.contiguous(), dt
+
+    def forward(self, u: torch.Tensor, walks, seed: int = 0, instance: int = 0, stream=None,
+                allow=()):
+        """exp(beta A) u by the forward representation, the plan built on A^T (on A when A
+        is symmetric): walks[q] total walks at level l0 + q. Returns (x, per-entry variance,
+        stats)."""
+        u, dt = self._u_only(u)
+        walks_arr = np.ascontiguousarray(walks, dtype=np.int64)
+        opts = _abi.RunOpts(seed, instance, int(walks_arr.size),
+                            walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0, 0, 0, 0)
+        x = torch.empty(self.n, dtype=torch.float64, device=u.device)
+        var = torch.empty(self.n, dtype=torch.float64, device=u.device)
+        st = _abi.Stats()
+        check(self._lib.mlmc_expv_forward(self._handle, _dev_ptr(u), dt, ctypes.byref(opts),
+                                          _dev_ptr(x), _dev_ptr(var), ctypes.byref(st),
+                                          _stream_ptr(stream)), allow)
+        del walks_arr
+        return x, var, st.to_dict()
+
+    def forward_level_sums(self, u: torch.Tensor, level: int, walk0: int, walks: int,
+                           seed: int = 0, instance: int = 0, hashes: bool = False, stream=None):
+        """Per-state sums of the deposits (without U) and of their squares (device, n
+        doubles each), jumps, hash sum (with hashes) and U, of one level."""
+        u, dt = self._u_only(u)
+        s1 = torch.empty(self.n, dtype=torch.float64, device=u.device)
+        s2 = torch.empty(self.n, dtype=torch.float64, device=u.device)
+        j = ctypes.c_int64()
+        h = ctypes.c_uint64()
+        U = ctypes.c_double()
+        check(self._lib.mlmc_expv_forward_level_sums(
+            self._handle, _dev_ptr(u), dt, seed, instance, level, walk0, walks, _dev_ptr(s1),
+            _dev_ptr(s2), ctypes.byref(j), ctypes.byref(h) if hashes else None, ctypes.byref(U),
+            _stream_ptr(stream)))
+        return s1, s2, int(j.value), (int(h.value) if hashes else None), float(U.value)
+
     # ---- learned proposal (importance sampling of the jump law) -----------------------
     @staticmethod
     def _params(params):

@@ -52,6 +52,72 @@ __global__ __launch_bounds__(kBlock) void functional_walks(LevelArgs L, AliasSta
     }
 }
 
+// The forward representation of the full vector: the same walks deposit their samples at
+// their final states.
+template <typename R, bool kHash>
+__global__ __launch_bounds__(kBlock) void forward_walks(LevelArgs L, AliasStart st, uint32_t walk0, uint32_t M,
+                                                        uint32_t items, double *sum1, double *sum2,
+                                                        unsigned long long *counters,
+                                                        unsigned long long *hash_sum)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t item = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (item >= items) return;
+    const uint64_t wb = static_cast<uint64_t>(item) * kFuncChunk;
+    const uint64_t we = (wb + kFuncChunk < M) ? wb + kFuncChunk : static_cast<uint64_t>(M);
+    SinkDeposit<R> sink{sum1, sum2};
+    walk_range_from<R, kHash, false, false>(L, st, walk0, wb, we, sink);
+    const unsigned long long jumps = wave_sum_u(sink.jumps);
+    const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
+    const unsigned long long hsum = wave_sum_u(sink.hash);
+    if (lane == 0) {
+        unsigned long long *c = counter_slot(counters, item);
+        atomicAdd(&c[0], jumps);
+        if (nonfinite) atomicAdd(&c[1], nonfinite);
+        if (kHash) atomicAdd(hash_sum, hsum);
+    }
+}
+
+// x += scale sum1 and, with var, var += scale^2 (sum2 / M - (sum1 / M)^2) / M (a level's
+// term of the forward estimate and of its per-entry variance).
+__global__ void forward_combine(const double *__restrict__ sum1, const double *__restrict__ sum2, int64_t n,
+                                double U, double M, double *x, double *var)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double m = sum1[j] / M;
+    x[j] += U * m;
+    if (var) var[j] += U * U * fmax(sum2[j] / M - m * m, 0.0) / M;
+}
+
+// Per-level moments over the entries: sum of (U m_j)^2 and of U^2 (sum2_j / M - m_j^2), in a
+// fixed order (one workgroup).
+__global__ void forward_moments(const double *__restrict__ sum1, const double *__restrict__ sum2, int64_t n,
+                                double U, double M, double *out)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+        const double m = sum1[j] / M;
+        a += (U * m) * (U * m);
+        b += U * U * fmax(sum2[j] / M - m * m, 0.0);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) {
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s1[0];
+        out[1] = s2[0];
+    }
+}
+
 // Sums of the items' partial sums in a fixed order.
 __global__ void functional_total(const double *partial, uint32_t items, double *out)
 {
@@ -225,6 +291,55 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     (void)hipEventDestroy(e1);
     out.s1 = tot[0];
     out.s2 = tot[1];
+    out.jumps = c[0];
+    out.nonfinite = c[1];
+    out.hash = c[2];
+    return MLMC_OK;
+}
+
+// Walks [walk0, walk0 + M) of one level of the forward representation: the deposits into
+// sum1, sum2 (zeroed first), counters and hash sum. Waits.
+int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, int lev, uint32_t walk0,
+                      uint64_t M, bool hash, double *sum1, double *sum2, LevelOut &out, hipStream_t s)
+{
+    out = LevelOut{};
+    if (p->n == 0) return MLMC_OK;
+    MLMC_HIP_TRY(hipMemsetAsync(sum1, 0, p->n * sizeof(double), s));
+    MLMC_HIP_TRY(hipMemsetAsync(sum2, 0, p->n * sizeof(double), s));
+    if (M == 0 || fc.U == 0.0) return MLMC_OK;
+    if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
+        return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
+    int rc = upload_level(p, lev, s);
+    if (rc) return rc;
+    LevelArgs L = level_args(p, lev, seed, instance);
+    L.is_slots = nullptr;
+    L.src = nullptr;
+    AliasStart st{fc.thr, fc.alias, fc.neg, static_cast<uint32_t>(p->n), stream_word(lev, instance, 2)};
+    const uint32_t items = static_cast<uint32_t>((M + kFuncChunk - 1) / kFuncChunk);
+    MLMC_HIP_TRY(hipMemsetAsync(fc.ctr, 0, (kCounterSetU64 + 3) * sizeof(unsigned long long), s));
+    hipEvent_t e0, e1;
+    MLMC_HIP_TRY(hipEventCreate(&e0));
+    MLMC_HIP_TRY(hipEventCreate(&e1));
+    MLMC_HIP_TRY(hipEventRecord(e0, s));
+    const dim3 grid((items + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
+    const uint32_t Mu = static_cast<uint32_t>(M);
+    unsigned long long *hs = fc.ctr + kCounterSetU64 + 2;
+    if (p->precision == MLMC_PRECISION_FP64) {
+        if (hash) hipLaunchKernelGGL((forward_walks<double, true>), grid, block, 0, s, L, st, walk0, Mu, items, sum1, sum2, fc.ctr, hs);
+        else hipLaunchKernelGGL((forward_walks<double, false>), grid, block, 0, s, L, st, walk0, Mu, items, sum1, sum2, fc.ctr, hs);
+    } else {
+        if (hash) hipLaunchKernelGGL((forward_walks<float, true>), grid, block, 0, s, L, st, walk0, Mu, items, sum1, sum2, fc.ctr, hs);
+        else hipLaunchKernelGGL((forward_walks<float, false>), grid, block, 0, s, L, st, walk0, Mu, items, sum1, sum2, fc.ctr, hs);
+    }
+    MLMC_HIP_TRY(hipGetLastError());
+    MLMC_HIP_TRY(hipEventRecord(e1, s));
+    MLMC_HIP_TRY(launch_counter_sum(fc.ctr, 1, fc.ctr + kCounterSetU64, s));
+    unsigned long long c[3];
+    MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
+    (void)hipEventElapsedTime(&out.ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     out.jumps = c[0];
     out.nonfinite = c[1];
     out.hash = c[2];
@@ -417,6 +532,115 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
     (void)hipEventDestroy(e1);
     if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
+    return MLMC_OK;
+}
+
+int mlmc_expv_forward_level_sums(mlmc_plan_t *p, const void *u, int32_t dtype, uint64_t seed, int32_t instance,
+                                 int32_t level, uint32_t walk0, uint32_t walks, double *sum1, double *sum2,
+                                 int64_t *jumps, uint64_t *hash_sum, double *U, void *stream)
+{
+    int rc = check_args(p, u, u, dtype);
+    if (rc) return rc;
+    if (p->n > 0 && (!sum1 || !sum2)) return fail(MLMC_ERR_INVALID_ARG, "sum1 or sum2 is null");
+    if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    if (level < 0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level out of range [0, 28]");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    FuncCall fc;
+    if ((rc = prepare(fc, p, u, dtype == MLMC_DTYPE_F64, s))) return rc;
+    LevelOut o;
+    if ((rc = run_forward_level(fc, p, seed, instance, level, walk0, walks, hash_sum != nullptr, sum1, sum2, o, s)))
+        return rc;
+    if (jumps) *jumps = static_cast<int64_t>(o.jumps);
+    if (hash_sum) *hash_sum = o.hash;
+    if (U) *U = fc.U;
+    if (o.nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(o.nonfinite) + " non-finite samples");
+    return MLMC_OK;
+}
+
+int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_run_opts_t *o, double *x,
+                      double *variance, mlmc_stats_t *stats, void *stream)
+{
+    int rc = check_args(p, u, u, dtype);
+    if (rc) return rc;
+    if (!o) return fail(MLMC_ERR_INVALID_ARG, "null options");
+    if (p->n > 0 && !x) return fail(MLMC_ERR_INVALID_ARG, "x is null");
+    if (o->eps > 0.0) return fail(MLMC_ERR_UNSUPPORTED, "the forward full vector takes a fixed schedule (eps = 0)");
+    if (o->instance < 0 || o->instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    if (o->num_levels < 1 || o->num_levels > MLMC_MAX_LEVELS || p->l0 + o->num_levels - 1 > kMaxLevel)
+        return fail(MLMC_ERR_INVALID_ARG, "num_levels out of range");
+    if (!o->walks) return fail(MLMC_ERR_INVALID_ARG, "walks is null");
+    for (int q = 0; q < o->num_levels; ++q)
+        if (o->walks[q] < 1 || o->walks[q] >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "walks per level must be in [1, 2^32)");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = p->n;
+    FuncCall fc;
+    if ((rc = prepare(fc, p, u, dtype == MLMC_DTYPE_F64, s))) return rc;
+    double *sums = nullptr;   // sum1, sum2 of a level, then two moments
+    if ((rc = dalloc(&sums, 2 * static_cast<size_t>(n) + 2))) return rc;
+    struct Free {
+        double *q;
+        ~Free() { (void)hipFree(q); }
+    } free_sums{sums};
+    double *sum1 = sums, *sum2 = sums + n, *mom = sums + 2 * n;
+    if (n > 0) {
+        MLMC_HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
+        if (variance) MLMC_HIP_TRY(hipMemsetAsync(variance, 0, n * sizeof(double), s));
+    }
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    unsigned long long nonfinite = 0;
+    double wk_ms = 0.0, est_var = 0.0;
+    hipEvent_t e0, e1;
+    MLMC_HIP_TRY(hipEventCreate(&e0));
+    MLMC_HIP_TRY(hipEventCreate(&e1));
+    MLMC_HIP_TRY(hipEventRecord(e0, s));
+    for (int q = 0; q < o->num_levels; ++q) {
+        LevelOut lo;
+        const uint64_t M = static_cast<uint64_t>(o->walks[q]);
+        if ((rc = run_forward_level(fc, p, o->seed, o->instance, p->l0 + q, 0u, M, false, sum1, sum2, lo, s)))
+            return rc;
+        nonfinite += lo.nonfinite;
+        wk_ms += lo.ms;
+        double h[2] = {0.0, 0.0};
+        if (n > 0) {
+            const double Md = static_cast<double>(M);
+            hipLaunchKernelGGL(forward_combine, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, s, sum1,
+                               sum2, n, fc.U, Md, x, variance);
+            MLMC_HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(forward_moments, dim3(1), dim3(256), 0, s, sum1, sum2, n, fc.U, Md, mom);
+            MLMC_HIP_TRY(hipGetLastError());
+            MLMC_HIP_TRY(hipMemcpyAsync(h, mom, sizeof h, hipMemcpyDeviceToHost, s));
+            MLMC_HIP_TRY(hipStreamSynchronize(s));
+        }
+        const double nn = static_cast<double>(std::max<int64_t>(n, 1));
+        est_var += h[1] / nn / static_cast<double>(M);
+        if (stats) {
+            stats->walks[q] = static_cast<int64_t>(M);
+            stats->jumps[q] = static_cast<int64_t>(lo.jumps);
+            stats->level_mean_rms[q] = std::sqrt(h[0] / nn);
+            stats->level_var[q] = h[1] / nn;
+            stats->level_cost[q] = std::ldexp(1.0, p->l0 + q) + 4.0 * static_cast<double>(lo.jumps) / static_cast<double>(M);
+            stats->steps += static_cast<int64_t>(M) * (int64_t(1) << (p->l0 + q));
+            stats->total_jumps += static_cast<int64_t>(lo.jumps);
+        }
+    }
+    MLMC_HIP_TRY(hipEventRecord(e1, s));
+    MLMC_HIP_TRY(hipEventSynchronize(e1));
+    if (stats) {
+        stats->l0 = p->l0;
+        stats->num_levels = o->num_levels;
+        stats->converged = 1;
+        stats->nonfinite = static_cast<int64_t>(nonfinite);
+        stats->est_variance = est_var;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        stats->kernel_ms = ms;
+        stats->walk_kernel_ms = wk_ms;
+        stats->walk_launches = o->num_levels;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
     return MLMC_OK;
 }
 

@@ -654,6 +654,27 @@ struct SinkR1 {
     }
 };
 
+// Forward representation of the full vector: each sample is deposited at the walk's final
+// state (FP64 atomic adds of the sample and of its square; hipMalloc memory is coarse-grained,
+// so these are the hardware's global_atomic_add_f64).
+template <typename R>
+struct SinkDeposit {
+    static constexpr bool kLaneLocal = true;   // take() touches only the calling lane
+    double *sum1, *sum2;
+    unsigned long long jumps = 0, hash = 0;
+    uint32_t nonfinite = 0;
+    __device__ __forceinline__ void take(bool done, const Finished<R> &f)
+    {
+        if (!done) return;
+        const double y = static_cast<double>(f.W);
+        jumps += f.jumps;
+        hash += f.hash;
+        nonfinite += !isfinite(y);
+        unsafeAtomicAdd(&sum1[f.k], y);
+        unsafeAtomicAdd(&sum2[f.k], y * y);
+    }
+};
+
 // Several right-hand sides: the finished walks of an iteration are broadcast one by one
 // and lane r adds right-hand side r (+64 g) from the contiguous row u[k, :]. Walks
 // without a jump all end at the start row with the same weight; they are only counted.

@@ -102,3 +102,75 @@ def test_total_communicability_forward_and_backward(api):
     _say(f"TC backward: {back:.6f}, sd {sd_back:.2e}")
     assert abs(back - val) < 5 * np.sqrt(var + sd_back ** 2) + 2 * eps
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_forward_level_sums_match_oracle(api, precision):
+    """The forward representation of the full vector: the walks of the functional deposit
+    their samples at their final states. Paths (jumps, path hashes) and U bit-exact against
+    the oracle; per-state sums within the bars relative to the state's deposited mass (the
+    device adds the deposits with FP64 atomics, in the order the walks end)."""
+    rng = np.random.default_rng(22)
+    n = 90
+    a = rng.normal(size=(n, n)) * (rng.random((n, n)) < 0.08)
+    AT = inputs.from_dense(a.T)
+    beta = 0.35
+    dt = np.float64 if precision == "fp64" else np.float32
+    u = rng.normal(size=n).astype(dt)
+    u[7] = 0.0
+    plan = api.Plan(AT, beta, precision=precision)
+    tT = orc.decompose(n, AT.row_ptr, AT.col_idx, AT.values)
+    ut = torch.as_tensor(u, device="cuda")
+    for lev in range(plan.l0, plan.l0 + 3):
+        M = 60_003 + lev
+        _say(f"forward level sums prec={precision} level={lev} M={M}")
+        s1, s2, jumps, hsum, U = plan.forward_level_sums(ut, lev, 29, M, seed=43, hashes=True)
+        o = orc.forward_sums(tT, beta, lev, plan.l0, 43, u.astype(np.float64), 29, M)
+        assert U == o.U
+        assert jumps == o.jumps
+        assert hsum == o.hash_sum
+        g1 = s1.cpu().numpy()
+        g2 = s2.cpu().numpy()
+        assert np.all(g1[o.count == 0] == 0.0) and np.all(g2[o.count == 0] == 0.0)
+        assert np.all(np.abs(g1 - o.sum1) <= TOL[precision] * o.mass + 1e-300)
+        assert np.all(np.abs(g2 - o.sum2) <= 4 * TOL[precision] * o.mass ** 2 + 1e-300)
+    plan.close()
+
+
+def test_forward_full_vector_matches_oracle_and_backward(api):
+    """The forward full vector with a fixed schedule equals the oracle's (per entry, within
+    the FP64 bar of its standard deviation); it estimates the finest product (u, S^N e_j)
+    within 5 sigma per entry, and it agrees with the backward per-row estimate of the same
+    exp(beta A) u on a symmetric Laplacian (where the plan of A serves for A^T)."""
+    rng = np.random.default_rng(23)
+    n = 50
+    a = rng.normal(size=(n, n)) * (rng.random((n, n)) < 0.12)
+    AT = inputs.from_dense(a.T)
+    beta = 0.3
+    u = rng.normal(size=n)
+    plan = api.Plan(AT, beta, precision="fp64")
+    walks = [300_000, 100_000, 30_000]
+    x, var, st = plan.forward(torch.as_tensor(u, device="cuda"), walks=walks, seed=5)
+    xg, vg = x.cpu().numpy(), var.cpu().numpy()
+    tT = orc.decompose(n, AT.row_ptr, AT.col_idx, AT.values)
+    est, ovar = orc.forward_fixed(tT, beta, u, plan.l0, plan.l0 + 2, walks, 5)
+    assert np.all(np.abs(xg - est) <= 1e-10 * (np.abs(est) + np.sqrt(ovar)) + 1e-300)
+    assert np.all(np.abs(vg - ovar) <= 1e-8 * ovar + 1e-300)
+    eye = np.eye(n)
+    L = plan.l0 + 2
+    exact_L = np.column_stack([reference.strang_level(a.T, eye[j], beta, L) for j in range(n)]).T @ u
+    assert np.all(np.abs(xg - exact_L) < 5 * np.sqrt(vg) + 1e-12)
+    assert st["walks"][:3] == walks
+    plan.close()
+    # symmetric 2D Laplacian: the plan of A serves for A^T, and the forward and backward
+    # estimates of the same exp(beta A) v agree within their estimated errors
+    A2, t2, v2 = inputs.workload_laplace2d(16)
+    p2 = api.Plan(A2, t2, precision="fp64")
+    vt = torch.as_tensor(v2, device="cuda")
+    xf, vf, _ = p2.forward(vt, walks=[400_000, 100_000, 40_000], seed=6)
+    xb, stb = p2.run(vt, walks=[4000, 1000, 400], seed=7)
+    xf, vf = xf.cpu().numpy(), vf.cpu().numpy()
+    xb = xb.cpu().numpy()[:, 0]
+    d = xf - xb
+    assert np.sqrt(np.mean(d * d)) < 5 * np.sqrt(np.mean(vf) + stb["est_variance"])
+    p2.close()
