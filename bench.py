@@ -201,8 +201,9 @@ def tc_bench(args):
     Barabasi-Albert graph (n = 1e6, m = 5, symmetric 0/1 adjacency stored as FP32),
     beta = 1/d_max, levels l0..l0+4 with 128 walks per row per level, FP32 weights, 64
     right-hand sides carried by every path, in one persistent launch (a batch of this one
-    instance replayed from a graph); also timed as five per-level launches of one run, and
-    the forward scalar estimate of the total communicability."""
+    instance replayed from a graph); also timed as five per-level launches of one run, the
+    forward scalar estimate of the total communicability, and the forward full vector
+    exp(beta A) 1 against the backward run's first column."""
     import numpy as np
     import torch
 
@@ -235,6 +236,23 @@ def tc_bench(args):
     tc_f, var_f, st_f = plan.functional(ones, ones, eps=sd_back, seed=3, pilot_walks=1 << 16)
     torch.cuda.synchronize()
     t_f = time.perf_counter() - t0
+    # the vector exp(beta A) 1 by the forward representation: as many walks per level as the
+    # backward run spends on one right-hand side (128 per row), from uniformly drawn rows,
+    # deposited at their final states; compared with the backward run's first column
+    fwd_walks = [128 * A.n] * 5
+    plan.forward(ones, walks=fwd_walks, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xf, vf, st_fw = plan.forward(ones, walks=fwd_walks, seed=5)
+    torch.cuda.synchronize()
+    t_fw = time.perf_counter() - t0
+    dfb = xf - x[:, 0]
+    fwd = {"seconds": t_fw, "steps": st_fw["steps"], "walks": fwd_walks,
+           "rms_forward_minus_backward": float(torch.sqrt(torch.mean(dfb * dfb)).item()),
+           "rms_expected": math.sqrt(float(vf.mean().item()) + st["est_variance"]),
+           "rms_of_x": float(torch.sqrt(torch.mean(x[:, 0] * x[:, 0])).item()),
+           "note": "exp(beta A) 1 by walks deposited at their final states; rms_expected from "
+                   "the two estimated variances"}
     # the same five levels as one persistent launch: a batch of this one instance, captured
     # in a graph and replayed
     batch = api.Batch([plan], [u], np.array([walks], dtype=np.int64), autotune=True)
@@ -264,6 +282,7 @@ def tc_bench(args):
                            "walks": st_f["walks"][:st_f["num_levels"]],
                            "steps": st_f["steps"],
                            "note": "Algorithm 1 on the scalar to the backward run's sd"},
+        "forward_full_vector": fwd,
         "config": {"workload": f"Barabasi-Albert n={A.n} m=5, beta=1/d_max={beta:.3e}, "
                                f"{u.shape[1]} right-hand sides (ones + Rademacher), "
                                f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level, "
