@@ -239,11 +239,13 @@ int mlmc_expv_functional_level_sums(mlmc_plan_t *plan, const void *u, const void
  *   DEVICE, n doubles each, overwritten with the per-state sums of the deposits (without U)
  *   and of their squares. HOST outputs (nullable): jumps, the sum (mod 2^64) of the path
  *   hashes, U.
- * mlmc_expv_forward: fixed schedule only (opts->walks[q] = total walks at level l0 + q,
- *   opts->num_levels levels; opts->eps must be 0). x: DEVICE, n doubles; variance: DEVICE,
- *   n doubles or null (the per-entry variance of the estimate). stats (nullable): per level
- *   the walks, jumps, root mean square of the level term over the entries, mean over the
- *   entries of the per-walk variance of U times the deposit, cost.
+ * mlmc_expv_forward: fixed schedule (opts->walks[q] = total walks at level l0 + q) or
+ *   Algorithm 1 (opts->eps > 0, pilot_walks total walks per level) on the mean over the
+ *   entries of the per-entry variance, with the bias test on the root-mean-square level
+ *   terms, as for the backward full vector. x: DEVICE, n doubles; variance: DEVICE, n doubles
+ *   or null (the per-entry variance of the estimate). stats (nullable): per level the total
+ *   walks, jumps, root mean square of the level term over the entries, mean over the entries
+ *   of the per-walk variance of U times the deposit, cost.
  * Both wait for the stream. */
 int mlmc_expv_forward(mlmc_plan_t *plan, const void *u, int32_t dtype, const mlmc_run_opts_t *opts,
                       double *x, double *variance, mlmc_stats_t *stats, void *stream);

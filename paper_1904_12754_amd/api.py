@@ -220,15 +220,22 @@ class Plan:
         dt = _abi.MLMC_DTYPE_F64 if u.dtype == torch.float64 else _abi.MLMC_DTYPE_F32
         return u.contiguous(), dt
 
-    def forward(self, u: torch.Tensor, walks, seed: int = 0, instance: int = 0, stream=None,
-                allow=()):
+    def forward(self, u: torch.Tensor, walks=None, eps: float | None = None, seed: int = 0,
+                instance: int = 0, pilot_walks: int = 1 << 16, max_levels: int = 20,
+                max_walks: int = 0, stream=None, allow=()):
         """exp(beta A) u by the forward representation, the plan built on A^T (on A when A
-        is symmetric): walks[q] total walks at level l0 + q. Returns (x, per-entry variance,
-        stats)."""
+        is symmetric): walks[q] total walks at level l0 + q, or Algorithm 1 to eps (RMS over
+        the entries). Returns (x, per-entry variance, stats)."""
         u, dt = self._u_only(u)
-        walks_arr = np.ascontiguousarray(walks, dtype=np.int64)
-        opts = _abi.RunOpts(seed, instance, int(walks_arr.size),
-                            walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0, 0, 0, 0)
+        if eps is not None and eps > 0:
+            walks_arr = None
+            opts = _abi.RunOpts(seed, instance, 0, None, float(eps), int(pilot_walks),
+                                int(max_levels), int(max_walks))
+        else:
+            walks_arr = np.ascontiguousarray(walks, dtype=np.int64)
+            opts = _abi.RunOpts(seed, instance, int(walks_arr.size),
+                                walks_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 0.0,
+                                0, 0, 0)
         x = torch.empty(self.n, dtype=torch.float64, device=u.device)
         var = torch.empty(self.n, dtype=torch.float64, device=u.device)
         st = _abi.Stats()

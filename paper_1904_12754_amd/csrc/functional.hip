@@ -300,12 +300,15 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
 // Walks [walk0, walk0 + M) of one level of the forward representation: the deposits into
 // sum1, sum2 (zeroed first), counters and hash sum. Waits.
 int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, int lev, uint32_t walk0,
-                      uint64_t M, bool hash, double *sum1, double *sum2, LevelOut &out, hipStream_t s)
+                      uint64_t M, bool hash, double *sum1, double *sum2, LevelOut &out, hipStream_t s,
+                      bool accumulate = false)
 {
     out = LevelOut{};
     if (p->n == 0) return MLMC_OK;
-    MLMC_HIP_TRY(hipMemsetAsync(sum1, 0, p->n * sizeof(double), s));
-    MLMC_HIP_TRY(hipMemsetAsync(sum2, 0, p->n * sizeof(double), s));
+    if (!accumulate) {
+        MLMC_HIP_TRY(hipMemsetAsync(sum1, 0, p->n * sizeof(double), s));
+        MLMC_HIP_TRY(hipMemsetAsync(sum2, 0, p->n * sizeof(double), s));
+    }
     if (M == 0 || fc.U == 0.0) return MLMC_OK;
     if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
         return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
@@ -564,83 +567,174 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
     if (rc) return rc;
     if (!o) return fail(MLMC_ERR_INVALID_ARG, "null options");
     if (p->n > 0 && !x) return fail(MLMC_ERR_INVALID_ARG, "x is null");
-    if (o->eps > 0.0) return fail(MLMC_ERR_UNSUPPORTED, "the forward full vector takes a fixed schedule (eps = 0)");
     if (o->instance < 0 || o->instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
-    if (o->num_levels < 1 || o->num_levels > MLMC_MAX_LEVELS || p->l0 + o->num_levels - 1 > kMaxLevel)
-        return fail(MLMC_ERR_INVALID_ARG, "num_levels out of range");
-    if (!o->walks) return fail(MLMC_ERR_INVALID_ARG, "walks is null");
-    for (int q = 0; q < o->num_levels; ++q)
-        if (o->walks[q] < 1 || o->walks[q] >= (int64_t(1) << 32))
-            return fail(MLMC_ERR_INVALID_ARG, "walks per level must be in [1, 2^32)");
+    const bool adaptive = o->eps > 0.0;
+    int max_levels;
+    if (adaptive) {
+        if (o->pilot_walks < 2 || o->pilot_walks >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be in [2, 2^32)");
+        max_levels = o->max_levels > 0 ? o->max_levels : 20;
+        max_levels = std::min(max_levels, std::min(MLMC_MAX_LEVELS, kMaxLevel - p->l0 + 1));
+        if (max_levels < 2) return fail(MLMC_ERR_INVALID_ARG, "max_levels must allow at least two levels");
+    } else {
+        if (o->num_levels < 1 || o->num_levels > MLMC_MAX_LEVELS || p->l0 + o->num_levels - 1 > kMaxLevel)
+            return fail(MLMC_ERR_INVALID_ARG, "num_levels out of range");
+        if (!o->walks) return fail(MLMC_ERR_INVALID_ARG, "walks is null");
+        for (int q = 0; q < o->num_levels; ++q)
+            if (o->walks[q] < 1 || o->walks[q] >= (int64_t(1) << 32))
+                return fail(MLMC_ERR_INVALID_ARG, "walks per level must be in [1, 2^32)");
+        max_levels = o->num_levels;
+    }
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = p->n;
     FuncCall fc;
     if ((rc = prepare(fc, p, u, dtype == MLMC_DTYPE_F64, s))) return rc;
-    double *sums = nullptr;   // sum1, sum2 of a level, then two moments
-    if ((rc = dalloc(&sums, 2 * static_cast<size_t>(n) + 2))) return rc;
-    struct Free {
-        double *q;
-        ~Free() { (void)hipFree(q); }
-    } free_sums{sums};
-    double *sum1 = sums, *sum2 = sums + n, *mom = sums + 2 * n;
-    if (n > 0) {
-        MLMC_HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
-        if (variance) MLMC_HIP_TRY(hipMemsetAsync(variance, 0, n * sizeof(double), s));
-    }
-    if (stats) std::memset(stats, 0, sizeof *stats);
+    const double UU = fc.U;
+    // per level: the deposit sums (2n doubles, kept while walks are added), then two moments
+    struct Sums {
+        std::vector<double *> v;
+        ~Sums()
+        {
+            for (double *q : v) (void)hipFree(q);
+        }
+    } lv;
+    double *mom = nullptr;
+    if ((rc = dalloc(&mom, 2))) return rc;
+    lv.v.push_back(mom);
+    std::vector<double *> sums(static_cast<size_t>(max_levels), nullptr);
+    std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
+    std::vector<double> rms(max_levels, 0.0), V(max_levels, 0.0);
+    std::vector<unsigned long long> J(max_levels, 0);
     unsigned long long nonfinite = 0;
-    double wk_ms = 0.0, est_var = 0.0;
-    hipEvent_t e0, e1;
-    MLMC_HIP_TRY(hipEventCreate(&e0));
-    MLMC_HIP_TRY(hipEventCreate(&e1));
-    MLMC_HIP_TRY(hipEventRecord(e0, s));
-    for (int q = 0; q < o->num_levels; ++q) {
+    double wk_ms = 0.0;
+    int64_t launches = 0;
+    const double nn = static_cast<double>(std::max<int64_t>(n, 1));
+    // walks [M[q], M[q] + extra) of level l0 + q added to its sums; then the level's moments
+    auto add = [&](int q, int64_t extra) -> int {
+        if (!sums[q]) {
+            int r2 = dalloc(&sums[q], 2 * static_cast<size_t>(n));
+            if (r2) return r2;
+            lv.v.push_back(sums[q]);
+            if (n > 0) MLMC_HIP_TRY(hipMemsetAsync(sums[q], 0, 2 * n * sizeof(double), s));
+        }
         LevelOut lo;
-        const uint64_t M = static_cast<uint64_t>(o->walks[q]);
-        if ((rc = run_forward_level(fc, p, o->seed, o->instance, p->l0 + q, 0u, M, false, sum1, sum2, lo, s)))
-            return rc;
+        int r2 = run_forward_level(fc, p, o->seed, o->instance, p->l0 + q, static_cast<uint32_t>(M[q]),
+                                   static_cast<uint64_t>(extra), false, sums[q], sums[q] + n, lo, s, true);
+        if (r2) return r2;
+        M[q] += extra;
+        J[q] += lo.jumps;
         nonfinite += lo.nonfinite;
         wk_ms += lo.ms;
+        ++launches;
         double h[2] = {0.0, 0.0};
         if (n > 0) {
-            const double Md = static_cast<double>(M);
-            hipLaunchKernelGGL(forward_combine, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, s, sum1,
-                               sum2, n, fc.U, Md, x, variance);
-            MLMC_HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL(forward_moments, dim3(1), dim3(256), 0, s, sum1, sum2, n, fc.U, Md, mom);
+            hipLaunchKernelGGL(forward_moments, dim3(1), dim3(256), 0, s, sums[q], sums[q] + n, n, UU,
+                               static_cast<double>(M[q]), mom);
             MLMC_HIP_TRY(hipGetLastError());
             MLMC_HIP_TRY(hipMemcpyAsync(h, mom, sizeof h, hipMemcpyDeviceToHost, s));
             MLMC_HIP_TRY(hipStreamSynchronize(s));
         }
-        const double nn = static_cast<double>(std::max<int64_t>(n, 1));
-        est_var += h[1] / nn / static_cast<double>(M);
-        if (stats) {
-            stats->walks[q] = static_cast<int64_t>(M);
-            stats->jumps[q] = static_cast<int64_t>(lo.jumps);
-            stats->level_mean_rms[q] = std::sqrt(h[0] / nn);
-            stats->level_var[q] = h[1] / nn;
-            stats->level_cost[q] = std::ldexp(1.0, p->l0 + q) + 4.0 * static_cast<double>(lo.jumps) / static_cast<double>(M);
-            stats->steps += static_cast<int64_t>(M) * (int64_t(1) << (p->l0 + q));
-            stats->total_jumps += static_cast<int64_t>(lo.jumps);
+        rms[q] = std::sqrt(h[0] / nn);   // root mean square over the entries of the level term
+        V[q] = h[1] / nn;                // mean over the entries of the per-walk variance
+        return MLMC_OK;
+    };
+    auto cost_of = [&](int q) {
+        return std::ldexp(1.0, p->l0 + q) + 4.0 * static_cast<double>(J[q]) / static_cast<double>(M[q]);
+    };
+    int levels = 0, iterations = 0;
+    bool converged = false;
+    double bias = 0.0;
+    hipEvent_t e0, e1;
+    MLMC_HIP_TRY(hipEventCreate(&e0));
+    MLMC_HIP_TRY(hipEventCreate(&e1));
+    MLMC_HIP_TRY(hipEventRecord(e0, s));
+    if (!adaptive) {
+        levels = o->num_levels;
+        for (int q = 0; q < levels; ++q)
+            if ((rc = add(q, o->walks[q]))) return rc;
+        converged = true;
+    } else {
+        // Algorithm 1 on the mean over the entries of the per-entry variance, as for the
+        // backward full vector: pilot on l0 .. l0 + 4, Giles' optimal M_l, variance and
+        // weak-order-2 bias tests on the root-mean-square level terms, one level at a time
+        const int64_t cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
+        const double eps2 = o->eps * o->eps;
+        levels = std::min(5, max_levels);
+        for (int q = 0; q < levels; ++q)
+            if ((rc = add(q, o->pilot_walks))) return rc;
+        for (;;) {
+            ++iterations;
+            double tot = 0.0;
+            for (int q = 0; q < levels; ++q) tot += std::sqrt(std::max(V[q], 1e-300) * cost_of(q));
+            bool nan_size = false;
+            for (int q = 0; q < levels; ++q) {
+                const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(std::max(V[q], 1e-300) / cost_of(q)) * tot);
+                if (std::isnan(Mopt)) {   // non-finite samples: stop here and report them
+                    nan_size = true;
+                    break;
+                }
+                const int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
+                if (target > M[q] && (rc = add(q, target - M[q]))) return rc;
+            }
+            if (nan_size) break;
+            double var = 0.0;
+            for (int q = 0; q < levels; ++q) var += V[q] / static_cast<double>(M[q]);
+            bias = std::max(rms[levels - 1], rms[levels - 2] / 4.0) / 3.0;
+            bool capped = false;
+            for (int q = 0; q < levels; ++q) capped = capped || M[q] >= cap;
+            if (var <= eps2 / 2.0 * 1.0000001 && bias <= o->eps / std::sqrt(2.0)) {
+                converged = true;
+                break;
+            }
+            if (levels >= max_levels || (capped && var > eps2 / 2.0 * 1.0000001)) break;
+            ++levels;
+            if ((rc = add(levels - 1, o->pilot_walks))) return rc;
+        }
+    }
+    // x = sum over levels of U sum1 / M, and its per-entry variance
+    double est_var = 0.0;
+    if (n > 0) {
+        MLMC_HIP_TRY(hipMemsetAsync(x, 0, n * sizeof(double), s));
+        if (variance) MLMC_HIP_TRY(hipMemsetAsync(variance, 0, n * sizeof(double), s));
+    }
+    for (int q = 0; q < levels; ++q) {
+        est_var += V[q] / static_cast<double>(M[q]);
+        if (n > 0) {
+            hipLaunchKernelGGL(forward_combine, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, s,
+                               sums[q], sums[q] + n, n, UU, static_cast<double>(M[q]), x, variance);
+            MLMC_HIP_TRY(hipGetLastError());
         }
     }
     MLMC_HIP_TRY(hipEventRecord(e1, s));
     MLMC_HIP_TRY(hipEventSynchronize(e1));
     if (stats) {
+        std::memset(stats, 0, sizeof *stats);
         stats->l0 = p->l0;
-        stats->num_levels = o->num_levels;
-        stats->converged = 1;
+        stats->num_levels = levels;
+        stats->converged = converged ? 1 : 0;
+        stats->driver_iterations = iterations;
+        for (int q = 0; q < levels; ++q) {
+            stats->walks[q] = M[q];
+            stats->jumps[q] = static_cast<int64_t>(J[q]);
+            stats->level_mean_rms[q] = rms[q];
+            stats->level_var[q] = V[q];
+            stats->level_cost[q] = cost_of(q);
+            stats->steps += M[q] * (int64_t(1) << (p->l0 + q));
+            stats->total_jumps += static_cast<int64_t>(J[q]);
+        }
         stats->nonfinite = static_cast<int64_t>(nonfinite);
         stats->est_variance = est_var;
+        stats->est_bias = adaptive ? bias : 0.0;
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         stats->kernel_ms = ms;
         stats->walk_kernel_ms = wk_ms;
-        stats->walk_launches = o->num_levels;
+        stats->walk_launches = launches;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
+    if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
     return MLMC_OK;
 }
 

@@ -174,3 +174,29 @@ def test_forward_full_vector_matches_oracle_and_backward(api):
     d = xf - xb
     assert np.sqrt(np.mean(d * d)) < 5 * np.sqrt(np.mean(vf) + stb["est_variance"])
     p2.close()
+
+
+def test_forward_adaptive_run_equals_the_fixed_schedule_and_reaches_the_target(api):
+    """Algorithm 1 on the forward full vector adds walks to levels it already sampled; the
+    result equals the fixed-schedule run at its final sample sizes (same walks, same paths;
+    the deposits agree within the FP64 bar of the per-entry deviation), and its error
+    against the dense exponential over the entries is within the target."""
+    A, t, v = inputs.workload_laplace2d(12)
+    plan = api.Plan(A, t, precision="fp64")
+    vt = torch.as_tensor(v, device="cuda")
+    eps = 2e-2
+    xa, va, st = plan.forward(vt, eps=eps, seed=8, pilot_walks=4096)
+    assert st["converged"] and st["num_levels"] >= 5
+    xf, vf, stf = plan.forward(vt, walks=st["walks"], seed=8)
+    xa, va, xf, vf = (z.cpu().numpy() for z in (xa, va, xf, vf))
+    assert np.all(np.abs(xa - xf) <= 1e-10 * (np.abs(xf) + np.sqrt(vf)) + 1e-300)
+    assert stf["total_jumps"] == st["total_jumps"]
+    n = A.n
+    dense = np.zeros((n, n))
+    for i in range(n):
+        dense[i, A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]]] = A.values[A.row_ptr[i]:A.row_ptr[i + 1]]
+    exact = reference.expm_action(dense, v, t)
+    rmse = float(np.sqrt(np.mean((xa - exact) ** 2)))
+    _say(f"forward adaptive: levels {st['num_levels']} walks {st['walks']} rmse {rmse:.3e} (eps {eps})")
+    assert rmse < 1.5 * eps
+    plan.close()
