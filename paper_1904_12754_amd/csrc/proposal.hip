@@ -812,18 +812,20 @@ __global__ __launch_bounds__(kGradParams * kGradGroups) void grad_sum_kernel(
     P[t] -= lr * (m[t] / c1) / (sqrtf(v[t] / c2) + eps);
 }
 
-// Sum of n floats in FP64 in a fixed order (thread t adds t, t + 256, ...; the 256 partial
+// Sum of n floats in FP64 in a fixed order (thread t adds t, t + 1024, ...; the 1024 partial
 // sums meet in a fixed tree): the loss of a minibatch or of the held-out set, kept on the
 // device so that the training loop does not wait for the host.
-__global__ __launch_bounds__(256) void loss_sum_kernel(const float *__restrict__ x, int n, double *out)
+constexpr int kLossThreads = 1024;
+
+__global__ __launch_bounds__(kLossThreads) void loss_sum_kernel(const float *__restrict__ x, int n, double *out)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[kLossThreads];
     const int t = static_cast<int>(threadIdx.x);
     double acc = 0.0;
-    for (int i = t; i < n; i += 256) acc += static_cast<double>(x[i]);
+    for (int i = t; i < n; i += kLossThreads) acc += static_cast<double>(x[i]);
     sh[t] = acc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
         if (t < o) sh[t] += sh[t + o];
         __syncthreads();
     }
@@ -1222,7 +1224,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     // held-out loss of the current parameters into *out (on the device)
     auto val_loss = [&](double *out) -> int {
         MLMC_HIP_TRY(train_pass(false, p->prop_P, F, p, level, vsrc, static_cast<int>(n_val), shrink, part, lossv, s));
-        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, lossv, static_cast<int>(n_val), out);
+        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kLossThreads), 0, s, lossv, static_cast<int>(n_val), out);
         MLMC_HIP_TRY(hipGetLastError());
         return MLMC_OK;
     };
@@ -1255,7 +1257,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
                                1e-8f, c1, c2);
             MLMC_HIP_TRY(hipGetLastError());
             if (eval_after(step)) {
-                hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, lossb, B, d_loss + e);
+                hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kLossThreads), 0, s, lossb, B, d_loss + e);
                 MLMC_HIP_TRY(hipGetLastError());
                 ++e;
                 if (n_val > 0 && step > 0) {
