@@ -34,10 +34,18 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// Waves per SIMD the single-level kernel is compiled for. The loop's dependent gathers leave
+// latency that more resident waves hide: with FP32 weights five waves (96 VGPRs, a few of
+// them spilled) run faster than the four that the loop's 126 VGPRs allow, and with FP64
+// weights three faster than two; walks under a proposal measured slower that way and keep
+// what their registers give.
+template <typename R, bool kIS>
+constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? 5 : 3); }
+
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
 template <typename R, typename U, bool kHash, bool kIS, bool kSrc>
-__global__ __launch_bounds__(kBlock) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
                                                          uint32_t M, uint32_t chunk,
