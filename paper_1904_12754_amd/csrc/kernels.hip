@@ -44,7 +44,7 @@ constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? 5 : 3); }
 
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
-template <typename R, typename U, bool kHash, bool kIS, bool kSrc>
+template <typename R, typename U, bool kHash, bool kIS, bool kSrc, bool kBase>
 __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
@@ -76,11 +76,11 @@ __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walk
         if (lpr == kWave) {
             const uint32_t urow = __builtin_amdgcn_readfirstlane(row);
             const uint64_t uwb = uniform64(wb), uwe = uniform64(we);
-            walk_range<R, kHash, kIS, kSrc>(L, urow, walk0, uwb, uwe, sink);
+            walk_range<R, kHash, kIS, kSrc, kBase>(L, urow, walk0, uwb, uwe, sink);
             done = true;
         }
     }
-    if (!done) walk_range<R, kHash, kIS, kSrc>(L, row, walk0, wb, we, sink, lpr);
+    if (!done) walk_range<R, kHash, kIS, kSrc, kBase>(L, row, walk0, wb, we, sink, lpr);
     const double a = group_sum(sink.s1.value(), lpr);
     const double b = group_sum(sink.s2.value(), lpr);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
@@ -369,11 +369,15 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
 #define MLMC_LAUNCH_WALKS(R, U, H, IS)                                                        \
     do {                                                                                      \
         if (nrhs == 1 && L.src)                                                               \
-            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, true>), grid, block, 0, s, L,     \
-                               static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
-                               lpr, out, counters, hash_sums);                                \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, true, false>), grid, block, 0, s, \
+                               L, static_cast<const U *>(u), rows, nr, walk0, M, chunk,       \
+                               chunks, lpr, out, counters, hash_sums);                        \
+        else if (nrhs == 1 && !(IS) && L.base)   /* the base level, compiled as such */      \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false, !(IS)>), grid, block, 0,   \
+                               s, L, static_cast<const U *>(u), rows, nr, walk0, M, chunk,    \
+                               chunks, lpr, out, counters, hash_sums);                        \
         else if (nrhs == 1)                                                                   \
-            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false>), grid, block, 0, s, L,    \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false, false>), grid, block, 0, s, L, \
                                static_cast<const U *>(u), rows, nr, walk0, M, chunk, chunks,  \
                                lpr, out, counters, hash_sums);                                \
         else                                                                                  \

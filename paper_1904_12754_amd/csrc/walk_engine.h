@@ -453,24 +453,28 @@ struct AliasStart {
     __device__ __forceinline__ uint32_t start_row() const { return 0u; }   // per lane instead
 };
 
-template <typename R, bool kHash, bool kIS, bool kSrc, typename Sink, typename Start>
+// kBase: the level is the coarsest (l0) by construction, so the code for the coarse
+// functional and for held walks is left out; otherwise L.base decides at run time.
+template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase = false, typename Sink, typename Start>
 __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
                                                 uint64_t wb, uint64_t we, Sink &sink,
                                                 uint32_t lpr = kWave);
 
-template <typename R, bool kHash, bool kIS, bool kSrc = false, typename Sink>
+template <typename R, bool kHash, bool kIS, bool kSrc = false, bool kBase = false, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
                                            uint64_t wb, uint64_t we, Sink &sink,
                                            uint32_t lpr = kWave)
 {
     const FixedStart st{row, L.rec[row]};
-    walk_range_from<R, kHash, kIS, kSrc>(L, st, walk0, wb, we, sink, lpr);
+    walk_range_from<R, kHash, kIS, kSrc, kBase>(L, st, walk0, wb, we, sink, lpr);
 }
 
-template <typename R, bool kHash, bool kIS, bool kSrc, typename Sink, typename Start>
+template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase, typename Sink, typename Start>
 __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
                                                 uint64_t wb, uint64_t we, Sink &sink, uint32_t lpr)
 {
+    const bool base = kBase || L.base != 0;
+    const int ibase = base ? 1 : 0;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t group = lpr >= kWave ? ~0ull : ((1ull << lpr) - 1ull) << (lane & ~(lpr - 1u));
     const R hd = static_cast<R>(L.half_dt);
@@ -584,7 +588,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         if (chain || finish) {
             const uint32_t run_end = chain ? s.n : L.N;
             if constexpr (kSrc) source_run<R>(s, d_of<R>(s.cur), hd, s.run_start, run_end, L.N, sink.source(s.k));
-            add_run<R>(d_of<R>(s.cur), s.run_start, run_end, L.N, s.ef2, s.ec2, s.ed2, L.base != 0);
+            add_run<R>(d_of<R>(s.cur), s.run_start, run_end, L.N, s.ef2, s.ec2, s.ed2, base);
         }
         if (chain) {
             chain_start(s, chain_word);
@@ -599,7 +603,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
         // At the coarsest level the sample is one exponential, so a sink that adds each
         // lane's samples on its own lane takes it at once (the lane's samples are added in
         // the order its walks end either way, so the sums are the same).
-        const bool direct = Sink::kLaneLocal && L.base != 0;
+        const bool direct = Sink::kLaneLocal && base;
         if (finish) {
             if (direct) {
                 Pending<R, kSrc> now;
@@ -607,7 +611,7 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 sink.take(true, now.finished(1, hd));
                 s.st = kIdle;
             } else if (!pend.valid) {
-                pend.hold(s, L.base, hd);
+                pend.hold(s, ibase, hd);
                 s.st = kIdle;
             } else {
                 s.st = kWait;
@@ -618,16 +622,16 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
             if (__popcll(__ballot(pend.valid)) >= kFlushAt ||
                 (waiting != 0 && (__popcll(waiting) >= kMaxWaiting ||
                                   __ballot(s.st < kWait) == 0))) {
-                sink.take(pend.valid, pend.finished(L.base, hd));
+                sink.take(pend.valid, pend.finished(ibase, hd));
                 pend.valid = false;
                 if (s.st == kWait) {
-                    pend.hold(s, L.base, hd);
+                    pend.hold(s, ibase, hd);
                     s.st = kIdle;
                 }
             }
         }
     }
-    sink.take(pend.valid, pend.finished(L.base, hd));
+    sink.take(pend.valid, pend.finished(ibase, hd));
 }
 
 // Single right-hand side: each lane adds its own samples to compensated sums (kSrc: the
