@@ -272,9 +272,9 @@ struct Walker {
     RowRec cur;
     // the holding time accumulated in step n: bracket [tau_h - tau_e, tau_h + tau_e] around
     // the exact FP64 value, and what is needed to replay it exactly (state and jump count
-    // at the start of the chain, and the step's word)
+    // at the start of the chain; the step's word is in the cached block)
     float tau_h = 0.0f, tau_e = 0.0f;
-    uint32_t chain_k = 0, chain_J = 0, chain_word = 0;
+    uint32_t chain_k = 0, chain_J = 0;
     R ef2 = 0, ec2 = 0, ed2 = 0;
     R wr = 1;                             // likelihood ratio of the path under a proposal
     R jf = 0, jc = 0;                     // source term: fine and coarse Simpson sums
@@ -409,7 +409,6 @@ __device__ __forceinline__ void chain_start(Walker<R, kHash> &s, uint32_t word)
     s.tau_e = (kFastLogAbs + kFastLogRel * e) * ir + s.tau_h * 0x1p-21f;
     s.chain_k = s.k;
     s.chain_J = s.J;
-    s.chain_word = word;
 }
 
 // The wave's lanes form groups of lpr lanes (lpr a power of two, 1..64); the lanes of a group
@@ -537,12 +536,12 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 s.hash = (s.hash ^ static_cast<uint64_t>(s.n + 1)) * kFnvPrime;
             }
             // add the holding time at the new state; the chain goes on while the total is
-            // below dt. An absorbing state (1/r infinite in FP64) holds forever; a rate so
-            // small that only the FP32 copy of 1/r is infinite makes the bracket infinite or
-            // NaN, and every comparison with one sends the decision to the exact path.
+            // below dt. An absorbing state (no off-diagonal entry: r = 0) holds forever; a
+            // rate so small that 1/r is infinite in FP32 (or FP64) makes the bracket infinite
+            // or NaN, and every comparison with one sends the decision to the exact path.
             const float ir = static_cast<float>(s.cur.inv_r);
             bool chain_over;
-            if (!(s.cur.inv_r < INFINITY)) {
+            if (s.cur.deg == 0u) {
                 chain_over = true;
             } else {
                 const float e = neg_log_uniform_fast(ph.z);
@@ -553,8 +552,13 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
                 const float lo = s.tau_h - s.tau_e;
                 if (hi < L.dt_below) chain_over = false;
                 else if (lo >= L.dt_above) chain_over = true;
-                else chain_over = !(chain_tau_exact<kIS>(L, row0, s.w, s.chain_k, s.chain_J, s.J,
-                                                         s.chain_word) < L.dt);
+                else {
+                    // the chain's first word is that of step n in the cached block
+                    const uint32_t m = s.n & 3u;
+                    const uint32_t word = m == 0u ? s.b0 : m == 1u ? s.b1 : m == 2u ? s.b2 : s.b3;
+                    chain_over = !(chain_tau_exact<kIS>(L, row0, s.w, s.chain_k, s.chain_J, s.J, word) <
+                                   L.dt);
+                }
             }
             if (chain_over) {
                 // the chain of step n ends: the walk scans on from step n + 1 (below, in
