@@ -71,7 +71,7 @@ struct BatchParams {
 
 // Items [item_lo, item_hi) of the batch (one phase of the launch sequence).
 template <typename R, typename U, bool kMulti>
-__global__ __launch_bounds__(kBlock) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 4) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       BatchParams *prm)
 {

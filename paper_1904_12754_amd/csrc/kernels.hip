@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walk
 }
 
 template <typename R, typename U, bool kHash, bool kIS>
-__global__ __launch_bounds__(kBlock) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 3 : 2)) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
                                                           int32_t nrhs,
                                                           const int64_t *__restrict__ rows,
                                                           uint32_t n_rows, uint32_t walk0,
