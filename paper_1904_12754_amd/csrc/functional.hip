@@ -164,6 +164,16 @@ struct FuncCall {
     }
 };
 
+// A pair of timing events, destroyed when it goes out of scope.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 template <typename T>
 int dalloc(T **p, size_t count)
 {
@@ -258,7 +268,8 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
         fc.partial_items = items;
     }
     MLMC_HIP_TRY(hipMemsetAsync(fc.ctr, 0, (kCounterSetU64 + 3) * sizeof(unsigned long long), s));
-    hipEvent_t e0, e1;
+    EventPair ev;   // destroyed on every return path
+    hipEvent_t &e0 = ev.e0, &e1 = ev.e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     MLMC_HIP_TRY(hipEventRecord(e0, s));
@@ -287,8 +298,6 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     (void)hipEventElapsedTime(&out.ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     out.s1 = tot[0];
     out.s2 = tot[1];
     out.jumps = c[0];
@@ -320,7 +329,8 @@ int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, i
     AliasStart st{fc.thr, fc.alias, fc.neg, static_cast<uint32_t>(p->n), stream_word(lev, instance, 2)};
     const uint32_t items = static_cast<uint32_t>((M + kFuncChunk - 1) / kFuncChunk);
     MLMC_HIP_TRY(hipMemsetAsync(fc.ctr, 0, (kCounterSetU64 + 3) * sizeof(unsigned long long), s));
-    hipEvent_t e0, e1;
+    EventPair ev;   // destroyed on every return path
+    hipEvent_t &e0 = ev.e0, &e1 = ev.e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     MLMC_HIP_TRY(hipEventRecord(e0, s));
@@ -341,8 +351,6 @@ int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, i
     MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
     (void)hipEventElapsedTime(&out.ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     out.jumps = c[0];
     out.nonfinite = c[1];
     out.hash = c[2];
@@ -452,7 +460,8 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
     int levels = 0, iterations = 0;
     bool converged = false;
     double bias = 0.0;
-    hipEvent_t e0, e1;
+    EventPair ev;   // destroyed on every return path
+    hipEvent_t &e0 = ev.e0, &e1 = ev.e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     MLMC_HIP_TRY(hipEventRecord(e0, s));
@@ -531,8 +540,6 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
         stats->walk_kernel_ms = wk_ms;
         stats->walk_launches = launches;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
     return MLMC_OK;
@@ -644,7 +651,8 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
     int levels = 0, iterations = 0;
     bool converged = false;
     double bias = 0.0;
-    hipEvent_t e0, e1;
+    EventPair ev;   // destroyed on every return path
+    hipEvent_t &e0 = ev.e0, &e1 = ev.e1;
     MLMC_HIP_TRY(hipEventCreate(&e0));
     MLMC_HIP_TRY(hipEventCreate(&e1));
     MLMC_HIP_TRY(hipEventRecord(e0, s));
@@ -731,8 +739,6 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
         stats->walk_kernel_ms = wk_ms;
         stats->walk_launches = launches;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
     return MLMC_OK;
