@@ -320,6 +320,15 @@ def test_eigenvector_closed_form():
 # ----------------------------------------------------------------------------------
 # rates (section 4: the mean and the variance of P_l - P_{l-1} decay with slope -2)
 # ----------------------------------------------------------------------------------
+def _paper_rate(name):
+    """A rate the paper states (tests/golden/paper_rates.json, with its source)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_rates.json")
+    with open(path) as f:
+        return float(json.load(f)[name]["value"])
+
+
 def test_level_mean_and_variance_decay_with_slope_minus_two():
     a = _signed_matrix(10, 17, density=0.5)
     C = inputs.from_dense(a)
@@ -335,8 +344,8 @@ def test_level_mean_and_variance_decay_with_slope_minus_two():
     mm = np.array([np.sqrt(np.mean(m ** 2)) for m in m_exact])
     sv = np.polyfit(lv[1:], np.log2(V[1:]), 1)[0]
     sm = np.polyfit(lv[1:], np.log2(mm[1:]), 1)[0]
-    assert -2.5 < sv < -1.5, sv
-    assert -2.3 < sm < -1.7, sm
+    assert abs(sv - _paper_rate("level_variance_slope")) < 0.5, sv
+    assert abs(sm - _paper_rate("level_mean_slope")) < 0.3, sm
 
 
 def test_statistical_error_decays_as_inverse_square_root():
@@ -356,7 +365,7 @@ def test_statistical_error_decays_as_inverse_square_root():
             e2.append(np.mean((ls.sum1[:, 0] / M - exact) ** 2))
         errs.append(math.sqrt(np.mean(e2)))
     slope = np.polyfit(np.log(Ms), np.log(errs), 1)[0]
-    assert -0.62 < slope < -0.38, slope
+    assert abs(slope - _paper_rate("statistical_error_slope")) < 0.12, slope
 
 
 # ----------------------------------------------------------------------------------
