@@ -71,7 +71,7 @@ struct BatchParams {
 
 // Items [item_lo, item_hi) of the batch (one phase of the launch sequence).
 template <typename R, typename U, bool kMulti>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 4) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       BatchParams *prm)
 {
@@ -449,8 +449,9 @@ uint32_t items_chunk(const mlmc_batch *b)
     return static_cast<uint32_t>(std::min(4096.0, std::max(64.0, c)));
 }
 
-// Time candidate shapes (walks per item: 256, 1024, 4096 and the size rule's choice; waves
-// per CU: 8, 16, 32) on every kTuneStride-th instance of the batch at its full sample sizes,
+// Time candidate shapes (walks per item: 1024, 4096 and the size rule's choice; waves per CU:
+// 8, 16, 20, 32, where 20 fills the 5 waves per SIMD of the FP32 one-right-hand-side kernel in
+// one round) on every kTuneStride-th instance of the batch at its full sample sizes,
 // with the phases of the real launch, and keep the fastest. The choice is cached per class of
 // batch for the process.
 constexpr int kTuneStride = 8;
@@ -483,11 +484,11 @@ int autotune(mlmc_batch *b, hipStream_t s)
     }
     std::vector<Shape> cands;
     {
-        std::vector<uint32_t> chunks = {256, 1024, 4096};
+        std::vector<uint32_t> chunks = {1024, 4096};
         if (std::find(chunks.begin(), chunks.end(), b->shape.chunk) == chunks.end())
             chunks.push_back(b->shape.chunk);
         for (uint32_t c : chunks)
-            for (int w : {8, 16, 32}) cands.push_back(Shape{c, w});
+            for (int w : {8, 16, 20, 32}) cands.push_back(Shape{c, w});
     }
     const int stride = b->count >= kTuneStride ? kTuneStride : b->count;
     double best = 1e300;
