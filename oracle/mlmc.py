@@ -407,9 +407,15 @@ class _Acc:
 
 def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | None = None,
                   pilot: int = 256, max_levels: int = 20, rows=None, instance: int = 0,
-                  threads: int = 0, max_walks: int | None = None):
+                  threads: int = 0, max_walks: int | None = None, max_iterations: int = 100):
     """Algorithm 1: pilot M0 walks on levels l0..l0+4, then repeat {optimal M_l; run the
-    extra walks; stop when the variance and bias tests pass, else add a level}."""
+    extra walks; stop when the error is below eps, else add a level}.
+
+    The error is read as two parts: the estimator's variance sum_l V_l / M_l against the
+    budget eps^2 / 2, and the extrapolated bias of the finest level against eps / sqrt(2).
+    The optimal sample sizes are recomputed from the updated variances, and the missing
+    walks run, until they ask for no more walks (so the variance part holds); only then is
+    the bias tested, and a failed bias test adds the level L + 1 with M0 walks."""
     if l0 is None:
         l0 = default_l0(t, beta)
     L = l0 + 4
@@ -428,35 +434,43 @@ def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | No
             prev.mass = prev.mass + ls.mass
             prev.jumps += int(ls.jumps.sum())
 
+    def level_var(lev):          # row-mean per-walk variance of the level's samples
+        a = acc[lev]
+        m = a.s1 / a.M
+        return float(np.mean(np.maximum(a.s2 / a.M - m * m, 0.0)))
+
+    def level_rms(lev):          # root mean square over rows of the level term
+        a = acc[lev]
+        return float(np.sqrt(np.mean((a.s1 / a.M) ** 2)))
+
     for lev in range(l0, L + 1):
         run(lev, pilot)
     converged = False
-    while True:
+    iterations = 0
+    while iterations < max_iterations:
+        iterations += 1
         levs = list(range(l0, L + 1))
         nrows = acc[l0].s1.shape[0]
-        V = []
-        C = []
-        for lev in levs:
-            a = acc[lev]
-            m = a.s1 / a.M
-            V.append(max(float(np.mean(np.maximum(a.s2 / a.M - m * m, 0.0))), 1e-300))
-            C.append((1 << lev) + JUMP_COST * a.jumps / (a.M * nrows))
+        V = [max(level_var(lev), 1e-300) for lev in levs]
+        C = [(1 << lev) + JUMP_COST * acc[lev].jumps / (acc[lev].M * nrows) for lev in levs]
         Mopt = optimal_M(V, C, eps)
+        topped = False
         for lev, Mo in zip(levs, Mopt):
             extra = int(Mo) - acc[lev].M
             if max_walks is not None:
                 extra = min(extra, max_walks - acc[lev].M)
             if extra > 0:
                 run(lev, extra)
-        var = sum(float(np.mean(np.maximum(acc[l].s2 / acc[l].M - (acc[l].s1 / acc[l].M) ** 2,
-                                           0.0))) / acc[l].M for l in levs)
-        rms = lambda l: float(np.sqrt(np.mean((acc[l].s1 / acc[l].M) ** 2)))
-        bias = bias_estimate(rms(L), rms(L - 1))
+                topped = True
+        if topped:
+            continue                   # the variance part: re-estimate V_l, resize
+        var = sum(level_var(lev) / acc[lev].M for lev in levs)
+        bias = bias_estimate(level_rms(L), level_rms(L - 1))
         if var <= eps * eps / 2.0 * 1.0000001 and bias <= eps / math.sqrt(2.0):
             converged = True
             break
-        if L - l0 + 1 >= max_levels:
-            break
+        if var > eps * eps / 2.0 * 1.0000001 or L - l0 + 1 >= max_levels:
+            break                      # walk cap reached, or no level left to add
         L += 1
         run(L, pilot)
     levels = [LevelStats(l, acc[l].M, acc[l].s1, acc[l].s2, acc[l].mass, acc[l].jumps)
@@ -467,6 +481,7 @@ def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | No
     steps = sum(st.M * (1 << st.level) * nrows for st in levels)
     res = Result(x, levels, l0, mass, steps, sum(st.jumps for st in levels))
     res.converged = converged
+    res.iterations = iterations
     return res
 
 

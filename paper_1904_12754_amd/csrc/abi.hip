@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -592,53 +593,24 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
         MLMC_HIP_TRY(hipEventRecord(p->ev1, s));
         converged = true;
     } else {
-        // Algorithm 1: pilot on l0 .. l0 + 4, then optimal M_l, variance and bias tests
-        const int64_t cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
-        const double eps2 = o->eps * o->eps;
-        levels = std::min(5, max_levels);
-        for (int qq = 0; qq < levels; ++qq)
-            if ((rc = add_walks(qq, o->pilot_walks))) return rc;
-        for (;;) {
-            ++iterations;
-            if ((rc = read_moments(levels))) return rc;
-            std::vector<double> V(levels), C(levels);
-            double tot = 0.0;
-            for (int qq = 0; qq < levels; ++qq) {
-                V[qq] = std::max(level_var(qq), 1e-300);
-                C[qq] = level_cost(qq);
-                tot += std::sqrt(V[qq] * C[qq]);
-            }
-            bool added = false, nan_size = false;
-            for (int qq = 0; qq < levels; ++qq) {
-                const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(V[qq] / C[qq]) * tot);
-                if (std::isnan(Mopt)) {   // non-finite samples: stop here and write what there is
-                    nan_size = true;
-                    break;
-                }
-                int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
-                if (target > M[qq]) {
-                    if ((rc = add_walks(qq, target - M[qq]))) return rc;
-                    added = true;
-                }
-            }
-            if (added && (rc = read_moments(levels))) return rc;
-            if (nan_size) break;
-            double var = 0.0;
-            for (int qq = 0; qq < levels; ++qq) var += level_var(qq) / static_cast<double>(M[qq]);
-            bias = std::max(level_rms(levels - 1), level_rms(levels - 2) / 4.0) / 3.0;
-            const bool capped = [&] {
-                for (int qq = 0; qq < levels; ++qq)
-                    if (M[qq] >= cap) return true;
-                return false;
-            }();
-            if (var <= eps2 / 2.0 * 1.0000001 && bias <= o->eps / std::sqrt(2.0)) {
-                converged = true;
-                break;
-            }
-            if (levels >= max_levels || (capped && var > eps2 / 2.0 * 1.0000001)) break;
-            ++levels;
-            if ((rc = add_walks(levels - 1, o->pilot_walks))) return rc;
-        }
+        // Algorithm 1 on the row means: V_l = mean_i V_{l,i}, m_l = RMS_i m_{l,i}
+        DriverOpts d;
+        d.eps = o->eps;
+        d.pilot = o->pilot_walks;
+        d.max_levels = max_levels;
+        d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
+        auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {
+            const int r2 = read_moments(lv);
+            if (r2) return r2;
+            for (int qq = 0; qq < lv; ++qq) est[qq] = LevelEstimate{level_var(qq), level_cost(qq), level_rms(qq)};
+            return MLMC_OK;
+        };
+        DriverOut out;
+        if ((rc = algorithm1(d, M, add_walks, measure, out))) return rc;
+        levels = out.levels;
+        converged = out.converged;
+        iterations = out.iterations;
+        bias = out.bias;
         MLMC_HIP_TRY(hipEventRecord(p->ev1, s));
     }
     // x = sum_l m_l (FP64 combine)

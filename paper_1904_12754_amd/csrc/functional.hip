@@ -15,6 +15,7 @@
 
 #include "../../include/mlmc_expv.h"
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 #include "plan.h"
 #include "walk_engine.h"
@@ -471,41 +472,22 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
             if ((rc = add(q, o->walks[q]))) return rc;
         converged = true;
     } else {
-        // Algorithm 1 on the scalar: pilot on l0 .. l0 + 4, Giles' optimal M_l, variance and
-        // weak-order-2 bias tests, one more level at a time
-        const int64_t cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
-        const double eps2 = o->eps * o->eps;
-        levels = std::min(5, max_levels);
-        for (int q = 0; q < levels; ++q)
-            if ((rc = add(q, o->pilot_walks))) return rc;
-        for (;;) {
-            ++iterations;
-            double tot = 0.0;
-            for (int q = 0; q < levels; ++q) tot += std::sqrt(std::max(var_of(q), 1e-300) * cost_of(q));
-            bool nan_size = false;
-            for (int q = 0; q < levels; ++q) {
-                const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(std::max(var_of(q), 1e-300) / cost_of(q)) * tot);
-                if (std::isnan(Mopt)) {   // non-finite samples: stop here and report them
-                    nan_size = true;
-                    break;
-                }
-                const int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
-                if (target > M[q] && (rc = add(q, target - M[q]))) return rc;
-            }
-            if (nan_size) break;
-            double var = 0.0;
-            for (int q = 0; q < levels; ++q) var += var_of(q) / static_cast<double>(M[q]);
-            bias = std::max(std::fabs(mean_of(levels - 1)), std::fabs(mean_of(levels - 2)) / 4.0) / 3.0;
-            bool capped = false;
-            for (int q = 0; q < levels; ++q) capped = capped || M[q] >= cap;
-            if (var <= eps2 / 2.0 * 1.0000001 && bias <= o->eps / std::sqrt(2.0)) {
-                converged = true;
-                break;
-            }
-            if (levels >= max_levels || (capped && var > eps2 / 2.0 * 1.0000001)) break;
-            ++levels;
-            if ((rc = add(levels - 1, o->pilot_walks))) return rc;
-        }
+        // Algorithm 1 on the scalar's variance
+        DriverOpts d;
+        d.eps = o->eps;
+        d.pilot = o->pilot_walks;
+        d.max_levels = max_levels;
+        d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
+        auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {
+            for (int q = 0; q < lv; ++q) est[q] = LevelEstimate{var_of(q), cost_of(q), mean_of(q)};
+            return MLMC_OK;
+        };
+        DriverOut out;
+        if ((rc = algorithm1(d, M, add, measure, out))) return rc;
+        levels = out.levels;
+        converged = out.converged;
+        iterations = out.iterations;
+        bias = out.bias;
     }
     MLMC_HIP_TRY(hipEventRecord(e1, s));
     MLMC_HIP_TRY(hipEventSynchronize(e1));
@@ -662,42 +644,23 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
             if ((rc = add(q, o->walks[q]))) return rc;
         converged = true;
     } else {
-        // Algorithm 1 on the mean over the entries of the per-entry variance, as for the
-        // backward full vector: pilot on l0 .. l0 + 4, Giles' optimal M_l, variance and
-        // weak-order-2 bias tests on the root-mean-square level terms, one level at a time
-        const int64_t cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
-        const double eps2 = o->eps * o->eps;
-        levels = std::min(5, max_levels);
-        for (int q = 0; q < levels; ++q)
-            if ((rc = add(q, o->pilot_walks))) return rc;
-        for (;;) {
-            ++iterations;
-            double tot = 0.0;
-            for (int q = 0; q < levels; ++q) tot += std::sqrt(std::max(V[q], 1e-300) * cost_of(q));
-            bool nan_size = false;
-            for (int q = 0; q < levels; ++q) {
-                const double Mopt = std::ceil(2.0 / eps2 * std::sqrt(std::max(V[q], 1e-300) / cost_of(q)) * tot);
-                if (std::isnan(Mopt)) {   // non-finite samples: stop here and report them
-                    nan_size = true;
-                    break;
-                }
-                const int64_t target = Mopt >= static_cast<double>(cap) ? cap : static_cast<int64_t>(Mopt);
-                if (target > M[q] && (rc = add(q, target - M[q]))) return rc;
-            }
-            if (nan_size) break;
-            double var = 0.0;
-            for (int q = 0; q < levels; ++q) var += V[q] / static_cast<double>(M[q]);
-            bias = std::max(rms[levels - 1], rms[levels - 2] / 4.0) / 3.0;
-            bool capped = false;
-            for (int q = 0; q < levels; ++q) capped = capped || M[q] >= cap;
-            if (var <= eps2 / 2.0 * 1.0000001 && bias <= o->eps / std::sqrt(2.0)) {
-                converged = true;
-                break;
-            }
-            if (levels >= max_levels || (capped && var > eps2 / 2.0 * 1.0000001)) break;
-            ++levels;
-            if ((rc = add(levels - 1, o->pilot_walks))) return rc;
-        }
+        // Algorithm 1 on the mean over the entries of the per-entry variance and the
+        // root-mean-square level terms, as for the backward full vector
+        DriverOpts d;
+        d.eps = o->eps;
+        d.pilot = o->pilot_walks;
+        d.max_levels = max_levels;
+        d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
+        auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {
+            for (int q = 0; q < lv; ++q) est[q] = LevelEstimate{V[q], cost_of(q), rms[q]};
+            return MLMC_OK;
+        };
+        DriverOut out;
+        if ((rc = algorithm1(d, M, add, measure, out))) return rc;
+        levels = out.levels;
+        converged = out.converged;
+        iterations = out.iterations;
+        bias = out.bias;
     }
     // x = sum over levels of U sum1 / M, and its per-entry variance
     double est_var = 0.0;

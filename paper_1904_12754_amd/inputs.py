@@ -295,6 +295,25 @@ def workload_uneven_batch(count: int = 512, nmin: int = 1000, nmax: int = 100_00
     return out
 
 
+def small_chain(n: int, seed: int, signed: bool, density: float, d_spread: float):
+    """A small dense-ish matrix for pins of the level structure: off-diagonal entries
+    U(-1, 1) (signed) or U(0.3, 1) (positive) kept with probability `density`, scaled so
+    that the largest off-diagonal absolute row sum is 1, and a diagonal chosen so that the
+    row's diagonal weight a_ii + sum_{j != i} |a_ij| is U(-d_spread, d_spread); right-hand
+    side U(-1, 1) (signed) or U(0.5, 1.5). Returns (CSR, u); a time beta makes beta the
+    largest jump rate times beta."""
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-1.0, 1.0, (n, n)) if signed else rng.uniform(0.3, 1.0, (n, n))
+    off = off * (rng.uniform(size=(n, n)) < density)
+    np.fill_diagonal(off, 0.0)
+    rowabs = np.abs(off).sum(axis=1)
+    off = off / rowabs.max()
+    weight = rng.uniform(-d_spread, d_spread, n)
+    a = off + np.diag(weight - np.abs(off).sum(axis=1))
+    u = rng.uniform(-1.0, 1.0, n) if signed else rng.uniform(0.5, 1.5, n)
+    return from_dense(a), u
+
+
 def workload_convdiff3d(m: int = 128):
     """3D 7-point convection-diffusion, m^3 cells on [-4, 4]^3, ||tA||_1 = 4,
     v = exp(-|x|^2)."""

@@ -281,6 +281,36 @@ def test_adaptive_run_equals_the_oracle_at_its_final_sample_sizes(api, precision
     plan.close()
 
 
+def test_adaptive_run_takes_the_oracles_levels_and_sample_sizes(api):
+    """Algorithm 1's decisions: on a chain whose splitting bias at the pilot's finest level
+    is 1.25 eps / sqrt(2) (dense truth; beta r_max = 16, l0 = 0), the FP64 GPU run must add
+    the same level as the oracle's driver and end with the same walks per level (a sample
+    size may differ by one walk where a rounded optimum falls on an integer), and its
+    estimate must equal the oracle's at those sizes within the FP64 bar."""
+    A, u = inputs.small_chain(20, 7, False, 0.5, 0.3)
+    beta = 16.0
+    a = A.to_dense()
+    x_true = reference.expm_action(a, u, beta)
+    bias4 = math.sqrt(float(np.mean((reference.strang_level(a, u, beta, 4) - x_true) ** 2)))
+    eps = bias4 * math.sqrt(2.0) / 1.25
+    tt = _tables(A)
+    res = orc.mlmc_adaptive(tt, beta, u, eps, seed=5, l0=0, pilot=256)
+    want = [st.M for st in res.levels]
+    plan = api.Plan(A, beta, precision="fp64", l0=0)
+    x, st = plan.run(torch.as_tensor(u, device="cuda"), eps=eps, seed=5, pilot_walks=256)
+    nl = st["num_levels"]
+    got = list(st["walks"][:nl])
+    _say(f"adaptive bias case: gpu levels {nl} walks {got}; oracle levels {len(want)} walks {want}")
+    assert st["converged"] and res.converged
+    assert nl == len(want) == 6
+    assert all(abs(g - w) <= 1 for g, w in zip(got, want)), (got, want)
+    ref = res if got == want else orc.mlmc_fixed(tt, beta, u, 0, nl - 1, got, seed=5)
+    xg = x.cpu().numpy()[:, 0]
+    assert np.all(np.abs(xg - ref.x[:, 0]) <= TOL["fp64"] * ref.mass[:, 0] + 1e-300)
+    assert st["est_bias"] <= eps / math.sqrt(2.0)
+    plan.close()
+
+
 def test_classical_single_level_mc_estimates_the_finest_strang_product(api):
     """Classical Monte Carlo is the base estimator at one fine level L: a plan with l0 = L
     and one level. Its expectation is the Strang product x^L, the same as that of MLMC on

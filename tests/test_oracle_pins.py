@@ -395,3 +395,67 @@ def test_adaptive_driver_reaches_the_target():
     exact = reference.laplace1d_exact(v, t)
     rmse = float(np.sqrt(np.mean((res.x[:, 0] - exact) ** 2)))
     assert rmse < 3 * eps
+
+
+# ----------------------------------------------------------------------------------
+# Algorithm 1's error test: the extrapolated bias (weak order 2 of the Strang splitting,
+# section 4) and the level it adds when the bias is above its share of eps
+# ----------------------------------------------------------------------------------
+# signed 5 x 5 chains, beta r_max = 8, l0 = 0: single entries whose level terms change
+# sign before the asymptotic regime (the finest term alone underestimates their bias)
+SIGNED_CHAINS = (26, 108, 131)
+
+
+def _dense_levels(A, u, beta, l0, L):
+    a = A.to_dense()
+    x = reference.expm_action(a, u, beta)
+    xs = [reference.strang_level(a, u, beta, lev) for lev in range(l0, L + 1)]
+    return x, xs
+
+
+@pytest.mark.parametrize("seed", SIGNED_CHAINS)
+def test_bias_estimate_bounds_the_true_splitting_bias(seed):
+    """Algorithm 1 stops when its error estimate is below eps; the bias part extrapolates
+    the level terms m_L = x^L - x^{L-1} with the weak order 2 of the splitting (section 4).
+    Against the true bias x^L - x of the dense Strang products and the dense exponential:
+    per entry it never falls far below the truth (also where m_L alone is small because the
+    terms change sign), and in the asymptotic regime its root mean square over the entries
+    equals the true one within 10 %."""
+    A, u = inputs.small_chain(5, seed, True, 0.7, 1.0)
+    beta = 8.0
+    x, xs = _dense_levels(A, u, beta, 0, 8)
+    m = [xs[0]] + [xs[q] - xs[q - 1] for q in range(1, len(xs))]
+    scale = float(np.abs(x).max())
+    worst = np.inf
+    for L in range(2, 9):
+        true = np.abs(xs[L] - x)
+        est = np.array([mlmc.bias_estimate(abs(m[L][i]), abs(m[L - 1][i])) for i in range(5)])
+        keep = true > 1e-6 * scale
+        worst = min(worst, float(np.min(est[keep] / true[keep])))
+        if L >= 5:
+            rms_true = math.sqrt(float(np.mean((xs[L] - x) ** 2)))
+            rms_m = lambda q: math.sqrt(float(np.mean(m[q] ** 2)))
+            ratio = mlmc.bias_estimate(rms_m(L), rms_m(L - 1)) / rms_true
+            assert 0.9 < ratio < 1.1, (L, ratio)
+    assert worst > 0.6, worst
+
+
+def test_adaptive_driver_adds_the_levels_the_bias_requires():
+    """A fast-mixing 20-state chain (beta r_max = 16, l0 = 0) whose splitting bias at the
+    pilot's finest level L = l0 + 4 is 1.25 eps / sqrt(2) and at L + 1 about a quarter of
+    that (true values from the dense products): Algorithm 1 must add exactly one level,
+    meet the variance budget eps^2 / 2, and reach the true solution within eps."""
+    A, u = inputs.small_chain(20, 7, False, 0.5, 0.3)
+    beta = 16.0
+    x, xs = _dense_levels(A, u, beta, 0, 6)
+    true_bias = [math.sqrt(float(np.mean((xl - x) ** 2))) for xl in xs]
+    eps = true_bias[4] * math.sqrt(2.0) / 1.25
+    needed = next(L for L in range(4, 7) if true_bias[L] <= eps / math.sqrt(2.0))
+    assert needed == 5
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    res = mlmc.mlmc_adaptive(tt, beta, u, eps, seed=5, l0=0, pilot=256)
+    assert res.converged
+    assert res.levels[-1].level == needed, [st.level for st in res.levels]
+    assert res.est_mse() <= eps * eps / 2.0 * (1.0 + 1e-6)
+    rmse = math.sqrt(float(np.mean((res.x[:, 0] - x) ** 2)))
+    assert rmse < eps, (rmse, eps)

@@ -25,6 +25,8 @@ SOURCE = "tests/test_oracle_source.py"
 FUNCTIONAL = "tests/test_oracle_functional.py"
 PROPOSAL = "tests/test_oracle_proposal.py::"
 LEVEL_MEANS = PINS + "test_level_means_match_dense_strang_products"
+BIAS = PINS + "test_bias_estimate_bounds_the_true_splitting_bias"
+DRIVER_LEVELS = PINS + "test_adaptive_driver_adds_the_levels_the_bias_requires"
 C = "mlmc_oracle.c"
 
 # (name, file in oracle/, [(text, replacement)], pin tests that must catch it)
@@ -128,10 +130,22 @@ PLANTS = [
        "        orc_add(&a1[j], y);")],
      [FUNCTIONAL + "::test_forward_deposits_give_every_functional",
       FUNCTIONAL + "::test_forward_level_means_match_dense_strang_products"]),
-    # Algorithm 1's sample sizes
+    # Algorithm 1's sample sizes and error test
     ("optimal M without the factor 2", "mlmc.py",
      [("np.ceil(2.0 * eps ** -2 *", "np.ceil(eps ** -2 *")],
      [PINS + "test_optimal_sample_sizes_meet_the_variance_budget"]),
+    ("bias divided by 2^alpha + 1", "mlmc.py",
+     [("/ (2.0 ** ALPHA - 1.0)", "/ (2.0 ** ALPHA + 1.0)")],
+     [BIAS, DRIVER_LEVELS]),
+    ("bias without the coarser level's term", "mlmc.py",
+     [("max(abs(mL), abs(mLm1) / 2.0 ** ALPHA)", "abs(mL)")],
+     [BIAS, DRIVER_LEVELS]),
+    ("bias with weak order 1", "mlmc.py",
+     [("ALPHA = 2.0 ", "ALPHA = 1.0 ")],
+     [BIAS, DRIVER_LEVELS]),
+    ("driver never adds a level", "mlmc.py",
+     [("        L += 1\n        run(L, pilot)", "        break")],
+     [BIAS, DRIVER_LEVELS]),
     # the learned proposal
     ("likelihood ratio q/p", "proposal.py",
      [("ratio = np.where(q_slot > 0, p_slot / np.where(q_slot > 0, q_slot, 1.0), 1.0)",
