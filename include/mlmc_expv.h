@@ -168,6 +168,29 @@ int mlmc_expv_level_sums(mlmc_plan_t *plan, const void *u, int32_t nrhs, int32_t
                          uint32_t walks, double *sum1, double *sum2, int64_t *jumps,
                          uint64_t *hash_sums, void *stream);
 
+/* mlmc_expv_level_sums without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Arguments, outputs and results are those of mlmc_expv_level_sums; the differences:
+ *   - the per-(row, chunk) partial sums of a launch live in a fixed 32 MiB device array of
+ *     the library (one per device, held until the process ends) instead of a plan-owned
+ *     buffer grown with hipMalloc; any walk count is accepted: the walks are split into
+ *     consecutive launches whose partials fit in the array (a launch with one chunk per row
+ *     writes the sums directly and uses none of it);
+ *   - the level's tables must exist already: the plan builds level l0 at creation, and any
+ *     earlier call at a level (run, level sums, trace) builds that level; otherwise
+ *     MLMC_ERR_INVALID_ARG and nothing is launched;
+ *   - counters and hash_sums are cleared by a kernel (no memset node), and no timing events
+ *     are recorded, so the call can be captured into a graph when jumps is NULL (asking for
+ *     jumps waits for the stream).
+ * The array is shared by every call on a device and keeps the last call's contents; calls
+ * that overlap on one device (on different streams, or on different plans) race on it and
+ * must be serialised by the caller, as must calls on one plan. */
+int mlmc_expv_level_sums_noalloc(mlmc_plan_t *plan, const void *u, int32_t nrhs,
+                                 int32_t u_dtype, uint64_t seed, int32_t instance,
+                                 int32_t level, uint32_t walk0, uint32_t walks, double *sum1,
+                                 double *sum2, int64_t *jumps, uint64_t *hash_sums,
+                                 void *stream);
+
 /* Individual walks at one level, for inspection: walk walks[q] from row rows[q]
  * (rows[q] is a row index of A, not an index into the requested rows).
  * All arrays DEVICE, count entries: final state, sign (+1/-1), jump count, a 64-bit

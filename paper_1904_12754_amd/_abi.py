@@ -28,6 +28,7 @@ MLMC_MAX_LEVELS = 40
 
 # every symbol the header declares
 EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_level_sums",
+           "mlmc_expv_level_sums_noalloc",
            "mlmc_expv_run_source", "mlmc_expv_level_sums_source", "mlmc_expv_functional",
            "mlmc_expv_functional_level_sums", "mlmc_expv_forward", "mlmc_expv_forward_level_sums",
            "mlmc_expv_trace", "mlmc_expv_destroy", "mlmc_expv_batch_create",
@@ -185,6 +186,8 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_level_sums.argtypes = [vp, vp, i32, i32, u64, i32, i32, u32, u32, vp, vp,
                                        ctypes.POINTER(i64), vp, vp]
     L.mlmc_expv_level_sums.restype = ctypes.c_int
+    L.mlmc_expv_level_sums_noalloc.argtypes = L.mlmc_expv_level_sums.argtypes
+    L.mlmc_expv_level_sums_noalloc.restype = ctypes.c_int
     L.mlmc_expv_run_source.argtypes = [vp, vp, vp, i32, ctypes.POINTER(RunOpts), vp,
                                         ctypes.POINTER(Stats), vp]
     L.mlmc_expv_run_source.restype = ctypes.c_int

@@ -115,30 +115,46 @@ class Plan:
 
     def level_sums(self, u: torch.Tensor, level: int, walk0: int, walks: int, seed: int = 0,
                    instance: int = 0, stream=None, hashes: bool = False,
-                   source: torch.Tensor | None = None):
+                   source: torch.Tensor | None = None, noalloc: bool = False, out=None,
+                   want_jumps: bool = True):
         """Algorithm 2's accumulators at one level (Algorithm 3's with a source vector):
         (sum Y, sum Y^2) per (row, rhs), jumps, and with hashes=True the per-row sum
-        (mod 2^64) of the path hashes."""
+        (mod 2^64) of the path hashes. noalloc=True calls the allocation-free entry point
+        (no source term); out = (s1, s2[, hash_sums]) supplies the output tensors;
+        want_jumps=False skips the jump count (no wait for the stream; jumps is None)."""
         u, R, dt = _u_args(u, self.n)
         F = self._source(source, u)
-        s1 = torch.empty((self.n_rows, R), dtype=torch.float64, device=u.device)
-        s2 = torch.empty_like(s1)
-        hs = torch.empty(self.n_rows, dtype=torch.int64, device=u.device) if hashes else None
+        if out is not None:
+            s1, s2 = out[0], out[1]
+            hs = out[2] if hashes else None
+        else:
+            s1 = torch.empty((self.n_rows, R), dtype=torch.float64, device=u.device)
+            s2 = torch.empty_like(s1)
+            hs = torch.empty(self.n_rows, dtype=torch.int64, device=u.device) if hashes else None
         jumps = ctypes.c_int64()
-        if F is None:
+        jp = ctypes.byref(jumps) if want_jumps else None
+        if noalloc:
+            if F is not None:
+                raise ValueError("the allocation-free level sums take no source term")
+            check(self._lib.mlmc_expv_level_sums_noalloc(self._handle, _dev_ptr(u), R, dt, seed,
+                                                         instance, level, walk0, walks,
+                                                         _dev_ptr(s1), _dev_ptr(s2), jp,
+                                                         _dev_ptr(hs) if hashes else None,
+                                                         _stream_ptr(stream)))
+        elif F is None:
             check(self._lib.mlmc_expv_level_sums(self._handle, _dev_ptr(u), R, dt, seed, instance,
                                                  level, walk0, walks, _dev_ptr(s1), _dev_ptr(s2),
-                                                 ctypes.byref(jumps),
-                                                 _dev_ptr(hs) if hashes else None,
+                                                 jp, _dev_ptr(hs) if hashes else None,
                                                  _stream_ptr(stream)))
         else:
             check(self._lib.mlmc_expv_level_sums_source(
                 self._handle, _dev_ptr(u), _dev_ptr(F), dt, seed, instance, level, walk0, walks,
-                _dev_ptr(s1), _dev_ptr(s2), ctypes.byref(jumps),
+                _dev_ptr(s1), _dev_ptr(s2), jp,
                 _dev_ptr(hs) if hashes else None, _stream_ptr(stream)))
+        nj = int(jumps.value) if want_jumps else None
         if hashes:
-            return s1, s2, int(jumps.value), hs
-        return s1, s2, int(jumps.value)
+            return s1, s2, nj, hs
+        return s1, s2, nj
 
     def trace(self, level: int, rows, walks, seed: int = 0, instance: int = 0, stream=None):
         dev = torch.device("cuda")
@@ -349,6 +365,12 @@ class Plan:
         del P
         return out, st.to_dict()
 
+    def current_info(self) -> dict:
+        """mlmc_expv_plan_info now (device_bytes grows as levels and buffers are added)."""
+        info = _abi.PlanInfo()
+        check(self._lib.mlmc_expv_plan_info(self._handle, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in _abi.PlanInfo._fields_}
+
     def close(self):
         if getattr(self, "_handle", None) and self._handle.value:
             self._lib.mlmc_expv_destroy(self._handle)
@@ -440,3 +462,4 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+

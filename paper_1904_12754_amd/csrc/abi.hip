@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -66,28 +67,28 @@ int dev_alloc(mlmc_plan *p, T **ptr, size_t count)
 void free_plan(mlmc_plan *p)
 {
     if (!p) return;
-    hipFree(p->slots);
-    hipFree(p->rows_base);
-    for (auto &r : p->level_rec) hipFree(r);
-    for (auto *t : p->is_slots) hipFree(t);
-    hipFree(p->p_slot);
-    hipFree(p->prop_P);
-    hipFree(p->prop_frag);
-    hipFree(p->prop_xhat);
-    hipFree(p->prop_xmax);
-    for (auto &b : p->train_pool) hipFree(b.first);
-    for (auto &b : p->grad_pool) hipFree(b.first);
-    hipFree(p->req_rows);
-    hipFree(p->partial);
-    hipFree(p->counters);
-    hipFree(p->counter_sums);
-    hipFree(p->bad);
-    hipFree(p->moments);
-    hipFree(p->moment_scratch);
-    hipFree(p->acc);
-    if (p->ev0) hipEventDestroy(p->ev0);
-    if (p->ev1) hipEventDestroy(p->ev1);
-    for (hipEvent_t e : p->tev) hipEventDestroy(e);
+    (void)hipFree(p->slots);
+    (void)hipFree(p->rows_base);
+    for (auto &r : p->level_rec) (void)hipFree(r);
+    for (auto *t : p->is_slots) (void)hipFree(t);
+    (void)hipFree(p->p_slot);
+    (void)hipFree(p->prop_P);
+    (void)hipFree(p->prop_frag);
+    (void)hipFree(p->prop_xhat);
+    (void)hipFree(p->prop_xmax);
+    for (auto &b : p->train_pool) (void)hipFree(b.first);
+    for (auto &b : p->grad_pool) (void)hipFree(b.first);
+    (void)hipFree(p->req_rows);
+    (void)hipFree(p->partial);
+    (void)hipFree(p->counters);
+    (void)hipFree(p->counter_sums);
+    (void)hipFree(p->bad);
+    (void)hipFree(p->moments);
+    (void)hipFree(p->moment_scratch);
+    (void)hipFree(p->acc);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    for (hipEvent_t e : p->tev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -184,7 +185,7 @@ namespace {
 int ensure_partial(mlmc_plan *p, size_t bytes)
 {
     if (bytes <= p->partial_bytes) return MLMC_OK;
-    hipFree(p->partial);
+    (void)hipFree(p->partial);
     p->bytes -= static_cast<int64_t>(p->partial_bytes);
     p->partial = nullptr;
     p->partial_bytes = 0;
@@ -194,24 +195,44 @@ int ensure_partial(mlmc_plan *p, size_t bytes)
     return MLMC_OK;
 }
 
+// Where level_sums keeps the per-(row, chunk) partial sums of a sub-launch: the plan's own
+// buffer (grown with hipMalloc as needed), or a fixed caller-provided buffer, in which case
+// nothing is allocated, the level's tables must exist already and no timing events are
+// recorded.
+struct PartialBuf {
+    double *fixed = nullptr;
+    size_t fixed_bytes = 0;
+};
+
 // Walks [walk0, walk0 + M) of every requested row at `level`: per-(row, rhs) sums of Y and
 // Y^2 into out1/out2 (overwritten, or added to when accumulate). Jump and non-finite
 // counts are added to the counter set `counters`.
 int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void *u, int u_f64,
                int32_t nrhs, uint32_t walk0, uint64_t M, double *out1, double *out2, int accumulate,
-               unsigned long long *counters, unsigned long long *hash_sums, hipStream_t s)
+               unsigned long long *counters, unsigned long long *hash_sums, hipStream_t s,
+               const PartialBuf &buf = PartialBuf{})
 {
+    const bool fixed = buf.fixed != nullptr;
     if (M == 0 || p->n_rows == 0) {
         if (!accumulate && p->n_rows) {
-            MLMC_HIP_TRY(hipMemsetAsync(out1, 0, sizeof(double) * p->n_rows * nrhs, s));
-            MLMC_HIP_TRY(hipMemsetAsync(out2, 0, sizeof(double) * p->n_rows * nrhs, s));
+            const int64_t cnt = p->n_rows * nrhs;   // doubles are zero as u64 zero words
+            MLMC_HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long *>(out1), cnt, s));
+            MLMC_HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long *>(out2), cnt, s));
         }
         return MLMC_OK;
     }
     if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
         return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
-    int rc = upload_level(p, level, s);
-    if (rc) return rc;
+    int rc;
+    if (fixed) {
+        if (!p->level_rec[level])
+            return fail(MLMC_ERR_INVALID_ARG, "the tables of level " + std::to_string(level) +
+                        " are not built yet (a plan builds l0 at creation; any earlier call at a "
+                        "level builds it)");
+    } else if ((rc = upload_level(p, level, s))) {
+        return rc;
+    }
+    const bool timing = p->timing && !fixed;
     const LevelArgs L = level_args(p, level, seed, instance);
     const Prec prec = p->precision == MLMC_PRECISION_FP64 ? Prec::FP64 : Prec::FP32;
     // walks per item: enough items to fill the chip, at most 64 walks per lane
@@ -220,19 +241,27 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
     chunk = std::min<uint64_t>(std::max<uint64_t>((chunk + 63) / 64 * 64, 64), 64 * 64);
     if (M < 64) chunk = M;   // one item per row; the kernel packs several rows into a wave
     // bound the scratch: sub-launches over walk ranges
+    // (one chunk per launch writes the row sums directly and needs no partials)
     const uint64_t bytes_per_item = static_cast<uint64_t>(nrhs) * 2 * sizeof(double);
-    uint64_t max_items = std::max<uint64_t>(1, kPartialCapBytes / bytes_per_item);
+    const uint64_t cap = fixed ? buf.fixed_bytes : kPartialCapBytes;
+    uint64_t max_items = std::max<uint64_t>(1, cap / bytes_per_item);
     uint64_t chunks_per_launch = std::max<uint64_t>(1, max_items / static_cast<uint64_t>(p->n_rows));
     const uint64_t total_chunks = (M + chunk - 1) / chunk;
     chunks_per_launch = std::min(chunks_per_launch, total_chunks);
-    rc = ensure_partial(p, chunks_per_launch * p->n_rows * bytes_per_item);
-    if (rc) return rc;
+    double *partial = buf.fixed;
+    if (!fixed) {
+        rc = ensure_partial(p, chunks_per_launch * p->n_rows * bytes_per_item);
+        if (rc) return rc;
+        partial = p->partial;
+    } else if (chunks_per_launch > 1 && chunks_per_launch * p->n_rows * bytes_per_item > buf.fixed_bytes) {
+        return fail(MLMC_ERR_INVALID_ARG, "partial sums exceed the fixed scratch");   // not reached
+    }
     bool first = true;
     for (uint64_t c0 = 0; c0 < total_chunks; c0 += chunks_per_launch) {
         const uint64_t nch = std::min(chunks_per_launch, total_chunks - c0);
         const uint64_t wb = c0 * chunk;
         const uint64_t Msub = std::min<uint64_t>(M - wb, nch * chunk);
-        if (p->timing) {
+        if (timing) {
             while (p->tev.size() < p->tev_used + 2) {
                 hipEvent_t e;
                 MLMC_HIP_TRY(hipEventCreate(&e));
@@ -242,17 +271,17 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
         }
         // one chunk per row: the kernel writes (or adds) the row sums itself
         const bool direct = nch == 1;
-        const SumsOut lo{p->partial, out1, out2, direct ? ((first && !accumulate) ? 1 : 2) : 0};
+        const SumsOut lo{partial, out1, out2, direct ? ((first && !accumulate) ? 1 : 2) : 0};
         MLMC_HIP_TRY(launch_level_walks(L, prec, u, u_f64, nrhs, p->req_rows, p->n_rows,
                                         walk0 + static_cast<uint32_t>(wb), static_cast<uint32_t>(Msub),
                                         static_cast<uint32_t>(chunk), static_cast<uint32_t>(nch),
                                         lo, counters, hash_sums, s));
-        if (p->timing) {
+        if (timing) {
             MLMC_HIP_TRY(hipEventRecord(p->tev[p->tev_used + 1], s));
             p->tev_used += 2;
         }
         if (!direct)
-            MLMC_HIP_TRY(launch_finalize(p->partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
+            MLMC_HIP_TRY(launch_finalize(partial, p->n_rows, static_cast<uint32_t>(nch), nrhs, out1,
                                          out2, (first && !accumulate) ? 0 : 1, s));
         first = false;
     }
@@ -272,7 +301,7 @@ int ensure_acc(mlmc_plan *p, int levels, int32_t nrhs)
 {
     const size_t need = static_cast<size_t>(levels) * 2 * p->n_rows * nrhs;
     if (need <= p->acc_doubles) return MLMC_OK;
-    hipFree(p->acc);
+    (void)hipFree(p->acc);
     p->bytes -= static_cast<int64_t>(p->acc_doubles * sizeof(double));
     p->acc = nullptr;
     p->acc_doubles = 0;
@@ -493,6 +522,78 @@ int mlmc_expv_level_sums(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_
     return MLMC_OK;
 }
 
+}  // extern "C"
+
+// ---- allocation-free level sums ---------------------------------------------------------
+// The per-(row, chunk) partial sums of mlmc_expv_level_sums_noalloc live in this fixed device
+// array (one copy per device, loaded with the code object and held until the process ends)
+// instead of the plan's hipMalloc-grown buffer. Host code never passes the array's name to a
+// kernel: its device address is looked up once per device with hipGetSymbolAddress.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's device address on the current device (looked up on first use).
+int scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    MLMC_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MLMC_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MLMC_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MLMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlmc_expv_level_sums_noalloc(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype,
+                                 uint64_t seed, int32_t instance, int32_t level, uint32_t walk0,
+                                 uint32_t walks, double *sum1, double *sum2, int64_t *jumps,
+                                 uint64_t *hash_sums, void *stream)
+{
+    if (!p) return fail(MLMC_ERR_INVALID_ARG, "null plan");
+    if (p->n_rows > 0 && (!sum1 || !sum2)) return fail(MLMC_ERR_INVALID_ARG, "null output");
+    int rc = check_u(u, nrhs, u_dtype);
+    if (rc) return rc;
+    if (instance < 0 || instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
+    if (level < p->l0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level must be in [l0, 28]");
+    double *scr = nullptr;
+    if ((rc = scratch_on_current_device(&scr))) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    MLMC_HIP_TRY(launch_zero_u64(p->counters, static_cast<int64_t>(kCounterSetU64), s));
+    if (hash_sums && p->n_rows > 0)
+        MLMC_HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long *>(hash_sums), p->n_rows, s));
+    PartialBuf buf;
+    buf.fixed = scr;
+    buf.fixed_bytes = kNoAllocScratchBytes;
+    rc = level_sums(p, level, seed, instance, u, u_dtype == MLMC_DTYPE_F64, nrhs, walk0, walks, sum1,
+                    sum2, 0, p->counters, reinterpret_cast<unsigned long long *>(hash_sums), s, buf);
+    if (rc) return rc;
+    if (jumps) {
+        unsigned long long c[2];
+        MLMC_HIP_TRY(launch_counter_sum(p->counters, 1, p->counter_sums, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(c, p->counter_sums, sizeof c, hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+        *jumps = static_cast<int64_t>(c[0]);
+        if (c[1]) return fail(MLMC_ERR_NONFINITE, std::to_string(c[1]) + " non-finite samples");
+    }
+    return MLMC_OK;
+}
+
 int mlmc_expv_trace(mlmc_plan_t *p, uint64_t seed, int32_t instance, int32_t level, int64_t count,
                     const int64_t *rows, const uint32_t *walks, int64_t *final_state, int32_t *sign,
                     int64_t *jumps, uint64_t *hash, double *log_fine, double *log_coarse, void *stream)
@@ -547,6 +648,10 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
     p->timing = stats != nullptr;
     p->tev_used = 0;
+    struct TimingOff {   // the events time this run's launches only
+        mlmc_plan *p;
+        ~TimingOff() { p->timing = false; }
+    } timing_off{p};
     MLMC_HIP_TRY(hipMemsetAsync(p->counters, 0, kCounterSetU64 * sizeof(unsigned long long) * max_levels, s));
     MLMC_HIP_TRY(hipEventRecord(p->ev0, s));
     // add `extra` walks at level index qq

@@ -87,6 +87,9 @@ struct CombineArgs {
 };
 hipError_t launch_combine(const CombineArgs &a, int64_t count, double *x, hipStream_t s);
 
+// dst[0 .. count) = 0 by a kernel (no memset node, so the call may sit in a captured graph).
+hipError_t launch_zero_u64(unsigned long long *dst, int64_t count, hipStream_t s);
+
 hipError_t launch_trace(const LevelArgs &L, Prec prec, int64_t count, const int64_t *rows,
                         const uint32_t *walks, int64_t *final_state, int32_t *sign,
                         int64_t *jumps, uint64_t *hash, double *log_fine, double *log_coarse,

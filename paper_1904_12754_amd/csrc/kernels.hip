@@ -305,6 +305,12 @@ uint32_t blocks_for(int64_t n, int threads)
     return static_cast<uint32_t>((n + threads - 1) / threads);
 }
 
+__global__ void zero_u64_kernel(unsigned long long *dst, int64_t count)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = 0ull;
+}
+
 __global__ void counter_sum_kernel(const unsigned long long *sets, int slots, unsigned long long *out)
 {
     // one block per set, thread t adds the slots t, t + 256, ... of both counters
@@ -338,6 +344,13 @@ hipError_t launch_counter_sum(const unsigned long long *sets, int nsets, unsigne
 {
     if (nsets <= 0) return hipSuccess;
     hipLaunchKernelGGL(counter_sum_kernel, dim3(nsets), dim3(256), 0, s, sets, slots, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *dst, int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, dst, count);
     return hipGetLastError();
 }
 
