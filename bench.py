@@ -554,11 +554,12 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1904_12754_amd import api, exact, inputs
+    import bench_reference
+    from paper_1904_12754_amd import api, inputs
 
     dev = torch.device("cuda:0")
     A, t, v = inputs.workload_laplace2d(args.grid)
-    x_exact = exact.expv_laplace2d(v, t)
+    x_exact = bench_reference.expv_laplace2d(v, t)
     u = torch.as_tensor(v.astype(np.float32), device=dev)
     plan = api.Plan(A, t, precision="fp32")
     stream = torch.cuda.current_stream()

@@ -11,12 +11,18 @@ TEST INFRASTRUCTURE (see oracle/__init__.py).
   laplace1d_exact    exp(tA) v for the 1D Dirichlet Laplacian by its sine eigenbasis.
   laplace2d_exact    the same for the 2D 5-point Laplacian (tensor product).
   decomposition      D and T of section 2.1 built densely from A.
+  expm_action_sparse x = exp(beta A) u for a sparse A too large to exponentiate densely: the
+                     truncated Taylor method with scaling of Al-Mohy & Higham (the reference
+                     the paper cites for the action of the matrix exponential), by the library
+                     routine scipy.sparse.linalg.expm_multiply, in FP64.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.fft
 import scipy.linalg
+import scipy.sparse
+import scipy.sparse.linalg
 
 
 def decomposition(a: np.ndarray):
@@ -125,3 +131,10 @@ def laplace2d_exact(v: np.ndarray, t: float) -> np.ndarray:
     C = _dst_ortho(_dst_ortho(V, axis=0), axis=1)
     C = C * np.exp(t * (lam[:, None] + lam[None, :]))
     return _dst_ortho(_dst_ortho(C, axis=1), axis=0).reshape(-1)
+
+
+def expm_action_sparse(n: int, row_ptr, col_idx, values, u, beta: float) -> np.ndarray:
+    """exp(beta A) u for A in CSR form (u: n or n x R), FP64."""
+    a = scipy.sparse.csr_matrix((np.asarray(values, np.float64), np.asarray(col_idx),
+                                 np.asarray(row_ptr)), shape=(n, n))
+    return scipy.sparse.linalg.expm_multiply(beta * a, np.asarray(u, np.float64))

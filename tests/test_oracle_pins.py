@@ -294,6 +294,44 @@ def test_strang_bias_is_second_order_and_dst_reference_is_exact():
                          reference.expm_action(A2.to_dense(), v2, t2))) < 1e-13
 
 
+def _sparse_cases():
+    """Small sparse matrices of the workloads' kinds, with a scale beta and right-hand sides."""
+    rng = np.random.default_rng(17)
+    cases = []
+    for norm in (0.5, 4.0, 20.0):                    # signed nonsymmetric, ||beta A||_1 = norm
+        a = rng.normal(size=(60, 60)) * (rng.random((60, 60)) < 0.1)
+        A = inputs.from_dense(a)
+        cases.append((A, norm / A.norm1(), rng.normal(size=(60, 3))))
+    A = inputs.convection_diffusion_3d(8, seed=3)    # nonsymmetric PDE operator
+    cases.append((A, 4.0 / A.norm1(), rng.normal(size=A.n)))
+    A = inputs.barabasi_albert(300, 5, seed=2)       # network adjacency, beta = 1/d_max
+    cases.append((A, 1.0 / np.diff(A.row_ptr).max(), inputs.rhs_ones_rademacher(A.n, 4, 1)))
+    return cases
+
+
+def test_sparse_expm_action_matches_the_dense_exponential():
+    """The sparse reference of the larger workloads (Al-Mohy & Higham's truncated Taylor
+    method with scaling, by library routine) against the dense scaling-and-squaring
+    exponential, on small matrices of each kind (a transposed operand, a wrong scale or a
+    dropped column would fail it)."""
+    for A, beta, U in _sparse_cases():
+        x = reference.expm_action_sparse(A.n, A.row_ptr, A.col_idx, A.values, U, beta)
+        ref = reference.expm_action(A.to_dense(), U, beta)
+        assert x.shape == ref.shape
+        assert np.max(np.abs(x - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_sparse_expm_action_matches_the_dst_closed_form():
+    """On a 2D Laplacian larger than the dense check can afford: the sine-eigenbasis form."""
+    A = inputs.laplacian_2d(40)
+    v = np.random.default_rng(4).normal(size=A.n)
+    for norm in (4.0, 40.0):
+        t = norm / A.norm1()
+        x = reference.expm_action_sparse(A.n, A.row_ptr, A.col_idx, A.values, v, t)
+        ref = reference.laplace2d_exact(v, t)
+        assert np.max(np.abs(x - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
 def test_eigenvector_closed_form():
     """1D Laplacian eigenvector v_k = sin(k pi i h): exp(tA) v_k = e^{t lambda_k} v_k;
     the MLMC estimate of x^L tends to it with the splitting bias."""
