@@ -1,10 +1,17 @@
-"""Benchmark: walk steps/s of the MLMC solve of x = exp(tA) v on one MI355X.
+"""Benchmark: walk steps/s and time-to-RMSE of the MLMC solve of x = exp(tA) v on one MI355X.
 
-Workload (one "step" of this benchmark = one complete MLMC solve, Algorithm 1 to a
+Headline workload (one "step" of this benchmark = one complete MLMC solve, Algorithm 1 to a
 target RMSE, through the C-ABI): the 2D 5-point Dirichlet Laplacian on a 256 x 256 grid
 (n = 65536), t = h^2/2 so that ||tA||_1 = 4, v ~ N(0, 1) (seeded), full vector, FP32
 path weights with compensated FP32 row sums and an FP64 level combine, levels from
-l0 = 2 (six levels at the default target). Inputs are resident in HBM before timing.
+l0 = 2. Inputs are resident in HBM before timing.
+
+The same run also measures the other four workloads (outside the timed region): the FP64
+1D Laplacian against the dense exponential, the Barabasi-Albert graph with 64 right-hand
+sides, the batch of 512 uneven instances, and the learned proposal against the plain jump
+law on the 3D convection-diffusion operator; every result states its true error against
+an FP64 reference (bench_reference.py). Machine probes (random 16-byte gathers at several
+table sizes, integer VALU issue) calibrate the rooflines.
 
 Prints one JSON line with the metric, a roofline entry for the walk kernel and the
 oracle's CPU throughput on a bounded sample of the same workload.
@@ -22,25 +29,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work of the walk kernel, in lane-instructions of a minimal gfx950
-# sequence: a step consumes a quarter of a Philox4x32-10 block (10 rounds of two
-# v_mad_u64_u32 and two v_bitop3_b32 three-input xors: 40 per block, 10 per step) and one
-# compare; a jump consumes one block (40), the alias selection and gather addressing (~8),
-# the holding-time bracket (~8) and the run update of the weights (~9); a walk end scales
-# and exponentiates its exponent and applies the sign (3), gathers u and multiplies (2),
-# adds to the two compensated sums (9) and to the counters (3), plus an expm1 (~23) above
-# the base level.
+# Minimal VALU work of the walks, in lane-instructions of a gfx950 sequence: a step consumes
+# a quarter of a Philox4x32-10 block (10 rounds of two v_mad_u64_u32 and two v_bitop3_b32
+# three-input xors: 40 per block, 10 per step) and one compare; a jump consumes one block
+# (40), the alias selection and gather addressing (~8), the holding-time bracket (~8) and the
+# run update of the weights (~9); a walk end scales and exponentiates its exponent and
+# applies the sign (3), gathers u and multiplies (2), adds to the two compensated sums (9)
+# and to the counters (3), plus an expm1 (~23) above the base level; with several
+# right-hand sides a walk that moved adds one product and two compensated sums per
+# right-hand side (10). The random draws are part of the method's cost (the per-step term
+# of the cost model of section 4), so the generator counts as work.
 OPS_PER_STEP = 11
 OPS_PER_JUMP = 65
 OPS_PER_WALK_BASE = 17
 OPS_PER_WALK_ABOVE = 40
-# MI355X vector ALU: 256 CUs x 128 32-bit lanes per clock x 2.4 GHz (the FP32 vector rate
-# of 157.3 TFLOP/s counts two flops per FMA lane)
-VALU_PEAK_LANE_OPS = 256 * 128 * 2.4e9
+OPS_PER_RHS_SAMPLE = 10
+# MI355X integer VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (a wave64
+# instruction issues over four cycles; the FP32 vector figure of 157.3 TFLOP/s counts two
+# flops per FMA and dual-issue, which 32-bit integer instructions do not have)
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # MI355X HBM3E peak bandwidth
 HBM_PEAK_BPS = 8.0e12
-# bytes the jumps must gather: one 16-byte alias slot and one 32-byte row record
-BYTES_PER_JUMP = 48
+# Algorithmic bytes: a jump gathers its 16-byte alias slot and the 24-byte record of the row
+# it lands on (the layout here pads that record to 32 bytes); a walk end reads R values of
+# u (4 bytes each; a walk that never jumped ends at its start row, whose u row is read once
+# per row and level); each (row, level, right-hand side) writes two FP64 sums.
+BYTES_PER_JUMP = 40
 # HBM traffic of the walk kernel from the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
 # plain copy), recorded with the hash of the kernel source it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_traffic.json")
@@ -89,16 +103,96 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-loose", action="store_true",
                     help="skip the solves to RMSE 1e-2 after the timed region")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the 1D Laplacian, Barabasi-Albert and batch workloads")
     ap.add_argument("--mode", choices=["bench", "kernel", "copy", "batch", "tc", "learned",
-                                       "classical", "config1"],
+                                       "classical", "config1", "probe"],
                     default="bench",
                     help="kernel: only the dominant walk-kernel launch (level l0 + --level, "
                          "--walks per row), for counter runs; copy: a plain device copy of "
-                         "--bytes, the calibration for the traffic counters")
+                         "--bytes, the calibration for the traffic counters; probe: the "
+                         "machine probes alone")
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--walks", type=int, default=65536)
     ap.add_argument("--bytes", type=int, default=1 << 30)
     return ap.parse_args()
+
+
+# ---- machine probes and rooflines -------------------------------------------------------
+PROBE_LOG2 = (18, 19, 21, 23, 25, 28)      # 4 MB .. 4 GB tables of 16-byte records
+
+
+def machine_probes():
+    """Integer VALU issue rate and uniformly random 16-byte gather rates by table size."""
+    import torch
+
+    from paper_1904_12754_amd import api
+
+    n, s = api.probe_valu(32, 8192)
+    out = {"valu_lane_ops_per_s": n / s, "gather_per_s": {}}
+    table = torch.zeros((16 << max(PROBE_LOG2)) // 4, dtype=torch.int32, device="cuda")
+    for lg in PROBE_LOG2:
+        g, s = api.probe_gather(table, lg, 32, 64 if lg <= 21 else 32)
+        out["gather_per_s"][str(16 << lg)] = g / s
+    del table
+    torch.cuda.empty_cache()
+    return out
+
+
+def probe_rate_for(probes, ws_bytes):
+    """The probe's gather rate at the smallest measured table holding ws_bytes."""
+    sizes = sorted(int(k) for k in probes["gather_per_s"])
+    size = next((z for z in sizes if z >= ws_bytes), sizes[-1])
+    return size, probes["gather_per_s"][str(size)]
+
+
+def walk_roofline(kernel, seconds, launches, steps, jumps, walks_base, walks_above, rows_levels,
+                  nrhs, ws_bytes, probes, traffic=None):
+    """Rooflines of one walk kernel over `seconds` of its launches (summed event-pair
+    durations): VALU issue (the binding one for these workloads), and the algorithmic bytes
+    and gathers against the HBM peak and the probe's gather rate at the working-set size."""
+    walks = walks_base + walks_above
+    moved = min(walks, jumps) if nrhs > 1 else walks
+    ops = (OPS_PER_STEP * steps + OPS_PER_JUMP * jumps + OPS_PER_WALK_BASE * walks_base +
+           OPS_PER_WALK_ABOVE * walks_above + (OPS_PER_RHS_SAMPLE * nrhs * moved if nrhs > 1 else 0))
+    nbytes = BYTES_PER_JUMP * jumps + 4 * nrhs * moved + (4 + 16) * nrhs * rows_levels
+    gathers = 2 * jumps + moved
+    size, prate = probe_rate_for(probes, ws_bytes)
+    achieved = ops / seconds
+    return {
+        "bound": "alu", "kernel": kernel,
+        "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+        "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": traffic,
+        "peak_measured_probe": probes["valu_lane_ops_per_s"] / 1e12,
+        "frac_of_measured_peak": achieved / probes["valu_lane_ops_per_s"],
+        "launch_avg_ms": seconds / max(launches, 1) * 1e3, "launches": launches,
+        "per_unit": {"ops_per_step": OPS_PER_STEP, "ops_per_jump": OPS_PER_JUMP,
+                     "ops_per_walk_base": OPS_PER_WALK_BASE, "ops_per_walk_above": OPS_PER_WALK_ABOVE,
+                     "ops_per_rhs_sample": OPS_PER_RHS_SAMPLE, "bytes_per_jump": BYTES_PER_JUMP,
+                     "bytes_per_walk_end": 4 * nrhs},
+        "memory": {
+            "algorithmic_GBps": nbytes / seconds / 1e9,
+            "frac_of_hbm_peak": nbytes / seconds / HBM_PEAK_BPS,
+            "working_set_MB": ws_bytes / 2 ** 20,
+            "gathers_per_s": gathers / seconds,
+            "probe_table_MB": size / 2 ** 20,
+            "probe_gathers_per_s": prate,
+            "frac_of_probe_gather_rate": gathers / seconds / prate,
+        },
+    }
+
+
+def kernel_sums(stats_list):
+    """Summed walk-kernel time, launches, steps, jumps, base-level and other walks."""
+    out = {"ms": 0.0, "launches": 0, "steps": 0, "jumps": 0, "walks_base": 0, "walks_above": 0}
+    for st, n_rows in stats_list:
+        out["ms"] += st["walk_kernel_ms"]
+        out["launches"] += st["walk_launches"]
+        out["steps"] += st["steps"]
+        out["jumps"] += st["total_jumps"]
+        out["walks_base"] += st["walks"][0] * n_rows
+        out["walks_above"] += sum(st["walks"][1:]) * n_rows
+    return out
 
 
 def kernel_only(args):
@@ -125,10 +219,10 @@ def kernel_only(args):
     plan.close()
 
 
-def _batch_vs_runs(insts, steps):
+def _batch_vs_runs(insts, steps, keep_x=False):
     """Times one graph replay of the batch of `insts` (four levels from each instance's l0,
     64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32 weights) and the same work as
-    one fixed-schedule run per instance."""
+    one fixed-schedule run per instance. keep_x: also return the batch's estimates (host)."""
     import numpy as np
     import torch
 
@@ -154,6 +248,7 @@ def _batch_vs_runs(insts, steps):
     st = batch.stats()
     total_steps = sum(x["steps"] for x in st)
     jumps = sum(x["total_jumps"] for x in st)
+    xs = [x.cpu().numpy()[:, 0] for x in batch.xs] if keep_x else None
     # the same work, one fixed-schedule run per instance
     for b, p in enumerate(plans[:8]):
         p.run(us[b], walks=walks[b], seed=99, instance=b, want_stats=False)
@@ -163,47 +258,98 @@ def _batch_vs_runs(insts, steps):
         p.run(us[b], walks=walks[b], seed=100, instance=b, want_stats=False)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t0
+    rows = int(sum(A.n for A, _, _ in insts))
     out = {"steps_per_s": total_steps / el, "ms_per_launch": el * 1e3,
            "steps_per_launch": total_steps, "jumps_per_launch": jumps,
+           "graph_ms": st[0]["kernel_ms"],
            "one_run_per_instance_ms": el_seq * 1e3, "speedup_vs_one_run_per_instance": el_seq / el,
-           "rows_total": int(sum(A.n for A, _, _ in insts)),
+           "rows_total": rows,
            "walks_per_row_per_level": walks[0].tolist(), "batch": batch.info,
-           "host_s": {"plans": t_plan, "create_with_autotune": t_create}}
+           "host_s": {"plans": t_plan, "create_with_autotune": t_create},
+           "est_rmse": [math.sqrt(x["est_variance"]) for x in st],
+           "_kernel": {"seconds": st[0]["kernel_ms"] * 1e-3, "launches": batch.info["phases"],
+                       "steps": total_steps, "jumps": jumps,
+                       "walks_base": int(sum(walks[b][0] * A.n for b, (A, _, _) in enumerate(insts))),
+                       "walks_above": int(sum(walks[b][1:].sum() * A.n for b, (A, _, _) in enumerate(insts))),
+                       "rows_levels": 4 * rows,
+                       "ws_bytes": int(sum(A.nnz * 16 + A.n * (32 * 4 + 4) for A, _, _ in insts))}}
     batch.close()
     for p in plans:
         p.close()
-    return out
+    return out, xs
 
 
-def batch_bench(args):
-    """The uneven batch: 512 instances (1D/2D Laplacians and Erdos-Renyi graphs, n
-    log-uniform in [1e3, 1e5], ||tA||_1 log-uniform in [0.5, 8], v ~ N(0, 1)), four levels
-    per instance, in one graph replay; and a batch of 2048 small instances (n log-uniform in
-    [100, 2000]) where one run per instance is dominated by launch and host costs."""
+def batch_part(args, probes=None, small=False):
+    """The uneven batch: `args.instances` instances (1D/2D Laplacians and Erdos-Renyi graphs,
+    n log-uniform in [1e3, 1e5], ||tA||_1 log-uniform in [0.5, 8], v ~ N(0, 1)), four levels
+    per instance, in one graph replay; with small=True also a batch of 2048 small instances
+    (n log-uniform in [100, 2000]) where one run per instance is dominated by launch and host
+    costs. Returns the result and a closure that computes the true errors (CPU)."""
     from paper_1904_12754_amd import inputs
 
     t0 = time.perf_counter()
     insts = inputs.workload_uneven_batch(args.instances)
     t_gen = time.perf_counter() - t0
-    big = _batch_vs_runs(insts, args.steps)
-    del insts
-    small = _batch_vs_runs(inputs.workload_uneven_batch(2048, nmin=100, nmax=2000), args.steps)
+    big, xs = _batch_vs_runs(insts, args.steps, keep_x=True)
     big["host_s"]["generate"] = t_gen
-    print(json.dumps({
-        "metric": "walk steps/s", "value": big.pop("steps_per_s"), "unit": "steps/s", **big,
-        "config": {"workload": f"{args.instances} uneven instances (1D/2D Laplacian, ER mean degree 8, "
-                               "n in [1e3, 1e5]), 4 levels, FP32 weights, one graph replay"},
-        "small_instances": {"workload": "2048 uneven instances, n in [100, 2000], same schedule", **small},
-    }), flush=True)
+    k = big.pop("_kernel")
+    if probes is not None:
+        big["roofline"] = walk_roofline("batch_walks<float,float>", k["seconds"], k["launches"],
+                                        k["steps"], k["jumps"], k["walks_base"], k["walks_above"],
+                                        k["rows_levels"], 1, k["ws_bytes"], probes)
+        big["roofline"]["note"] = ("time = the whole graph (walk phases plus the per-row sums "
+                                   "and the combine), so the rates are lower bounds")
+    out = {"metric": "walk steps/s", "value": big.pop("steps_per_s"), "unit": "steps/s", **big,
+           "config": {"workload": f"{args.instances} uneven instances (1D/2D Laplacian, ER mean "
+                                  "degree 8, n in [1e3, 1e5]), 4 levels, FP32 weights, one graph "
+                                  "replay"}}
+    if small:
+        s, _ = _batch_vs_runs(inputs.workload_uneven_batch(2048, nmin=100, nmax=2000), args.steps)
+        s.pop("_kernel")
+        out["small_instances"] = {"workload": "2048 uneven instances, n in [100, 2000], same "
+                                              "schedule", **s}
+    est = out.pop("est_rmse")
 
-def tc_bench(args):
+    def truth():
+        import numpy as np
+
+        refs = bench_reference_many(insts)
+        errs = np.array([float(np.sqrt(np.mean((x - r) ** 2))) for x, r in zip(xs, refs)])
+        ratio = errs / np.maximum(np.array(est), 1e-300)
+        return {"true_rmse_median": float(np.median(errs)), "true_rmse_max": float(errs.max()),
+                "true_over_est_rmse_median": float(np.median(ratio)),
+                "true_over_est_rmse_p95": float(np.quantile(ratio, 0.95)),
+                "instances_checked": len(errs),
+                "reference": "exp(tA)v per instance in FP64 (truncated Taylor with scaling, "
+                             "Al-Mohy & Higham)"}
+    return out, truth
+
+
+def bench_reference_many(insts):
+    """FP64 references of many small instances, in threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import bench_reference
+
+    with ThreadPoolExecutor(16) as ex:
+        return list(ex.map(lambda it: bench_reference.expv_sparse(it[0], it[2], it[1]), insts))
+
+
+def batch_bench(args):
+    out, truth = batch_part(args, machine_probes(), small=True)
+    out["true_error"] = truth()
+    print(json.dumps(out), flush=True)
+
+
+def tc_part(args, probes=None):
     """Total communicability with many right-hand sides: exp(beta A) [1, r_1..r_63] on a
     Barabasi-Albert graph (n = 1e6, m = 5, symmetric 0/1 adjacency stored as FP32),
     beta = 1/d_max, levels l0..l0+4 with 128 walks per row per level, FP32 weights, 64
     right-hand sides carried by every path, in one persistent launch (a batch of this one
     instance replayed from a graph); also timed as five per-level launches of one run, the
     forward scalar estimate of the total communicability, and the forward full vector
-    exp(beta A) 1 against the backward run's first column."""
+    exp(beta A) 1 against the backward run's first column. Returns the result and a closure
+    that computes the true errors (CPU)."""
     import numpy as np
     import torch
 
@@ -221,12 +367,16 @@ def tc_bench(args):
     plan.run(u, walks=walks, seed=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    sts = []
     for k in range(args.steps):
         x, st = plan.run(u, walks=walks, seed=10 + k)
+        sts.append(st)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
-    tc = float(x[:, 0].sum().item())
+    x_host = x.cpu().numpy()
+    tc = float(x_host[:, 0].sum())
     sd_back = math.sqrt(st["est_variance"] * A.n)
+    ks = kernel_sums([(s_, A.n) for s_ in sts])
     # the same quantity by the forward scalar representation: walks from uniformly drawn
     # start rows, Algorithm 1 to the backward run's standard deviation
     ones = torch.ones(A.n, dtype=torch.float32, device="cuda")
@@ -246,11 +396,12 @@ def tc_bench(args):
     xf, vf, st_fw = plan.forward(ones, walks=fwd_walks, seed=5)
     torch.cuda.synchronize()
     t_fw = time.perf_counter() - t0
-    dfb = xf - x[:, 0]
+    xf_host = xf.cpu().numpy()
+    dfb = xf_host - x_host[:, 0]
     fwd = {"seconds": t_fw, "steps": st_fw["steps"], "walks": fwd_walks,
-           "rms_forward_minus_backward": float(torch.sqrt(torch.mean(dfb * dfb)).item()),
+           "rms_forward_minus_backward": float(np.sqrt(np.mean(dfb * dfb))),
            "rms_expected": math.sqrt(float(vf.mean().item()) + st["est_variance"]),
-           "rms_of_x": float(torch.sqrt(torch.mean(x[:, 0] * x[:, 0])).item()),
+           "rms_of_x": float(np.sqrt(np.mean(x_host[:, 0] ** 2))),
            "note": "exp(beta A) 1 by walks deposited at their final states; rms_expected from "
                    "the two estimated variances"}
     # the same five levels as one persistent launch: a batch of this one instance, captured
@@ -264,13 +415,17 @@ def tc_bench(args):
     torch.cuda.synchronize()
     el_b = (time.perf_counter() - t0) / args.steps
     st_b = batch.stats()[0]
-    tc_b = float(batch.xs[0][:, 0].sum().item())
+    xb_host = batch.xs[0].cpu().numpy()
+    tc_b = float(xb_host[:, 0].sum())
     info_b = {k: batch.info[k] for k in ("walks_per_item", "waves_per_cu", "phases", "items")}
     batch.close()
-    print(json.dumps({
+    n_slots = plan.info["n_slots"]
+    plan.close()
+    del u
+    out = {
         "metric": "walk steps/s", "value": st_b["steps"] / el_b, "unit": "steps/s",
         "ms_per_launch": el_b * 1e3, "batch": info_b,
-        "rhs_samples_per_s": st_b["steps"] * u.shape[1] / el_b,
+        "rhs_samples_per_s": st_b["steps"] * U.shape[1] / el_b,
         "jumps": st_b["total_jumps"], "steps": st_b["steps"],
         "total_communicability_estimate_batch": tc_b,
         "per_level_runs": {"ms_per_run": el * 1e3, "walk_kernel_ms": st["walk_kernel_ms"],
@@ -278,28 +433,58 @@ def tc_bench(args):
                            "note": "the same walks as five launches (one per level) of one run"},
         "total_communicability_estimate": tc,
         "total_communicability_sd": sd_back,
+        "est_rmse": math.sqrt(st["est_variance"]),
         "forward_scalar": {"estimate": tc_f, "sd": math.sqrt(var_f), "seconds": t_f,
                            "walks": st_f["walks"][:st_f["num_levels"]],
                            "steps": st_f["steps"],
                            "note": "Algorithm 1 on the scalar to the backward run's sd"},
         "forward_full_vector": fwd,
         "config": {"workload": f"Barabasi-Albert n={A.n} m=5, beta=1/d_max={beta:.3e}, "
-                               f"{u.shape[1]} right-hand sides (ones + Rademacher), "
+                               f"{U.shape[1]} right-hand sides (ones + Rademacher), "
                                f"levels {st['l0']}..{st['l0'] + 4}, 128 walks per row per level, "
                                "one persistent launch (graph replay)",
                    "nnz": A.nnz, "d_max": int(round(1 / beta)),
                    "host_s": {"generate": t_gen, "plan": t_plan}},
-    }), flush=True)
-    plan.close()
+    }
+    if probes is not None:
+        R = U.shape[1]
+        ws = n_slots * 16 + A.n * 32 + A.n * 4 * R
+        out["roofline"] = walk_roofline("level_walks_rhs<float,float>", ks["ms"] * 1e-3,
+                                        ks["launches"], ks["steps"], ks["jumps"], ks["walks_base"],
+                                        ks["walks_above"], 5 * A.n * len(sts), R, ws, probes)
+        out["roofline"]["note"] = "the per-level runs' walk launches (event pairs around each)"
+
+    def truth():
+        import bench_reference
+
+        ref = bench_reference.expv_sparse(A, U, beta, threads=16)
+        e = x_host - ref
+        eb = xb_host - ref
+        return {"true_rmse": float(np.sqrt(np.mean(e ** 2))),
+                "true_rmse_batch": float(np.sqrt(np.mean(eb ** 2))),
+                "true_rmse_column0": float(np.sqrt(np.mean(e[:, 0] ** 2))),
+                "forward_full_vector_true_rmse": float(np.sqrt(np.mean((xf_host - ref[:, 0]) ** 2))),
+                "total_communicability_exact": float(ref[:, 0].sum()),
+                "reference": "exp(beta A) U for all 64 right-hand sides in FP64 (truncated "
+                             "Taylor with scaling, Al-Mohy & Higham)"}
+    return out, truth
 
 
-def learned_bench(args):
+def tc_bench(args):
+    out, truth = tc_part(args, machine_probes())
+    out["true_error"] = truth()
+    print(json.dumps(out), flush=True)
+
+
+def learned_part(args):
     """Time to a target RMSE with the learned proposal against the plain jump law, on the 3D
     7-point convection-diffusion operator (m^3 cells, lognormal(0, 0.5) diffusivity,
     uniform(-1, 1) velocity per cell, ||tA||_1 = 4, v = exp(-|x|^2)), FP32 weights,
     Algorithm 1 with the same pilot in both cases, at the target eps, eps / 10 and eps / 30. The
     proposal is trained once (pilot estimate, transition capture, Adam, table build: the
-    whole call is timed) and then used for both targets."""
+    whole call is timed) and then used for all targets; if the variance judge rejects it, the
+    'learned' rows run with the plain law the library fell back to, and say so. Returns the
+    result and a closure that computes the true errors (CPU)."""
     import numpy as np
     import torch
 
@@ -339,6 +524,7 @@ def learned_bench(args):
                       sample_stride=max(1, A.n // 65536), steps=200, batch=4096, lr=1e-2,
                       shrink=10.0, num_levels=1, judge_walks=8)
     (params, tst), t_train = timed(lambda: plan.train_proposal(u, P0, **train_opts))
+    accepted = bool(tst["accepted"])
     out = {
         "workload": f"3D 7-point convection-diffusion {args.cd_grid}^3 (n={A.n}, nonsymmetric), "
                     f"lognormal(0,0.5) diffusivity, U(-1,1) velocity, ||tA||_1=4, "
@@ -349,15 +535,21 @@ def learned_bench(args):
                                          "train_ms", "first_val_loss", "best_val_loss",
                                          "judge_var_plain", "judge_var_learned", "accepted")},
         "train_options": train_opts,
+        "learned_law": "trained proposal" if accepted else
+                       "plain law (the variance judge rejected the trained proposal)",
         "targets": [],
         "host_s": {"generate": t_gen, "plan": t_plan},
     }
+    xs = []
     for k, eps in enumerate((args.eps, args.eps / 10, args.eps / 30)):
         plan.enable_proposal(False)
         (xp, stp), tp = solve(eps, 100 + k)
-        plan.enable_proposal(True)
+        plan.enable_proposal(accepted)
         (xl, stl), tl = solve(eps, 200 + k)
-        d = (xl - xp).cpu().numpy()[:, 0]
+        xp_h = xp.cpu().numpy()[:, 0]
+        xl_h = xl.cpu().numpy()[:, 0]
+        xs.append((xp_h, xl_h))
+        d = xl_h - xp_h
         out["targets"].append({
             "eps": eps, "plain": summary(stp, tp), "learned": summary(stl, tl),
             "speedup_solve": tp / tl, "speedup_incl_training": tp / (tl + t_train),
@@ -367,7 +559,22 @@ def learned_bench(args):
             "rms_learned_minus_plain": float(np.sqrt(np.mean(d * d))),
         })
     plan.close()
-    return out
+
+    def truth():
+        import bench_reference
+
+        ref = bench_reference.expv_sparse(A, v, t)
+        for tg, (xp_h, xl_h) in zip(out["targets"], xs):
+            tg["plain"]["true_rmse"] = float(np.sqrt(np.mean((xp_h - ref) ** 2)))
+            tg["learned"]["true_rmse"] = float(np.sqrt(np.mean((xl_h - ref) ** 2)))
+        return "exp(tA)v in FP64 (truncated Taylor with scaling, Al-Mohy & Higham)"
+    return out, truth
+
+
+def learned_bench(args):
+    out, truth = learned_part(args)
+    out["true_error_reference"] = truth()
+    print(json.dumps(out), flush=True)
 
 
 def classical_bench(args):
@@ -461,11 +668,11 @@ def copy_only(args):
                           "seconds": el, "GBps": 8 * n / el / 1e9}), flush=True)
 
 
-def cpu_baseline(A, t, v, l0, walks, target_s, threads=0):
+def cpu_baseline(A, t, v, l0, walks, target_s, threads=0, min_steps=1.2e9):
     """The oracle (plain FP64 C, OpenMP over rows; `threads` 0 = all of the host's) on a
     bounded sample of the same workload: a random subset of rows with the solve's sample
-    sizes scaled down so that the run takes about target_s seconds. Returns walk steps per
-    second."""
+    sizes scaled down so that the run takes about target_s seconds, and at least min_steps
+    walk steps. Returns walk steps per second."""
     import numpy as np
 
     from oracle import mlmc as orc
@@ -473,14 +680,16 @@ def cpu_baseline(A, t, v, l0, walks, target_s, threads=0):
     tables = orc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
     threads = threads or orc.max_threads()
     rng = np.random.default_rng(5)
-    # calibration on a small slice
-    rows = rng.choice(A.n, size=256, replace=False)
+    # calibration on a slice of about 0.1 s of work
+    rows = rng.choice(A.n, size=1024, replace=False)
+    orc.level_sums(tables, t, l0, l0, 1, v, rows[:64], 0, 64, threads=threads)
     t0 = time.perf_counter()
     orc.level_sums(tables, t, l0, l0, 1, v, rows, 0, 256, threads=threads)
     cal = time.perf_counter() - t0
-    speed = 256 * 256 * (1 << l0) / max(cal, 1e-6)
+    speed = 1024 * 256 * (1 << l0) / max(cal, 1e-6)
     steps_full = sum(w * (1 << (l0 + q)) for q, w in enumerate(walks)) * A.n
-    frac = min(1.0, target_s * speed / steps_full)
+    target = max(min_steps, target_s * speed)
+    frac = min(1.0, target / steps_full)
     n_rows = max(64, min(A.n, int(A.n * math.sqrt(frac))))
     scale = min(1.0, frac * A.n / n_rows)
     rows = np.sort(rng.choice(A.n, size=n_rows, replace=False))
@@ -497,18 +706,18 @@ def cpu_baseline(A, t, v, l0, walks, target_s, threads=0):
                       f"{steps:.3e} steps in {el:.1f} s"}
 
 
-def config1_bench(args):
+def config1_part(args):
     """The FP64 1D Dirichlet Laplacian (n = 100, t = 1e-4, v = sin(pi i h) + U(0, 0.1)),
     full vector, 1e4 walks per row at the finest of four levels (coarser levels by the ratio
     2^{1.5}), FP64 weights; error against the dense FP64 matrix exponential."""
     import numpy as np
-    import scipy.linalg
     import torch
 
+    import bench_reference
     from paper_1904_12754_amd import api, inputs
 
     A, t, v = inputs.workload_laplace1d()
-    exact = scipy.linalg.expm(t * A.to_dense()) @ v
+    exact = bench_reference.expv_dense(A.to_dense(), v, t)
     plan = api.Plan(A, t, precision="fp64")
     u = torch.as_tensor(v, device="cuda")
     walks = [int(round(1e4 * 2 ** (1.5 * (3 - q)))) for q in range(4)]
@@ -523,7 +732,7 @@ def config1_bench(args):
     return {"workload": "1D Dirichlet Laplacian n=100, t=1e-4, FP64, levels "
                         f"{st['l0']}..{st['l0'] + 3}, walks per row {walks}",
             "seconds": el, "steps": st["steps"], "steps_per_s": st["steps"] / el,
-            "rmse_vs_dense_expm": float(np.sqrt(np.mean(err ** 2))),
+            "true_rmse_vs_dense_expm": float(np.sqrt(np.mean(err ** 2))),
             "max_abs_error": float(np.abs(err).max()),
             "est_rmse": math.sqrt(st["est_variance"])}
 
@@ -535,19 +744,21 @@ def main():
                                    "measured at one GPU's share of the work (--gpus 1)"}))
         sys.exit(2)
     if args.mode == "config1":
-        print(json.dumps(config1_bench(args)), flush=True)
+        print(json.dumps(config1_part(args)), flush=True)
         return
     if args.mode == "kernel":
         return kernel_only(args)
     if args.mode == "copy":
         return copy_only(args)
+    if args.mode == "probe":
+        print(json.dumps(machine_probes()), flush=True)
+        return
     if args.mode == "batch":
         return batch_bench(args)
     if args.mode == "tc":
         return tc_bench(args)
     if args.mode == "learned":
-        print(json.dumps(learned_bench(args)), flush=True)
-        return
+        return learned_bench(args)
     if args.mode == "classical":
         print(json.dumps(classical_bench(args)), flush=True)
         return
@@ -558,6 +769,7 @@ def main():
     from paper_1904_12754_amd import api, inputs
 
     dev = torch.device("cuda:0")
+    probes = machine_probes()
     A, t, v = inputs.workload_laplace2d(args.grid)
     x_exact = bench_reference.expv_laplace2d(v, t)
     u = torch.as_tensor(v.astype(np.float32), device=dev)
@@ -579,37 +791,18 @@ def main():
     elapsed = time.perf_counter() - t0
     stream.synchronize()
 
-    steps = sum(s["steps"] for s in stats)
-    jumps = sum(s["total_jumps"] for s in stats)
-    walks_total = sum(sum(s["walks"]) * plan.n_rows for s in stats)
-    walks_base = sum(s["walks"][0] * plan.n_rows for s in stats)
-    wk_ms = sum(s["walk_kernel_ms"] for s in stats)
-    launches = sum(s["walk_launches"] for s in stats)
+    ks = kernel_sums([(s_, plan.n_rows) for s_ in stats])
+    steps = ks["steps"]
+    jumps = ks["jumps"]
     last = stats[-1]
     xg = x.cpu().numpy()[:, 0]
     true_rmse = float(np.sqrt(np.mean((xg - x_exact) ** 2)))
-
-    ops = (OPS_PER_STEP * steps + OPS_PER_JUMP * jumps + OPS_PER_WALK_BASE * walks_base +
-           OPS_PER_WALK_ABOVE * (walks_total - walks_base))
-    achieved = ops / (wk_ms * 1e-3)
-    roofline = {
-        "bound": "alu",
-        "kernel": "level_walks_r1<float,float>",
-        "achieved": achieved / 1e12,
-        "peak": VALU_PEAK_LANE_OPS / 1e12,
-        "unit": "T lane-ops/s",
-        "frac": achieved / VALU_PEAK_LANE_OPS,
-        "traffic": kernel_traffic(walks_total / max(launches, 1)),
-        "per_unit": {"ops_per_step": OPS_PER_STEP, "ops_per_jump": OPS_PER_JUMP,
-                     "ops_per_walk_base": OPS_PER_WALK_BASE,
-                     "ops_per_walk_above": OPS_PER_WALK_ABOVE},
-        "launch_avg_ms": wk_ms / max(launches, 1),
-        "launches": launches,
-        "gathered_GBps": BYTES_PER_JUMP * jumps / (wk_ms * 1e-3) / 1e9,
-        # the same algorithmic gather rate against the HBM peak (the gathers are served by the
-        # caches, so this is the gather-bound roofline, not the kernel's binding limit)
-        "gathered_frac_of_hbm_peak": BYTES_PER_JUMP * jumps / (wk_ms * 1e-3) / HBM_PEAK_BPS,
-    }
+    walks_total = ks["walks_base"] + ks["walks_above"]
+    ws = plan.info["n_slots"] * 16 + A.n * (32 + 4)
+    roofline = walk_roofline("level_walks_r1<float,float>", ks["ms"] * 1e-3, ks["launches"], steps,
+                             jumps, ks["walks_base"], ks["walks_above"],
+                             plan.n_rows * sum(s_["num_levels"] for s_ in stats), 1, ws, probes,
+                             traffic=kernel_traffic(walks_total / max(ks["launches"], 1)))
     line = {
         "metric": "walk steps/s",
         "value": steps / elapsed,
@@ -633,10 +826,11 @@ def main():
             "true_rmse_vs_exact": true_rmse,
             "est_rmse": math.sqrt(last["est_variance"] + last["est_bias"] ** 2),
             "jumps_per_s": jumps / elapsed,
-            "walk_kernel_share": wk_ms * 1e-3 / elapsed,
+            "walk_kernel_share": ks["ms"] * 1e-3 / elapsed,
             "path_decisions": "fp64 + u32 (bit-identical to the FP64 oracle)",
         },
         "roofline": roofline,
+        "probes": probes,
     }
     # the same solve to a looser target (outside the timed region)
     if not args.no_loose:
@@ -652,11 +846,31 @@ def main():
             "true_rmse_vs_exact": float(np.sqrt(np.mean((x2.cpu().numpy()[:, 0] - x_exact) ** 2))),
             "steps_per_s": st2["steps"] / el2}
     plan.close()
+    del u
+    torch.cuda.empty_cache()
+    truths = {}
+    others = {}
+    if not args.no_others:
+        others["laplace1d_fp64"] = config1_part(args)
+        print("bench: workload 1 done", file=sys.stderr, flush=True)
+        others["barabasi_albert_64rhs"], truths["barabasi_albert_64rhs"] = tc_part(args, probes)
+        torch.cuda.empty_cache()
+        print("bench: workload 3 done", file=sys.stderr, flush=True)
+        others["uneven_batch"], truths["uneven_batch"] = batch_part(args, probes)
+        torch.cuda.empty_cache()
+        print("bench: workload 4 done", file=sys.stderr, flush=True)
     if not args.no_learned:
-        line["learned_proposal"] = learned_bench(args)
+        line["learned_proposal"], learned_truth = learned_part(args)
+        print("bench: workload 5 done", file=sys.stderr, flush=True)
+        line["learned_proposal"]["true_error_reference"] = learned_truth()
+    for key, fn in truths.items():
+        others[key]["true_error"] = fn()
+    if others:
+        line["other_workloads"] = others
     if not args.no_cpu_baseline:
         cb = cpu_baseline(A, t, v, last["l0"], last["walks"], args.cpu_seconds)
-        one = cpu_baseline(A, t, v, last["l0"], last["walks"], args.cpu_seconds / 3, threads=1)
+        one = cpu_baseline(A, t, v, last["l0"], last["walks"], args.cpu_seconds / 3, threads=1,
+                           min_steps=0)
         cb["one_core"] = {"value": one["value"], "sample": one["sample"]}
         line["cpu_baseline"] = cb
     print(json.dumps(line), flush=True)

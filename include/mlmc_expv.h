@@ -305,8 +305,8 @@ typedef struct {
     double *const *x;                 /* count DEVICE outputs, n_rows_b x nrhs_b FP64 */
     int32_t num_levels;               /* levels l0_b .. l0_b + num_levels - 1 of each plan */
     const int64_t *walks;             /* HOST, count x num_levels walks per row (row major) */
-    int32_t autotune;                 /* 1: time candidate launch shapes (walks per item 256,
-                                         1024, 4096 and the size rule's choice x 8, 16, 32
+    int32_t autotune;                 /* 1: time candidate launch shapes (walks per item 1024,
+                                         4096 and the size rule's choice x 8, 16, 20, 32
                                          resident waves per CU) on every 8th instance at full
                                          sample sizes and keep the fastest; the choice is
                                          cached per class of batch for the process.
@@ -339,7 +339,9 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *desc, vo
 int mlmc_expv_batch_launch(mlmc_batch_t *batch, uint64_t seed, void *stream);
 
 /* Statistics of the last launch, one struct per instance (HOST array of count). Waits for
- * `stream`. kernel_ms is the device time of the whole graph. */
+ * `stream`. kernel_ms and walk_kernel_ms are both the device time of the whole graph (its walk
+ * phases and the short per-row sum and combine kernels after them); walk_launches is the
+ * number of walk phases the graph launches. */
 int mlmc_expv_batch_stats(mlmc_batch_t *batch, mlmc_stats_t *per_instance, void *stream);
 
 int mlmc_expv_batch_info(const mlmc_batch_t *batch, mlmc_batch_info_t *info);

@@ -463,3 +463,28 @@ class Batch:
     def __exit__(self, *exc):
         self.close()
 
+
+# ---- measurement probes (include/mlmc_probe.h) -----------------------------------------
+def probe_gather(table: torch.Tensor, log2_records: int, waves_per_cu: int = 16, iters: int = 64,
+                 stream=None):
+    """Random 16-byte gathers from the first 2^log2_records records of `table` (a device
+    tensor of at least 16 * 2^log2_records bytes). Returns (gathers, seconds) of one timed
+    launch."""
+    if not table.is_cuda or table.numel() * table.element_size() < (16 << log2_records):
+        raise ValueError("table must be a device tensor of at least 16 * 2^log2_records bytes")
+    lib = _abi.load()
+    g = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    check(lib.mlmc_probe_gather(_dev_ptr(table), int(log2_records), int(waves_per_cu), int(iters),
+                                ctypes.byref(g), ctypes.byref(ms), _stream_ptr(stream)))
+    return int(g.value), ms.value * 1e-3
+
+
+def probe_valu(waves_per_cu: int = 16, iters: int = 4096, stream=None):
+    """Integer VALU issue probe. Returns (lane-instructions, seconds) of one timed launch."""
+    lib = _abi.load()
+    n = ctypes.c_uint64()
+    ms = ctypes.c_double()
+    check(lib.mlmc_probe_valu(int(waves_per_cu), int(iters), ctypes.byref(n), ctypes.byref(ms),
+                              _stream_ptr(stream)))
+    return int(n.value), ms.value * 1e-3

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlmc_expv.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
-SOURCES = ["kernels.hip", "abi.hip", "batch.hip", "proposal.hip", "functional.hip"]
+SOURCES = ["kernels.hip", "abi.hip", "batch.hip", "proposal.hip", "functional.hip", "probe.hip"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",

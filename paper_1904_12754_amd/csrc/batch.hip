@@ -703,8 +703,8 @@ int mlmc_expv_batch_stats(mlmc_batch_t *b, mlmc_stats_t *per_instance, void *str
         }
         st.est_variance = var;
         st.kernel_ms = ms;
-        st.walk_kernel_ms = ms;
-        st.walk_launches = 1;
+        st.walk_kernel_ms = ms;   // the graph's time: the walk phases plus the short sums
+        st.walk_launches = b->phases;
         nonfinite += st.nonfinite;
     }
     if (nonfinite) return fail(MLMC_ERR_NONFINITE, std::to_string(nonfinite) + " non-finite samples");
