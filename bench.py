@@ -94,12 +94,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--pilot", type=int, default=4096)
+    ap.add_argument("--pilot", type=int, default=0,
+                    help="Algorithm 1's M0 (0: the library's rule, 2^18 samples per level)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--cd-grid", type=int, default=128)
-    ap.add_argument("--cd-pilot", type=int, default=2)
+    ap.add_argument("--cd-pilot", type=int, default=0)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-loose", action="store_true",
                     help="skip the solves to RMSE 1e-2 after the timed region")
@@ -528,8 +529,9 @@ def learned_part(args):
     out = {
         "workload": f"3D 7-point convection-diffusion {args.cd_grid}^3 (n={A.n}, nonsymmetric), "
                     f"lognormal(0,0.5) diffusivity, U(-1,1) velocity, ||tA||_1=4, "
-                    f"v=exp(-|x|^2); Algorithm 1 (pilot {args.cd_pilot} walks per row on "
-                    f"l0..l0+4); FP32 weights",
+                    f"v=exp(-|x|^2); Algorithm 1 (pilot "
+                    f"{args.cd_pilot or 'from the row count: max(2, 2^18 / n)'} walks per row "
+                    f"on l0..l0+4); FP32 weights",
         "train_s": t_train,
         "training": {k: tst[k] for k in ("transitions", "held_out", "steps", "best_step",
                                          "train_ms", "first_val_loss", "best_val_loss",

@@ -110,7 +110,10 @@ typedef struct {
                                  (host array of num_levels entries, each in [1, 2^32)) */
     double eps;               /* > 0 selects Algorithm 1 with target RMSE eps (the fixed
                                  schedule fields are then ignored) */
-    int64_t pilot_walks;      /* Algorithm 1: walks per row per level of the pilot run */
+    int64_t pilot_walks;      /* Algorithm 1: walks per row per level of the pilot run;
+                                 0 selects max(2, ceil(2^18 / (rows x right-hand sides))),
+                                 at least 2^18 samples per pilot level (functional and
+                                 forward runs: total walks per level; 0 selects 2^18) */
     int32_t max_levels;       /* Algorithm 1: cap on the number of levels */
     int64_t max_walks;        /* Algorithm 1: cap on walks per row per level (0 = 2^32 - 1) */
 } mlmc_run_opts_t;
@@ -121,8 +124,11 @@ typedef struct {
     int32_t l0, num_levels, converged, driver_iterations;
     int64_t walks[MLMC_MAX_LEVELS];          /* M_l per row */
     int64_t jumps[MLMC_MAX_LEVELS];          /* total jumps taken at the level */
-    double level_mean_rms[MLMC_MAX_LEVELS];  /* sqrt(mean m_{l,i}^2) */
-    double level_var[MLMC_MAX_LEVELS];       /* mean V_{l,i} (per-walk variance) */
+    double level_mean_rms[MLMC_MAX_LEVELS];  /* sqrt(mean m_{l,i}^2 - level_var / M_l): the
+                                                root mean square of the level term, less the
+                                                sampling noise of the M_l-walk means */
+    double level_var[MLMC_MAX_LEVELS];       /* mean V_{l,i}: per-walk sample variance, unbiased
+                                                (M/(M-1) times mean square less squared mean) */
     double level_cost[MLMC_MAX_LEVELS];      /* cost model N_l + 4 * jumps per walk */
     int64_t steps;                           /* sum over walks of N_l */
     int64_t total_jumps;

@@ -335,9 +335,8 @@ class LevelStats:
         return self.s1 / self.M
 
     @property
-    def var(self) -> np.ndarray:           # V_{l,i} = mean(Y^2) - mean(Y)^2
-        m = self.s1 / self.M
-        return np.maximum(self.s2 / self.M - m * m, 0.0)
+    def var(self) -> np.ndarray:           # V_{l,i}, the unbiased per-walk sample variance
+        return row_variances(self.s1, self.s2, self.M)
 
 
 @dataclass
@@ -390,10 +389,42 @@ def optimal_M(V, C, eps):
     return np.ceil(2.0 * eps ** -2 * np.sqrt(V / C) * tot).astype(np.int64)
 
 
+def row_variances(s1, s2, M: int) -> np.ndarray:
+    """Per-entry sample variance of M samples from their sum and sum of squares (Algorithm 2's
+    m_l and m2l, each divided by M once), with the factor M / (M - 1) that makes it unbiased;
+    clamped at 0 against rounding."""
+    m = s1 / M
+    raw = np.maximum(s2 / M - m * m, 0.0)
+    return raw * (M / (M - 1.0)) if M > 1 else raw
+
+
+def level_variance(s1, s2, M: int) -> float:
+    """V_l of Algorithm 1 for a vector: the mean over the entries of their per-walk variances."""
+    return float(np.mean(row_variances(s1, s2, M)))
+
+
+def level_term_rms(s1, s2, M: int) -> float:
+    """The root mean square over the entries of the level term m_{l,i}, from M-walk means:
+    mean_i mhat_i^2 overstates mean_i m_i^2 by the sampling noise mean_i V_{l,i} / M, which
+    is taken off (clamped at 0), so that small pilots do not inflate the bias estimate."""
+    m = s1 / M
+    return math.sqrt(max(float(np.mean(m * m)) - level_variance(s1, s2, M) / M, 0.0))
+
+
 def bias_estimate(mL: float, mLm1: float) -> float:
     """Extrapolated bias of the finest level, from the RMS level means of the two
     finest levels with weak order alpha."""
     return max(abs(mL), abs(mLm1) / 2.0 ** ALPHA) / (2.0 ** ALPHA - 1.0)
+
+
+PILOT_SAMPLES = 1 << 18
+
+
+def default_pilot(n_rows: int, u_shape) -> int:
+    """M0 when the caller leaves it to the driver: enough walks per row that every pilot level
+    holds at least 2^18 samples over its rows and right-hand sides, and at least 2."""
+    R = int(u_shape[1]) if len(u_shape) > 1 else 1
+    return max(2, -(-PILOT_SAMPLES // max(1, n_rows * R)))
 
 
 @dataclass
@@ -408,8 +439,9 @@ class _Acc:
 def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | None = None,
                   pilot: int = 256, max_levels: int = 20, rows=None, instance: int = 0,
                   threads: int = 0, max_walks: int | None = None, max_iterations: int = 100):
-    """Algorithm 1: pilot M0 walks on levels l0..l0+4, then repeat {optimal M_l; run the
-    extra walks; stop when the error is below eps, else add a level}.
+    """Algorithm 1: pilot M0 walks on levels l0..l0+4 (pilot = 0: default_pilot), then
+    repeat {optimal M_l; run the extra walks; stop when the error is below eps, else add a
+    level}.
 
     The error is read as two parts: the estimator's variance sum_l V_l / M_l against the
     budget eps^2 / 2, and the extrapolated bias of the finest level against eps / sqrt(2).
@@ -436,13 +468,14 @@ def mlmc_adaptive(t: Tables, beta: float, u, eps: float, seed: int, l0: int | No
 
     def level_var(lev):          # row-mean per-walk variance of the level's samples
         a = acc[lev]
-        m = a.s1 / a.M
-        return float(np.mean(np.maximum(a.s2 / a.M - m * m, 0.0)))
+        return level_variance(a.s1, a.s2, a.M)
 
     def level_rms(lev):          # root mean square over rows of the level term
         a = acc[lev]
-        return float(np.sqrt(np.mean((a.s1 / a.M) ** 2)))
+        return level_term_rms(a.s1, a.s2, a.M)
 
+    if pilot == 0:
+        pilot = default_pilot(len(rows) if rows is not None else t.n, np.shape(u))
     for lev in range(l0, L + 1):
         run(lev, pilot)
     converged = False
@@ -572,9 +605,8 @@ def forward_fixed(tT: Tables, beta: float, u, l0: int, L: int, M, seed: int, ins
     var = np.zeros(tT.n)
     for q, lev in enumerate(range(l0, L + 1)):
         fs = forward_sums(tT, beta, lev, l0, seed, u, 0, int(M[q]), instance)
-        m = fs.sum1 / fs.walks
-        est += fs.U * m
-        var += fs.U ** 2 * np.maximum(fs.sum2 / fs.walks - m * m, 0.0) / fs.walks
+        est += fs.U * (fs.sum1 / fs.walks)
+        var += fs.U ** 2 * row_variances(fs.sum1, fs.sum2, fs.walks) / fs.walks
     return est, var
 
 
@@ -584,8 +616,6 @@ def functional_fixed(tT: Tables, beta: float, u, w, l0: int, L: int, M, seed: in
     est = var = 0.0
     for q, lev in enumerate(range(l0, L + 1)):
         fs = functional_sums(tT, beta, lev, l0, seed, u, w, 0, int(M[q]), instance)
-        m = fs.sum1 / fs.walks
-        v = max(fs.sum2 / fs.walks - m * m, 0.0)
-        est += fs.U * m
-        var += fs.U ** 2 * v / fs.walks
+        est += fs.U * (fs.sum1 / fs.walks)
+        var += fs.U ** 2 * float(row_variances(fs.sum1, fs.sum2, fs.walks)) / fs.walks
     return est, var

@@ -626,9 +626,11 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     const int64_t count = p->n_rows * nrhs;
     const bool adaptive = o->eps > 0.0;
     int max_levels;
+    int64_t pilot = o->pilot_walks;
     if (adaptive) {
-        if (o->pilot_walks < 2 || o->pilot_walks >= (int64_t(1) << 32))
-            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be in [2, 2^32)");
+        if (pilot == 0) pilot = default_pilot(count);
+        if (pilot < 2 || pilot >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be 0 or in [2, 2^32)");
         max_levels = o->max_levels > 0 ? o->max_levels : 20;
         max_levels = std::min(max_levels, std::min(MLMC_MAX_LEVELS, kMaxLevel - p->l0 + 1));
         if (max_levels < 2) return fail(MLMC_ERR_INVALID_ARG, "max_levels must allow at least two levels");
@@ -681,8 +683,8 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
         return MLMC_OK;
     };
     const double cnt = static_cast<double>(std::max<int64_t>(count, 1));
-    auto level_var = [&](int qq) { return mom[qq].sum_v / cnt; };
-    auto level_rms = [&](int qq) { return std::sqrt(mom[qq].sum_m2 / cnt); };
+    auto level_var = [&](int qq) { return unbiased_var(mom[qq].sum_v / cnt, M[qq]); };
+    auto level_rms = [&](int qq) { return debiased_rms(mom[qq].sum_m2 / cnt, level_var(qq), M[qq]); };
     auto level_cost = [&](int qq) {
         const double walks_total = static_cast<double>(M[qq]) * std::max<int64_t>(p->n_rows, 1);
         return std::ldexp(1.0, p->l0 + qq) + 4.0 * static_cast<double>(ctr[2 * qq]) / walks_total;
@@ -701,7 +703,7 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
         // Algorithm 1 on the row means: V_l = mean_i V_{l,i}, m_l = RMS_i m_{l,i}
         DriverOpts d;
         d.eps = o->eps;
-        d.pilot = o->pilot_walks;
+        d.pilot = pilot;
         d.max_levels = max_levels;
         d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
         auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {

@@ -23,6 +23,7 @@
 
 #include "../../include/mlmc_expv.h"
 #include "common.h"
+#include "driver.h"
 #include "kernels.h"
 #include "plan.h"
 #include "walk_engine.h"
@@ -692,8 +693,8 @@ int mlmc_expv_batch_stats(mlmc_batch_t *b, mlmc_stats_t *per_instance, void *str
             const double cnt = std::max<double>(1.0, static_cast<double>(sg.n_rows) * sg.nrhs);
             st.walks[q] = sg.M;
             st.jumps[q] = static_cast<int64_t>(ctr[2 * g]);
-            st.level_mean_rms[q] = std::sqrt(mom[3 * g + 1] / cnt);
-            st.level_var[q] = mom[3 * g + 2] / cnt;
+            st.level_var[q] = unbiased_var(mom[3 * g + 2] / cnt, sg.M);
+            st.level_mean_rms[q] = debiased_rms(mom[3 * g + 1] / cnt, st.level_var[q], sg.M);
             const double walks_total = static_cast<double>(sg.M) * std::max<uint32_t>(sg.n_rows, 1);
             st.level_cost[q] = std::ldexp(1.0, p->l0 + q) + 4.0 * static_cast<double>(ctr[2 * g]) / walks_total;
             st.steps += static_cast<int64_t>(sg.M) * sg.n_rows * (int64_t(1) << (p->l0 + q));

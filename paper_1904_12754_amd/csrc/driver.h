@@ -23,9 +23,9 @@ namespace mlmc {
 
 // What the driver reads of level index q (level l0 + q) after its walks so far.
 struct LevelEstimate {
-    double var = 0.0;    // per-walk variance V_l (averaged over the estimated entries)
+    double var = 0.0;    // unbiased per-walk variance V_l (averaged over the estimated entries)
     double cost = 0.0;   // cost per walk C_l: N_l + 4 jumps per walk
-    double rms = 0.0;    // the level term m_l (root mean square over the entries)
+    double rms = 0.0;    // the level term m_l (root mean square over the entries, debiased)
 };
 
 struct DriverOpts {
@@ -43,6 +43,30 @@ struct DriverOut {
 };
 
 constexpr double kWeakOrder = 2.0;
+
+// M0 when the caller leaves it to the driver (pilot_walks = 0): enough walks per row that a
+// pilot level holds at least 2^18 samples over its rows and right-hand sides, and at least 2.
+constexpr int64_t kPilotSamples = int64_t(1) << 18;
+inline int64_t default_pilot(int64_t rows_times_rhs)
+{
+    const int64_t r = std::max<int64_t>(1, rows_times_rhs);
+    return std::max<int64_t>(2, (kPilotSamples + r - 1) / r);
+}
+
+// The per-walk variance from M samples' mean square minus squared mean (Algorithm 2's m_l
+// and m2l, each divided by M once), made unbiased by the factor M / (M - 1).
+inline double unbiased_var(double raw, int64_t M)
+{
+    return M > 1 ? raw * (static_cast<double>(M) / static_cast<double>(M - 1)) : raw;
+}
+
+// The root mean square of a level term over its entries from M-walk means: the mean of the
+// squared means overstates the mean square of the terms by the sampling noise var / M
+// (var the unbiased per-walk variance averaged over the entries), which is taken off.
+inline double debiased_rms(double mean_sq, double var, int64_t M)
+{
+    return std::sqrt(std::max(mean_sq - var / static_cast<double>(std::max<int64_t>(M, 1)), 0.0));
+}
 
 // The extrapolated bias of the finest level from the two finest level terms.
 inline double extrapolated_bias(double mL, double mLm1)

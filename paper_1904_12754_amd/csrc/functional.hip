@@ -79,8 +79,9 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void forward_walk
     }
 }
 
-// x += scale sum1 and, with var, var += scale^2 (sum2 / M - (sum1 / M)^2) / M (a level's
-// term of the forward estimate and of its per-entry variance).
+// x += scale sum1 and, with var, var += scale^2 (sum2 / M - (sum1 / M)^2) / (M - 1) (a level's
+// term of the forward estimate and of its per-entry variance, the per-walk variance made
+// unbiased; M = 1 divides by M).
 __global__ void forward_combine(const double *__restrict__ sum1, const double *__restrict__ sum2, int64_t n,
                                 double U, double M, double *x, double *var)
 {
@@ -88,7 +89,7 @@ __global__ void forward_combine(const double *__restrict__ sum1, const double *_
     if (j >= n) return;
     const double m = sum1[j] / M;
     x[j] += U * m;
-    if (var) var[j] += U * U * fmax(sum2[j] / M - m * m, 0.0) / M;
+    if (var) var[j] += U * U * fmax(sum2[j] / M - m * m, 0.0) / (M > 1.0 ? M - 1.0 : M);
 }
 
 // Per-level moments over the entries: sum of (U m_j)^2 and of U^2 (sum2_j / M - m_j^2), in a
@@ -410,9 +411,10 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const bool adaptive = o->eps > 0.0;
     int max_levels;
+    const int64_t pilot = o->pilot_walks == 0 ? default_pilot(1) : o->pilot_walks;
     if (adaptive) {
-        if (o->pilot_walks < 2 || o->pilot_walks >= (int64_t(1) << 32))
-            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be in [2, 2^32)");
+        if (pilot < 2 || pilot >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be 0 or in [2, 2^32)");
         max_levels = o->max_levels > 0 ? o->max_levels : 20;
         max_levels = std::min(max_levels, std::min(MLMC_MAX_LEVELS, kMaxLevel - p->l0 + 1));
         if (max_levels < 2) return fail(MLMC_ERR_INVALID_ARG, "max_levels must allow at least two levels");
@@ -452,7 +454,7 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
     // per-walk variance of U * sample, and the cost per walk N_l + 4 jumps
     auto var_of = [&](int q) {
         const double m = S1[q] / static_cast<double>(M[q]);
-        return std::max(S2[q] / static_cast<double>(M[q]) - m * m, 0.0) * UU * UU;
+        return unbiased_var(std::max(S2[q] / static_cast<double>(M[q]) - m * m, 0.0) * UU * UU, M[q]);
     };
     auto cost_of = [&](int q) {
         return std::ldexp(1.0, p->l0 + q) + 4.0 * static_cast<double>(J[q]) / static_cast<double>(M[q]);
@@ -475,11 +477,12 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
         // Algorithm 1 on the scalar's variance
         DriverOpts d;
         d.eps = o->eps;
-        d.pilot = o->pilot_walks;
+        d.pilot = pilot;
         d.max_levels = max_levels;
         d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
         auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {
-            for (int q = 0; q < lv; ++q) est[q] = LevelEstimate{var_of(q), cost_of(q), mean_of(q)};
+            for (int q = 0; q < lv; ++q)
+                est[q] = LevelEstimate{var_of(q), cost_of(q), debiased_rms(mean_of(q) * mean_of(q), var_of(q), M[q])};
             return MLMC_OK;
         };
         DriverOut out;
@@ -507,7 +510,7 @@ int mlmc_expv_functional(mlmc_plan_t *p, const void *u, const void *w, int32_t d
         for (int q = 0; q < levels; ++q) {
             stats->walks[q] = M[q];
             stats->jumps[q] = static_cast<int64_t>(J[q]);
-            stats->level_mean_rms[q] = std::fabs(mean_of(q));
+            stats->level_mean_rms[q] = debiased_rms(mean_of(q) * mean_of(q), var_of(q), M[q]);
             stats->level_var[q] = var_of(q);
             stats->level_cost[q] = cost_of(q);
             stats->steps += M[q] * (int64_t(1) << (p->l0 + q));
@@ -559,9 +562,10 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
     if (o->instance < 0 || o->instance > 4095) return fail(MLMC_ERR_INVALID_ARG, "instance must be in [0, 4095]");
     const bool adaptive = o->eps > 0.0;
     int max_levels;
+    const int64_t pilot = o->pilot_walks == 0 ? default_pilot(1) : o->pilot_walks;
     if (adaptive) {
-        if (o->pilot_walks < 2 || o->pilot_walks >= (int64_t(1) << 32))
-            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be in [2, 2^32)");
+        if (pilot < 2 || pilot >= (int64_t(1) << 32))
+            return fail(MLMC_ERR_INVALID_ARG, "pilot_walks must be 0 or in [2, 2^32)");
         max_levels = o->max_levels > 0 ? o->max_levels : 20;
         max_levels = std::min(max_levels, std::min(MLMC_MAX_LEVELS, kMaxLevel - p->l0 + 1));
         if (max_levels < 2) return fail(MLMC_ERR_INVALID_ARG, "max_levels must allow at least two levels");
@@ -623,8 +627,8 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
             MLMC_HIP_TRY(hipMemcpyAsync(h, mom, sizeof h, hipMemcpyDeviceToHost, s));
             MLMC_HIP_TRY(hipStreamSynchronize(s));
         }
-        rms[q] = std::sqrt(h[0] / nn);   // root mean square over the entries of the level term
-        V[q] = h[1] / nn;                // mean over the entries of the per-walk variance
+        V[q] = unbiased_var(h[1] / nn, M[q]);        // mean over the entries of the per-walk variance
+        rms[q] = debiased_rms(h[0] / nn, V[q], M[q]);  // root mean square of the level term
         return MLMC_OK;
     };
     auto cost_of = [&](int q) {
@@ -648,7 +652,7 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
         // root-mean-square level terms, as for the backward full vector
         DriverOpts d;
         d.eps = o->eps;
-        d.pilot = o->pilot_walks;
+        d.pilot = pilot;
         d.max_levels = max_levels;
         d.cap = o->max_walks > 0 ? std::min<int64_t>(o->max_walks, 0xFFFFFFFFll) : 0xFFFFFFFFll;
         auto measure = [&](int lv, std::vector<LevelEstimate> &est) -> int {

@@ -342,3 +342,27 @@ def test_classical_single_level_mc_estimates_the_finest_strang_product(api):
     assert st_mc["steps"] == M * 40 * (1 << L)
     mc_plan.close()
     mlmc_plan.close()
+
+
+def test_adaptive_run_with_the_default_pilot_takes_the_oracles_decisions(api):
+    """pilot_walks = 0 lets the driver size M0 from the row count (at least 2^18 samples per
+    pilot level: 2622 walks per row for 100 rows); with the variance estimate made unbiased
+    and the level terms' root mean square freed of the sampling noise, the FP64 GPU run must
+    take the oracle's levels and sample sizes (each within one walk) and reach the target."""
+    A, t, v = inputs.workload_laplace1d()
+    tt = _tables(A)
+    eps = 1e-3
+    res = orc.mlmc_adaptive(tt, t, v, eps, seed=9, pilot=0)
+    want = [st.M for st in res.levels]
+    plan = api.Plan(A, t, precision="fp64")
+    x, st = plan.run(torch.as_tensor(v, device="cuda"), eps=eps, seed=9, pilot_walks=0)
+    nl = st["num_levels"]
+    got = list(st["walks"][:nl])
+    _say(f"default pilot: gpu levels {nl} walks {got}; oracle walks {want}")
+    assert st["converged"] and res.converged
+    assert nl == len(want)
+    assert all(abs(g - w) <= 1 for g, w in zip(got, want)), (got, want)
+    assert min(got) >= 2622
+    exact = reference.laplace1d_exact(v, t)
+    assert float(np.sqrt(np.mean((x.cpu().numpy()[:, 0] - exact) ** 2))) < 2 * eps
+    plan.close()

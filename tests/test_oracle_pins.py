@@ -436,6 +436,74 @@ def test_adaptive_driver_reaches_the_target():
 
 
 # ----------------------------------------------------------------------------------
+# Algorithm 1's statistics from few walks per row: the unbiased per-walk variance and the
+# level term's root mean square less the sampling noise of the row means
+# ----------------------------------------------------------------------------------
+def _pair_samples(A, u, beta, tt, level, l0, walks_per_row, seed=11):
+    """Per-walk samples Y of `level` (walk_trace's eta carries the path's sign), n x walks."""
+    rows = np.repeat(np.arange(A.n), walks_per_row)
+    walks = np.tile(np.arange(walks_per_row, dtype=np.uint32), A.n)
+    tr = mlmc.walk_trace(tt, beta, level, seed, rows, walks)
+    eta = tr.eta_fine if level == l0 else tr.eta_fine - tr.eta_coarse
+    return (u[tr.final_state] * eta).reshape(A.n, walks_per_row)
+
+
+def test_level_variance_is_unbiased_from_two_walks_per_row():
+    """Algorithm 1 sizes M_l from V_l. At the coarsest level the sample is phi u_j e^{E_f}, so
+    its second moment is the level's expectation for the matrix with the jump signs dropped
+    and the diagonal weights d doubled, applied to u^2 (dense Strang products): the exact
+    per-walk variance. Averaged over 4000 independent pairs of walks per row, the driver's
+    variance from two walks must match it (the plain mean-square-less-squared-mean form
+    gives half)."""
+    A, u = inputs.small_chain(8, 3, True, 0.6, 1.0)
+    beta = 2.0
+    a = A.to_dense()
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    l0 = mlmc.default_l0(tt, beta)
+    off = a - np.diag(np.diag(a))
+    a2 = np.abs(off) + np.diag(2.0 * np.diag(a) + np.abs(off).sum(axis=1))
+    m = reference.strang_level(a, u, beta, l0)
+    v_true = float(np.mean(reference.strang_level(a2, u * u, beta, l0) - m * m))
+    Y = _pair_samples(A, u, beta, tt, l0, l0, 8000).reshape(A.n, 4000, 2)
+    s1, s2 = Y.sum(axis=2), (Y * Y).sum(axis=2)
+    v = np.mean([mlmc.level_variance(s1[:, k], s2[:, k], 2) for k in range(4000)])
+    assert abs(v / v_true - 1.0) < 0.03, (v, v_true)
+
+
+def test_level_term_rms_removes_the_sampling_noise():
+    """The bias test reads the root mean square of the level terms from M-walk row means,
+    whose squares overstate m_i^2 by V_i / M (here by a fifth): the driver's figure, averaged
+    over 2000 batches of 16 walks per row, must match the dense level term's."""
+    A, u = inputs.small_chain(8, 3, True, 0.6, 1.0)
+    beta = 2.0
+    a = A.to_dense()
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    l0 = mlmc.default_l0(tt, beta)
+    m2_true = float(np.mean(reference.strang_level(a, u, beta, l0) ** 2))
+    Y = _pair_samples(A, u, beta, tt, l0, l0, 32000).reshape(A.n, 2000, 16)
+    s1, s2 = Y.sum(axis=2), (Y * Y).sum(axis=2)
+    got = np.mean([mlmc.level_term_rms(s1[:, k], s2[:, k], 16) ** 2 for k in range(2000)])
+    raw = np.mean([np.mean((s1[:, k] / 16) ** 2) for k in range(2000)])
+    assert raw > 1.15 * m2_true
+    assert abs(got / m2_true - 1.0) < 0.04, (got, m2_true)
+
+
+def test_adaptive_driver_with_a_two_walk_pilot_adds_no_needless_level():
+    """The 1D Laplacian (splitting bias far below eps) with a pilot of two walks per row:
+    noise-inflated level terms would fail the bias test and add levels; the driver must stop
+    at the pilot's five levels and reach the target."""
+    A, t, v = inputs.workload_laplace1d()
+    tt = mlmc.decompose(A.n, A.row_ptr, A.col_idx, A.values)
+    eps = 2e-3
+    res = mlmc.mlmc_adaptive(tt, t, v, eps, seed=6, pilot=2)
+    assert res.converged
+    assert len(res.levels) == 5, [st.level for st in res.levels]
+    assert res.est_mse() <= eps * eps / 2 * 1.01
+    exact = reference.laplace1d_exact(v, t)
+    assert float(np.sqrt(np.mean((res.x[:, 0] - exact) ** 2))) < 3 * eps
+
+
+# ----------------------------------------------------------------------------------
 # Algorithm 1's error test: the extrapolated bias (weak order 2 of the Strang splitting,
 # section 4) and the level it adds when the bias is above its share of eps
 # ----------------------------------------------------------------------------------

@@ -143,6 +143,13 @@ PLANTS = [
     ("bias with weak order 1", "mlmc.py",
      [("ALPHA = 2.0 ", "ALPHA = 1.0 ")],
      [BIAS, DRIVER_LEVELS]),
+    ("per-walk variance without the factor M / (M - 1)", "mlmc.py",
+     [("return raw * (M / (M - 1.0)) if M > 1 else raw", "return raw")],
+     [PINS + "test_level_variance_is_unbiased_from_two_walks_per_row"]),
+    ("level term's root mean square keeps the sampling noise", "mlmc.py",
+     [("float(np.mean(m * m)) - level_variance(s1, s2, M) / M", "float(np.mean(m * m))")],
+     [PINS + "test_level_term_rms_removes_the_sampling_noise",
+      PINS + "test_adaptive_driver_with_a_two_walk_pilot_adds_no_needless_level"]),
     ("driver never adds a level", "mlmc.py",
      [("        L += 1\n        run(L, pilot)", "        break")],
      [BIAS, DRIVER_LEVELS]),
