@@ -262,84 +262,96 @@ static double simpson_weight(int64_t n, int64_t K)
 #define ORC_FNV_OFFSET 14695981039346656037ull
 #define ORC_FNV_PRIME 1099511628211ull
 
-/* One sample of Algorithm 2 (Algorithm 3 when F is given: the source term's integral
- * int_0^beta exp(sA) F ds at the walk's row, by the composite Simpson rule on the fine grid
- * (step dt, N intervals) and, for the coarse functional, on the coarse grid (step 2 dt,
- * its N/2 intervals at the even fine points); F is read at the path's state at each grid
- * time). */
+/* The source term's Simpson sums at one grid point (Algorithm 3): weight w of the point on
+ * its grid, the path's weight eta there, F at the path's state. */
+static void add_source_point(double w, double eta, double Fs, double *integ, double *imag)
+{
+    *integ += w * eta * Fs;
+    *imag += w * fabs(eta * Fs);
+}
+
+/* One sample at `level`: the single-entry representation of section 2.1 with the Strang
+ * splitting on the fine grid (step dt) and, on the same path, on the coarse grid (step 2 dt),
+ * the coupling of the level terms (section 2.2, Algorithm 2); with a source vector F, also
+ * the source integral int_0^beta exp(sA) F ds of Algorithm 3 by the composite Simpson rule on
+ * both grids (F read at the path's state at each grid time).
+ *
+ * The path. Over each fine step the chain holds at its state for an exponential time of rate
+ * r (section 3); while the time accumulated in the step stays below dt it jumps by the jump
+ * law of the row it leaves and draws the next holding time at the state it reached. Only the
+ * states at the grid points enter the weights.
+ *
+ * The weights. The Strang step e^{dt D/2} e^{-dt T} e^{dt D/2} contributes e^{dt d/2} at each
+ * end of a fine step, so the fine weight multiplies, step by step, the factors at the step's
+ * two ends; the coarse weight multiplies e^{dt d} at the two ends of each pair of fine steps.
+ * Both carry the product of the jump signs (under a proposal also the likelihood ratios p/q
+ * of the jumps taken). */
 static void orc_one_walk(const orc_tables *t, double beta, int level, const uint32_t key[2],
                          uint32_t inst, int64_t row, uint32_t walk, const double *F,
                          orc_walk_out *o)
 {
     const int64_t N = (int64_t)1 << level;
     const double dt = ldexp(beta, -level);
-    double eta2 = 1.0, eta1 = 1.0;   /* fine and coarse functionals */
-    int64_t j = row, jumps = 0;
+    int64_t s = row;                  /* the chain's state */
+    int64_t pair_start = row;         /* its state at the start of the current pair of steps */
+    int64_t jumps = 0;
     uint64_t h = ORC_FNV_OFFSET;
+    double phi = 1.0;                 /* jump signs (and likelihood ratios) so far */
+    double fine = 1.0, coarse = 1.0;  /* Strang factors on the two grids so far */
     double integ2 = 0.0, integ1 = 0.0, imag2 = 0.0, imag1 = 0.0;
     if (F) {
-        /* grid point 0: no time elapsed, both functionals are 1 */
-        integ2 += simpson_weight(0, N) * eta2 * F[j];
-        imag2 += simpson_weight(0, N) * fabs(eta2 * F[j]);
-        if (N >= 2) {
-            integ1 += simpson_weight(0, N / 2) * eta1 * F[j];
-            imag1 += simpson_weight(0, N / 2) * fabs(eta1 * F[j]);
-        }
+        /* grid point 0: no time elapsed, both weights are 1 */
+        add_source_point(simpson_weight(0, N), 1.0, F[s], &integ2, &imag2);
+        if (N >= 2) add_source_point(simpson_weight(0, N / 2), 1.0, F[s], &integ1, &imag1);
     }
     for (int64_t n = 1; n <= N; ++n) {
-        eta2 = eta2 * exp(t->d[j] * dt / 2.0);
-        if (n % 2 != 0) eta1 = eta1 * exp(t->d[j] * dt);
-        /* holding time at the current state: -ln(U) / r_j */
+        const int64_t step_start = s;
+        /* the step from grid point n - 1 to n */
         double tau = -orc_log(orc_uniform(step_word(key, level, inst, (uint32_t)row, walk,
-                                                    (uint32_t)(n - 1)))) * t->inv_r[j];
+                                                    (uint32_t)(n - 1)))) * t->inv_r[s];
         while (tau < dt) {
-            int64_t k = j;
+            const int64_t k = s;
             uint32_t w[3];
             jump_words(key, level, inst, (uint32_t)row, walk, (uint32_t)jumps, w);
-            /* next state from the jump law k_kj (alias table of row k) */
-            uint32_t dg = (uint32_t)t->deg[k];
-            uint32_t slot = (uint32_t)(((uint64_t)w[0] * (uint64_t)dg) >> 32);
-            int64_t sb = t->slot_begin[k];
+            const uint32_t slot = (uint32_t)(((uint64_t)w[0] * (uint64_t)(uint32_t)t->deg[k]) >> 32);
+            const int64_t sb = t->slot_begin[k];
             uint32_t pick;
             if (t->q_thr) {
+                /* the proposal's alias table; its likelihood ratio keeps the estimator unbiased */
                 pick = (w[1] < t->q_thr[sb + slot]) ? slot : (uint32_t)t->q_alias[sb + slot];
-                /* likelihood ratio of the proposal: keeps the estimator unbiased */
-                eta2 = eta2 * t->q_ratio[sb + pick];
-                eta1 = eta1 * t->q_ratio[sb + pick];
+                phi = phi * t->q_ratio[sb + pick];
             } else {
                 pick = (w[1] < t->slot_thr[sb + slot]) ? slot : (uint32_t)t->slot_alias[sb + slot];
             }
-            j = t->slot_col[sb + pick];
-            int neg = t->slot_sign[sb + pick];
-            /* holding time at the new state */
-            double S = -orc_log(orc_uniform(w[2])) * t->inv_r[j];
+            if (t->slot_sign[sb + pick]) phi = -phi;
+            s = t->slot_col[sb + pick];
+            double S = -orc_log(orc_uniform(w[2])) * t->inv_r[s];
             tau = tau + S;
-            if (neg) {
-                eta2 = -eta2;
-                eta1 = -eta1;
-            }
             ++jumps;
-            h = (h ^ (uint64_t)(uint32_t)j) * ORC_FNV_PRIME;
+            h = (h ^ (uint64_t)(uint32_t)s) * ORC_FNV_PRIME;
             h = (h ^ (uint64_t)n) * ORC_FNV_PRIME;
         }
-        eta2 = eta2 * exp(t->d[j] * dt / 2.0);
-        if (n % 2 == 0) eta1 = eta1 * exp(t->d[j] * dt);
+        /* the fine Strang factors at the two ends of step n */
+        fine = fine * exp(t->d[step_start] * dt / 2.0);
+        fine = fine * exp(t->d[s] * dt / 2.0);
+        const int pair_ends = (n % 2 == 0);
+        if (pair_ends) {
+            /* the coarse factors at the two ends of the pair of steps n - 1, n */
+            coarse = coarse * exp(t->d[pair_start] * dt);
+            coarse = coarse * exp(t->d[s] * dt);
+            pair_start = s;
+        }
         if (F) {
-            /* eta2 is now the fine weight of time n dt, eta1 (at even n) the coarse one */
-            integ2 += simpson_weight(n, N) * eta2 * F[j];
-            imag2 += simpson_weight(n, N) * fabs(eta2 * F[j]);
-            if (n % 2 == 0) {
-                integ1 += simpson_weight(n / 2, N / 2) * eta1 * F[j];
-                imag1 += simpson_weight(n / 2, N / 2) * fabs(eta1 * F[j]);
-            }
+            add_source_point(simpson_weight(n, N), phi * fine, F[s], &integ2, &imag2);
+            if (pair_ends) add_source_point(simpson_weight(n / 2, N / 2), phi * coarse, F[s], &integ1, &imag1);
         }
     }
-    o->final_state = j;
-    o->sign = (eta2 < 0.0) ? -1 : 1;
+    o->final_state = s;
+    o->sign = (phi < 0.0) ? -1 : 1;
     o->jumps = jumps;
     o->hash = h;
-    o->eta_fine = eta2;
-    o->eta_coarse = eta1;
+    o->eta_fine = phi * fine;
+    o->eta_coarse = phi * coarse;
     o->integ_fine = dt / 3.0 * integ2;
     o->integ_coarse = 2.0 * dt / 3.0 * integ1;
     o->integ_mag = dt / 3.0 * imag2 + 2.0 * dt / 3.0 * imag1;

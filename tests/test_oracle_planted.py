@@ -64,21 +64,17 @@ PLANTS = [
      [PINS + "test_alias_tables_reproduce_the_jump_law"]),
     # Algorithm 2
     ("holding time at the old state's rate", C,
-     [("double S = -orc_log(orc_uniform(w[2])) * t->inv_r[j];",
+     [("double S = -orc_log(orc_uniform(w[2])) * t->inv_r[s];",
        "double S = -orc_log(orc_uniform(w[2])) * t->inv_r[k];")],
      [PINS + "test_one_step_law_matches_the_ctmc_transition_matrix", LEVEL_MEANS]),
     ("coarse functional keeps its sign at a negative jump", C,
-     [("                eta1 = -eta1;\n", "")],
+     [("o->eta_coarse = phi * coarse;", "o->eta_coarse = coarse;")],
      [LEVEL_MEANS]),
     ("coarse half steps on the wrong parity", C,
-     [("if (n % 2 != 0) eta1 = eta1 * exp(t->d[j] * dt);",
-       "if (n % 2 == 0) eta1 = eta1 * exp(t->d[j] * dt);"),
-      ("        if (n % 2 == 0) eta1 = eta1 * exp(t->d[j] * dt);\n        if (F) {",
-       "        if (n % 2 != 0) eta1 = eta1 * exp(t->d[j] * dt);\n        if (F) {")],
+     [("const int pair_ends = (n % 2 == 0);", "const int pair_ends = (n % 2 != 0);")],
      [LEVEL_MEANS]),
     ("fine functional loses its closing half step", C,
-     [("        eta2 = eta2 * exp(t->d[j] * dt / 2.0);\n        if (n % 2 == 0) eta1",
-       "        if (n % 2 == 0) eta1")],
+     [("        fine = fine * exp(t->d[s] * dt / 2.0);\n", "")],
      [LEVEL_MEANS, PINS + "test_diagonal_matrix_is_exact"]),
     ("time step beta / 2N", C,
      [("const double dt = ldexp(beta, -level);", "const double dt = ldexp(beta, -level - 1);")],
@@ -88,20 +84,21 @@ PLANTS = [
      [LEVEL_MEANS]),
     # Algorithm 3 (section 5)
     ("source term read at the start row", C,
-     [("integ2 += simpson_weight(n, N) * eta2 * F[j];", "integ2 += simpson_weight(n, N) * eta2 * F[row];")],
+     [("add_source_point(simpson_weight(n, N), phi * fine, F[s], &integ2, &imag2);",
+       "add_source_point(simpson_weight(n, N), phi * fine, F[row], &integ2, &imag2);")],
      [SOURCE]),
     ("coarse source sum with fine weights", C,
-     [("integ1 += simpson_weight(n / 2, N / 2) * eta1 * F[j];",
-       "integ1 += simpson_weight(n, N) * eta1 * F[j] / 2.0;")],
+     [("add_source_point(simpson_weight(n / 2, N / 2), phi * coarse,",
+       "add_source_point(simpson_weight(n, N) / 2.0, phi * coarse,")],
      [SOURCE]),
     ("source sum without grid point 0", C,
-     [("integ2 += simpson_weight(0, N) * eta2 * F[j];", "")],
+     [("add_source_point(simpson_weight(0, N), 1.0, F[s], &integ2, &imag2);", "")],
      [SOURCE]),
     ("Simpson factor 1/2 for 1/3", C,
      [("o->integ_fine = dt / 3.0 * integ2;", "o->integ_fine = dt / 2.0 * integ2;")],
      [SOURCE]),
     ("coarse source terms at odd points too", C,
-     [("            if (n % 2 == 0) {\n                integ1", "            if (1) {\n                integ1")],
+     [("if (pair_ends) add_source_point(simpson_weight(n / 2", "if (1) add_source_point(simpson_weight(n / 2")],
      [SOURCE]),
     # the forward representation as a scalar functional
     ("start sign dropped", C,
