@@ -62,7 +62,9 @@ constexpr size_t kSegSetU64 = static_cast<size_t>(kSegSlots) * kCounterStride;
 struct InstanceOut {
     double *x;
     uint64_t pair_begin;              // first global (row, rhs) pair of the instance
-    int32_t seg0, levels;
+    int32_t seg0, levels;             // its coarsest level's segment, and its levels
+    int32_t seg_stride;               // segments between two of its levels
+    int32_t pad;
 };
 
 struct BatchParams {
@@ -70,8 +72,10 @@ struct BatchParams {
     uint32_t k0, k1;                  // Philox key of the current launch
 };
 
-// Items [item_lo, item_hi) of the batch (one phase of the launch sequence).
-template <typename R, typename U, bool kMulti>
+// Items [item_lo, item_hi) of the batch (one phase of the launch sequence). kBase: every item
+// of the range is at its instance's coarsest level (the segments are ordered level by level),
+// so the walks are compiled for it (fine functional only, each sample taken as its walk ends).
+template <typename R, typename U, bool kMulti, bool kBase>
 __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       BatchParams *prm)
@@ -104,14 +108,14 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) vo
         const uint64_t local = item - sg.item_begin;
         const uint32_t q = static_cast<uint32_t>(local / sg.chunks);
         const uint32_t c = static_cast<uint32_t>(local % sg.chunks);
-        const uint32_t row = sg.rows ? static_cast<uint32_t>(sg.rows[q]) : q;
+        const uint32_t row = __builtin_amdgcn_readfirstlane(sg.rows ? static_cast<uint32_t>(sg.rows[q]) : q);
         const uint64_t wb = static_cast<uint64_t>(c) * sg.chunk;
         const uint64_t we = min(wb + sg.chunk, static_cast<uint64_t>(sg.M));
         const U *u = static_cast<const U *>(sg.u);
         unsigned long long jumps, nonfinite;
         if (!kMulti) {
             SinkR1<R, U> sink{u};
-            walk_range<R, false, false>(L, row, 0u, wb, we, sink);
+            walk_range<R, false, false, false, kBase>(L, row, 0u, wb, we, sink);
             const double a = wave_sum(sink.s1.value());
             const double b = wave_sum(sink.s2.value());
             jumps = wave_sum_u(sink.jumps);
@@ -225,7 +229,7 @@ __global__ void batch_combine(const Segment *__restrict__ segs, const InstanceOu
     const uint64_t local = t - o.pair_begin;
     double v = 0.0;
     for (int q = 0; q < o.levels; ++q) {
-        const Segment &sg = segs[o.seg0 + q];
+        const Segment &sg = segs[o.seg0 + q * o.seg_stride];
         v += sg.acc[local] * sg.inv_M;
     }
     o.x[local] = v;
@@ -269,6 +273,7 @@ struct mlmc_batch {
     double *d_moments = nullptr;
     double *d_moment_scratch = nullptr;
     uint64_t total_items = 0, total_pairs = 0, total_out_pairs = 0;
+    uint64_t base_items = 0;          // items of the coarsest levels: [0, base_items)
     int32_t phases = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -321,23 +326,34 @@ int balloc(mlmc_batch *b, T **ptr, size_t count)
 
 // Segment tables for a shape and sample sizes (walks[b * levels + q]) of every instance, or of
 // every stride-th one; device buffers are laid out by the caller through the offsets returned
-// in the segments.
+// in the segments. The segments are ordered level by level (every instance's coarsest level
+// first, then every instance's next level, ...), so the items of the coarsest levels form the
+// range [0, base_items) and run in a kernel compiled for them.
 void layout(const mlmc_batch *b, const Shape &sh, const std::vector<int64_t> &walks,
             std::vector<Segment> &segs, std::vector<InstanceOut> &outs, uint64_t &items,
-            uint64_t &pairs, uint64_t &out_pairs, uint64_t &partial_doubles, int stride = 1)
+            uint64_t &pairs, uint64_t &out_pairs, uint64_t &partial_doubles, uint64_t &base_items,
+            int stride = 1)
 {
     segs.clear();
     outs.clear();
-    items = pairs = out_pairs = partial_doubles = 0;
-    for (int i = 0; i < b->count; i += stride) {
-        mlmc_plan *p = b->plans[i];
+    items = pairs = out_pairs = partial_doubles = base_items = 0;
+    std::vector<int> inst;
+    for (int i = 0; i < b->count; i += stride) inst.push_back(i);
+    const int32_t n_inst = static_cast<int32_t>(inst.size());
+    for (int32_t k = 0; k < n_inst; ++k) {
+        const int i = inst[static_cast<size_t>(k)];
         InstanceOut o{};
         o.pair_begin = out_pairs;
-        o.seg0 = static_cast<int32_t>(segs.size());
+        o.seg0 = k;
         o.levels = b->levels;
-        out_pairs += static_cast<uint64_t>(p->n_rows) * b->nrhs[i];
+        o.seg_stride = n_inst;
+        out_pairs += static_cast<uint64_t>(b->plans[i]->n_rows) * b->nrhs[i];
         outs.push_back(o);
-        for (int q = 0; q < b->levels; ++q) {
+    }
+    for (int q = 0; q < b->levels; ++q) {
+        if (q == 1) base_items = items;
+        for (int i : inst) {
+            mlmc_plan *p = b->plans[i];
             Segment sg{};
             const int level = p->l0 + q;
             sg.L = level_args(p, level, 0, i);
@@ -360,17 +376,24 @@ void layout(const mlmc_batch *b, const Shape &sh, const std::vector<int64_t> &wa
             segs.push_back(sg);
         }
     }
+    if (b->levels == 1) base_items = items;
 }
 
 hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
-                        uint64_t item_lo, uint64_t item_hi, hipStream_t s)
+                        uint64_t item_lo, uint64_t item_hi, bool base, hipStream_t s)
 {
     const dim3 grid(static_cast<uint32_t>(kCUs * sh.waves_per_cu / kWavesPerBlock));
     if (grid.x % kXcds != 0) return hipErrorInvalidConfiguration;
     const dim3 block(kBlock);
-#define MLMC_BATCH(R, U, MULTI)                                                               \
-    hipLaunchKernelGGL((batch_walks<R, U, MULTI>), grid, block, 0, s, d_segs, nseg, item_lo, item_hi, \
-                       b->d_prm)
+#define MLMC_BATCH(R, U, MULTI)                                                                        \
+    do {                                                                                               \
+        if (!(MULTI) && base)                                                                          \
+            hipLaunchKernelGGL((batch_walks<R, U, MULTI, true>), grid, block, 0, s, d_segs, nseg,      \
+                               item_lo, item_hi, b->d_prm);                                            \
+        else                                                                                           \
+            hipLaunchKernelGGL((batch_walks<R, U, MULTI, false>), grid, block, 0, s, d_segs, nseg,     \
+                               item_lo, item_hi, b->d_prm);                                            \
+    } while (0)
     if (b->precision == MLMC_PRECISION_FP64) {
         if (b->u_f64) {
             if (b->multi) MLMC_BATCH(double, double, true); else MLMC_BATCH(double, double, false);
@@ -392,16 +415,21 @@ hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_s
 // items. Within a launch the waves drift apart (their items differ in cost) and the chip
 // ends up working on many instances at once, whose tables then compete for the L2; the end
 // of each launch brings the waves back together. On the 512-instance batch this halves the
-// L2 misses of one long launch.
+// L2 misses of one long launch. The phases of the coarsest levels' items [0, base_items) use
+// the kernel compiled for the coarsest level.
 hipError_t launch_phases(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
-                         uint64_t total_items, hipStream_t s, int32_t *phases)
+                         uint64_t total_items, uint64_t base_items, hipStream_t s, int32_t *phases)
 {
     const uint64_t per_phase = static_cast<uint64_t>(kCUs) * sh.waves_per_cu * kItemsPerWavePhase;
     *phases = 0;
-    for (uint64_t lo = 0; lo < total_items; lo += per_phase) {
-        const hipError_t e = launch_walks(b, sh, d_segs, nseg, lo, std::min(total_items, lo + per_phase), s);
-        if (e != hipSuccess) return e;
-        ++*phases;
+    for (int part = 0; part < 2; ++part) {
+        const uint64_t begin = part == 0 ? 0 : base_items, end = part == 0 ? base_items : total_items;
+        for (uint64_t lo = begin; lo < end; lo += per_phase) {
+            const hipError_t e = launch_walks(b, sh, d_segs, nseg, lo, std::min(end, lo + per_phase),
+                                              part == 0, s);
+            if (e != hipSuccess) return e;
+            ++*phases;
+        }
     }
     return hipSuccess;
 }
@@ -411,7 +439,7 @@ int build_tables(mlmc_batch *b, hipStream_t s)
 {
     uint64_t partial_doubles = 0;
     layout(b, b->shape, b->walks, b->h_segs, b->h_outs, b->total_items, b->total_pairs,
-           b->total_out_pairs, partial_doubles);
+           b->total_out_pairs, partial_doubles, b->base_items);
     int rc;
     if ((rc = balloc(b, &b->d_partial, partial_doubles))) return rc;
     if ((rc = balloc(b, &b->d_acc, 2 * b->total_pairs))) return rc;
@@ -502,8 +530,8 @@ int autotune(mlmc_batch *b, hipStream_t s)
     for (size_t ci = 0; ci < cands.size() && rc == MLMC_OK; ++ci) {
         std::vector<Segment> segs;
         std::vector<InstanceOut> outs;
-        uint64_t items, pairs, opairs, pdoubles;
-        layout(b, cands[ci], b->walks, segs, outs, items, pairs, opairs, pdoubles, stride);
+        uint64_t items, pairs, opairs, pdoubles, base;
+        layout(b, cands[ci], b->walks, segs, outs, items, pairs, opairs, pdoubles, base, stride);
         double *part = nullptr;
         unsigned long long *ctr = nullptr;
         Segment *dseg = nullptr;
@@ -529,8 +557,8 @@ int autotune(mlmc_batch *b, hipStream_t s)
                 hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, 0x5EEDu, rep + 1u);
                 hipEventRecord(e0, s);
                 int32_t phases = 0;
-                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, s, &phases) !=
-                    hipSuccess)
+                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, base, s,
+                                  &phases) != hipSuccess)
                     rc = fail(MLMC_ERR_HIP, "autotune launch");
                 hipEventRecord(e1, s);
                 if (hipEventSynchronize(e1) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune sync");
@@ -624,8 +652,8 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     const int32_t nseg = static_cast<int32_t>(b->h_segs.size());
     hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * nseg, 256)), dim3(256), 0, b->cap_stream,
                        b->d_prm, b->d_counters, static_cast<int32_t>(kSegSetU64 * nseg));
-    hipError_t le = launch_phases(b, b->shape, b->d_segs, nseg, b->total_items, b->cap_stream,
-                                  &b->phases);
+    hipError_t le = launch_phases(b, b->shape, b->d_segs, nseg, b->total_items, b->base_items,
+                                  b->cap_stream, &b->phases);
     if (b->total_pairs)
         hipLaunchKernelGGL(batch_finalize, dim3(blocks_of(b->total_pairs, 256)), dim3(256), 0,
                            b->cap_stream, b->d_segs, nseg, b->total_pairs);
@@ -688,7 +716,7 @@ int mlmc_expv_batch_stats(mlmc_batch_t *b, mlmc_stats_t *per_instance, void *str
         st.converged = 1;
         double var = 0.0;
         for (int q = 0; q < b->levels; ++q) {
-            const size_t g = static_cast<size_t>(i) * b->levels + q;
+            const size_t g = static_cast<size_t>(q) * b->count + i;   // segments level by level
             const Segment &sg = b->h_segs[g];
             const double cnt = std::max<double>(1.0, static_cast<double>(sg.n_rows) * sg.nrhs);
             st.walks[q] = sg.M;
