@@ -18,8 +18,8 @@
  *
  * All entry points return an int status (MLMC_OK = 0). On failure a thread-local detail
  * string is available from mlmc_last_error(). Nothing here allocates on behalf of the
- * caller: A and the plan options are read (host memory) and copied, u and x are caller
- * owned device buffers. A plan owns its device tables until mlmc_expv_destroy.
+ * caller: A (host or device memory) and the plan options are read and copied, u and x are
+ * caller owned device buffers. A plan owns its device tables until mlmc_expv_destroy.
  *
  * Streams: every call that takes `stream` (a hipStream_t, or NULL for the default
  * stream) orders its device work on that stream. Fixed-schedule runs are asynchronous
@@ -32,7 +32,11 @@
  * stream 0 gives the per-step holding-time tests (step n reads word n%4 of block n/4),
  * stream 1 the jumps (the walk's j-th jump reads block j: slot, alias coin, next holding
  * time). Results are therefore a pure function of (A, u, beta, levels, walks, seed,
- * instance), independent of launch shape and of how walk ranges are split.
+ * instance), independent of launch shape and of how walk ranges are split. Every reduction
+ * (per-lane compensated sums, wave and chunk sums, the level combine) runs in a fixed order
+ * and the counters are integers, so results are bitwise reproducible from run to run: there
+ * is no faster non-deterministic mode to select. The paths themselves are returned by
+ * mlmc_expv_trace.
  */
 #ifndef MLMC_EXPV_H
 #define MLMC_EXPV_H
@@ -55,6 +59,10 @@ extern "C" {
 #define MLMC_ERR_NOT_CONVERGED 6   /* Algorithm 1 hit its level or walk cap before reaching
                                       eps; the best estimate is still written               */
 #define MLMC_ERR_UNSUPPORTED 7     /* a valid request this build does not serve             */
+#define MLMC_ERR_RNG_OVERFLOW 8    /* a Philox counter word would wrap: a walk index reaches
+                                      2^32, or a walk's expected number of jumps
+                                      (beta * max_i r_i) reaches 2^31 (its jump index is a
+                                      32-bit counter word)                                  */
 
 /* ---- element types and precision --------------------------------------------------- */
 #define MLMC_DTYPE_F32 0
@@ -71,15 +79,24 @@ extern "C" {
 
 typedef struct mlmc_plan mlmc_plan_t;
 
-/* A general sparse matrix in CSR form, in HOST memory. Columns within a row need not be
+/* Where the arrays of a matrix live. */
+#define MLMC_MEMORY_HOST 0
+#define MLMC_MEMORY_DEVICE 1
+
+/* A general sparse matrix in CSR form, in host memory or in device memory of the current
+ * device (`memory`; a zero-initialised struct means host). Columns within a row need not be
  * sorted but must not repeat. A missing diagonal entry means a_ii = 0; explicit zeros
- * are ignored. n < 2^31, number of off-diagonal nonzeros < 2^32. */
+ * are ignored. n < 2^31, number of off-diagonal nonzeros < 2^32. The plan reads the arrays
+ * once, while it is built (device arrays are copied to the host on the plan's stream, which
+ * the call waits for: the plan is built on the host, section 2.1's split and the alias
+ * tables), and keeps no pointer to them. */
 typedef struct {
     int64_t n;
     const int64_t *row_ptr;   /* n + 1 entries, row_ptr[0] = 0 */
     const int32_t *col_idx;   /* row_ptr[n] entries */
     const void *values;       /* row_ptr[n] entries of values_dtype */
     int32_t values_dtype;     /* MLMC_DTYPE_F32 or MLMC_DTYPE_F64 */
+    int32_t memory;           /* MLMC_MEMORY_HOST or MLMC_MEMORY_DEVICE */
 } mlmc_csr_t;
 
 /* Options fixed when a plan is built. */
@@ -146,7 +163,9 @@ typedef struct {
 /* Build a plan: validate A, split A = D - T, build the alias tables of the jump law and
  * the per-level step thresholds, and upload them. `stream` orders the uploads.
  * Returns INVALID_ARG for beta <= 0 or a coarsest level so coarse that some row would
- * jump in every step with certainty at 32-bit resolution (r_i dt_l0 > 22). */
+ * jump in every step with certainty at 32-bit resolution (r_i dt_l0 > 22), INVALID_MATRIX
+ * for a malformed CSR, HIP_ERROR if device arrays cannot be read, and RNG_OVERFLOW when
+ * beta * max_i r_i >= 2^31. */
 int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_t *opts,
                    void *stream);
 

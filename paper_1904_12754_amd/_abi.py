@@ -19,6 +19,10 @@ MLMC_ERR_HIP = 4
 MLMC_ERR_NONFINITE = 5
 MLMC_ERR_NOT_CONVERGED = 6
 MLMC_ERR_UNSUPPORTED = 7
+MLMC_ERR_RNG_OVERFLOW = 8
+
+MLMC_MEMORY_HOST = 0
+MLMC_MEMORY_DEVICE = 1
 
 MLMC_DTYPE_F32 = 0
 MLMC_DTYPE_F64 = 1
@@ -47,7 +51,8 @@ class CSR(ctypes.Structure):
                 ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
                 ("col_idx", ctypes.POINTER(ctypes.c_int32)),
                 ("values", ctypes.c_void_p),
-                ("values_dtype", ctypes.c_int32)]
+                ("values_dtype", ctypes.c_int32),
+                ("memory", ctypes.c_int32)]
 
 
 class PlanOpts(ctypes.Structure):

@@ -38,7 +38,8 @@ def _u_args(u: torch.Tensor, n: int):
 class Plan:
     """A prepared matrix: A = D - T split, alias tables and step thresholds in HBM.
 
-    A: an object with n, row_ptr, col_idx, values (numpy arrays, host).
+    A: an object with n, row_ptr, col_idx, values: numpy arrays (host), or device tensors
+       (int64 row_ptr, int32 col_idx, float32 or float64 values; values_dtype is then ignored).
     precision: "fp32" (FP32 path weights, compensated FP32 sums, FP64 combine) or "fp64".
     """
 
@@ -47,13 +48,29 @@ class Plan:
         self._lib = _abi.load()
         self._handle = ctypes.c_void_p()
         self.n = int(A.n)
-        self._row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
-        self._col_idx = np.ascontiguousarray(A.col_idx, dtype=np.int32)
-        self._values = np.ascontiguousarray(A.values, dtype=values_dtype)
-        csr = _abi.CSR(self.n, self._row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                       self._col_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                       ctypes.c_void_p(self._values.ctypes.data),
-                       _abi.MLMC_DTYPE_F64 if self._values.dtype == np.float64 else _abi.MLMC_DTYPE_F32)
+        if isinstance(A.row_ptr, torch.Tensor) and A.row_ptr.is_cuda:
+            self._row_ptr = A.row_ptr.contiguous()
+            self._col_idx = A.col_idx.contiguous()
+            self._values = A.values.contiguous()
+            if (self._row_ptr.dtype != torch.int64 or self._col_idx.dtype != torch.int32 or
+                    self._values.dtype not in (torch.float32, torch.float64) or
+                    not (self._col_idx.is_cuda and self._values.is_cuda)):
+                raise ValueError("device CSR: int64 row_ptr, int32 col_idx, float32/float64 "
+                                 "values, all on the device")
+            csr = _abi.CSR(self.n, ctypes.cast(_dev_ptr(self._row_ptr), ctypes.POINTER(ctypes.c_int64)),
+                           ctypes.cast(_dev_ptr(self._col_idx), ctypes.POINTER(ctypes.c_int32)),
+                           _dev_ptr(self._values),
+                           _abi.MLMC_DTYPE_F64 if self._values.dtype == torch.float64
+                           else _abi.MLMC_DTYPE_F32, _abi.MLMC_MEMORY_DEVICE)
+        else:
+            self._row_ptr = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+            self._col_idx = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+            self._values = np.ascontiguousarray(A.values, dtype=values_dtype)
+            csr = _abi.CSR(self.n, self._row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                           self._col_idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           ctypes.c_void_p(self._values.ctypes.data),
+                           _abi.MLMC_DTYPE_F64 if self._values.dtype == np.float64
+                           else _abi.MLMC_DTYPE_F32, _abi.MLMC_MEMORY_HOST)
         prec = {"fp64": _abi.MLMC_PRECISION_FP64, "fp32": _abi.MLMC_PRECISION_FP32}[precision]
         self._rows = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
         opts = _abi.PlanOpts(float(beta), prec, -1 if l0 is None else int(l0),

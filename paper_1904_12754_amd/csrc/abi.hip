@@ -222,7 +222,7 @@ int level_sums(mlmc_plan *p, int level, uint64_t seed, int instance, const void 
         return MLMC_OK;
     }
     if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
-        return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
+        return fail(MLMC_ERR_RNG_OVERFLOW, "walk indices must stay below 2^32 (the walk word of the Philox counter)");
     int rc;
     if (fixed) {
         if (!p->level_rec[level])
@@ -326,11 +326,58 @@ const char *mlmc_status_string(int status)
     case MLMC_ERR_NONFINITE: return "non-finite samples";
     case MLMC_ERR_NOT_CONVERGED: return "not converged";
     case MLMC_ERR_UNSUPPORTED: return "unsupported";
+    case MLMC_ERR_RNG_OVERFLOW: return "random-number counter overflow";
     default: return "unknown status";
     }
 }
 
 const char *mlmc_last_error(void) { return g_last_error.c_str(); }
+
+// A matrix whose arrays are in device memory, copied to the host (the plan is built there).
+struct HostCopy {
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col_idx;
+    std::vector<double> values;     // FP64 values
+    std::vector<float> values32;    // FP32 values (value_at widens them)
+    mlmc_csr_t csr{};
+};
+
+int copy_to_host(const mlmc_csr_t *A, HostCopy &h, hipStream_t s)
+{
+    const int64_t n = A->n;
+    try {
+        h.row_ptr.resize(static_cast<size_t>(n) + 1);
+        MLMC_HIP_TRY(hipMemcpyAsync(h.row_ptr.data(), A->row_ptr, sizeof(int64_t) * (n + 1),
+                                    hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+        const int64_t nnz = h.row_ptr[n];
+        if (h.row_ptr[0] != 0) return fail(MLMC_ERR_INVALID_MATRIX, "row_ptr[0] != 0");
+        if (nnz < 0 || nnz >= (int64_t(1) << 40)) return fail(MLMC_ERR_INVALID_MATRIX, "row_ptr[n] out of range");
+        h.col_idx.resize(static_cast<size_t>(nnz));
+        if (A->values_dtype == MLMC_DTYPE_F64) h.values.resize(static_cast<size_t>(nnz));
+        else h.values32.resize(static_cast<size_t>(nnz));
+    } catch (const std::bad_alloc &) {
+        return fail(MLMC_ERR_OUT_OF_MEMORY, "host copy of the matrix");
+    }
+    const size_t nnz = h.col_idx.size();
+    if (nnz) {
+        if (!A->values) return fail(MLMC_ERR_INVALID_ARG, "null values");
+        MLMC_HIP_TRY(hipMemcpyAsync(h.col_idx.data(), A->col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+        if (A->values_dtype == MLMC_DTYPE_F64)
+            MLMC_HIP_TRY(hipMemcpyAsync(h.values.data(), A->values, sizeof(double) * nnz, hipMemcpyDeviceToHost, s));
+        else
+            MLMC_HIP_TRY(hipMemcpyAsync(h.values32.data(), A->values, sizeof(float) * nnz, hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipStreamSynchronize(s));
+    }
+    h.csr.n = n;
+    h.csr.row_ptr = h.row_ptr.data();
+    h.csr.col_idx = h.col_idx.data();
+    h.csr.values = A->values_dtype == MLMC_DTYPE_F64 ? static_cast<const void *>(h.values.data())
+                                                     : static_cast<const void *>(h.values32.data());
+    h.csr.values_dtype = A->values_dtype;
+    h.csr.memory = MLMC_MEMORY_HOST;
+    return MLMC_OK;
+}
 
 int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_t *o, void *stream)
 {
@@ -342,6 +389,14 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     if (n > 0 && (!A->row_ptr || !A->col_idx)) return fail(MLMC_ERR_INVALID_ARG, "null CSR array");
     if (A->values_dtype != MLMC_DTYPE_F32 && A->values_dtype != MLMC_DTYPE_F64)
         return fail(MLMC_ERR_INVALID_ARG, "values_dtype must be MLMC_DTYPE_F32 or MLMC_DTYPE_F64");
+    if (A->memory != MLMC_MEMORY_HOST && A->memory != MLMC_MEMORY_DEVICE)
+        return fail(MLMC_ERR_INVALID_ARG, "memory must be MLMC_MEMORY_HOST or MLMC_MEMORY_DEVICE");
+    HostCopy host;
+    if (A->memory == MLMC_MEMORY_DEVICE && n > 0) {
+        const int rc = copy_to_host(A, host, s);
+        if (rc) return rc;
+        A = &host.csr;
+    }
     if (!(o->beta > 0.0) || !std::isfinite(o->beta)) return fail(MLMC_ERR_INVALID_ARG, "beta must be finite and > 0");
     if (o->precision != MLMC_PRECISION_FP64 && o->precision != MLMC_PRECISION_FP32)
         return fail(MLMC_ERR_INVALID_ARG, "precision must be MLMC_PRECISION_FP64 or MLMC_PRECISION_FP32");
@@ -436,6 +491,10 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
         }
     }
     if (l0 > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "coarsest level from the l0 rule exceeds 28");
+    // a walk takes beta r jumps on average, the j-th reading Philox block j of its jump stream
+    if (o->beta * r_max >= 2147483648.0)
+        return fail(MLMC_ERR_RNG_OVERFLOW, "beta * max_i r_i >= 2^31: a walk's jump index (a 32-bit counter "
+                                           "word) could wrap");
     // ---- upload
     auto *p = new (std::nothrow) mlmc_plan;
     if (!p) return fail(MLMC_ERR_OUT_OF_MEMORY, "host allocation");

@@ -255,7 +255,7 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     out = LevelOut{};
     if (M == 0 || p->n == 0 || fc.U == 0.0) return MLMC_OK;
     if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
-        return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
+        return fail(MLMC_ERR_RNG_OVERFLOW, "walk indices must stay below 2^32 (the walk word of the Philox counter)");
     int rc = upload_level(p, lev, s);
     if (rc) return rc;
     LevelArgs L = level_args(p, lev, seed, instance);
@@ -322,7 +322,7 @@ int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, i
     }
     if (M == 0 || fc.U == 0.0) return MLMC_OK;
     if (static_cast<uint64_t>(walk0) + M > 0x100000000ull)
-        return fail(MLMC_ERR_INVALID_ARG, "walk indices must stay below 2^32");
+        return fail(MLMC_ERR_RNG_OVERFLOW, "walk indices must stay below 2^32 (the walk word of the Philox counter)");
     int rc = upload_level(p, lev, s);
     if (rc) return rc;
     LevelArgs L = level_args(p, lev, seed, instance);

@@ -40,13 +40,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = _lib()
-    for code in range(8):
+    for code in range(9):
         assert lib.mlmc_status_string(code).decode() != "unknown status"
     assert lib.mlmc_status_string(99).decode() == "unknown status"
 
 
 def _plan_status(A, beta=1.0, precision=_abi.MLMC_PRECISION_FP32, l0=-1, rows=None,
-                 values_dtype=np.float64):
+                 values_dtype=np.float64, memory=_abi.MLMC_MEMORY_HOST):
     lib = _lib()
     rp = np.ascontiguousarray(A.row_ptr, np.int64)
     ci = np.ascontiguousarray(A.col_idx, np.int32)
@@ -54,7 +54,8 @@ def _plan_status(A, beta=1.0, precision=_abi.MLMC_PRECISION_FP32, l0=-1, rows=No
     csr = _abi.CSR(A.n, rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                    ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                    ctypes.c_void_p(va.ctypes.data),
-                   _abi.MLMC_DTYPE_F64 if values_dtype == np.float64 else _abi.MLMC_DTYPE_F32)
+                   _abi.MLMC_DTYPE_F64 if values_dtype == np.float64 else _abi.MLMC_DTYPE_F32,
+                   memory)
     rr = None if rows is None else np.ascontiguousarray(rows, np.int64)
     opts = _abi.PlanOpts(beta, precision, l0,
                          None if rr is None else rr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
@@ -73,8 +74,21 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert _plan_status(A, l0=99)[0] == _abi.MLMC_ERR_INVALID_ARG
     # the l0 rule with 2 beta r_max beyond the double range: refused, not a wrapped level
     assert _plan_status(A, beta=1e308)[0] == _abi.MLMC_ERR_INVALID_ARG
+    assert _plan_status(A, memory=2)[0] == _abi.MLMC_ERR_INVALID_ARG
     lib = _lib()
     assert lib.mlmc_expv_plan(None, None, None, None) == _abi.MLMC_ERR_INVALID_ARG
+
+
+def test_jump_counter_overflow_is_refused_on_the_host():
+    """A walk's j-th jump reads Philox block j of its jump stream (a 32-bit counter word):
+    a plan whose walks take beta * max r >= 2^31 jumps on average is refused before anything
+    is uploaded; just below that it passes the host checks."""
+    A = inputs.laplacian_1d(10)          # r = 2 / h^2 = 242 on interior rows
+    code, msg = _plan_status(A, beta=2.0 ** 31 / 242, l0=28)      # r dt_28 = 8: otherwise valid
+    assert code == _abi.MLMC_ERR_RNG_OVERFLOW, msg
+    assert "2^31" in msg
+    code, msg = _plan_status(A, beta=2.0 ** 31 / 242 * 0.999, l0=28)
+    assert code != _abi.MLMC_ERR_RNG_OVERFLOW, msg
 
 
 def test_invalid_matrices_are_rejected_on_the_host():
