@@ -113,6 +113,10 @@ def parse():
                          "--walks per row), for counter runs; copy: a plain device copy of "
                          "--bytes, the calibration for the traffic counters; probe: the "
                          "machine probes alone")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="batch, tc and learned modes under a counter profiler: only the "
+                         "workload itself (no one-run-per-instance comparison, no small-"
+                         "instance batch, no machine probes, no CPU reference)")
     ap.add_argument("--level", type=int, default=0)
     ap.add_argument("--walks", type=int, default=65536)
     ap.add_argument("--bytes", type=int, default=1 << 30)
@@ -220,10 +224,15 @@ def kernel_only(args):
     plan.close()
 
 
-def _batch_vs_runs(insts, steps, keep_x=False):
+def _progress(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _batch_vs_runs(insts, steps, keep_x=False, compare=True):
     """Times one graph replay of the batch of `insts` (four levels from each instance's l0,
-    64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32 weights) and the same work as
-    one fixed-schedule run per instance. keep_x: also return the batch's estimates (host)."""
+    64 * 2^(1.5 (3 - q)) walks per row at level l0 + q, FP32 weights) and, with compare, the
+    same work as one fixed-schedule run per instance. keep_x: also return the batch's
+    estimates (host)."""
     import numpy as np
     import torch
 
@@ -233,12 +242,14 @@ def _batch_vs_runs(insts, steps, keep_x=False):
     plans = [api.Plan(A, t, precision="fp32") for A, t, v in insts]
     us = [torch.as_tensor(v.astype(np.float32), device="cuda") for A, t, v in insts]
     t_plan = time.perf_counter() - t0
+    _progress(f"batch of {len(insts)}: plans built in {t_plan:.1f} s")
     walks = np.array([[int(round(64 * 2 ** (1.5 * (3 - q)))) for q in range(4)]
                       for _ in insts], dtype=np.int64)
     t0 = time.perf_counter()
     batch = api.Batch(plans, us, walks, autotune=True)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
+    _progress(f"batch of {len(insts)}: created and tuned in {t_create:.1f} s")
     batch.launch(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -246,24 +257,29 @@ def _batch_vs_runs(insts, steps, keep_x=False):
         batch.launch(100 + k)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
+    _progress(f"batch of {len(insts)}: {steps} replays, {el * 1e3:.1f} ms each")
     st = batch.stats()
     total_steps = sum(x["steps"] for x in st)
     jumps = sum(x["total_jumps"] for x in st)
     xs = [x.cpu().numpy()[:, 0] for x in batch.xs] if keep_x else None
-    # the same work, one fixed-schedule run per instance
-    for b, p in enumerate(plans[:8]):
-        p.run(us[b], walks=walks[b], seed=99, instance=b, want_stats=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for b, p in enumerate(plans):
-        p.run(us[b], walks=walks[b], seed=100, instance=b, want_stats=False)
-    torch.cuda.synchronize()
-    el_seq = time.perf_counter() - t0
+    el_seq = None
+    if compare:
+        # the same work, one fixed-schedule run per instance
+        for b, p in enumerate(plans[:8]):
+            p.run(us[b], walks=walks[b], seed=99, instance=b, want_stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b, p in enumerate(plans):
+            p.run(us[b], walks=walks[b], seed=100, instance=b, want_stats=False)
+        torch.cuda.synchronize()
+        el_seq = time.perf_counter() - t0
+        _progress(f"batch of {len(insts)}: one run per instance, {el_seq * 1e3:.1f} ms")
     rows = int(sum(A.n for A, _, _ in insts))
     out = {"steps_per_s": total_steps / el, "ms_per_launch": el * 1e3,
            "steps_per_launch": total_steps, "jumps_per_launch": jumps,
            "graph_ms": st[0]["kernel_ms"],
-           "one_run_per_instance_ms": el_seq * 1e3, "speedup_vs_one_run_per_instance": el_seq / el,
+           "one_run_per_instance_ms": None if el_seq is None else el_seq * 1e3,
+           "speedup_vs_one_run_per_instance": None if el_seq is None else el_seq / el,
            "rows_total": rows,
            "walks_per_row_per_level": walks[0].tolist(), "batch": batch.info,
            "host_s": {"plans": t_plan, "create_with_autotune": t_create},
@@ -291,7 +307,7 @@ def batch_part(args, probes=None, small=False):
     t0 = time.perf_counter()
     insts = inputs.workload_uneven_batch(args.instances)
     t_gen = time.perf_counter() - t0
-    big, xs = _batch_vs_runs(insts, args.steps, keep_x=True)
+    big, xs = _batch_vs_runs(insts, args.steps, keep_x=True, compare=not args.profile_run)
     big["host_s"]["generate"] = t_gen
     k = big.pop("_kernel")
     if probes is not None:
@@ -337,8 +353,11 @@ def bench_reference_many(insts):
 
 
 def batch_bench(args):
-    out, truth = batch_part(args, machine_probes(), small=True)
-    out["true_error"] = truth()
+    if args.profile_run:
+        out, _ = batch_part(args)
+    else:
+        out, truth = batch_part(args, machine_probes(), small=True)
+        out["true_error"] = truth()
     print(json.dumps(out), flush=True)
 
 
@@ -484,8 +503,11 @@ def tc_part(args, probes=None):
 
 
 def tc_bench(args):
-    out, truth = tc_part(args, machine_probes())
-    out["true_error"] = truth()
+    if args.profile_run:
+        out, _ = tc_part(args)
+    else:
+        out, truth = tc_part(args, machine_probes())
+        out["true_error"] = truth()
     print(json.dumps(out), flush=True)
 
 
@@ -607,7 +629,8 @@ def learned_part(args):
 
 def learned_bench(args):
     out, truth = learned_part(args)
-    out["true_error_reference"] = truth()
+    if not args.profile_run:
+        out["true_error_reference"] = truth()
     print(json.dumps(out), flush=True)
 
 

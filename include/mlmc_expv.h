@@ -307,12 +307,13 @@ void mlmc_expv_destroy(mlmc_plan_t *plan);
 
 /* ---- batched runs ------------------------------------------------------------------
  * Many plans (different matrices, right-hand sides or times) with fixed level schedules
- * in a few persistent launches: every (instance, level) is split into items of whole walks
- * of one row, and the waves of a persistent grid take the items in a fixed interleaved
- * order (wave w takes items w, w + waves, ...), so instances of very different sizes share
- * the chip without a launch per instance; the item space runs as a sequence of launches
- * over consecutive item ranges (phases), which keeps the waves on a few instances at a
- * time. Plans with an active proposal are rejected. The sequence (reset, walk phases,
+ * in a few launches: every (instance, level) is split into items of whole walks of one
+ * row, so instances of very different sizes share the chip without a launch per instance.
+ * The items run either on a grid of one wave per item (the dispatcher hands them out in
+ * order as waves end, so the waves in flight hold neighbouring rows and none idles before
+ * the end) or on a resident grid whose waves take the items of a phase (a range of
+ * consecutive items) in a fixed interleaved order (wave w takes items w, w + waves, ...).
+ * Plans with an active proposal are rejected. The sequence (reset, walk phases,
  * per-row sums, per-instance FP64 combine of the levels, section 2.2) is captured once in a
  * hipGraph at creation and replayed by mlmc_expv_batch_launch. Instance b draws the
  * random streams of instance number b (the `instance` of a single run), so its estimate
@@ -331,18 +332,26 @@ typedef struct {
     int32_t num_levels;               /* levels l0_b .. l0_b + num_levels - 1 of each plan */
     const int64_t *walks;             /* HOST, count x num_levels walks per row (row major) */
     int32_t autotune;                 /* 1: time candidate launch shapes (walks per item 1024,
-                                         4096 and the size rule's choice x 8, 16, 20, 32
-                                         resident waves per CU) on every 8th instance at full
-                                         sample sizes and keep the fastest; the choice is
-                                         cached per class of batch for the process.
+                                         4096 and the size rule's choice x a grid of one wave
+                                         per item or a resident grid of 16, 20 or 32 waves
+                                         per CU) on every 8th instance at full sample sizes
+                                         and keep the fastest; the choice is cached per class
+                                         of batch for the process.
                                          0: walks per item from the total walk count
-                                         (64 .. 4096), 16 waves per CU. */
+                                         (64 .. 4096) and the grid of waves_per_cu. */
+    int32_t waves_per_cu;             /* without autotune: 0 = a grid of one wave per item
+                                         (two walk launches, the coarsest levels then the
+                                         rest); 1..64 = a resident grid of that many waves
+                                         per CU taking the items of a phase round robin */
 } mlmc_batch_desc_t;
 
 #define MLMC_BATCH_TUNE_MAX 12   /* autotuner candidates reported in mlmc_batch_info_t */
 
 typedef struct {
-    int32_t count, segments, walks_per_item, waves_per_cu, graph_nodes;
+    int32_t count, segments, walks_per_item;
+    int32_t waves_per_cu;             /* resident waves per CU of the walk grid, 0 for a grid
+                                         of one wave per item */
+    int32_t graph_nodes;
     int32_t phases;                   /* walk launches in the graph (phases of consecutive
                                          items) */
     int64_t items;                    /* (row, walk chunk) items per launch */
@@ -350,7 +359,7 @@ typedef struct {
     int32_t tune_count;               /* candidates the autotuner timed (0 when the choice
                                          came from the cache or autotune was off) */
     int32_t tune_walks_per_item[MLMC_BATCH_TUNE_MAX];
-    int32_t tune_waves_per_cu[MLMC_BATCH_TUNE_MAX];
+    int32_t tune_waves_per_cu[MLMC_BATCH_TUNE_MAX];   /* 0: one wave per item */
     int32_t pad;
     double tune_ms[MLMC_BATCH_TUNE_MAX];  /* their times on the instance subset (ms) */
 } mlmc_batch_info_t;

@@ -121,7 +121,8 @@ class BatchDesc(ctypes.Structure):
                 ("x", ctypes.POINTER(ctypes.c_void_p)),
                 ("num_levels", ctypes.c_int32),
                 ("walks", ctypes.POINTER(ctypes.c_int64)),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):

@@ -407,15 +407,17 @@ class Plan:
 
 
 class Batch:
-    """Many plans with fixed level schedules in one persistent, graph-captured launch.
+    """Many plans with fixed level schedules in a few walk launches, captured in a graph.
 
     plans: list of Plan (one precision); us: list of device tensors (n_b or n_b x R_b, one
     dtype); walks: (count, num_levels) walks per row at levels l0_b + q. Instance b draws
     the streams of instance number b, so its paths are those of plans[b].run(us[b],
-    walks=walks[b], instance=b) with the same seed.
+    walks=walks[b], instance=b) with the same seed. Without autotune, waves_per_cu picks
+    the grid: 0 for one wave per item, else a resident grid of that many waves per CU.
     """
 
-    def __init__(self, plans, us, walks, autotune: bool = True, stream=None):
+    def __init__(self, plans, us, walks, autotune: bool = True, waves_per_cu: int = 0,
+                 stream=None):
         self._lib = _abi.load()
         self._handle = ctypes.c_void_p()
         walks = np.ascontiguousarray(walks, dtype=np.int64)
@@ -443,7 +445,7 @@ class Batch:
         desc = _abi.BatchDesc(count, self._plan_ptrs, self._u_ptrs, self._nrhs, dts.pop(),
                               self._x_ptrs, int(walks.shape[1]),
                               walks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                              1 if autotune else 0)
+                              1 if autotune else 0, int(waves_per_cu))
         check(self._lib.mlmc_expv_batch_create(ctypes.byref(self._handle), ctypes.byref(desc),
                                                _stream_ptr(stream)))
         info = _abi.BatchInfo()

@@ -1,15 +1,16 @@
 // Batched runs: many plans (matrices, right-hand sides, times) with fixed level schedules in
-// a few persistent launches, captured once in a hipGraph and replayed.
+// a few launches, captured once in a hipGraph and replayed.
 //
 // The batch is a list of segments, one per (instance, level). A segment's work is split into
-// items of `chunk` walks of one requested row; a persistent grid of waves deals the items
-// round robin, so instances of very different sizes and levels of very different walk
-// lengths share the chip without a launch per segment. The graph is: reset the counters ->
-// persistent walks (in phases of consecutive items) -> per-row chunk sums -> per-instance
-// FP64 combine of the levels (the estimator of section 2.2). The launch shape (walks per item,
-// resident waves per CU) comes from a small autotuner that times candidates on a subset of
-// the batch's instances at full sample sizes and caches the winner per class of batch;
-// without it, the walks per item follow from the batch's total walk count.
+// items of `chunk` walks of one requested row, so instances of very different sizes and
+// levels of very different walk lengths share the chip without a launch per segment. The
+// items are run either by a grid of one wave per item (two launches: the coarsest levels,
+// then the rest) or by a resident grid whose waves deal the items of a phase round robin.
+// The graph is: reset the counters -> walks -> per-row chunk sums -> per-instance FP64
+// combine of the levels (the estimator of section 2.2). The launch shape (walks per item,
+// grid) comes from a small autotuner that times candidates on a subset of the batch's
+// instances at full sample sizes and caches the winner per class of batch; without it, the
+// walks per item follow from the batch's total walk count and the grid has one wave per item.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -33,8 +34,12 @@ namespace {
 
 constexpr int kCUs = 256;
 constexpr uint32_t kXcds = 8;
-// Items per wave in one phase of the walk launches.
+// Items per wave in one phase of the walk launches of a resident grid.
 constexpr uint64_t kItemsPerWavePhase = 64;
+// Items per launch of a grid of one wave per item (grid.x stays far below 2^32 workgroups).
+constexpr uint64_t kItemsPerGridLaunch = uint64_t(1) << 28;
+// Consecutive workgroups an XCD takes in a grid of one wave per item.
+constexpr uint32_t kXcdRun = 16;
 // Items per launch the walks-per-item rule aims for: about 128 per wave of a 32-waves-per-CU
 // grid, so that the end of the launch is short against its length.
 constexpr double kBatchTargetItems = 1 << 20;
@@ -75,25 +80,38 @@ struct BatchParams {
 // Items [item_lo, item_hi) of the batch (one phase of the launch sequence). kBase: every item
 // of the range is at its instance's coarsest level (the segments are ordered level by level),
 // so the walks are compiled for it (fine functional only, each sample taken as its walk ends).
+// Workgroup b runs on XCD b mod 8 (the dispatcher deals them to the XCDs in turn). Renumber
+// them so that within each window of 8 * run workgroups, XCD x takes the run consecutive
+// numbers x * run .. x * run + run - 1: neighbouring items then share one XCD's L2. A last
+// partial window keeps its order. A bijection of [0, G).
+__device__ __forceinline__ uint32_t xcd_renumber(uint32_t b, uint32_t G, uint32_t run)
+{
+    const uint32_t win = kXcds * run;
+    if (b >= G / win * win) return b;
+    const uint32_t p = b % win;
+    return b - p + (p % kXcds) * run + p / kXcds;
+}
+
 template <typename R, typename U, bool kMulti, bool kBase>
 __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
-                                                      BatchParams *prm)
+                                                      uint32_t xcd_run, BatchParams *prm)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t k0 = prm->k0, k1 = prm->k1;
-    // Items are dealt to the waves round robin (wave v takes v, v + W, v + 2W, ...):
-    // consecutive items belong to the same (instance, level), so every wave gets a mix of all
-    // segments. Workgroups go to the XCDs in turn (workgroup b to XCD b mod 8), so the wave
-    // index is renumbered to give each XCD a contiguous eighth of every round of W items:
-    // walks that start on neighbouring rows then share one XCD's L2. The index is read with
-    // readfirstlane so the loop is wave-uniform in the compiled control flow. (A shared
-    // atomic work counter was measured to serialise at about one returning atomic per
-    // microsecond across the XCDs.) The grid is a multiple of kXcds workgroups.
+    // Items are dealt to the waves round robin (wave v takes v, v + W, v + 2W, ...; with a
+    // grid of one wave per item, just v): consecutive items belong to the same (instance,
+    // level), so a resident wave gets a mix of all segments. The workgroups are renumbered
+    // so that each XCD takes runs of neighbouring items (a resident grid passes run = G / 8:
+    // a contiguous eighth of every round of W items; a grid of one wave per item a short
+    // run, so that the XCDs sweep the range together and none is left with a costlier
+    // stretch of it). The index is read with readfirstlane so the loop is wave-uniform in the
+    // compiled control flow. (A shared atomic work counter was measured to serialise at about
+    // one returning atomic per microsecond across the XCDs.)
     const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWavesPerBlock;
-    const uint32_t xcd_block = (blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+    const uint32_t xcd_block = xcd_renumber(blockIdx.x, gridDim.x, xcd_run);
     const uint64_t wave_id = __builtin_amdgcn_readfirstlane(
-        xcd_block * kWavesPerBlock + threadIdx.x / kWave);
+        static_cast<uint64_t>(xcd_block) * kWavesPerBlock + threadIdx.x / kWave);
     for (uint64_t item = item_lo + wave_id; item < item_hi; item += waves) {
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
@@ -240,7 +258,8 @@ uint32_t blocks_of(uint64_t n, uint32_t threads)
     return static_cast<uint32_t>((n + threads - 1) / threads);
 }
 
-// A launch shape: walks per item and resident waves per CU of the persistent grid.
+// A launch shape: walks per item, and resident waves per CU of a grid that loops over the
+// items of a phase (0: one wave per item).
 struct Shape {
     uint32_t chunk;
     int32_t waves_per_cu;
@@ -260,7 +279,7 @@ struct mlmc_batch {
     std::vector<int32_t> nrhs;
     std::vector<const void *> u;      // count device pointers
     std::vector<int64_t> walks;       // count x levels
-    Shape shape{4096, 16};
+    Shape shape{4096, 0};
     std::vector<Segment> h_segs;
     std::vector<InstanceOut> h_outs;
     Segment *d_segs = nullptr;
@@ -382,17 +401,23 @@ void layout(const mlmc_batch *b, const Shape &sh, const std::vector<int64_t> &wa
 hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
                         uint64_t item_lo, uint64_t item_hi, bool base, hipStream_t s)
 {
-    const dim3 grid(static_cast<uint32_t>(kCUs * sh.waves_per_cu / kWavesPerBlock));
-    if (grid.x % kXcds != 0) return hipErrorInvalidConfiguration;
+    // a resident grid of waves_per_cu waves per CU, or one wave per item; a multiple of kXcds
+    // workgroups either way (the kernel's renumbering of the waves needs it)
+    const uint64_t waves = sh.waves_per_cu > 0 ? static_cast<uint64_t>(kCUs) * sh.waves_per_cu
+                                               : item_hi - item_lo;
+    const uint64_t blocks = (waves + kWavesPerBlock * kXcds - 1) / (kWavesPerBlock * kXcds) * kXcds;
+    if (blocks == 0 || blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
+    const dim3 grid(static_cast<uint32_t>(blocks));
+    const uint32_t xcd_run = sh.waves_per_cu > 0 ? grid.x / kXcds : kXcdRun;
     const dim3 block(kBlock);
 #define MLMC_BATCH(R, U, MULTI)                                                                        \
     do {                                                                                               \
         if (!(MULTI) && base)                                                                          \
             hipLaunchKernelGGL((batch_walks<R, U, MULTI, true>), grid, block, 0, s, d_segs, nseg,      \
-                               item_lo, item_hi, b->d_prm);                                            \
+                               item_lo, item_hi, xcd_run, b->d_prm);                                   \
         else                                                                                           \
             hipLaunchKernelGGL((batch_walks<R, U, MULTI, false>), grid, block, 0, s, d_segs, nseg,     \
-                               item_lo, item_hi, b->d_prm);                                            \
+                               item_lo, item_hi, xcd_run, b->d_prm);                                   \
     } while (0)
     if (b->precision == MLMC_PRECISION_FP64) {
         if (b->u_f64) {
@@ -412,15 +437,20 @@ hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_s
 }
 
 // The walks of items [0, total_items) as a sequence of launches (phases) of consecutive
-// items. Within a launch the waves drift apart (their items differ in cost) and the chip
-// ends up working on many instances at once, whose tables then compete for the L2; the end
-// of each launch brings the waves back together. On the 512-instance batch this halves the
-// L2 misses of one long launch. The phases of the coarsest levels' items [0, base_items) use
-// the kernel compiled for the coarsest level.
+// items. With a resident grid, the waves of a launch drift apart (their items differ in
+// cost) and the chip ends up working on many instances at once, whose tables then compete
+// for the L2; the end of each launch brings the waves back together (on the 512-instance
+// batch this halves the L2 misses of one long launch), at the price of the waves that idle
+// while the launch drains. A grid of one wave per item has neither problem: the dispatcher
+// hands out the items in order as waves end, so the waves in flight hold a window of
+// neighbouring rows and no slot idles before the end of the range. The phases of the
+// coarsest levels' items [0, base_items) use the kernel compiled for the coarsest level.
 hipError_t launch_phases(const mlmc_batch *b, const Shape &sh, const Segment *d_segs, int32_t nseg,
                          uint64_t total_items, uint64_t base_items, hipStream_t s, int32_t *phases)
 {
-    const uint64_t per_phase = static_cast<uint64_t>(kCUs) * sh.waves_per_cu * kItemsPerWavePhase;
+    const uint64_t per_phase = sh.waves_per_cu > 0
+                                   ? static_cast<uint64_t>(kCUs) * sh.waves_per_cu * kItemsPerWavePhase
+                                   : kItemsPerGridLaunch;
     *phases = 0;
     for (int part = 0; part < 2; ++part) {
         const uint64_t begin = part == 0 ? 0 : base_items, end = part == 0 ? base_items : total_items;
@@ -478,11 +508,11 @@ uint32_t items_chunk(const mlmc_batch *b)
     return static_cast<uint32_t>(std::min(4096.0, std::max(64.0, c)));
 }
 
-// Time candidate shapes (walks per item: 1024, 4096 and the size rule's choice; waves per CU:
-// 8, 16, 20, 32, where 20 fills the 5 waves per SIMD of the FP32 one-right-hand-side kernel in
-// one round) on every kTuneStride-th instance of the batch at its full sample sizes,
-// with the phases of the real launch, and keep the fastest. The choice is cached per class of
-// batch for the process.
+// Time candidate shapes (walks per item: 1024, 4096 and the size rule's choice; a grid of one
+// wave per item, or resident grids of 16, 20 or 32 waves per CU, where 20 fills the 5 waves
+// per SIMD of the FP32 one-right-hand-side kernel in one round) on every kTuneStride-th
+// instance of the batch at its full sample sizes, with the phases of the real launch, and
+// keep the fastest. The choice is cached per class of batch for the process.
 constexpr int kTuneStride = 8;
 
 int autotune(mlmc_batch *b, hipStream_t s)
@@ -517,7 +547,7 @@ int autotune(mlmc_batch *b, hipStream_t s)
         if (std::find(chunks.begin(), chunks.end(), b->shape.chunk) == chunks.end())
             chunks.push_back(b->shape.chunk);
         for (uint32_t c : chunks)
-            for (int w : {8, 16, 20, 32}) cands.push_back(Shape{c, w});
+            for (int w : {0, 16, 20, 32}) cands.push_back(Shape{c, w});
     }
     const int stride = b->count >= kTuneStride ? kTuneStride : b->count;
     double best = 1e300;
@@ -638,7 +668,10 @@ int mlmc_expv_batch_create(mlmc_batch_t **out, const mlmc_batch_desc_t *d, void 
     if ((rc = balloc(b, &b->d_prm, 1))) return rc;
     MLMC_HIP_TRY(hipEventCreate(&b->ev0));
     MLMC_HIP_TRY(hipEventCreate(&b->ev1));
+    if (!d->autotune && (d->waves_per_cu < 0 || d->waves_per_cu > 64))
+        return fail(MLMC_ERR_INVALID_ARG, "waves_per_cu must be in [0, 64]");
     b->shape.chunk = items_chunk(b);
+    b->shape.waves_per_cu = d->autotune ? 0 : d->waves_per_cu;
     if (d->autotune && (rc = autotune(b, s))) return rc;
     if ((rc = build_tables(b, s))) return rc;
     for (int i = 0; i < b->count; ++i) b->h_outs[i].x = d->x[i];

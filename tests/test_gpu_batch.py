@@ -101,8 +101,10 @@ def test_batch_matches_oracle_and_graph_replays_are_exact(api, R):
 
 def test_batch_in_several_phases_matches_oracle(api):
     """A batch large enough in items (rows x levels) to be split into several walk launches
-    (phases of consecutive items): every instance against the oracle, and a replay with
-    another key set in between reproduces the result exactly."""
+    of a resident grid (phases of consecutive items): every instance against the oracle, a
+    replay with another key set in between reproduces the result exactly, and a grid of one
+    wave per item gives bit-identical estimates (the sums of an item do not depend on the
+    wave that takes it)."""
     insts = [(inputs.laplacian_1d(120_000), None, None),
              (inputs.laplacian_2d(300), None, None),
              (inputs.erdos_renyi(50_000, 8.0, 5), None, None)]
@@ -111,9 +113,9 @@ def test_batch_in_several_phases_matches_oracle(api):
     walks = np.array([[3, 2, 1, 1]] * len(insts), dtype=np.int64)
     plans = [api.Plan(A, t, precision="fp32") for A, t, _ in insts]
     us = [torch.as_tensor(v.astype(np.float32), device="cuda") for _, _, v in insts]
-    batch = api.Batch(plans, us, walks, autotune=False)
+    batch = api.Batch(plans, us, walks, autotune=False, waves_per_cu=16)
     _say(f"phased batch info {batch.info}")
-    assert batch.info["phases"] >= 2
+    assert batch.info["phases"] >= 2 and batch.info["waves_per_cu"] == 16
     seed = 4242
     xs = [x.clone() for x in batch.launch(seed)]
     st = batch.stats()
@@ -130,5 +132,15 @@ def test_batch_in_several_phases_matches_oracle(api):
     for b in range(len(insts)):
         assert torch.equal(again[b], xs[b]), b
     batch.close()
+    grid = api.Batch(plans, us, walks, autotune=False, waves_per_cu=0)
+    _say(f"one-wave-per-item batch info {grid.info}")
+    assert grid.info["phases"] == 2 and grid.info["waves_per_cu"] == 0
+    per_item = grid.launch(seed)
+    st_g = grid.stats()
+    torch.cuda.synchronize()
+    for b in range(len(insts)):
+        assert torch.equal(per_item[b], xs[b]), b
+        assert st_g[b]["total_jumps"] == st[b]["total_jumps"], b
+    grid.close()
     for p in plans:
         p.close()
