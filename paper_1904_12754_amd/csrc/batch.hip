@@ -134,8 +134,8 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) vo
         if (!kMulti) {
             SinkR1<R, U> sink{u};
             walk_range<R, false, false, false, kBase>(L, row, 0u, wb, we, sink);
-            const double a = wave_sum(sink.s1.value());
-            const double b = wave_sum(sink.s2.value());
+            const double a = wave_sum(sink.mom.first());
+            const double b = wave_sum(sink.mom.second());
             jumps = wave_sum_u(sink.jumps);
             nonfinite = wave_sum_u(sink.nonfinite);
             if (lane == 0) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : 5) : 2)) vo
             for (int g = 0; g < kMaxRhsGroups; ++g) {
                 const int r = static_cast<int>(lane) + g * kWave;
                 if (g < sink.groups && r < nrhs) {
-                    double a = sink.s1[g].value(), b = sink.s2[g].value();
+                    double a = sink.mom[g].first(), b = sink.mom[g].second();
                     if (y0 != static_cast<R>(0)) {
                         const double yr = static_cast<double>(
                             y0 * static_cast<R>(u[static_cast<uint64_t>(row) * nrhs + r]));

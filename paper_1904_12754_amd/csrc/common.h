@@ -170,6 +170,31 @@ __host__ __device__ __forceinline__ double neg_log_uniform(uint32_t w)
     return -ln_x;
 }
 
+// The same value for code inside a hot loop: the series coefficients 1/(2k+1) are divided
+// out (correctly rounded, so equal to the constants above) in a loop that is not unrolled,
+// instead of being held as eleven FP64 constants, which the compiler keeps live in 22
+// VGPRs across the whole walk loop when the function is inlined there.
+__device__ __forceinline__ double neg_log_uniform_rt(uint32_t w)
+{
+    const double x = uniform_of(w);
+    const uint64_t b = bits_of(x);
+    int ex = static_cast<int>(b >> 52) - 1023;
+    double m = double_of((b & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull);
+    if (m > 0x1.6a09e667f3bcdp+0) {
+        m = m * 0.5;
+        ex = ex + 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 0.0;                                  // fma(0, z, 1/23) = 1/23 exactly
+#pragma clang loop unroll(disable)
+    for (int k = 11; k >= 0; --k) p = fma(p, z, 1.0 / static_cast<double>(2 * k + 1));
+    const double twice_atanh = 2.0 * (s * p);
+    const double de = static_cast<double>(ex);
+    const double ln_x = de * 0x1.62e42ffp-1 + (de * -0x1.718432a1b0e26p-35 + twice_atanh);
+    return -ln_x;
+}
+
 // ------------------------------------------------------------------------------------
 // Fast bracket of -ln U(w) in FP32 from the hardware base-2 logarithm. For every 32-bit
 // word w,

@@ -38,8 +38,8 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void functional_w
     const uint64_t we = (wb + kFuncChunk < M) ? wb + kFuncChunk : static_cast<uint64_t>(M);
     SinkR1<R, U> sink{w, nullptr};
     walk_range_from<R, kHash, false, false>(L, st, walk0, wb, we, sink);
-    const double a = wave_sum(sink.s1.value());
-    const double b = wave_sum(sink.s2.value());
+    const double a = wave_sum(sink.mom.first());
+    const double b = wave_sum(sink.mom.second());
     const unsigned long long jumps = wave_sum_u(sink.jumps);
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
     const unsigned long long hsum = wave_sum_u(sink.hash);

@@ -81,8 +81,8 @@ __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walk
         }
     }
     if (!done) walk_range<R, kHash, kIS, kSrc, kBase>(L, row, walk0, wb, we, sink, lpr);
-    const double a = group_sum(sink.s1.value(), lpr);
-    const double b = group_sum(sink.s2.value(), lpr);
+    const double a = group_sum(sink.mom.first(), lpr);
+    const double b = group_sum(sink.mom.second(), lpr);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
     const unsigned long long hsum = group_sum_u(sink.hash, lpr);
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 3 : 2)) void level_walks_
     for (int g = 0; g < kMaxRhsGroups; ++g) {
         const int r = static_cast<int>(lane) + g * kWave;
         if (g < sink.groups && r < nrhs) {
-            double a = sink.s1[g].value(), b = sink.s2[g].value();
+            double a = sink.mom[g].first(), b = sink.mom[g].second();
             if (y0 != static_cast<R>(0)) {
                 const double yr = static_cast<double>(
                     y0 * static_cast<R>(u[static_cast<uint64_t>(row) * nrhs + r]));

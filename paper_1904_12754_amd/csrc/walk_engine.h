@@ -185,6 +185,36 @@ struct Kahan {
     }
 };
 
+// Per-lane running sums of the samples and of their squares. FP32 samples are summed in
+// FP64: a conversion, an add and a fused multiply-add per sample, fewer instructions than
+// compensated FP32 sums and more accurate (FP64 adds issue at the FP32 rate). FP64 samples
+// go to compensated FP64 sums.
+template <typename R>
+struct LaneMoments;
+template <>
+struct LaneMoments<float> {
+    double m1 = 0.0, m2 = 0.0;
+    __device__ __forceinline__ void add(float y)
+    {
+        const double d = static_cast<double>(y);
+        m1 += d;
+        m2 = fma(d, d, m2);
+    }
+    __device__ __forceinline__ double first() const { return m1; }
+    __device__ __forceinline__ double second() const { return m2; }
+};
+template <>
+struct LaneMoments<double> {
+    Kahan<double> k1, k2;
+    __device__ __forceinline__ void add(double y)
+    {
+        k1.add(y);
+        k2.add(y * y);
+    }
+    __device__ __forceinline__ double first() const { return k1.value(); }
+    __device__ __forceinline__ double second() const { return k2.value(); }
+};
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -387,14 +417,14 @@ __device__ __forceinline__ double chain_tau_exact(const LevelArgs &L, uint32_t r
                                                   uint32_t word)
 {
     RowRec rk = L.rec[k0];
-    double tau = neg_log_uniform(word) * rk.inv_r;
+    double tau = neg_log_uniform_rt(word) * rk.inv_r;
     for (uint32_t J = J0; J < J1; ++J) {
         const Word4 ph = philox10(Word4{J, walk, row, L.c3_jump}, L.k0, L.k1);
         const uint32_t slot = mulhi32(ph.x, rk.deg);
         float unused = 1.0f;
         const uint32_t cs = jump_pick<float, kIS>(L, rk.slot_begin + slot, ph.y, unused);
         rk = L.rec[cs & kColMask];
-        tau = tau + neg_log_uniform(ph.z) * rk.inv_r;
+        tau = tau + neg_log_uniform_rt(ph.z) * rk.inv_r;
     }
     return tau;
 }
@@ -638,14 +668,14 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
     sink.take(pend.valid, pend.finished(ibase, hd));
 }
 
-// Single right-hand side: each lane adds its own samples to compensated sums (kSrc: the
+// Single right-hand side: each lane adds its own samples to its running sums (kSrc: the
 // samples carry a source-term part).
 template <typename R, typename U, bool kSrc = false>
 struct SinkR1 {
     static constexpr bool kLaneLocal = true;   // take() touches only the calling lane
     const U *u;
     const U *F;       // source vector (Algorithm 3), or null
-    Kahan<R> s1, s2;
+    LaneMoments<R> mom;
     unsigned long long jumps = 0, hash = 0;
     uint32_t nonfinite = 0;   // a lane evaluates fewer than 2^32 samples in a launch
     __device__ __forceinline__ R source(uint32_t k) const { return static_cast<R>(F[k]); }
@@ -657,8 +687,7 @@ struct SinkR1 {
         jumps += f.jumps;
         hash += f.hash;
         nonfinite += !isfinite(y);
-        s1.add(y);
-        s2.add(y * y);
+        mom.add(y);
     }
 };
 
@@ -694,7 +723,7 @@ struct SinkRhs {
     const U *u;
     int32_t nrhs;
     int groups;
-    Kahan<R> s1[kMaxRhsGroups], s2[kMaxRhsGroups];
+    LaneMoments<R> mom[kMaxRhsGroups];
     unsigned long long jumps = 0, nojump = 0, nonfinite = 0, hash = 0;
     __device__ __forceinline__ void take(bool done, const Finished<R> &f)
     {
@@ -717,8 +746,7 @@ struct SinkRhs {
                 if (g < groups && r < nrhs) {
                     const R y = Wt * static_cast<R>(u[static_cast<uint64_t>(kt) * nrhs + r]);
                     nonfinite += !isfinite(y);
-                    s1[g].add(y);
-                    s2[g].add(y * y);
+                    mom[g].add(y);
                 }
             }
         }
