@@ -39,13 +39,13 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // them spilled) run faster than the four that the loop's 126 VGPRs allow, and with FP64
 // weights three faster than two; walks under a proposal measured slower that way and keep
 // what their registers give.
-template <typename R, bool kIS>
-constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? 5 : 3); }
+template <typename R, bool kIS, bool kBase>
+constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? (kBase ? 6 : 5) : 3); }
 
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
 template <typename R, typename U, bool kHash, bool kIS, bool kSrc, bool kBase>
-__global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS, kBase>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
                                                          uint32_t M, uint32_t chunk,
