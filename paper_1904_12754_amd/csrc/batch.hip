@@ -93,7 +93,7 @@ __device__ __forceinline__ uint32_t xcd_renumber(uint32_t b, uint32_t G, uint32_
 }
 
 template <typename R, typename U, bool kMulti, bool kBase>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : (kBase ? 6 : 5)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : (kBase ? 7 : 6)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       uint32_t xcd_run, BatchParams *prm)
 {

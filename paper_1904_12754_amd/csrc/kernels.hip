@@ -40,7 +40,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // weights three faster than two; walks under a proposal measured slower that way and keep
 // what their registers give.
 template <typename R, bool kIS, bool kBase>
-constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? (kBase ? 6 : 5) : 3); }
+constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? (kBase ? 7 : 6) : 3); }
 
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
