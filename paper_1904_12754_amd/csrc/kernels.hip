@@ -34,11 +34,12 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Waves per SIMD the single-level kernel is compiled for. The loop's dependent gathers leave
-// latency that more resident waves hide: with FP32 weights five waves (96 VGPRs, a few of
-// them spilled) run faster than the four that the loop's 126 VGPRs allow, and with FP64
-// weights three faster than two; walks under a proposal measured slower that way and keep
-// what their registers give.
+// Waves per SIMD the single-level kernel is compiled for. The loop waits on dependent
+// gathers and long-latency instructions more than it issues, so more resident waves run it
+// faster even at the price of a few spilled registers: with FP32 weights seven on the
+// coarsest level (72 VGPRs, 10 spilled) and six above it (80, 11 spilled); eight and seven
+// spill 30-43. With FP64 weights three run faster than two; walks under a proposal measured
+// slower that way and keep what their registers give.
 template <typename R, bool kIS, bool kBase>
 constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? (kBase ? 7 : 6) : 3); }
 
