@@ -93,10 +93,10 @@ __device__ __forceinline__ uint32_t xcd_renumber(uint32_t b, uint32_t G, uint32_
 }
 
 // Waves per SIMD as for the single-level kernels: with FP32 weights and one right-hand side,
-// seven on the coarsest levels and six above; three with several right-hand sides (their
+// seven on the coarsest levels and six above; four with several right-hand sides (their
 // per-lane sums of up to 256 right-hand sides take registers), two with FP64 weights.
 template <typename R, typename U, bool kMulti, bool kBase>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 3 : (kBase ? 7 : 6)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 : 6)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       uint32_t xcd_run, BatchParams *prm)
 {

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void functional_w
 // The forward representation of the full vector: the same walks deposit their samples at
 // their final states.
 template <typename R, bool kHash>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void forward_walks(LevelArgs L, AliasStart st, uint32_t walk0, uint32_t M,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 6 : 2)) void forward_walks(LevelArgs L, AliasStart st, uint32_t walk0, uint32_t M,
                                                         uint32_t items, double *sum1, double *sum2,
                                                         unsigned long long *counters,
                                                         unsigned long long *hash_sum)

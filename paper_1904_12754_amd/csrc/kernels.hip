@@ -37,16 +37,19 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // Waves per SIMD the single-level kernel is compiled for. The loop waits on dependent
 // gathers and long-latency instructions more than it issues, so more resident waves run it
 // faster even at the price of a few spilled registers: with FP32 weights seven on the
-// coarsest level (72 VGPRs, 10 spilled) and six above it (80, 11 spilled); eight and seven
-// spill 30-43. With FP64 weights three run faster than two; walks under a proposal measured
-// slower that way and keep what their registers give.
-template <typename R, bool kIS, bool kBase>
-constexpr int walk_min_waves() { return kIS ? 1 : (sizeof(R) == 4 ? (kBase ? 7 : 6) : 3); }
+// coarsest level (72 VGPRs, 10 spilled) and six above it (80, 11 spilled), five under a
+// proposal or with a source term (96, 2 and 4 spilled); eight and seven spill 30-43. With
+// FP64 weights three run faster than two.
+template <typename R, bool kIS, bool kSrc, bool kBase>
+constexpr int walk_min_waves()
+{
+    return sizeof(R) == 4 ? (kIS ? 5 : kSrc ? 5 : kBase ? 7 : 6) : 3;
+}
 
 // Items are (requested row, walk chunk) pairs; a wave takes 64 / lpr consecutive items, one
 // per group of lpr lanes (lpr a power of two, 1..64).
 template <typename R, typename U, bool kHash, bool kIS, bool kSrc, bool kBase>
-__global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS, kBase>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS, kSrc, kBase>())) void level_walks_r1(LevelArgs L, const U *__restrict__ u,
                                                          const int64_t *__restrict__ rows,
                                                          uint32_t n_rows, uint32_t walk0,
                                                          uint32_t M, uint32_t chunk,
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS, kBase>())) void lev
 }
 
 template <typename R, typename U, bool kHash, bool kIS>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 3 : 2)) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
                                                           int32_t nrhs,
                                                           const int64_t *__restrict__ rows,
                                                           uint32_t n_rows, uint32_t walk0,
