@@ -34,17 +34,16 @@ if ROOT not in sys.path:
 # three-input xors: 40 per block, 10 per step) and one compare; a jump consumes one block
 # (40), the alias selection and gather addressing (~8), the holding-time bracket (~8) and the
 # run update of the weights (~9); a walk end scales and exponentiates its exponent and
-# applies the sign (3), gathers u and multiplies (2), adds the sample and its square to FP64
-# sums (a conversion, an add and a fused multiply-add: 3) and to the counters (3), plus an
-# expm1 (~23) above the base level; with several right-hand sides a walk that moved adds
-# one product and the FP64 sums per right-hand side (4). The random draws are part of the
-# method's cost (the per-step term of the cost model of section 4), so the generator counts
-# as work.
+# applies the sign (3), gathers u and multiplies (2), adds to the two compensated sums (9)
+# and to the counters (3), plus an expm1 (~23) above the base level; with several
+# right-hand sides a walk that moved adds one product and two compensated sums per
+# right-hand side (10). The random draws are part of the method's cost (the per-step term
+# of the cost model of section 4), so the generator counts as work.
 OPS_PER_STEP = 11
 OPS_PER_JUMP = 65
-OPS_PER_WALK_BASE = 11
-OPS_PER_WALK_ABOVE = 34
-OPS_PER_RHS_SAMPLE = 4
+OPS_PER_WALK_BASE = 17
+OPS_PER_WALK_ABOVE = 40
+OPS_PER_RHS_SAMPLE = 10
 # MI355X integer VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (a wave64
 # instruction issues over four cycles; the FP32 vector figure of 157.3 TFLOP/s counts two
 # flops per FMA and dual-issue, which 32-bit integer instructions do not have)

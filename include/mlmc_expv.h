@@ -33,7 +33,7 @@
  * stream 1 the jumps (the walk's j-th jump reads block j: slot, alias coin, next holding
  * time). Results are therefore a pure function of (A, u, beta, levels, walks, seed,
  * instance), independent of launch shape and of how walk ranges are split. Every reduction
- * (per-lane sums, wave and chunk sums, the level combine) runs in a fixed order
+ * (per-lane compensated sums, wave and chunk sums, the level combine) runs in a fixed order
  * and the counters are integers, so results are bitwise reproducible from run to run: there
  * is no faster non-deterministic mode to select. The paths themselves are returned by
  * mlmc_expv_trace.
@@ -69,7 +69,7 @@ extern "C" {
 #define MLMC_DTYPE_F64 1
 
 /* Weights along a path (the exponents of the Strang factors and the sample Y):
- * FP64 (compensated FP64 per-lane sums), or FP32 (FP32 samples, per-lane sums in FP64).
+ * FP64, or FP32 with compensated (Kahan) FP32 per-lane sums.
  * Path decisions (holding times, jump choice) are FP64/integer in both modes, so both
  * modes follow identical paths. Per-row and cross-level combination is always FP64. */
 #define MLMC_PRECISION_FP64 0

@@ -40,7 +40,7 @@ class Plan:
 
     A: an object with n, row_ptr, col_idx, values: numpy arrays (host), or device tensors
        (int64 row_ptr, int32 col_idx, float32 or float64 values; values_dtype is then ignored).
-    precision: "fp32" (FP32 path weights, FP64 per-lane sums, FP64 combine) or "fp64".
+    precision: "fp32" (FP32 path weights, compensated FP32 sums, FP64 combine) or "fp64".
     """
 
     def __init__(self, A, beta: float, precision: str = "fp32", l0: int | None = None,

@@ -36,10 +36,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 
 // Waves per SIMD the single-level kernel is compiled for. The loop waits on dependent
 // gathers and long-latency instructions more than it issues, so more resident waves run it
-// faster even at the price of a few spilled registers: with FP32 weights seven on the
-// coarsest level (72 VGPRs, 10 spilled) and six above it (80, 11 spilled), five under a
-// proposal or with a source term (96, 2 and 4 spilled); eight and seven spill 30-43. With
-// FP64 weights three run faster than two.
+// faster even at the price of spilled registers: with FP32 weights seven on the coarsest
+// level (72 VGPRs, 26 spilled) and six above it (80, 21 spilled), five under a proposal or
+// with a source term (96, 4 and 10 spilled). With FP64 weights three run faster than two.
 template <typename R, bool kIS, bool kSrc, bool kBase>
 constexpr int walk_min_waves()
 {

@@ -185,28 +185,12 @@ struct Kahan {
     }
 };
 
-// Per-lane running sums of the samples and of their squares. FP32 samples are summed in
-// FP64: a conversion, an add and a fused multiply-add per sample, fewer instructions than
-// compensated FP32 sums and more accurate (FP64 adds issue at the FP32 rate). FP64 samples
-// go to compensated FP64 sums.
+// Per-lane running sums of the samples and of their squares, compensated in the precision
+// of the weights (Kahan sums).
 template <typename R>
-struct LaneMoments;
-template <>
-struct LaneMoments<float> {
-    double m1 = 0.0, m2 = 0.0;
-    __device__ __forceinline__ void add(float y)
-    {
-        const double d = static_cast<double>(y);
-        m1 += d;
-        m2 = fma(d, d, m2);
-    }
-    __device__ __forceinline__ double first() const { return m1; }
-    __device__ __forceinline__ double second() const { return m2; }
-};
-template <>
-struct LaneMoments<double> {
-    Kahan<double> k1, k2;
-    __device__ __forceinline__ void add(double y)
+struct LaneMoments {
+    Kahan<R> k1, k2;
+    __device__ __forceinline__ void add(R y)
     {
         k1.add(y);
         k2.add(y * y);
