@@ -176,8 +176,12 @@ def walk_roofline(kernel, seconds, launches, steps, jumps, walks_base, walks_abo
                      "ops_per_rhs_sample": OPS_PER_RHS_SAMPLE, "bytes_per_jump": BYTES_PER_JUMP,
                      "bytes_per_walk_end": 4 * nrhs},
         "memory": {
+            # the algorithmic bytes over the HBM peak; the caches serve most of them, and the
+            # HBM traffic the counters measured is hbm_GBps_from_counters
             "algorithmic_GBps": nbytes / seconds / 1e9,
-            "frac_of_hbm_peak": nbytes / seconds / HBM_PEAK_BPS,
+            "algorithmic_over_hbm_peak": nbytes / seconds / HBM_PEAK_BPS,
+            "hbm_GBps_from_counters": (traffic * launches / seconds / 1e9
+                                       if traffic is not None else None),
             "working_set_MB": ws_bytes / 2 ** 20,
             "gathers_per_s": gathers / seconds,
             "probe_table_MB": size / 2 ** 20,
