@@ -116,6 +116,13 @@ typedef struct {
     int32_t l0, precision;
     double beta, r_max, d_min, d_max;
     int64_t device_bytes;         /* device memory the plan holds */
+    double jump_probability;      /* mean over the requested rows of 1 - exp(-beta r_i): the
+                                     share of walks that leave their start row */
+    int32_t screened;             /* 1 when jump_probability < 1/4: the walk kernels with
+                                     several right-hand sides then first draw the steps of
+                                     each walk at its start row and run in full only the
+                                     walks that jump (same paths and samples) */
+    int32_t pad;
 } mlmc_plan_info_t;
 
 /* Options of one run. */

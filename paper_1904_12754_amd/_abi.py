@@ -68,7 +68,8 @@ class PlanInfo(ctypes.Structure):
                 ("l0", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("beta", ctypes.c_double), ("r_max", ctypes.c_double),
                 ("d_min", ctypes.c_double), ("d_max", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("jump_probability", ctypes.c_double),
+                ("screened", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class RunOpts(ctypes.Structure):

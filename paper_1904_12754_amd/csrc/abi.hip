@@ -175,6 +175,7 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
     L.k1 = static_cast<uint32_t>(seed >> 32);
     L.c3_step = stream_word(level, instance, 0);
     L.c3_jump = stream_word(level, instance, 1);
+    L.screen = static_cast<uint32_t>(p->screen);
     return L;
 }
 
@@ -508,6 +509,19 @@ int mlmc_expv_plan(mlmc_plan_t **out, const mlmc_csr_t *A, const mlmc_plan_opts_
     p->r_max = r_max;
     p->d_min = n ? d_min : 0.0;
     p->d_max = n ? d_max : 0.0;
+    // the share of walks that jump at all: a walk from row i holds there for the whole time
+    // beta with probability e^{-beta r_i}
+    {
+        double sum = 0.0;
+        const int64_t cnt = o->rows ? o->n_rows : n;
+        for (int64_t t = 0; t < cnt; ++t) {
+            const RowRec &rr = rows[static_cast<size_t>(o->rows ? req[static_cast<size_t>(t)] : t)];
+            const double r = rr.deg ? 1.0 / rr.inv_r : 0.0;
+            sum += -std::expm1(-o->beta * r);
+        }
+        p->jump_probability = cnt ? sum / static_cast<double>(cnt) : 0.0;
+        p->screen = p->jump_probability < 0.25 ? 1 : 0;
+    }
     p->p_slot_host.swap(p_slot);
     int rc;
     if ((rc = dev_alloc(p, &p->slots, slots.size()))) return rc;
@@ -548,6 +562,9 @@ int mlmc_expv_plan_info(const mlmc_plan_t *p, mlmc_plan_info_t *info)
     info->d_min = p->d_min;
     info->d_max = p->d_max;
     info->device_bytes = p->bytes;
+    info->jump_probability = p->jump_probability;
+    info->screened = p->screen;
+    info->pad = 0;
     return MLMC_OK;
 }
 

@@ -96,7 +96,7 @@ __device__ __forceinline__ uint32_t xcd_renumber(uint32_t b, uint32_t G, uint32_
 // seven on the coarsest levels and six above; four with several right-hand sides (their
 // per-lane sums of up to 256 right-hand sides take registers), two with FP64 weights.
 template <typename R, typename U, bool kMulti, bool kBase>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 : 6)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
+__global__ __launch_bounds__((kMulti ? kRhsBlock : kBlock), (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 : 6)) : 2)) void batch_walks(const Segment *__restrict__ segs, int32_t nseg,
                                                       uint64_t item_lo, uint64_t item_hi,
                                                       uint32_t xcd_run, BatchParams *prm)
 {
@@ -111,10 +111,11 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 
     // stretch of it). The index is read with readfirstlane so the loop is wave-uniform in the
     // compiled control flow. (A shared atomic work counter was measured to serialise at about
     // one returning atomic per microsecond across the XCDs.)
-    const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWavesPerBlock;
+    constexpr int kWpb = kMulti ? kRhsBlock / kWave : kWavesPerBlock;   // waves per workgroup
+    const uint64_t waves = static_cast<uint64_t>(gridDim.x) * kWpb;
     const uint32_t xcd_block = xcd_renumber(blockIdx.x, gridDim.x, xcd_run);
     const uint64_t wave_id = __builtin_amdgcn_readfirstlane(
-        static_cast<uint64_t>(xcd_block) * kWavesPerBlock + threadIdx.x / kWave);
+        static_cast<uint64_t>(xcd_block) * kWpb + threadIdx.x / kWave);
     for (uint64_t item = item_lo + wave_id; item < item_hi; item += waves) {
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 
         } else {
             const int32_t nrhs = sg.nrhs;
             SinkRhs<R, U> sink{u, nrhs, (nrhs + kWave - 1) / kWave};
-            walk_range<R, false, false>(L, row, 0u, wb, we, sink);
+            walk_range<R, false, false, false, false, true>(L, row, 0u, wb, we, sink);
             jumps = wave_sum_u(sink.jumps);
             nonfinite = wave_sum_u(sink.nonfinite);
             const unsigned long long nojump = wave_sum_u(sink.nojump);
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? (kMulti ? 4 : (kBase ? 7 
         }
         if (lane == 0) {
             unsigned long long *c = sg.counters + (wave_id % kSegSlots) * kCounterStride;
-            atomicAdd(&c[0], jumps);
+            if (jumps) atomicAdd(&c[0], jumps);   // most items of a screened level have none
             if (nonfinite) atomicAdd(&c[1], nonfinite);
         }
     }
@@ -314,20 +315,21 @@ namespace {
 void free_batch(mlmc_batch *b)
 {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
-    if (b->ev0) hipEventDestroy(b->ev0);
-    if (b->ev1) hipEventDestroy(b->ev1);
-    hipFree(b->d_segs);
-    hipFree(b->d_outs);
-    hipFree(b->d_prm);
-    hipFree(b->d_counters);
-    hipFree(b->d_counter_sums);
-    hipFree(b->d_partial);
-    hipFree(b->d_acc);
-    hipFree(b->d_moments);
-    hipFree(b->d_moment_scratch);
+    // teardown: a failure here leaves nothing to recover, so the statuses are not kept
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    (void)hipFree(b->d_segs);
+    (void)hipFree(b->d_outs);
+    (void)hipFree(b->d_prm);
+    (void)hipFree(b->d_counters);
+    (void)hipFree(b->d_counter_sums);
+    (void)hipFree(b->d_partial);
+    (void)hipFree(b->d_acc);
+    (void)hipFree(b->d_moments);
+    (void)hipFree(b->d_moment_scratch);
     delete b;
 }
 
@@ -408,11 +410,12 @@ hipError_t launch_walks(const mlmc_batch *b, const Shape &sh, const Segment *d_s
     // workgroups either way (the kernel's renumbering of the waves needs it)
     const uint64_t waves = sh.waves_per_cu > 0 ? static_cast<uint64_t>(kCUs) * sh.waves_per_cu
                                                : item_hi - item_lo;
-    const uint64_t blocks = (waves + kWavesPerBlock * kXcds - 1) / (kWavesPerBlock * kXcds) * kXcds;
+    const uint64_t wpb = b->multi ? kRhsBlock / kWave : kWavesPerBlock;   // waves per workgroup
+    const uint64_t blocks = (waves + wpb * kXcds - 1) / (wpb * kXcds) * kXcds;
     if (blocks == 0 || blocks > 0x7FFFFFFFull) return hipErrorInvalidConfiguration;
     const dim3 grid(static_cast<uint32_t>(blocks));
     const uint32_t xcd_run = sh.waves_per_cu > 0 ? grid.x / kXcds : kXcdRun;
-    const dim3 block(kBlock);
+    const dim3 block(b->multi ? kRhsBlock : kBlock);
 #define MLMC_BATCH(R, U, MULTI)                                                                        \
     do {                                                                                               \
         if (!(MULTI) && base)                                                                          \
@@ -588,14 +591,16 @@ int autotune(mlmc_batch *b, hipStream_t s)
                 hipLaunchKernelGGL(batch_reset, dim3(blocks_of(kSegSetU64 * segs.size(), 256)), dim3(256), 0, s,
                                    b->d_prm, ctr, static_cast<int32_t>(kSegSetU64 * segs.size()));
                 hipLaunchKernelGGL(batch_set_key, dim3(1), dim3(64), 0, s, b->d_prm, 0x5EEDu, rep + 1u);
-                hipEventRecord(e0, s);
+                if (hipEventRecord(e0, s) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune event");
                 int32_t phases = 0;
-                if (launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, base, s,
+                if (rc == MLMC_OK &&
+                    launch_phases(b, cands[ci], dseg, static_cast<int32_t>(segs.size()), items, base, s,
                                   &phases) != hipSuccess)
                     rc = fail(MLMC_ERR_HIP, "autotune launch");
-                hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune sync");
-                hipEventElapsedTime(&ms, e0, e1);
+                if (rc == MLMC_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune event");
+                if (rc == MLMC_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(MLMC_ERR_HIP, "autotune sync");
+                if (rc == MLMC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    rc = fail(MLMC_ERR_HIP, "autotune timing");
             }
             if (rc == MLMC_OK && b->tune_n < MLMC_BATCH_TUNE_MAX) {
                 b->tune_ms[b->tune_n] = ms;
@@ -608,12 +613,12 @@ int autotune(mlmc_batch *b, hipStream_t s)
                 pick = cands[ci];
             }
         }
-        hipFree(part);
-        hipFree(ctr);
-        hipFree(dseg);
+        (void)hipFree(part);
+        (void)hipFree(ctr);
+        (void)hipFree(dseg);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->shape = pick;
     std::lock_guard<std::mutex> lk(g_tune_mutex);

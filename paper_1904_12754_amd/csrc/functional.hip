@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void functional_w
         partial[static_cast<size_t>(item) * 2 + 0] = a;
         partial[static_cast<size_t>(item) * 2 + 1] = b;
         unsigned long long *c = counter_slot(counters, item);
-        atomicAdd(&c[0], jumps);
+        if (jumps) atomicAdd(&c[0], jumps);
         if (nonfinite) atomicAdd(&c[1], nonfinite);
         if (kHash) atomicAdd(hash_sum, hsum);
     }
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 6 : 2)) void forward_walk
     const unsigned long long hsum = wave_sum_u(sink.hash);
     if (lane == 0) {
         unsigned long long *c = counter_slot(counters, item);
-        atomicAdd(&c[0], jumps);
+        if (jumps) atomicAdd(&c[0], jumps);
         if (nonfinite) atomicAdd(&c[1], nonfinite);
         if (kHash) atomicAdd(hash_sum, hsum);
     }

@@ -20,6 +20,8 @@ struct LevelArgs {
     float dt_below, dt_above;  // FP32 bounds around dt for the certified holding-time test
     uint32_t k0, k1;         // Philox key (seed)
     uint32_t c3_step, c3_jump;
+    uint32_t screen;         // 1: most walks never jump, so kernels that can screen them
+                             // first test every step of each walk at its start row
 };
 
 enum class Prec { FP64, FP32 };

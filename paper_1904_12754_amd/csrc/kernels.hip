@@ -95,13 +95,13 @@ __global__ __launch_bounds__(kBlock, (walk_min_waves<R, kIS, kSrc, kBase>())) vo
     }
     if (lane == 0) {
         unsigned long long *c = counter_slot(counters, wave);
-        atomicAdd(&c[0], jumps);
+        if (jumps) atomicAdd(&c[0], jumps);
         if (nonfinite) atomicAdd(&c[1], nonfinite);
     }
 }
 
 template <typename R, typename U, bool kHash, bool kIS>
-__global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
+__global__ __launch_bounds__(kRhsBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_rhs(LevelArgs L, const U *__restrict__ u,
                                                           int32_t nrhs,
                                                           const int64_t *__restrict__ rows,
                                                           uint32_t n_rows, uint32_t walk0,
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_
                                                           unsigned long long *hash_sums)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * kWavesPerBlock + (threadIdx.x / kWave);
+    const uint64_t item = blockIdx.x;                  // one wave per workgroup
     if (item >= static_cast<uint64_t>(n_rows) * chunks) return;
     const uint32_t q = static_cast<uint32_t>(item / chunks);
     const uint32_t c = static_cast<uint32_t>(item % chunks);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_
     const uint64_t wb = static_cast<uint64_t>(c) * chunk;
     const uint64_t we = min(wb + chunk, static_cast<uint64_t>(M));
     SinkRhs<R, U> sink{u, nrhs, (nrhs + kWave - 1) / kWave};
-    walk_range<R, kHash, kIS>(L, row, walk0, wb, we, sink);
+    walk_range<R, kHash, kIS, false, false, !kHash>(L, row, walk0, wb, we, sink);
     const unsigned long long jumps = wave_sum_u(sink.jumps);
     const unsigned long long nojump = wave_sum_u(sink.nojump);
     const unsigned long long nonfinite = wave_sum_u(sink.nonfinite);
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock, (sizeof(R) == 4 ? 4 : 2)) void level_walks_
     }
     if (lane == 0) {
         unsigned long long *c = counter_slot(counters, item);
-        atomicAdd(&c[0], jumps);
+        if (jumps) atomicAdd(&c[0], jumps);   // most items of a screened level have none
         if (nonfinite) atomicAdd(&c[1], nonfinite);
         if (kHash) atomicAdd(&hash_sums[q], hsum);
     }
@@ -379,8 +379,8 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
     if (nrhs == 1)
         while (lpr > 1 && lpr / 2 >= chunk) lpr /= 2;
     const uint64_t waves = nrhs == 1 ? (items + kWave / lpr - 1) / (kWave / lpr) : items;
-    const dim3 grid(static_cast<uint32_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock));
-    const dim3 block(kBlock);
+    const dim3 grid(static_cast<uint32_t>(nrhs == 1 ? (waves + kWavesPerBlock - 1) / kWavesPerBlock : waves));
+    const dim3 block(nrhs == 1 ? kBlock : kRhsBlock);
     const uint32_t nr = static_cast<uint32_t>(n_rows);
 #define MLMC_LAUNCH_WALKS(R, U, H, IS)                                                        \
     do {                                                                                      \

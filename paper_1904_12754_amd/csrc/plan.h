@@ -29,6 +29,8 @@ struct mlmc_plan {
     int64_t n = 0, n_rows = 0, n_slots = 0;
     int32_t l0 = 0, precision = 0;
     double beta = 0, r_max = 0, d_min = 0, d_max = 0;
+    double jump_probability = 0;             // mean over the requested rows of 1 - e^{-beta r_i}
+    int32_t screen = 0;                      // walks are screened (jump_probability < 1/4)
     SlotRec *slots = nullptr;
     RowRec *rows_base = nullptr;
     RowRec *level_rec[kMaxLevel + 1] = {};

@@ -35,6 +35,11 @@ namespace mlmc {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
+// The kernels with several right-hand sides run in workgroups of one wave: their waves are
+// short (an item of a screened level is its walks' step draws and the per-row sums), and a
+// slot of one wave is refilled as soon as that wave ends, where a slot of four waits for the
+// slowest of them.
+constexpr int kRhsBlock = kWave;
 
 template <typename R>
 __device__ __forceinline__ R d_of(const RowRec &r);
@@ -468,24 +473,51 @@ struct AliasStart {
 
 // kBase: the level is the coarsest (l0) by construction, so the code for the coarse
 // functional and for held walks is left out; otherwise L.base decides at run time.
-template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase = false, typename Sink, typename Start>
+// kScreen: when the level's walks mostly never jump (L.screen), each lane first draws the
+// step blocks of its walks wb + lane + 64 j (j < 64) and tests every step at the start row.
+// A walk none of whose steps jumps holds at its start row for the whole time: the sink
+// counts it as such (sink.no_jumps(): its sample is the same for every such walk), at the
+// cost of its step draws alone. The lane marks the others, and the loop runs them from
+// their first step like any walk (their paths and samples are those of the unscreened
+// loop). Only for one start row per range (the counters' row is the group's row), a
+// range of at most 4096 walks and a whole wave per range.
+template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase = false, bool kScreen = false,
+          typename Sink, typename Start>
 __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
                                                 uint64_t wb, uint64_t we, Sink &sink,
                                                 uint32_t lpr = kWave);
 
-template <typename R, bool kHash, bool kIS, bool kSrc = false, bool kBase = false, typename Sink>
+template <typename R, bool kHash, bool kIS, bool kSrc = false, bool kBase = false,
+          bool kScreen = false, typename Sink>
 __device__ __forceinline__ void walk_range(const LevelArgs &L, uint32_t row, uint32_t walk0,
                                            uint64_t wb, uint64_t we, Sink &sink,
                                            uint32_t lpr = kWave)
 {
     const FixedStart st{row, L.rec[row]};
-    walk_range_from<R, kHash, kIS, kSrc, kBase>(L, st, walk0, wb, we, sink, lpr);
+    walk_range_from<R, kHash, kIS, kSrc, kBase, kScreen>(L, st, walk0, wb, we, sink, lpr);
 }
 
-template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase, typename Sink, typename Start>
+constexpr uint64_t kScreenMaxWalks = static_cast<uint64_t>(kWave) * 64;
+
+// The screening state of a lane: whether the range was screened, and its walks
+// wb + lane + 64 j that jump (bit j). Empty where screening is compiled out.
+template <bool kOn>
+struct ScreenState {
+    bool on = false;
+    uint64_t marked = 0;
+};
+template <>
+struct ScreenState<false> {};
+__device__ __forceinline__ bool screening_on(const ScreenState<true> &s) { return s.on; }
+__device__ __forceinline__ constexpr bool screening_on(const ScreenState<false> &) { return false; }
+
+template <typename R, bool kHash, bool kIS, bool kSrc, bool kBase, bool kScreen, typename Sink,
+          typename Start>
 __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start &st, uint32_t walk0,
                                                 uint64_t wb, uint64_t we, Sink &sink, uint32_t lpr)
 {
+    static_assert(!kScreen || (!Start::kPerLaneRow && !kHash && !kSrc),
+                  "screening needs one start row per range and no path hash or source term");
     const bool base = kBase || L.base != 0;
     const int ibase = base ? 1 : 0;
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -494,9 +526,65 @@ __device__ __forceinline__ void walk_range_from(const LevelArgs &L, const Start 
     Walker<R, kHash> s;
     Pending<R, kSrc> pend;
     uint64_t pool = wb;                    // next unassigned walk of the group
+    [[maybe_unused]] ScreenState<kScreen> scr;
+    if constexpr (kScreen) {
+        scr.on = L.screen != 0 && lpr >= kWave && we - wb <= kScreenMaxWalks;
+        if (scr.on) {
+            const uint32_t thr = st.rec.thr;
+            const uint32_t row0 = st.start_row();
+            // the lane's (walk j, block q) pairs t = j * blocks + q, four independent Philox
+            // blocks at a time (a block is a chain of dependent multiplies: four chains keep
+            // the SIMD issuing while each waits)
+            const uint32_t lb = L.N >= 4u ? static_cast<uint32_t>(__builtin_ctz(L.N)) - 2u : 0u;
+            const uint32_t walks_lane = lane < we - wb ? static_cast<uint32_t>((we - wb - lane + kWave - 1) / kWave) : 0u;
+            const uint32_t pairs = walks_lane << lb;
+            const uint32_t pairs_max = static_cast<uint32_t>((we - wb + kWave - 1) / kWave) << lb;
+            for (uint32_t t0 = 0; t0 < pairs_max; t0 += 4) {
+                Word4 ph[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t t = t0 + v;
+                    const uint32_t w = walk0 + static_cast<uint32_t>(wb + static_cast<uint64_t>(t >> lb) * kWave + lane);
+                    ph[v] = philox10(Word4{t & ((1u << lb) - 1u), w, row0, L.c3_step}, L.k0, L.k1);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t t = t0 + v;
+                    // words past step N (levels 0 and 1) are not steps
+                    const bool jump = ph[v].x > thr || (L.N > 1u && ph[v].y > thr) ||
+                                      (L.N > 2u && (ph[v].z > thr || ph[v].w > thr));
+                    if (t < pairs && jump) scr.marked |= 1ull << (t >> lb);
+                }
+            }
+            sink.no_jumps(walks_lane - static_cast<uint32_t>(__popcll(scr.marked)));
+        }
+    }
     for (;;) {
-        // ---- refill idle lanes with the next walks of the group's range
-        const uint64_t idle = __ballot(s.st == kIdle) & group;
+        if constexpr (kScreen) {
+            if (scr.on) {
+                // ---- the lane's next marked walk
+                if (s.st == kIdle && scr.marked != 0) {
+                    const uint32_t j = static_cast<uint32_t>(__builtin_ctzll(scr.marked));
+                    scr.marked &= scr.marked - 1;
+                    s.st = kScan;
+                    s.w = walk0 + static_cast<uint32_t>(wb + static_cast<uint64_t>(j) * kWave + lane);
+                    uint32_t r0 = 0, ng = 0;
+                    st.pick(L, s.w, r0, s.cur, ng);
+                    s.k = r0;
+                    s.neg = ng;
+                    s.J = 0;
+                    s.run_start = 0;
+                    s.n = 0;
+                    s.bq = 0xFFFFFFFFu;
+                    s.ef2 = s.ec2 = s.ed2 = 0;
+                    s.wr = 1;
+                    s.jf = s.jc = 0;
+                }
+            }
+        }
+        // ---- refill idle lanes with the next walks of the group's range (a screened range
+        // runs its marked walks instead)
+        const uint64_t idle = screening_on(scr) ? 0ull : __ballot(s.st == kIdle) & group;
         if (idle) {
             // the idle lanes of the group below this one (v_mbcnt)
             const uint32_t below = __builtin_amdgcn_mbcnt_hi(
@@ -709,6 +797,9 @@ struct SinkRhs {
     int groups;
     LaneMoments<R> mom[kMaxRhsGroups];
     unsigned long long jumps = 0, nojump = 0, nonfinite = 0, hash = 0;
+    // a walk that never left its start row, screened before the loop (its path hash is not
+    // kept: screening runs without hashes)
+    __device__ __forceinline__ void no_jumps(uint32_t count) { nojump += count; }
     __device__ __forceinline__ void take(bool done, const Finished<R> &f)
     {
         const bool moved = done && f.jumps > 0;

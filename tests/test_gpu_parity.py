@@ -128,6 +128,7 @@ def _check_level_sums(api, A, beta, u, precision, nlev, walks, seed, rows=None,
     vals = np.asarray(A.values, dtype=values_dtype).astype(np.float64)
     t = orc.decompose(A.n, A.row_ptr, A.col_idx, vals)
     assert plan.l0 == orc.default_l0(t, beta)
+    screened = bool(plan.info["screened"])
     ut = torch.as_tensor(np.ascontiguousarray(u), device="cuda")
     for lev in range(plan.l0, plan.l0 + nlev):
         _say(f"level_sums n={A.n} prec={precision} level={lev} M={walks} R={ut.shape[-1] if ut.dim() > 1 else 1}")
@@ -136,15 +137,25 @@ def _check_level_sums(api, A, beta, u, precision, nlev, walks, seed, rows=None,
         assert jumps == int(o.jumps.sum())
         # the production kernel's paths: per-row sums of the path hashes, bit-exact
         assert np.array_equal(hs.cpu().numpy().view(np.uint64), o.hash_sum)
+        runs = [(s1, s2)]
         if hashes_only_check:
+            # the kernel without path hashes (the production one) takes the same paths; with
+            # several right-hand sides on a screened plan it first screens out the walks that
+            # never jump, so its compensated sums add the moved walks in another order
             s1b, s2b, jb = plan.level_sums(ut, lev, walk0, walks, seed=seed)
-            assert jb == jumps and torch.equal(s1b, s1) and torch.equal(s2b, s2)
-        g1 = s1.cpu().numpy()
-        g2 = s2.cpu().numpy()
-        assert np.all(np.abs(g1 - o.sum1) <= _mass_tol(o, precision))
-        # sums of squares: the error of each Y^2 is below 2 tol m_w^2
-        assert np.all(np.abs(g2 - o.sum2) <= 4 * TOL[precision] * (o.mass2 + 1e-300))
+            assert jb == jumps
+            if screened and ut.dim() > 1 and ut.shape[1] > 1:
+                runs.append((s1b, s2b))
+            else:
+                assert torch.equal(s1b, s1) and torch.equal(s2b, s2)
+        for a1, a2 in runs:
+            g1 = a1.cpu().numpy()
+            g2 = a2.cpu().numpy()
+            assert np.all(np.abs(g1 - o.sum1) <= _mass_tol(o, precision))
+            # sums of squares: the error of each Y^2 is below 2 tol m_w^2
+            assert np.all(np.abs(g2 - o.sum2) <= 4 * TOL[precision] * (o.mass2 + 1e-300))
     plan.close()
+    return screened
 
 
 def test_level_sums_fp64_laplace1d_ragged(api):
@@ -169,14 +180,39 @@ def test_level_sums_signed_u32_walk_offset(api, precision):
 
 @pytest.mark.parametrize("R", [3, 64, 130])
 def test_level_sums_multi_rhs(api, R):
+    """Several right-hand sides on a Barabasi-Albert graph at beta = 1/d_max, where few walks
+    jump: the plan screens its walks (each walk's steps drawn at its start row first), and
+    the screened kernel's sums, jumps and paths are the oracle's."""
     A = inputs.barabasi_albert(3000, 3, seed=4)
     dmax = float(np.diff(A.row_ptr).max())
     beta = 1.0 / dmax
     u = inputs.rhs_ones_rademacher(A.n, R, seed=7)
     rows = np.random.default_rng(3).choice(A.n, size=300, replace=False)
     rows[0] = int(np.argmax(np.diff(A.row_ptr)))            # the hub
-    _check_level_sums(api, A, beta, u, "fp32", 3, 200, seed=3, rows=rows,
-                      values_dtype=np.float32)
+    assert _check_level_sums(api, A, beta, u, "fp32", 3, 200, seed=3, rows=rows,
+                             values_dtype=np.float32)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_level_sums_multi_rhs_screened_ragged(api, precision):
+    """A screened plan (a signed matrix at a small beta) with 5 right-hand sides and 4096 and
+    777 walks per row, on levels 0..3 (levels 0 and 1 have fewer steps than a Philox block
+    has words)."""
+    a = _signed(40, 13, density=0.3)
+    A = inputs.from_dense(a)
+    u = np.random.default_rng(4).normal(size=(40, 5))
+    beta = 0.02
+    assert _check_level_sums(api, A, beta, u, precision, 4, 4096, seed=21)
+    assert _check_level_sums(api, A, beta, u, precision, 4, 777, seed=22, walk0=5)
+
+
+def test_level_sums_multi_rhs_screened_full_ranges(api):
+    """16384 rows with 4096 walks each: every wave screens one whole 4096-walk range (64
+    walks per lane, the most a screened range holds), 3 right-hand sides, FP32 weights."""
+    A = inputs.barabasi_albert(16384, 3, seed=8)
+    beta = 1.0 / float(np.diff(A.row_ptr).max())
+    u = inputs.rhs_ones_rademacher(A.n, 3, seed=9)
+    assert _check_level_sums(api, A, beta, u, "fp32", 2, 4096, seed=23, values_dtype=np.float32)
 
 
 @pytest.mark.parametrize("precision,M", [("fp64", 1), ("fp32", 5), ("fp64", 8), ("fp32", 17),
