@@ -202,6 +202,12 @@ def test_level_sums_multi_rhs_screened_ragged(api, precision):
     A = inputs.from_dense(a)
     u = np.random.default_rng(4).normal(size=(40, 5))
     beta = 0.02
+    # the plan's jump probability: the mean over the rows of 1 - exp(-beta r_i)
+    r = np.abs(a).sum(axis=1) - np.abs(np.diag(a))
+    plan = api.Plan(A, beta, precision=precision)
+    assert plan.info["jump_probability"] == pytest.approx(np.mean(-np.expm1(-beta * r)), rel=1e-12)
+    assert plan.info["screened"] == 1
+    plan.close()
     assert _check_level_sums(api, A, beta, u, precision, 4, 4096, seed=21)
     assert _check_level_sums(api, A, beta, u, precision, 4, 777, seed=22, walk0=5)
 
