@@ -486,6 +486,28 @@ int mlmc_expv_proposal_train(mlmc_plan_t *plan, const void *u, int32_t u_dtype,
                              const mlmc_train_opts_t *opts, float *params_out,
                              mlmc_train_stats_t *stats, void *stream);
 
+/* Algorithm 1 with the proposal of level l0 learned inside the run (a project addition;
+ * each level's expectation, and so the estimator of section 2.2, is unchanged).
+ *   1. The run's plain pilot: M0 walks per row on l0 .. l0 + 4 (as mlmc_expv_run).
+ *   2. Training on its estimate xhat = sum of the pilot's level means, as
+ *      mlmc_expv_proposal_train does after its own pilot: capture, Adam with early
+ *      stopping, tables. train->pilot_walks and train->judge_walks are not read;
+ *      train->num_levels must be 1.
+ *   3. The judge: M0 level-l0 walks under the proposal, with the pilot's walk indices.
+ *      They replace the plain pilot's level-l0 walks if their mean per-walk variance is
+ *      lower; otherwise they are dropped and the run keeps the plain law.
+ *   4. The rest of Algorithm 1, as mlmc_expv_run.
+ * The proposal stays set, and enabled iff it won. Needs nrhs = 1, u FP32 (DEVICE, n
+ * entries), a plan over all rows and opts->eps > 0.
+ * stats: walks[0] counts the walks of the estimate; steps and jumps count every walk run,
+ * the dropped ones included. train_stats (nullable): as mlmc_expv_proposal_train's, with
+ * train_ms the device time from the end of the pilot to the judge's verdict.
+ * params_out: HOST, nullable. Waits for the stream. */
+int mlmc_expv_run_learned(mlmc_plan_t *plan, const void *u, int32_t u_dtype,
+                          const mlmc_run_opts_t *opts, const mlmc_train_opts_t *train,
+                          float *params_out, double *x, mlmc_stats_t *stats,
+                          mlmc_train_stats_t *train_stats, void *stream);
+
 const char *mlmc_status_string(int status);
 const char *mlmc_last_error(void);
 

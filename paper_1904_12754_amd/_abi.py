@@ -39,7 +39,8 @@ EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_
            "mlmc_expv_batch_launch", "mlmc_expv_batch_stats", "mlmc_expv_batch_info",
            "mlmc_expv_batch_destroy", "mlmc_expv_proposal_set", "mlmc_expv_proposal_enable",
            "mlmc_expv_proposal_tables", "mlmc_expv_proposal_loss_grad",
-           "mlmc_expv_proposal_train", "mlmc_status_string", "mlmc_last_error",
+           "mlmc_expv_proposal_train", "mlmc_expv_run_learned", "mlmc_status_string",
+           "mlmc_last_error",
            "mlmc_probe_gather", "mlmc_probe_valu")
 
 MLMC_PROPOSAL_PARAMS = 5703
@@ -246,6 +247,10 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_proposal_train.argtypes = [vp, vp, i32, ctypes.POINTER(TrainOpts), fp,
                                            ctypes.POINTER(TrainStats), vp]
     L.mlmc_expv_proposal_train.restype = ctypes.c_int
+    L.mlmc_expv_run_learned.argtypes = [vp, vp, i32, ctypes.POINTER(RunOpts),
+                                        ctypes.POINTER(TrainOpts), fp, vp, ctypes.POINTER(Stats),
+                                        ctypes.POINTER(TrainStats), vp]
+    L.mlmc_expv_run_learned.restype = ctypes.c_int
     L.mlmc_probe_gather.argtypes = [vp, i32, i32, i32, ctypes.POINTER(u64), ctypes.POINTER(f64), vp]
     L.mlmc_probe_gather.restype = ctypes.c_int
     L.mlmc_probe_valu.argtypes = [i32, i32, ctypes.POINTER(u64), ctypes.POINTER(f64), vp]

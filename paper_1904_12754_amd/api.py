@@ -382,6 +382,34 @@ class Plan:
         del P
         return out, st.to_dict()
 
+    def run_learned(self, u: torch.Tensor, eps: float, init_params, seed: int = 0,
+                    instance: int = 0, pilot_walks: int = 0, max_levels: int = 20,
+                    max_walks: int = 0, train_seed: int = 0, capture_walks: int = 16,
+                    sample_stride: int = 1, steps: int = 16, batch: int = 4096,
+                    lr: float = 1e-2, shrink: float = 1.0, stream=None, allow=()):
+        """Algorithm 1 with the proposal of level l0 trained inside the run on the pilot's
+        estimate and judged against the pilot's plain level-l0 walks; returns
+        (x, stats, train_stats, params)."""
+        u, R, dt = _u_args(u, self.n)
+        if R != 1:
+            raise ValueError("the learned run reads one right-hand side")
+        x = torch.empty((self.n_rows, 1), dtype=torch.float64, device=u.device)
+        opts = _abi.RunOpts(seed, instance, 0, None, float(eps), int(pilot_walks),
+                            int(max_levels), int(max_walks))
+        P, pp = self._params(init_params)
+        topts = _abi.TrainOpts(int(train_seed), pp, 0, int(capture_walks), int(sample_stride),
+                               int(steps), int(batch), float(lr), float(shrink), 1, 0)
+        out = np.zeros(_abi.MLMC_PROPOSAL_PARAMS, np.float32)
+        stats = _abi.Stats()
+        tst = _abi.TrainStats()
+        code = self._lib.mlmc_expv_run_learned(
+            self._handle, _dev_ptr(u), dt, ctypes.byref(opts), ctypes.byref(topts),
+            out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _dev_ptr(x), ctypes.byref(stats),
+            ctypes.byref(tst), _stream_ptr(stream))
+        check(code, allow)
+        del P
+        return x, stats.to_dict(), tst.to_dict(), out
+
     def current_info(self) -> dict:
         """mlmc_expv_plan_info now (device_bytes grows as levels and buffers are added)."""
         info = _abi.PlanInfo()

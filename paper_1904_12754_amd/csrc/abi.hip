@@ -689,8 +689,13 @@ int mlmc_expv_trace(mlmc_plan_t *p, uint64_t seed, int32_t instance, int32_t lev
     return MLMC_OK;
 }
 
-int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, const mlmc_run_opts_t *o,
-                  double *x, mlmc_stats_t *stats, void *stream)
+namespace {
+
+// The full-vector run (fixed schedule or Algorithm 1). With `learn`, the adaptive run
+// trains the proposal of level l0 after its plain pilot (see mlmc_expv_run_learned).
+int run_impl(mlmc_plan *p, const void *u, int32_t nrhs, int32_t u_dtype, const mlmc_run_opts_t *o, double *x,
+             mlmc_stats_t *stats, const mlmc_train_opts_t *learn, float *params_out, mlmc_train_stats_t *tst,
+             void *stream)
 {
     if (!p || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
     if (!x && p->n_rows > 0) return fail(MLMC_ERR_INVALID_ARG, "x is null");
@@ -719,11 +724,16 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
                 return fail(MLMC_ERR_INVALID_ARG, "walks per level must be in [1, 2^32)");
         max_levels = o->num_levels;
     }
-    if ((rc = ensure_acc(p, max_levels, nrhs))) return rc;
+    // a learned run keeps one more pair of accumulators: level l0 under the proposal
+    if ((rc = ensure_acc(p, max_levels + (learn ? 1 : 0), nrhs))) return rc;
     const size_t stride = static_cast<size_t>(2) * count;
-    auto s1_of = [&](int qq) { return p->acc + qq * stride; };
-    auto s2_of = [&](int qq) { return p->acc + qq * stride + count; };
+    bool alt0 = false;   // level l0 sits in the spare pair
+    auto base_of = [&](int qq) { return p->acc + (qq == 0 && alt0 ? max_levels : qq) * stride; };
+    auto s1_of = [&](int qq) { return base_of(qq); };
+    auto s2_of = [&](int qq) { return base_of(qq) + count; };
     std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
+    int64_t extra0 = 0;  // walks of level l0 run but left out of the estimate
+    if (learn) p->proposal_on = false;   // the pilot walks with the plain law
     p->timing = stats != nullptr;
     p->tev_used = 0;
     struct TimingOff {   // the events time this run's launches only
@@ -762,7 +772,8 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     auto level_var = [&](int qq) { return unbiased_var(mom[qq].sum_v / cnt, M[qq]); };
     auto level_rms = [&](int qq) { return debiased_rms(mom[qq].sum_m2 / cnt, level_var(qq), M[qq]); };
     auto level_cost = [&](int qq) {
-        const double walks_total = static_cast<double>(M[qq]) * std::max<int64_t>(p->n_rows, 1);
+        const double walks_total =
+            static_cast<double>(M[qq] + (qq == 0 ? extra0 : 0)) * std::max<int64_t>(p->n_rows, 1);
         return std::ldexp(1.0, p->l0 + qq) + 4.0 * static_cast<double>(ctr[2 * qq]) / walks_total;
     };
     int levels = 0;
@@ -788,8 +799,64 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
             for (int qq = 0; qq < lv; ++qq) est[qq] = LevelEstimate{level_var(qq), level_cost(qq), level_rms(qq)};
             return MLMC_OK;
         };
+        // learned run: after the pilot, train on its estimate; the judge runs as many level-l0
+        // walks under the proposal (the same walk indices) into the spare pair and keeps them,
+        // in place of the plain ones, if their variance is lower
+        auto after_pilot = [&](int lv, std::vector<LevelEstimate> &est, bool &again) -> int {
+            if (!learn) return MLMC_OK;
+            hipEvent_t te[2] = {nullptr, nullptr};
+            struct Ev {
+                hipEvent_t *e;
+                ~Ev()
+                {
+                    for (int i = 0; i < 2; ++i)
+                        if (e[i]) (void)hipEventDestroy(e[i]);
+                }
+            } ev_guard{te};
+            MLMC_HIP_TRY(hipEventCreate(&te[0]));
+            MLMC_HIP_TRY(hipEventCreate(&te[1]));
+            MLMC_HIP_TRY(hipEventRecord(te[0], s));
+            CombineArgs xa{};
+            xa.levels = lv;
+            for (int qq = 0; qq < lv; ++qq) {
+                xa.s1[qq] = s1_of(qq);
+                xa.inv_M[qq] = 1.0 / static_cast<double>(M[qq]);
+            }
+            int r2 = train_from_levels(p, u, learn, xa, params_out, tst, s);
+            if (r2) return r2;
+            const double var_plain = est[0].var;
+            const int64_t m_plain = M[0];
+            p->proposal_on = true;
+            alt0 = true;
+            M[0] = 0;
+            if ((r2 = add_walks(0, m_plain))) return r2;
+            MLMC_HIP_TRY(launch_level_moments(s1_of(0), s2_of(0), count, static_cast<double>(M[0]), p->moments,
+                                              p->moment_scratch, s));
+            double h[3];
+            MLMC_HIP_TRY(hipMemcpyAsync(h, p->moments, sizeof h, hipMemcpyDeviceToHost, s));
+            MLMC_HIP_TRY(hipEventRecord(te[1], s));
+            MLMC_HIP_TRY(hipStreamSynchronize(s));
+            const double var_learned = unbiased_var(h[2] / cnt, M[0]);
+            const bool accepted = var_learned < var_plain;
+            if (!accepted) {
+                alt0 = false;
+                M[0] = m_plain;
+                p->proposal_on = false;
+            }
+            extra0 = m_plain;
+            if (tst) {
+                float ms = 0.0f;
+                MLMC_HIP_TRY(hipEventElapsedTime(&ms, te[0], te[1]));
+                tst->train_ms = ms;
+                tst->judge_var_plain = var_plain;
+                tst->judge_var_learned = var_learned;
+                tst->accepted = accepted ? 1 : 0;
+            }
+            again = true;
+            return MLMC_OK;
+        };
         DriverOut out;
-        if ((rc = algorithm1(d, M, add_walks, measure, out))) return rc;
+        if ((rc = algorithm1(d, M, add_walks, measure, after_pilot, out))) return rc;
         levels = out.levels;
         converged = out.converged;
         iterations = out.iterations;
@@ -820,7 +887,7 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
             stats->level_mean_rms[qq] = level_rms(qq);
             stats->level_var[qq] = level_var(qq);
             stats->level_cost[qq] = level_cost(qq);
-            stats->steps += M[qq] * p->n_rows * (int64_t(1) << (p->l0 + qq));
+            stats->steps += (M[qq] + (qq == 0 ? extra0 : 0)) * p->n_rows * (int64_t(1) << (p->l0 + qq));
             stats->total_jumps += static_cast<int64_t>(ctr[2 * qq]);
             stats->nonfinite += static_cast<int64_t>(ctr[2 * qq + 1]);
             var += level_var(qq) / static_cast<double>(M[qq]);
@@ -842,6 +909,28 @@ int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, 
     }
     if (adaptive && !converged) return fail(MLMC_ERR_NOT_CONVERGED, "level or walk cap reached before eps");
     return MLMC_OK;
+}
+
+}  // namespace
+
+int mlmc_expv_run(mlmc_plan_t *p, const void *u, int32_t nrhs, int32_t u_dtype, const mlmc_run_opts_t *o,
+                  double *x, mlmc_stats_t *stats, void *stream)
+{
+    return run_impl(p, u, nrhs, u_dtype, o, x, stats, nullptr, nullptr, nullptr, stream);
+}
+
+int mlmc_expv_run_learned(mlmc_plan_t *p, const void *u, int32_t u_dtype, const mlmc_run_opts_t *o,
+                          const mlmc_train_opts_t *t, float *params_out, double *x, mlmc_stats_t *stats,
+                          mlmc_train_stats_t *train_stats, void *stream)
+{
+    if (!p || !o || !t) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (!(o->eps > 0.0)) return fail(MLMC_ERR_INVALID_ARG, "the learned run is adaptive: eps must be > 0");
+    if (u_dtype != MLMC_DTYPE_F32) return fail(MLMC_ERR_UNSUPPORTED, "training reads an FP32 right-hand side");
+    if (t->num_levels != 1) return fail(MLMC_ERR_INVALID_ARG, "the learned run sets tables for level l0 only");
+    int rc;
+    if ((rc = check_learned_opts(p, t))) return rc;
+    if (train_stats) std::memset(train_stats, 0, sizeof *train_stats);
+    return run_impl(p, u, 1, u_dtype, o, x, stats, t, params_out, train_stats, stream);
 }
 
 

@@ -77,9 +77,12 @@ inline double extrapolated_bias(double mL, double mLm1)
 
 // add(q, extra) -> status: run `extra` more walks at level index q and count them in M[q].
 // measure(levels, est) -> status: fill est[q], q < levels, from the walks so far.
-template <class Add, class Measure>
+// after_pilot(levels, est, again) -> status: called once, after the pilot's measurement and
+// before any sample size is computed; it may replace walks (and M), and sets `again` when
+// the levels must be measured anew.
+template <class Add, class Measure, class AfterPilot>
 int algorithm1(const DriverOpts &o, std::vector<int64_t> &M, Add &&add, Measure &&measure,
-               DriverOut &out)
+               AfterPilot &&after_pilot, DriverOut &out)
 {
     const double eps2 = o.eps * o.eps;
     const double budget = eps2 / 2.0 * 1.0000001;
@@ -92,6 +95,11 @@ int algorithm1(const DriverOpts &o, std::vector<int64_t> &M, Add &&add, Measure 
     while (out.iterations < o.max_iterations) {
         ++out.iterations;
         if ((rc = measure(levels, est))) return rc;
+        if (out.iterations == 1) {
+            bool again = false;
+            if ((rc = after_pilot(levels, est, again))) return rc;
+            if (again && (rc = measure(levels, est))) return rc;
+        }
         double tot = 0.0;
         for (int q = 0; q < levels; ++q) tot += std::sqrt(std::max(est[q].var, 1e-300) * est[q].cost);
         bool topped = false, nan_size = false;
@@ -122,6 +130,13 @@ int algorithm1(const DriverOpts &o, std::vector<int64_t> &M, Add &&add, Measure 
     }
     out.levels = levels;
     return MLMC_OK;
+}
+
+template <class Add, class Measure>
+int algorithm1(const DriverOpts &o, std::vector<int64_t> &M, Add &&add, Measure &&measure,
+               DriverOut &out)
+{
+    return algorithm1(o, M, add, measure, [](int, std::vector<LevelEstimate> &, bool &) { return 0; }, out);
 }
 
 }  // namespace mlmc

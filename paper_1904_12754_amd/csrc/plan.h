@@ -74,5 +74,12 @@ namespace mlmc {
 int upload_level(mlmc_plan *p, int level, hipStream_t s);
 // Everything a walk of `level` of this plan reads.
 LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance);
+// Train the proposal on the pilot estimate xhat = sum_q s1_q inv_M_q (the level sums of a
+// run's pilot) and set it: capture, Adam, tables, as mlmc_expv_proposal_train without its
+// own pilot and judge (their options are not read). Waits for the stream.
+int train_from_levels(mlmc_plan *p, const void *u, const mlmc_train_opts_t *o, const CombineArgs &xhat,
+                      float *params_out, mlmc_train_stats_t *st, hipStream_t s);
+// The options train_from_levels reads, checked before a run starts.
+int check_learned_opts(const mlmc_plan *p, const mlmc_train_opts_t *o);
 
 }  // namespace mlmc

@@ -70,38 +70,56 @@ struct FeatureArgs {
     float dt, lvl;            // dt of the level, (l - l0) / 8
 };
 
-// Feature f (0..15) of row `row`, formed in FP64 and rounded once to FP32. Slot features are
-// 0 past the row's slots and for rows with more than NS slots.
-__device__ __forceinline__ float feature(const FeatureArgs &a, const RowRec &rr, uint32_t row,
-                                         int f, double xmax)
+// The 16 features of row `row`, each formed in FP64 and rounded once to FP32. Slot
+// features are 0 past the row's slots and for rows with more than NS slots. Every load of
+// the row (its slots' columns and plain probabilities, and the pilot estimate at those
+// columns) is issued before the first logarithm.
+__device__ __forceinline__ void row_features(const FeatureArgs &a, const RowRec &rr, uint32_t row, double xmax,
+                                             float f[NF])
 {
-    const bool elig = rr.deg >= 1 && rr.deg <= NS;
-    if (f < NS) {
-        if (!elig || f >= static_cast<int>(rr.deg)) return 0.0f;
-        return static_cast<float>(fmax(log(static_cast<double>(a.p_slot[rr.slot_begin + f])), kLogPMin));
-    }
-    if (f < 2 * NS) {
-        const int s = f - NS;
-        if (!elig || s >= static_cast<int>(rr.deg)) return 0.0f;
-        const uint32_t c = a.slots[rr.slot_begin + s].own & kColMask;
+    const uint32_t deg = rr.deg;
+    const bool elig = deg >= 1 && deg <= NS;
+    const double xr = fabs(a.xhat[row]);
+#pragma unroll
+    for (int s = 0; s < 2 * NS; ++s) f[s] = 0.0f;
+    if (elig) {
+        float ps[NS];
+        double xc[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            // slots past the row's last repeat its last slot (in range, results unused)
+            const uint32_t si = rr.slot_begin + min(static_cast<uint32_t>(s), deg - 1);
+            ps[s] = a.p_slot[si];
+            xc[s] = a.xhat[a.slots[si].own & kColMask];
+        }
         const double delta = 1e-6 * xmax;
-        const double lr = log((fabs(a.xhat[c]) + delta) / (fabs(a.xhat[row]) + delta));
-        return static_cast<float>(fmin(fmax(lr, -kLogRatioMax), kLogRatioMax));
+        const double xden = xr + delta;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (static_cast<uint32_t>(s) < deg) {
+                f[s] = static_cast<float>(fmax(log(static_cast<double>(ps[s])), kLogPMin));
+                const double lr = log((fabs(xc[s]) + delta) / xden);
+                f[NS + s] = static_cast<float>(fmin(fmax(lr, -kLogRatioMax), kLogRatioMax));
+            }
+        }
     }
-    if (f == 12) return (rr.inv_r < INFINITY) ? static_cast<float>(1.0 / rr.inv_r) * a.dt : 0.0f;
-    if (f == 13) return rr.d32 * a.dt;
-    if (f == 14) return static_cast<float>(fabs(a.xhat[row]) / xmax);
-    return a.lvl;
+    f[12] = (rr.inv_r < INFINITY) ? static_cast<float>(1.0 / rr.inv_r) * a.dt : 0.0f;
+    f[13] = rr.d32 * a.dt;
+    f[14] = static_cast<float>(xr / xmax);
+    f[15] = a.lvl;
 }
 
-__global__ void features_kernel(FeatureArgs a, float *F)
+// One row per thread; the row's 16 features are stored as four 16-byte vectors.
+__global__ __launch_bounds__(256) void features_kernel(FeatureArgs a, float *F)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const RowRec rr = a.rec[i];
-    const double xmax = *a.xmax;
+    float f[NF];
+    row_features(a, rr, static_cast<uint32_t>(i), *a.xmax, f);
+    float4_t *out = reinterpret_cast<float4_t *>(F + i * NF);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) F[i * NF + f] = feature(a, rr, static_cast<uint32_t>(i), f, xmax);
+    for (int v = 0; v < NF / 4; ++v) out[v] = float4_t{f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]};
 }
 
 // max |x| in two stages: kAbsmaxBlocks partial maxima, then the final one (1 when x is
@@ -272,89 +290,151 @@ __device__ void build_row(const TableArgs &a, const RowRec &rr, const float *q)
     }
 }
 
-// One wave per 16 rows: features -> MFMA MLP -> q -> alias tables and ratios.
-__global__ __launch_bounds__(256) void tables_kernel(TableArgs a)
+// Rows per workgroup and iteration of the tables kernel: four waves of 64 rows, one row
+// per lane. Each wave evaluates its 64 rows as four 16-row MFMA tiles.
+constexpr int kTabRows = 256;
+constexpr int kTabWaves = kTabRows / 64;
+constexpr int kTabGridMax = 256 * 4;   // four workgroups for each of the 256 CUs
+
+// Features -> MFMA MLP -> q -> alias tables and ratios. A workgroup stages the weight
+// fragments and biases in LDS once, then takes 256 rows per iteration (grid stride): every
+// lane forms its row's features, the wave's 64 rows pass through LDS into the B-operand
+// layout of the MFMA tiles, the tiles' outputs pass back through LDS to the row's lane, and
+// that lane builds the row's alias table.
+__global__ __launch_bounds__(kTabRows) void tables_kernel(TableArgs a)
 {
-    const int lane = static_cast<int>(threadIdx.x & 63);
-    const int r = lane % 16, g = lane / 16;
-    const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
-    const int64_t row64 = tile * 16 + r;
-    const bool inrow = row64 < a.fa.n;
-    const uint32_t row = inrow ? static_cast<uint32_t>(row64) : 0u;
-    const RowRec rr = a.fa.rec[row];
+    __shared__ short4_t s_frag[NFRAG / 4];
+    __shared__ float4_t s_b1[NH / 4], s_b2[NH / 4], s_b3[2];
+    __shared__ short4_t s_x[kTabWaves][64][NF / 4];   // BF16 features, row major
+    __shared__ float4_t s_o[kTabWaves][64][2];        // outputs 0..6 (+1 unused) per row
+    const int tid = static_cast<int>(threadIdx.x);
+    const int w = tid / 64, lane = tid & 63, r = lane % 16, g = lane / 16;
+    const int64_t n = a.fa.n;
+    const int64_t nit = (n + kTabRows - 1) / kTabRows;
     if (a.identity) {           // uniform over the launch
-        if (g == 0 && inrow) build_row(a, rr, nullptr);
+        for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
+            const int64_t row = it * kTabRows + tid;
+            if (row < n) build_row(a, a.fa.rec[row], nullptr);
+        }
         return;
     }
+    {
+        const short4_t *fr = reinterpret_cast<const short4_t *>(a.frag);
+        for (int i = tid; i < NFRAG / 4; i += kTabRows) s_frag[i] = fr[i];
+        const float4_t *P4 = reinterpret_cast<const float4_t *>(a.P);
+        if (tid < NH / 4) s_b1[tid] = P4[OFF_B1 / 4 + tid];
+        else if (tid < NH / 2) s_b2[tid - NH / 4] = P4[OFF_B2 / 4 + tid - NH / 4];
+        else if (tid < NH / 2 + 2) {
+            const int j = tid - NH / 2;
+            float4_t b;
+            b.x = a.P[OFF_B3 + 4 * j + 0];
+            b.y = a.P[OFF_B3 + 4 * j + 1];
+            b.z = a.P[OFF_B3 + 4 * j + 2];
+            b.w = 4 * j + 3 < NO ? a.P[OFF_B3 + 4 * j + 3] : 0.0f;
+            s_b3[j] = b;
+        }
+    }
     const double xmax = *a.fa.xmax;
-    float4_t xf;
-    xf.x = inrow ? feature(a.fa, rr, row, 4 * g + 0, xmax) : 0.0f;
-    xf.y = inrow ? feature(a.fa, rr, row, 4 * g + 1, xmax) : 0.0f;
-    xf.z = inrow ? feature(a.fa, rr, row, 4 * g + 2, xmax) : 0.0f;
-    xf.w = inrow ? feature(a.fa, rr, row, 4 * g + 3, xmax) : 0.0f;
-    const short4_t x = pack4(xf);
-    const short4_t *fr = reinterpret_cast<const short4_t *>(a.frag);
-    // layer 1: H1^T (64 x 16) in four 16-row tiles
-    short4_t h1[4];
+    for (int64_t it = blockIdx.x; it < nit; it += gridDim.x) {
+        const int64_t row64 = it * kTabRows + tid;
+        const bool inrow = row64 < n;
+        const uint32_t row = inrow ? static_cast<uint32_t>(row64) : 0u;
+        const RowRec rr = a.fa.rec[row];
+        // the log-ratio prior of the logits: features s and NS + s, summed in FP32
+        float prior[NS];
+        {
+            float f[NF];
+            row_features(a.fa, rr, row, xmax, f);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-        acc = mfma16(fr[(FR1 / 4) + c * 64 + lane], x, acc);
-        float4_t v;
-        v.x = fmaxf(acc.x + a.P[OFF_B1 + 16 * c + 4 * g + 0], 0.0f);
-        v.y = fmaxf(acc.y + a.P[OFF_B1 + 16 * c + 4 * g + 1], 0.0f);
-        v.z = fmaxf(acc.z + a.P[OFF_B1 + 16 * c + 4 * g + 2], 0.0f);
-        v.w = fmaxf(acc.w + a.P[OFF_B1 + 16 * c + 4 * g + 3], 0.0f);
-        h1[c] = pack4(v);
-    }
-    // layer 2
-    short4_t h2[4];
+            for (int v = 0; v < NF / 4; ++v) {
+                float4_t fv = {f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]};
+                if (!inrow) fv = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
+                s_x[w][lane][v] = pack4(fv);
+            }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) acc = mfma16(fr[(FR2 / 4) + (c * 4 + kk) * 64 + lane], h1[kk], acc);
-        float4_t v;
-        v.x = fmaxf(acc.x + a.P[OFF_B2 + 16 * c + 4 * g + 0], 0.0f);
-        v.y = fmaxf(acc.y + a.P[OFF_B2 + 16 * c + 4 * g + 1], 0.0f);
-        v.z = fmaxf(acc.z + a.P[OFF_B2 + 16 * c + 4 * g + 2], 0.0f);
-        v.w = fmaxf(acc.w + a.P[OFF_B2 + 16 * c + 4 * g + 3], 0.0f);
-        h2[c] = pack4(v);
-    }
-    // layer 3: outputs 4g + i of row r in this lane (valid for 4g + i < 7)
-    float4_t o = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) o = mfma16(fr[(FR3 / 4) + kk * 64 + lane], h2[kk], o);
-    float ov[4] = {o.x, o.y, o.z, o.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ov[i] += (4 * g + i < NO) ? a.P[OFF_B3 + 4 * g + i] : 0.0f;
-    // gather outputs 4..6 of row r from lane r + 16
-    const float o4 = __shfl(ov[0], r + 16, 64);
-    const float o5 = __shfl(ov[1], r + 16, 64);
-    const float o6 = __shfl(ov[2], r + 16, 64);
-    if (g != 0 || !inrow) return;
-    const float out[NO] = {ov[0], ov[1], ov[2], ov[3], o4, o5, o6};
-    float q[NS] = {0, 0, 0, 0, 0, 0};
-    const uint32_t k = rr.deg;
-    if (k >= 1 && k <= NS) {
-        // logits: the log-ratio prior (features s and NS + s, FP32) plus the correction
-        float z[NS];
-        float zmax = -INFINITY;
-        for (uint32_t s = 0; s < k; ++s) {
-            const int si = static_cast<int>(s);
-            z[s] = out[s] + (feature(a.fa, rr, row, si, xmax) + feature(a.fa, rr, row, NS + si, xmax));
-            zmax = fmaxf(zmax, z[s]);
+            for (int s = 0; s < NS; ++s) prior[s] = f[s] + f[NS + s];
         }
-        float den = 0.0f, e[NS];
-        for (uint32_t s = 0; s < k; ++s) {
-            e[s] = expf(z[s] - zmax);
-            den += e[s];
+        __syncthreads();
+        // four tiles of 16 rows: lane r + 16 g holds inputs 4g..4g+3 of tile row r, and
+        // the layer outputs 16 c + 4g + i of tile row r
+#pragma unroll 1
+        for (int t = 0; t < 4; ++t) {
+            // an opaque zero keeps the weight and bias reads from LDS inside the loop
+            // (hoisted out of it they would hold 84 registers for the whole kernel)
+            int z0 = 0;
+            asm volatile("" : "+v"(z0));
+            const short4_t *fr = s_frag + z0;
+            const float4_t *b1 = s_b1 + z0, *b2 = s_b2 + z0, *b3 = s_b3 + z0;
+            const short4_t x = s_x[w][16 * t + r][g];
+            short4_t h1[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = mfma16(fr[(FR1 / 4) + c * 64 + lane], x, acc);
+                const float4_t b = b1[4 * c + g];
+                float4_t v;
+                v.x = fmaxf(acc.x + b.x, 0.0f);
+                v.y = fmaxf(acc.y + b.y, 0.0f);
+                v.z = fmaxf(acc.z + b.z, 0.0f);
+                v.w = fmaxf(acc.w + b.w, 0.0f);
+                h1[c] = pack4(v);
+            }
+            short4_t h2[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) acc = mfma16(fr[(FR2 / 4) + (c * 4 + kk) * 64 + lane], h1[kk], acc);
+                const float4_t b = b2[4 * c + g];
+                float4_t v;
+                v.x = fmaxf(acc.x + b.x, 0.0f);
+                v.y = fmaxf(acc.y + b.y, 0.0f);
+                v.z = fmaxf(acc.z + b.z, 0.0f);
+                v.w = fmaxf(acc.w + b.w, 0.0f);
+                h2[c] = pack4(v);
+            }
+            float4_t o = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) o = mfma16(fr[(FR3 / 4) + kk * 64 + lane], h2[kk], o);
+            if (g < 2) {
+                const float4_t b = b3[g];
+                float4_t ob;
+                ob.x = o.x + b.x;
+                ob.y = o.y + b.y;
+                ob.z = o.z + b.z;
+                ob.w = o.w + b.w;
+                s_o[w][16 * t + r][g] = ob;
+            }
         }
-        const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
-        for (uint32_t s = 0; s < k; ++s)
-            q[s] = alpha * (e[s] / den) + (1.0f - alpha) * a.fa.p_slot[rr.slot_begin + s];
+        __syncthreads();
+        if (!inrow) continue;
+        const float4_t o0 = s_o[w][lane][0], o1 = s_o[w][lane][1];
+        const float out[NO] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z};
+        float q[NS] = {0, 0, 0, 0, 0, 0};
+        const uint32_t k = rr.deg;
+        if (k >= 1 && k <= NS) {
+            // logits: the log-ratio prior (features s and NS + s, FP32) plus the correction
+            float z[NS];
+            float zmax = -INFINITY;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                z[s] = out[s] + prior[s];
+                if (static_cast<uint32_t>(s) < k) zmax = fmaxf(zmax, z[s]);
+            }
+            float den = 0.0f, e[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                e[s] = expf(z[s] - zmax);
+                if (static_cast<uint32_t>(s) < k) den += e[s];
+            }
+            const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (static_cast<uint32_t>(s) < k)
+                    q[s] = alpha * (e[s] / den) + (1.0f - alpha) * a.fa.p_slot[rr.slot_begin + s];
+        }
+        build_row(a, rr, q);
     }
-    build_row(a, rr, q);
 }
 
 // ------------------------------------------------------------------------------------
@@ -967,21 +1047,26 @@ int build_tables(mlmc_plan *p, int level, SlotRecIS *out, uint32_t *x_thr, int32
     ta.x_ratio = x_ratio;
     ta.x_q = x_q;
     ta.identity = p->prop_identity;
-    const uint64_t tiles = (static_cast<uint64_t>(p->n) + 15) / 16;
-    if (tiles == 0) return MLMC_OK;
-    hipLaunchKernelGGL(tables_kernel, dim3(nblk(tiles, 4)), dim3(256), 0, s, ta);
+    const uint64_t iters = (static_cast<uint64_t>(p->n) + kTabRows - 1) / kTabRows;
+    if (iters == 0) return MLMC_OK;
+    const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(iters, kTabGridMax));
+    hipLaunchKernelGGL(tables_kernel, dim3(grid), dim3(kTabRows), 0, s, ta);
     MLMC_HIP_TRY(hipGetLastError());
     return MLMC_OK;
 }
 
 // Copy the parameters and the pilot estimate in, and build the tables of the levels.
-int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_levels, hipStream_t s)
+// params: host, or the device when params_on_device (p->prop_P itself is not copied).
+int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_levels, hipStream_t s,
+                 bool params_on_device = false)
 {
     int rc;
     if ((rc = ensure_proposal_buffers(p, s))) return rc;
     p->prop_identity = params == nullptr;
     if (params) {
-        MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+        if (params != p->prop_P)
+            MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, params, NPARAM * sizeof(float),
+                                        params_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(fragments_kernel, dim3(nblk(NFRAG, 256)), dim3(256), 0, s, p->prop_P, p->prop_frag);
         MLMC_HIP_TRY(hipGetLastError());
     }
@@ -1099,50 +1184,42 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
     return MLMC_OK;
 }
 
-int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, const mlmc_train_opts_t *o,
-                             float *params_out, mlmc_train_stats_t *st, void *stream)
+}  // extern "C"
+
+namespace mlmc {
+namespace {
+
+// What the training steps after the pilot leave: the kept parameters and the records.
+struct CoreOut {
+    std::vector<float> P;
+    uint64_t kept = 0, n_val = 0;
+    int best_step = 0;
+    double first_val = 0.0, best_val = 0.0;
+    std::vector<double> losses;
+};
+
+int check_train_opts(const mlmc_plan *p, const mlmc_train_opts_t *o, bool own_pilot)
 {
-    if (!p || !u || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
-    if (u_dtype != MLMC_DTYPE_F32) return fail(MLMC_ERR_UNSUPPORTED, "training reads an FP32 right-hand side");
     if (!o->init_params) return fail(MLMC_ERR_INVALID_ARG, "init_params is null");
-    if (o->pilot_walks < 1 || o->pilot_walks > 0xFFFFFFFFll || o->capture_walks < 1 || o->steps < 0 ||
-        o->batch < 1 || o->batch > (1 << 20) || o->num_levels < 1 || p->l0 + o->num_levels - 1 > kMaxLevel ||
-        o->sample_stride < 1 || !(o->lr > 0.0) || !(o->shrink >= 0.0) || !std::isfinite(o->shrink) ||
-        o->judge_walks < 0 || o->judge_walks == 1 || o->judge_walks > 65536)
+    if (o->capture_walks < 1 || o->steps < 0 || o->batch < 1 || o->batch > (1 << 20) || o->num_levels < 1 ||
+        p->l0 + o->num_levels - 1 > kMaxLevel || o->sample_stride < 1 || !(o->lr > 0.0) || !(o->shrink >= 0.0) ||
+        !std::isfinite(o->shrink))
+        return fail(MLMC_ERR_INVALID_ARG, "training options out of range");
+    if (own_pilot && (o->pilot_walks < 1 || o->pilot_walks > 0xFFFFFFFFll || o->judge_walks < 0 ||
+                      o->judge_walks == 1 || o->judge_walks > 65536))
         return fail(MLMC_ERR_INVALID_ARG, "training options out of range");
     if (p->n_rows != p->n) return fail(MLMC_ERR_UNSUPPORTED, "training needs a plan over all rows");
-    const hipStream_t s = static_cast<hipStream_t>(stream);
+    return MLMC_OK;
+}
+
+// The training steps after the pilot estimate (in p->prop_xhat, max |xhat| in xmax):
+// capture of plain walks' jumps, minibatch Adam with early stopping, and the tables of the
+// kept parameters. Waits for the stream once, to read the records.
+int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t *o, double *xmax, CoreOut &co,
+               hipStream_t s)
+{
     int rc;
     const int level = p->l0;
-    if ((rc = upload_level(p, level, s)) || (rc = ensure_proposal_buffers(p, s))) return rc;
-    hipEvent_t e0, e1;
-    MLMC_HIP_TRY(hipEventCreate(&e0));
-    MLMC_HIP_TRY(hipEventCreate(&e1));
-    struct Ev {
-        hipEvent_t a, b;
-        ~Ev()
-        {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-        }
-    } ev{e0, e1};
-    MLMC_HIP_TRY(hipEventRecord(e0, s));
-    Session ss(p, p->train_pool, s);
-    // 1. pilot estimate xhat: the level-l0 mean of plain walks (an independent stream family)
-    const bool was_on = p->proposal_on;
-    p->proposal_on = false;
-    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
-    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
-    rc = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0x9E3779B97F4A7C15ull, 4095, level, 0,
-                              static_cast<uint32_t>(o->pilot_walks), s1, s2, nullptr, nullptr, stream);
-    p->proposal_on = was_on;
-    if (rc) return rc;
-    CombineArgs ca{};
-    ca.levels = 1;
-    ca.s1[0] = s1;
-    ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
-    MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
-    absmax(p->prop_xhat, p->n, xmax, s);
     // 2. transitions of plain walks from every sample_stride-th row
     const uint32_t n_sample = static_cast<uint32_t>((p->n + o->sample_stride - 1) / o->sample_stride);
     const uint64_t walks_cap = static_cast<uint64_t>(n_sample) * static_cast<uint64_t>(o->capture_walks);
@@ -1193,7 +1270,8 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     const uint64_t kept = kept32;
     const uint64_t n_val = std::min<uint64_t>(kept / 8, static_cast<uint64_t>(kMaxHeldOut));
     const uint64_t n_train = kept - n_val;
-    std::vector<float> P(o->init_params, o->init_params + NPARAM);
+    co.P.assign(o->init_params, o->init_params + NPARAM);
+    std::vector<float> &P = co.P;
     float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
     const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
     const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
@@ -1271,20 +1349,110 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
         }
         if (n_val > 0) MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, best, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
-    std::vector<double> losses(static_cast<size_t>(n_eval));
-    double first_val = 0.0, best_val = 0.0;
-    int best_step = 0;
+    // 4. the levels' tables from the kept parameters (on the device) and the pilot estimate
+    if ((rc = set_proposal(p, p->prop_P, p->prop_xhat, o->num_levels, s, true))) return rc;
+    // the records, read once
+    co.kept = kept;
+    co.n_val = n_val;
+    co.losses.assign(static_cast<size_t>(n_eval), 0.0);
     MLMC_HIP_TRY(hipMemcpyAsync(P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
     if (n_eval > 0)
-        MLMC_HIP_TRY(hipMemcpyAsync(losses.data(), d_loss, losses.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(co.losses.data(), d_loss, co.losses.size() * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
     if (n_val > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(&first_val, d_val, sizeof(double), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(&best_val, d_best_val, sizeof(double), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(&best_step, d_best_step, sizeof(int), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(&co.first_val, d_val, sizeof(double), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(&co.best_val, d_best_val, sizeof(double), hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(&co.best_step, d_best_step, sizeof(int), hipMemcpyDeviceToHost, s));
     }
     MLMC_HIP_TRY(hipStreamSynchronize(s));
-    // 4. the levels' tables from the trained parameters and the pilot estimate
-    if ((rc = set_proposal(p, P.data(), p->prop_xhat, o->num_levels, s))) return rc;
+    return MLMC_OK;
+}
+
+void fill_train_stats(mlmc_train_stats_t *st, const mlmc_train_opts_t *o, const CoreOut &co)
+{
+    std::memset(st, 0, sizeof *st);
+    st->transitions = static_cast<int64_t>(co.kept);
+    st->held_out = static_cast<int64_t>(co.n_val);
+    st->steps = o->steps;
+    st->best_step = co.best_step;
+    st->first_val_loss = co.first_val;
+    st->best_val_loss = co.best_val;
+    const int nl = static_cast<int>(std::min<size_t>(co.losses.size(), 64));
+    st->n_losses = nl;
+    for (int i = 0; i < nl; ++i) st->losses[i] = co.losses[co.losses.size() - nl + i];
+    st->first_loss = co.losses.empty() ? 0.0 : co.losses.front();
+    st->last_loss = co.losses.empty() ? 0.0 : co.losses.back();
+    st->accepted = 1;
+}
+
+}  // namespace
+
+int check_learned_opts(const mlmc_plan *p, const mlmc_train_opts_t *o) { return check_train_opts(p, o, false); }
+
+int train_from_levels(mlmc_plan *p, const void *u, const mlmc_train_opts_t *o, const CombineArgs &xhat,
+                      float *params_out, mlmc_train_stats_t *st, hipStream_t s)
+{
+    int rc;
+    if ((rc = check_train_opts(p, o, false))) return rc;
+    if ((rc = upload_level(p, p->l0, s)) || (rc = ensure_proposal_buffers(p, s))) return rc;
+    Session ss(p, p->train_pool, s);
+    // the same first buffers as a training call with its own pilot, so that both calls
+    // reuse the pooled buffers in the same order
+    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
+    MLMC_HIP_TRY(launch_combine(xhat, p->n, p->prop_xhat, s));
+    absmax(p->prop_xhat, p->n, xmax, s);
+    CoreOut co;
+    if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
+    if (st) fill_train_stats(st, o, co);
+    if (params_out) std::memcpy(params_out, co.P.data(), NPARAM * sizeof(float));
+    return MLMC_OK;
+}
+
+}  // namespace mlmc
+
+extern "C" {
+
+int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, const mlmc_train_opts_t *o,
+                             float *params_out, mlmc_train_stats_t *st, void *stream)
+{
+    if (!p || !u || !o) return fail(MLMC_ERR_INVALID_ARG, "null argument");
+    if (u_dtype != MLMC_DTYPE_F32) return fail(MLMC_ERR_UNSUPPORTED, "training reads an FP32 right-hand side");
+    int rc;
+    if ((rc = check_train_opts(p, o, true))) return rc;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int level = p->l0;
+    if ((rc = upload_level(p, level, s)) || (rc = ensure_proposal_buffers(p, s))) return rc;
+    hipEvent_t e0, e1;
+    MLMC_HIP_TRY(hipEventCreate(&e0));
+    MLMC_HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    MLMC_HIP_TRY(hipEventRecord(e0, s));
+    Session ss(p, p->train_pool, s);
+    // 1. pilot estimate xhat: the level-l0 mean of plain walks (an independent stream family)
+    const bool was_on = p->proposal_on;
+    p->proposal_on = false;
+    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
+    rc = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0x9E3779B97F4A7C15ull, 4095, level, 0,
+                              static_cast<uint32_t>(o->pilot_walks), s1, s2, nullptr, nullptr, stream);
+    p->proposal_on = was_on;
+    if (rc) return rc;
+    CombineArgs ca{};
+    ca.levels = 1;
+    ca.s1[0] = s1;
+    ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
+    MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
+    absmax(p->prop_xhat, p->n, xmax, s);
+    CoreOut co;
+    if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
     // 5. the plain law judges: the per-walk variance at l0 (mean over rows) of fresh walks
     //    under the plain law and under the proposal; the proposal stays enabled only if it
     //    is lower
@@ -1313,24 +1481,13 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     MLMC_HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.0f;
     MLMC_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (params_out) std::memcpy(params_out, P.data(), NPARAM * sizeof(float));
+    if (params_out) std::memcpy(params_out, co.P.data(), NPARAM * sizeof(float));
     if (st) {
-        std::memset(st, 0, sizeof *st);
-        st->transitions = static_cast<int64_t>(kept);
-        st->held_out = static_cast<int64_t>(n_val);
-        st->steps = o->steps;
-        st->best_step = best_step;
-        st->first_val_loss = first_val;
-        st->best_val_loss = best_val;
+        fill_train_stats(st, o, co);
         st->judge_var_plain = judge_plain;
         st->judge_var_learned = judge_learned;
         st->accepted = accepted ? 1 : 0;
         st->train_ms = ms;
-        const int nl = static_cast<int>(std::min<size_t>(losses.size(), 64));
-        st->n_losses = nl;
-        for (int i = 0; i < nl; ++i) st->losses[i] = losses[losses.size() - nl + i];
-        st->first_loss = losses.empty() ? 0.0 : losses.front();
-        st->last_loss = losses.empty() ? 0.0 : losses.back();
     }
     return MLMC_OK;
 }

@@ -3,7 +3,8 @@ UndefinedBehaviorSanitizer (CPU test infrastructure; the device code is built as
 
 oracle_sanitized():  oracle/mlmc_oracle.c + oracle_sanitize.c, gcc, OpenMP.
 plan_sanitized():    the library's plan construction (csrc/abi.hip with the kernels it
-                     launches) + plan_sanitize.cpp, hipcc with the sanitizers on the host pass.
+                     launches, and csrc/proposal.hip, whose training the learned run calls)
+                     + plan_sanitize.cpp, hipcc with the sanitizers on the host pass.
 """
 import os
 import shutil
@@ -39,7 +40,7 @@ def plan_sanitized() -> str | None:
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "--offload-arch=gfx950",
            *host, "-I", os.path.join(ROOT, "include"), "-o", exe + ".tmp",
            os.path.join(csrc, "abi.hip"), os.path.join(csrc, "kernels.hip"),
-           os.path.join(HERE, "plan_sanitize.cpp")]
+           os.path.join(csrc, "proposal.hip"), os.path.join(HERE, "plan_sanitize.cpp")]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
     os.replace(exe + ".tmp", exe)
     return exe

@@ -77,6 +77,8 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert _plan_status(A, memory=2)[0] == _abi.MLMC_ERR_INVALID_ARG
     lib = _lib()
     assert lib.mlmc_expv_plan(None, None, None, None) == _abi.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_expv_run_learned(None, None, _abi.MLMC_DTYPE_F32, None, None, None, None,
+                                     None, None, None) == _abi.MLMC_ERR_INVALID_ARG
 
 
 def test_jump_counter_overflow_is_refused_on_the_host():
