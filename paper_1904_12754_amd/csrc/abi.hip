@@ -76,6 +76,8 @@ void free_plan(mlmc_plan *p)
     (void)hipFree(p->prop_frag);
     (void)hipFree(p->prop_xhat);
     (void)hipFree(p->prop_xmax);
+    (void)hipFree(p->prop_logp);
+    (void)hipFree(p->prop_logx);
     for (auto &b : p->train_pool) (void)hipFree(b.first);
     for (auto &b : p->grad_pool) (void)hipFree(b.first);
     (void)hipFree(p->req_rows);

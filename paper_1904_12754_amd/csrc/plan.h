@@ -59,6 +59,8 @@ struct mlmc_plan {
     short *prop_frag = nullptr;              // their BF16 MFMA fragments
     double *prop_xhat = nullptr;             // pilot estimate the features read
     double *prop_xmax = nullptr;             // max |xhat| (1 when zero)
+    float *prop_logp = nullptr;              // max(log p, -20) per slot (a feature)
+    double *prop_logx = nullptr;             // log(|xhat| + 1e-6 max |xhat|) per row
     int32_t prop_levels = 0;                 // levels l0 .. l0 + prop_levels - 1 carry tables
     int32_t prop_identity = 0;               // 1: the tables are the plain ones (ratio 1)
     // scratch buffers kept between proposal training calls and between gradient calls

@@ -52,6 +52,8 @@ static_assert(NPARAM == MLMC_PROPOSAL_PARAMS, "parameter layout");
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
+uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
+
 __device__ __forceinline__ short bf16_bits(float x)
 {
     // round to nearest even (finite inputs)
@@ -64,42 +66,56 @@ struct FeatureArgs {
     const RowRec *rec;        // the level's row records (d, 1/r, slot range)
     const SlotRec *slots;     // plain slots (own column)
     const float *p_slot;      // plain law per slot
+    const float *logp;        // max(log p_s, -20) per slot (formed in FP64, rounded once)
     const double *xhat;       // pilot estimate (nullable: zeros)
+    const double *logx;       // log(|xhat_i| + delta) per row, delta = 1e-6 max |xhat|
     const double *xmax;       // device scalar: max |xhat| (1 when xhat is null or zero)
     int64_t n;
     float dt, lvl;            // dt of the level, (l - l0) / 8
 };
 
+// The logarithms the features take, formed once: per slot of the plan, and per row for each
+// pilot estimate (the log value ratio of a slot is then a difference, in FP64).
+__global__ void logp_kernel(const float *p, int64_t n, float *out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = static_cast<float>(fmax(log(static_cast<double>(p[i])), kLogPMin));
+}
+
+__global__ void logx_kernel(const double *x, const double *xmax, int64_t n, double *out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = log((x ? fabs(x[i]) : 0.0) + 1e-6 * *xmax);
+}
+
 // The 16 features of row `row`, each formed in FP64 and rounded once to FP32. Slot
 // features are 0 past the row's slots and for rows with more than NS slots. Every load of
-// the row (its slots' columns and plain probabilities, and the pilot estimate at those
-// columns) is issued before the first logarithm.
+// the row (its slots' log probabilities and the log estimates at their columns) is issued
+// before the first use.
 __device__ __forceinline__ void row_features(const FeatureArgs &a, const RowRec &rr, uint32_t row, double xmax,
                                              float f[NF])
 {
     const uint32_t deg = rr.deg;
     const bool elig = deg >= 1 && deg <= NS;
-    const double xr = fabs(a.xhat[row]);
+    const double xr = a.xhat ? fabs(a.xhat[row]) : 0.0;
 #pragma unroll
     for (int s = 0; s < 2 * NS; ++s) f[s] = 0.0f;
     if (elig) {
-        float ps[NS];
-        double xc[NS];
+        float lp[NS];
+        double lx[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             // slots past the row's last repeat its last slot (in range, results unused)
             const uint32_t si = rr.slot_begin + min(static_cast<uint32_t>(s), deg - 1);
-            ps[s] = a.p_slot[si];
-            xc[s] = a.xhat[a.slots[si].own & kColMask];
+            lp[s] = a.logp[si];
+            lx[s] = a.logx[a.slots[si].own & kColMask];
         }
-        const double delta = 1e-6 * xmax;
-        const double xden = xr + delta;
+        const double lxr = a.logx[row];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (static_cast<uint32_t>(s) < deg) {
-                f[s] = static_cast<float>(fmax(log(static_cast<double>(ps[s])), kLogPMin));
-                const double lr = log((fabs(xc[s]) + delta) / xden);
-                f[NS + s] = static_cast<float>(fmin(fmax(lr, -kLogRatioMax), kLogRatioMax));
+                f[s] = lp[s];
+                f[NS + s] = static_cast<float>(fmin(fmax(lx[s] - lxr, -kLogRatioMax), kLogRatioMax));
             }
         }
     }
@@ -109,14 +125,16 @@ __device__ __forceinline__ void row_features(const FeatureArgs &a, const RowRec 
     f[15] = a.lvl;
 }
 
-// One row per thread; the row's 16 features are stored as four 16-byte vectors.
-__global__ __launch_bounds__(256) void features_kernel(FeatureArgs a, float *F)
+// Features of rows[i] (of row i when rows is null) into F[i], i < count; one record per
+// thread, stored as four 16-byte vectors.
+__global__ __launch_bounds__(256) void features_kernel(FeatureArgs a, const uint32_t *rows, int64_t count, float *F)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    const RowRec rr = a.rec[i];
+    if (i >= count) return;
+    const uint32_t row = rows ? rows[i] : static_cast<uint32_t>(i);
+    const RowRec rr = a.rec[row];
     float f[NF];
-    row_features(a, rr, static_cast<uint32_t>(i), *a.xmax, f);
+    row_features(a, rr, row, *a.xmax, f);
     float4_t *out = reinterpret_cast<float4_t *>(F + i * NF);
 #pragma unroll
     for (int v = 0; v < NF / 4; ++v) out[v] = float4_t{f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]};
@@ -159,6 +177,14 @@ void absmax(const double *x, int64_t n, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(absmax_partial, dim3(kAbsmaxBlocks), dim3(256), 0, s, x, n, out + 1);
     hipLaunchKernelGGL(absmax_final, dim3(1), dim3(kAbsmaxBlocks), 0, s, out + 1, out);
+}
+
+// What the features read of a pilot estimate: xmax[0] = max |x| (1 when zero) and
+// logx[i] = log(|x_i| + 1e-6 xmax[0]).
+void prepare_xhat(const double *x, int64_t n, double *xmax, double *logx, hipStream_t s)
+{
+    absmax(x, n, xmax, s);
+    if (n > 0) hipLaunchKernelGGL(logx_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, x, xmax, n, logx);
 }
 
 // ------------------------------------------------------------------------------------
@@ -634,6 +660,7 @@ __global__ __launch_bounds__(256) void train_kernel(const float *__restrict__ P,
     __shared__ int sSlot[kTC];
     __shared__ int sValid[kTC];           // bit s: slot s is one of the row's entries
     __shared__ uint32_t sRow[kTC];
+    __shared__ uint32_t sT[kTC];          // index of the transition (its record in F)
     __shared__ float sRed[256];
     const int tid = static_cast<int>(threadIdx.x);
     const int j = tid & (NH - 1), g = tid >> 6;
@@ -668,9 +695,10 @@ __global__ __launch_bounds__(256) void train_kernel(const float *__restrict__ P,
         if (tid < kTC) {
             int slot = -1, valid = 0;
             float w = 0.0f;
-            uint32_t row = 0;
+            uint32_t row = 0, tix = 0;
             if (tid < nb) {
                 const uint64_t t = src.at(b0 + tid);
+                tix = static_cast<uint32_t>(t);
                 row = src.row[t];
                 const RowRec rr = rec[row];
                 slot = src.slot[t];
@@ -688,11 +716,12 @@ __global__ __launch_bounds__(256) void train_kernel(const float *__restrict__ P,
             sValid[tid] = valid;
             sW[tid] = w;
             sRow[tid] = row;
+            sT[tid] = tix;
         }
         __syncthreads();
         for (int e = tid; e < kTC * NF; e += 256) {
             const int b = e / NF;
-            sX[e] = b < nb ? F[static_cast<size_t>(sRow[b]) * NF + (e % NF)] : 0.0f;
+            sX[e] = b < nb ? F[static_cast<size_t>(sT[b]) * NF + (e % NF)] : 0.0f;
         }
         __syncthreads();
         // forward: unit j of rows g kRG .. g kRG + kRG - 1
@@ -929,7 +958,6 @@ __global__ __launch_bounds__(256) void keep_best_kernel(const double *__restrict
     }
 }
 
-uint32_t nblk(uint64_t n, uint32_t t) { return static_cast<uint32_t>((n + t - 1) / t); }
 
 int train_blocks(int B) { return std::min(kMaxTrainBlocks, (B + kTC - 1) / kTC); }
 
@@ -984,13 +1012,15 @@ struct Session {
     }
 };
 
-FeatureArgs feature_args(const mlmc_plan *p, int level, const double *xhat, const double *xmax)
+FeatureArgs feature_args(const mlmc_plan *p, int level, const double *xhat, const double *logx, const double *xmax)
 {
     FeatureArgs fa;
     fa.rec = p->level_rec[level];
     fa.slots = p->slots;
     fa.p_slot = p->p_slot;
+    fa.logp = p->prop_logp;
     fa.xhat = xhat;
+    fa.logx = logx;
     fa.xmax = xmax;
     fa.n = p->n;
     fa.dt = static_cast<float>(std::ldexp(p->beta, -level));
@@ -1025,11 +1055,18 @@ int ensure_proposal_buffers(mlmc_plan *p, hipStream_t s)
     int rc;
     if ((rc = plan_alloc(p, &p->p_slot, p->p_slot_host.size())) || (rc = plan_alloc(p, &p->prop_P, NPARAM)) ||
         (rc = plan_alloc(p, &p->prop_frag, NFRAG)) || (rc = plan_alloc(p, &p->prop_xhat, static_cast<size_t>(p->n))) ||
-        (rc = plan_alloc(p, &p->prop_xmax, 1 + kAbsmaxBlocks)))
+        (rc = plan_alloc(p, &p->prop_xmax, 1 + kAbsmaxBlocks)) ||
+        (rc = plan_alloc(p, &p->prop_logp, p->p_slot_host.size())) ||
+        (rc = plan_alloc(p, &p->prop_logx, static_cast<size_t>(p->n))))
         return rc;
-    if (fresh)
+    if (fresh) {
         MLMC_HIP_TRY(hipMemcpyAsync(p->p_slot, p->p_slot_host.data(), p->p_slot_host.size() * sizeof(float),
                                     hipMemcpyHostToDevice, s));
+        const uint64_t ns = p->p_slot_host.size();
+        if (ns > 0) hipLaunchKernelGGL(logp_kernel, dim3(nblk(ns, 256)), dim3(256), 0, s, p->p_slot, static_cast<int64_t>(ns),
+                                       p->prop_logp);
+        MLMC_HIP_TRY(hipGetLastError());
+    }
     return MLMC_OK;
 }
 
@@ -1038,7 +1075,7 @@ int build_tables(mlmc_plan *p, int level, SlotRecIS *out, uint32_t *x_thr, int32
                  float *x_q, hipStream_t s)
 {
     TableArgs ta;
-    ta.fa = feature_args(p, level, p->prop_xhat, p->prop_xmax);
+    ta.fa = feature_args(p, level, p->prop_xhat, p->prop_logx, p->prop_xmax);
     ta.frag = p->prop_frag;
     ta.P = p->prop_P;
     ta.out = out;
@@ -1078,7 +1115,7 @@ int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_
             MLMC_HIP_TRY(hipMemsetAsync(p->prop_xhat, 0, p->n * sizeof(double), s));
         }
     }
-    absmax(p->prop_xhat, p->n, p->prop_xmax, s);
+    prepare_xhat(p->prop_xhat, p->n, p->prop_xmax, p->prop_logx, s);
     MLMC_HIP_TRY(hipGetLastError());
     if (p->is_slots.size() < static_cast<size_t>(kMaxLevel + 1)) p->is_slots.resize(kMaxLevel + 1, nullptr);
     for (int q = 0; q < num_levels; ++q) {
@@ -1155,20 +1192,21 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
     float *dP = nullptr, *F = nullptr, *d_w = nullptr, *part = nullptr, *G = nullptr, *lossb = nullptr;
     uint32_t *d_rows = nullptr;
     int32_t *d_slots = nullptr;
-    double *xmax = nullptr;
+    double *xmax = nullptr, *logx = nullptr;
     const int blocks = train_blocks(count);
-    if ((rc = ss.alloc(&dP, NPARAM)) || (rc = ss.alloc(&F, static_cast<size_t>(p->n) * NF)) ||
+    if ((rc = ss.alloc(&dP, NPARAM)) || (rc = ss.alloc(&F, static_cast<size_t>(count) * NF)) ||
         (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks)) || (rc = ss.alloc(&d_rows, count)) || (rc = ss.alloc(&d_slots, count)) ||
         (rc = ss.alloc(&d_w, count)) || (rc = ss.alloc(&part, static_cast<size_t>(blocks) * NPARAM)) ||
-        (rc = ss.alloc(&G, NPARAM)) || (rc = ss.alloc(&lossb, count)))
+        (rc = ss.alloc(&G, NPARAM)) || (rc = ss.alloc(&lossb, count)) || (rc = ss.alloc(&logx, p->n)))
         return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(dP, params, NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(d_rows, rows32.data(), count * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(d_slots, slots, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
     MLMC_HIP_TRY(hipMemcpyAsync(d_w, weights, count * sizeof(float), hipMemcpyHostToDevice, s));
-    absmax(xhat, p->n, xmax, s);
-    const FeatureArgs fa = feature_args(p, level, xhat, xmax);
-    if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
+    prepare_xhat(xhat, p->n, xmax, logx, s);
+    const FeatureArgs fa = feature_args(p, level, xhat, logx, xmax);
+    hipLaunchKernelGGL(features_kernel, dim3(nblk(count, 256)), dim3(256), 0, s, fa, d_rows,
+                       static_cast<int64_t>(count), F);
     const BatchSrc src{d_rows, d_slots, d_w, static_cast<uint64_t>(count), 0, 1};
     MLMC_HIP_TRY(train_pass(true, dP, F, p, level, src, count, static_cast<float>(shrink), part, lossb, s));
     hipLaunchKernelGGL(grad_sum_kernel<false>, dim3(nblk(NPARAM, kGradParams)), dim3(kGradParams * kGradGroups), 0,
@@ -1225,37 +1263,55 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     const uint64_t walks_cap = static_cast<uint64_t>(n_sample) * static_cast<uint64_t>(o->capture_walks);
     const uint64_t T = walks_cap * kCaptureJumps;
     if (T > (uint64_t(1) << 31)) return fail(MLMC_ERR_INVALID_ARG, "capture too large (rows x walks x 8 > 2^31)");
-    uint32_t *t_row = nullptr;
-    int32_t *t_slot = nullptr;
-    float *t_w = nullptr, *F = nullptr;
+    const uint64_t nb_keep = (T + kKeepBlock - 1) / kKeepBlock;
+    if (nb_keep > 0xFFFFFFFFull) return fail(MLMC_ERR_INVALID_ARG, "capture too large");
+    const uint64_t val_cap = std::min<uint64_t>(T / 8, static_cast<uint64_t>(kMaxHeldOut));
+    // the steps after which the minibatch loss is recorded (and, after the first, the
+    // held-out loss evaluated): the first, every kEvalEvery-th and the last
+    auto eval_after = [&](int step) { return step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0; };
+    int n_eval = 0;
+    for (int step = 0; step < o->steps; ++step) n_eval += eval_after(step) ? 1 : 0;
+    // buffers (in the same order on every call) and the parameters' initial state, all
+    // before the one wait for the count of kept transitions
+    uint32_t *t_row = nullptr, *keep_off = nullptr, *tr_row = nullptr, *v_row = nullptr;
+    int32_t *t_slot = nullptr, *tr_slot = nullptr, *v_slot = nullptr;
+    float *t_w = nullptr, *tr_w = nullptr, *v_w = nullptr;
+    float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
+    // device records: the best held-out loss, its step (an int in the next slot), the
+    // minibatch losses [n_eval] and the held-out losses [1 + n_eval] (the initial first)
+    double *recs = nullptr;
+    const size_t n_recs = 2 + 2 * static_cast<size_t>(n_eval) + 1;
     if ((rc = ss.alloc(&t_row, T)) || (rc = ss.alloc(&t_slot, T)) || (rc = ss.alloc(&t_w, T)) ||
-        (rc = ss.alloc(&F, static_cast<size_t>(p->n) * NF)))
+        (rc = ss.alloc(&keep_off, nb_keep + 1)) || (rc = ss.alloc(&tr_row, T)) || (rc = ss.alloc(&tr_slot, T)) ||
+        (rc = ss.alloc(&tr_w, T)) || (rc = ss.alloc(&v_row, val_cap)) || (rc = ss.alloc(&v_slot, val_cap)) ||
+        (rc = ss.alloc(&v_w, val_cap)) || (rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) ||
+        (rc = ss.alloc(&best, NPARAM)) ||
+        (rc = ss.alloc(&part, static_cast<size_t>(train_blocks(o->batch)) * NPARAM)) ||
+        (rc = ss.alloc(&lossb, static_cast<size_t>(o->batch))) || (rc = ss.alloc(&lossv, std::max<uint64_t>(val_cap, 1))) ||
+        (rc = ss.alloc(&recs, n_recs)))
         return rc;
+    double *d_best_val = recs;
+    int *d_best_step = reinterpret_cast<int *>(recs + 1);
+    double *d_loss = recs + 2, *d_val = recs + 2 + n_eval;
+    co.P.assign(o->init_params, o->init_params + NPARAM);
+    MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, co.P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
+    MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
+    MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
+    MLMC_HIP_TRY(hipMemsetAsync(recs, 0, n_recs * sizeof(double), s));
     LevelArgs L = level_args(p, level, o->seed, 4094);
     L.is_slots = nullptr;
-    const FeatureArgs fa = feature_args(p, level, p->prop_xhat, xmax);
     if (walks_cap > 0) {
         hipLaunchKernelGGL(capture_kernel, dim3(nblk(walks_cap, 256)), dim3(256), 0, s, L,
                            static_cast<const float *>(u), static_cast<uint32_t>(o->sample_stride), n_sample,
                            static_cast<uint32_t>(o->capture_walks), t_row, t_slot, t_w);
         MLMC_HIP_TRY(hipGetLastError());
     }
-    if (p->n > 0) hipLaunchKernelGGL(features_kernel, dim3(nblk(p->n, 256)), dim3(256), 0, s, fa, F);
     // 3. the transitions that carry a sample, in their recorded order: every 8th is held out
     //    (at most kMaxHeldOut of them), the rest train (compacted on the device). Adam on
     //    minibatches of the training transitions, taken by a fixed stride (coprime with the
     //    count) so that each batch spreads over all sampled rows; the parameters with the
     //    lowest held-out loss (the initial ones included) are kept
-    const uint64_t nb_keep = (T + kKeepBlock - 1) / kKeepBlock;
-    const uint64_t val_cap = std::min<uint64_t>(T / 8, static_cast<uint64_t>(kMaxHeldOut));
-    uint32_t *keep_off = nullptr, *tr_row = nullptr, *v_row = nullptr;
-    int32_t *tr_slot = nullptr, *v_slot = nullptr;
-    float *tr_w = nullptr, *v_w = nullptr;
-    if ((rc = ss.alloc(&keep_off, nb_keep + 1)) || (rc = ss.alloc(&tr_row, T)) || (rc = ss.alloc(&tr_slot, T)) ||
-        (rc = ss.alloc(&tr_w, T)) || (rc = ss.alloc(&v_row, val_cap)) || (rc = ss.alloc(&v_slot, val_cap)) ||
-        (rc = ss.alloc(&v_w, val_cap)))
-        return rc;
-    if (nb_keep > 0xFFFFFFFFull) return fail(MLMC_ERR_INVALID_ARG, "capture too large");
     uint32_t kept32 = 0;
     if (T > 0) {
         hipLaunchKernelGGL(keep_count_kernel, dim3(static_cast<uint32_t>(nb_keep)), dim3(256), 0, s, t_slot, t_w, T,
@@ -1270,38 +1326,25 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     const uint64_t kept = kept32;
     const uint64_t n_val = std::min<uint64_t>(kept / 8, static_cast<uint64_t>(kMaxHeldOut));
     const uint64_t n_train = kept - n_val;
-    co.P.assign(o->init_params, o->init_params + NPARAM);
-    std::vector<float> &P = co.P;
-    float *m = nullptr, *v = nullptr, *best = nullptr, *part = nullptr, *lossb = nullptr, *lossv = nullptr;
     const int B = static_cast<int>(std::min<uint64_t>(static_cast<uint64_t>(o->batch), std::max<uint64_t>(n_train, 1)));
-    const int V = static_cast<int>(std::max<uint64_t>(n_val, 1));
     const bool training = n_train > 0 && o->steps > 0;
-    // the steps after which the minibatch loss is recorded (and, after the first, the
-    // held-out loss evaluated): the first, every kEvalEvery-th and the last
-    auto eval_after = [&](int step) { return step == 0 || step == o->steps - 1 || (step + 1) % kEvalEvery == 0; };
-    int n_eval = 0;
-    if (training)
-        for (int step = 0; step < o->steps; ++step) n_eval += eval_after(step) ? 1 : 0;
-    // device records: minibatch losses [n_eval], held-out losses [1 + n_eval] (the initial
-    // parameters first), the best held-out loss and its step
-    double *d_loss = nullptr, *d_val = nullptr, *d_best_val = nullptr;
-    int *d_best_step = nullptr;
-    if ((rc = ss.alloc(&m, NPARAM)) || (rc = ss.alloc(&v, NPARAM)) || (rc = ss.alloc(&best, NPARAM)) ||
-        (rc = ss.alloc(&part, static_cast<size_t>(train_blocks(B)) * NPARAM)) || (rc = ss.alloc(&lossb, B)) ||
-        (rc = ss.alloc(&lossv, V)) || (rc = ss.alloc(&d_loss, static_cast<size_t>(n_eval))) ||
-        (rc = ss.alloc(&d_val, static_cast<size_t>(n_eval) + 1)) || (rc = ss.alloc(&d_best_val, 1)) ||
-        (rc = ss.alloc(&d_best_step, 1)))
+    // the network inputs of the kept transitions' rows, one record per transition
+    float *F_tr = nullptr, *F_v = nullptr;
+    if ((rc = ss.alloc(&F_tr, std::max<uint64_t>(n_train, 1) * NF)) || (rc = ss.alloc(&F_v, std::max<uint64_t>(n_val, 1) * NF)))
         return rc;
-    MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
-    MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
-    MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
-    MLMC_HIP_TRY(hipMemsetAsync(d_best_step, 0, sizeof(int), s));
+    const FeatureArgs fa = feature_args(p, level, p->prop_xhat, p->prop_logx, xmax);
+    if (n_train > 0)
+        hipLaunchKernelGGL(features_kernel, dim3(nblk(n_train, 256)), dim3(256), 0, s, fa, tr_row,
+                           static_cast<int64_t>(n_train), F_tr);
+    if (n_val > 0)
+        hipLaunchKernelGGL(features_kernel, dim3(nblk(n_val, 256)), dim3(256), 0, s, fa, v_row,
+                           static_cast<int64_t>(n_val), F_v);
+    MLMC_HIP_TRY(hipGetLastError());
     const BatchSrc vsrc{v_row, v_slot, v_w, std::max<uint64_t>(n_val, 1), 0, 1};
     const float shrink = static_cast<float>(o->shrink);
     // held-out loss of the current parameters into *out (on the device)
     auto val_loss = [&](double *out) -> int {
-        MLMC_HIP_TRY(train_pass(false, p->prop_P, F, p, level, vsrc, static_cast<int>(n_val), shrink, part, lossv, s));
+        MLMC_HIP_TRY(train_pass(false, p->prop_P, F_v, p, level, vsrc, static_cast<int>(n_val), shrink, part, lossv, s));
         hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kLossThreads), 0, s, lossv, static_cast<int>(n_val), out);
         MLMC_HIP_TRY(hipGetLastError());
         return MLMC_OK;
@@ -1310,7 +1353,7 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
         if ((rc = val_loss(d_val))) return rc;
         MLMC_HIP_TRY(hipMemcpyAsync(d_best_val, d_val, sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    int n_val_evals = 0;
+    int n_val_evals = 0, e = 0;
     if (training) {
         auto gcd = [](uint64_t a, uint64_t b) {
             while (b) {
@@ -1324,10 +1367,9 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
         while (n_train > 1 && (mult == 0 || gcd(mult, n_train) != 1)) mult = (mult + 1) % n_train;
         const float b1 = 0.9f, b2 = 0.999f;
         const int blocks = train_blocks(B);
-        int e = 0;
         for (int step = 0; step < o->steps; ++step) {
             const BatchSrc src{tr_row, tr_slot, tr_w, n_train, static_cast<uint64_t>(step) * B, mult};
-            MLMC_HIP_TRY(train_pass(true, p->prop_P, F, p, level, src, B, shrink, part, lossb, s));
+            MLMC_HIP_TRY(train_pass(true, p->prop_P, F_tr, p, level, src, B, shrink, part, lossb, s));
             const float c1 = 1.0f - std::pow(b1, static_cast<float>(step + 1));
             const float c2 = 1.0f - std::pow(b2, static_cast<float>(step + 1));
             hipLaunchKernelGGL(grad_sum_kernel<true>, dim3(nblk(NPARAM, kGradParams)), dim3(kGradParams * kGradGroups),
@@ -1351,20 +1393,19 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     }
     // 4. the levels' tables from the kept parameters (on the device) and the pilot estimate
     if ((rc = set_proposal(p, p->prop_P, p->prop_xhat, o->num_levels, s, true))) return rc;
-    // the records, read once
+    // the parameters and the records, read once
+    std::vector<double> h(n_recs);
+    MLMC_HIP_TRY(hipMemcpyAsync(co.P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(h.data(), recs, n_recs * sizeof(double), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipStreamSynchronize(s));
     co.kept = kept;
     co.n_val = n_val;
-    co.losses.assign(static_cast<size_t>(n_eval), 0.0);
-    MLMC_HIP_TRY(hipMemcpyAsync(P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
-    if (n_eval > 0)
-        MLMC_HIP_TRY(hipMemcpyAsync(co.losses.data(), d_loss, co.losses.size() * sizeof(double),
-                                    hipMemcpyDeviceToHost, s));
+    co.losses.assign(h.begin() + 2, h.begin() + 2 + e);
     if (n_val > 0) {
-        MLMC_HIP_TRY(hipMemcpyAsync(&co.first_val, d_val, sizeof(double), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(&co.best_val, d_best_val, sizeof(double), hipMemcpyDeviceToHost, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(&co.best_step, d_best_step, sizeof(int), hipMemcpyDeviceToHost, s));
+        co.best_val = h[0];
+        std::memcpy(&co.best_step, &h[1], sizeof(int));
+        co.first_val = h[2 + n_eval];
     }
-    MLMC_HIP_TRY(hipStreamSynchronize(s));
     return MLMC_OK;
 }
 
@@ -1401,7 +1442,7 @@ int train_from_levels(mlmc_plan *p, const void *u, const mlmc_train_opts_t *o, c
     double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
     if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
     MLMC_HIP_TRY(launch_combine(xhat, p->n, p->prop_xhat, s));
-    absmax(p->prop_xhat, p->n, xmax, s);
+    prepare_xhat(p->prop_xhat, p->n, xmax, p->prop_logx, s);
     CoreOut co;
     if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
     if (st) fill_train_stats(st, o, co);
@@ -1450,7 +1491,7 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     ca.s1[0] = s1;
     ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
     MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
-    absmax(p->prop_xhat, p->n, xmax, s);
+    prepare_xhat(p->prop_xhat, p->n, xmax, p->prop_logx, s);
     CoreOut co;
     if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
     // 5. the plain law judges: the per-walk variance at l0 (mean over rows) of fresh walks

@@ -78,7 +78,8 @@ def _kernel_features(t, xhat, beta, level, l0):
         ok = elig & (deg > s)
         idx = sb[:-1][ok] + s
         F[ok, s] = np.maximum(np.log(p32[idx].astype(np.float64)), prop.LOG_P_MIN)
-        lr = np.log((xabs[col[idx]] + delta) / (xabs[ok] + delta))
+        # the device forms the log value ratio as a difference of per-row logarithms
+        lr = np.log(xabs[col[idx]] + delta) - np.log(xabs[ok] + delta)
         F[ok, prop.NS + s] = np.clip(lr, -prop.LOG_RATIO_MAX, prop.LOG_RATIO_MAX)
     r = np.asarray(t.r)
     with np.errstate(divide="ignore"):
