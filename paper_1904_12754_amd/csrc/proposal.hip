@@ -316,25 +316,116 @@ __device__ void build_row(const TableArgs &a, const RowRec &rr, const float *q)
     }
 }
 
+// The alias table of one row's law q over its k <= NS slots, and the ratios p/q: the
+// construction of the plain plan (scaled probabilities k q_s in FP64; slots below 1 and at
+// or above 1 on two stacks; each step pairs the top small slot with the top large one).
+// The stacks and the alias slots are packed 4 bits per slot, and the arrays are read and
+// written by selects, so that the row stays in registers.
+__device__ __forceinline__ void build_row_q(const TableArgs &a, uint32_t sb, uint32_t k, const float p[NS],
+                                            const float q[NS])
+{
+    uint32_t own[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) own[s] = a.fa.slots[sb + min(static_cast<uint32_t>(s), k - 1)].own;
+    double qs[NS];
+    uint32_t thr[NS];
+    uint32_t alias = 0, small = 0, large = 0;
+    int ns = 0, nl = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        qs[s] = static_cast<double>(q[s]) * static_cast<double>(k);
+        thr[s] = 0xFFFFFFFFu;
+        alias |= static_cast<uint32_t>(s) << (4 * s);
+        if (static_cast<uint32_t>(s) < k) {
+            if (qs[s] < 1.0) {
+                small |= static_cast<uint32_t>(s) << (4 * ns);
+                ++ns;
+            } else {
+                large |= static_cast<uint32_t>(s) << (4 * nl);
+                ++nl;
+            }
+        }
+    }
+    while (ns > 0 && nl > 0) {
+        --ns;
+        --nl;
+        const int lo = static_cast<int>((small >> (4 * ns)) & 15u);
+        const int hi = static_cast<int>((large >> (4 * nl)) & 15u);
+        double qlo = 0.0, qhi = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            qlo = s == lo ? qs[s] : qlo;
+            qhi = s == hi ? qs[s] : qhi;
+        }
+        const uint32_t t = static_cast<uint32_t>(floor(qlo * 4294967296.0));
+        const double nh = (qhi + qlo) - 1.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            thr[s] = s == lo ? t : thr[s];
+            qs[s] = s == hi ? nh : qs[s];
+        }
+        alias = (alias & ~(15u << (4 * lo))) | (static_cast<uint32_t>(hi) << (4 * lo));
+        if (nh < 1.0) {
+            small = (small & ~(15u << (4 * ns))) | (static_cast<uint32_t>(hi) << (4 * ns));
+            ++ns;
+        } else {
+            large = (large & ~(15u << (4 * nl))) | (static_cast<uint32_t>(hi) << (4 * nl));
+            ++nl;
+        }
+    }
+    float ratio[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) ratio[s] = p[s] / q[s];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (static_cast<uint32_t>(s) >= k) break;
+        const int al = static_cast<int>((alias >> (4 * s)) & 15u);
+        uint32_t own_a = own[0];
+        float ratio_a = ratio[0];
+#pragma unroll
+        for (int j = 1; j < NS; ++j) {
+            own_a = j == al ? own[j] : own_a;
+            ratio_a = j == al ? ratio[j] : ratio_a;
+        }
+        SlotRecIS o;
+        o.own = own[s];
+        o.alias = own_a;
+        o.thr = thr[s];
+        o.pad = 0;
+        o.ratio_own = ratio[s];
+        o.ratio_alias = ratio_a;
+        o.pad2[0] = o.pad2[1] = 0;
+        a.out[sb + s] = o;
+        if (a.x_thr) {
+            a.x_thr[sb + s] = thr[s];
+            a.x_alias[sb + s] = al;
+            a.x_ratio[sb + s] = ratio[s];
+            a.x_q[sb + s] = q[s];
+        }
+    }
+}
+
 // Rows per workgroup and iteration of the tables kernel: four waves of 64 rows, one row
 // per lane. Each wave evaluates its 64 rows as four 16-row MFMA tiles.
 constexpr int kTabRows = 256;
 constexpr int kTabWaves = kTabRows / 64;
-constexpr int kTabGridMax = 256 * 4;   // four workgroups for each of the 256 CUs
+constexpr int kTabGridMax = 256 * 7;   // seven workgroups (28 waves) for each of the 256 CUs
 
 // Features -> MFMA MLP -> q -> alias tables and ratios. A workgroup stages the weight
 // fragments and biases in LDS once, then takes 256 rows per iteration (grid stride): every
 // lane forms its row's features, the wave's 64 rows pass through LDS into the B-operand
 // layout of the MFMA tiles, the tiles' outputs pass back through LDS to the row's lane, and
 // that lane builds the row's alias table.
-__global__ __launch_bounds__(kTabRows) void tables_kernel(TableArgs a)
+__global__ __launch_bounds__(kTabRows, 6) void tables_kernel(TableArgs a)
 {
     __shared__ short4_t s_frag[NFRAG / 4];
     __shared__ float4_t s_b1[NH / 4], s_b2[NH / 4], s_b3[2];
-    __shared__ short4_t s_x[kTabWaves][64][NF / 4];   // BF16 features, row major
-    __shared__ float4_t s_o[kTabWaves][64][2];        // outputs 0..6 (+1 unused) per row
+    // 32 bytes per row: its BF16 features, then (written after the row's tile has read
+    // them) its outputs 0..6 and one unused
+    __shared__ float4_t s_row[kTabWaves][64][2];
     const int tid = static_cast<int>(threadIdx.x);
     const int w = tid / 64, lane = tid & 63, r = lane % 16, g = lane / 16;
+    short4_t *const s_x = reinterpret_cast<short4_t *>(&s_row[w][0][0]);
     const int64_t n = a.fa.n;
     const int64_t nit = (n + kTabRows - 1) / kTabRows;
     if (a.identity) {           // uniform over the launch
@@ -375,7 +466,7 @@ __global__ __launch_bounds__(kTabRows) void tables_kernel(TableArgs a)
             for (int v = 0; v < NF / 4; ++v) {
                 float4_t fv = {f[4 * v], f[4 * v + 1], f[4 * v + 2], f[4 * v + 3]};
                 if (!inrow) fv = float4_t{0.0f, 0.0f, 0.0f, 0.0f};
-                s_x[w][lane][v] = pack4(fv);
+                s_x[lane * (NF / 4) + v] = pack4(fv);
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) prior[s] = f[s] + f[NS + s];
@@ -391,7 +482,7 @@ __global__ __launch_bounds__(kTabRows) void tables_kernel(TableArgs a)
             asm volatile("" : "+v"(z0));
             const short4_t *fr = s_frag + z0;
             const float4_t *b1 = s_b1 + z0, *b2 = s_b2 + z0, *b3 = s_b3 + z0;
-            const short4_t x = s_x[w][16 * t + r][g];
+            const short4_t x = s_x[(16 * t + r) * (NF / 4) + g];
             short4_t h1[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -429,37 +520,40 @@ __global__ __launch_bounds__(kTabRows) void tables_kernel(TableArgs a)
                 ob.y = o.y + b.y;
                 ob.z = o.z + b.z;
                 ob.w = o.w + b.w;
-                s_o[w][16 * t + r][g] = ob;
+                s_row[w][16 * t + r][g] = ob;
             }
         }
         __syncthreads();
         if (!inrow) continue;
-        const float4_t o0 = s_o[w][lane][0], o1 = s_o[w][lane][1];
-        const float out[NO] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z};
-        float q[NS] = {0, 0, 0, 0, 0, 0};
         const uint32_t k = rr.deg;
-        if (k >= 1 && k <= NS) {
-            // logits: the log-ratio prior (features s and NS + s, FP32) plus the correction
-            float z[NS];
-            float zmax = -INFINITY;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                z[s] = out[s] + prior[s];
-                if (static_cast<uint32_t>(s) < k) zmax = fmaxf(zmax, z[s]);
-            }
-            float den = 0.0f, e[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                e[s] = expf(z[s] - zmax);
-                if (static_cast<uint32_t>(s) < k) den += e[s];
-            }
-            const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                if (static_cast<uint32_t>(s) < k)
-                    q[s] = alpha * (e[s] / den) + (1.0f - alpha) * a.fa.p_slot[rr.slot_begin + s];
+        if (k < 1 || k > NS) {      // q = p: the plain row
+            build_row(a, rr, nullptr);
+            continue;
         }
-        build_row(a, rr, q);
+        float pl[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) pl[s] = a.fa.p_slot[rr.slot_begin + min(static_cast<uint32_t>(s), k - 1)];
+        const float4_t o0 = s_row[w][lane][0], o1 = s_row[w][lane][1];
+        const float out[NO] = {o0.x, o0.y, o0.z, o0.w, o1.x, o1.y, o1.z};
+        // logits: the log-ratio prior (features s and NS + s, FP32) plus the correction
+        float z[NS];
+        float zmax = -INFINITY;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            z[s] = out[s] + prior[s];
+            if (static_cast<uint32_t>(s) < k) zmax = fmaxf(zmax, z[s]);
+        }
+        float den = 0.0f, e[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            e[s] = expf(z[s] - zmax);
+            if (static_cast<uint32_t>(s) < k) den += e[s];
+        }
+        const float alpha = kAlphaMax / (1.0f + expf(-out[NS]));
+        float q[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) q[s] = alpha * (e[s] / den) + (1.0f - alpha) * pl[s];
+        build_row_q(a, rr.slot_begin, k, pl, q);
     }
 }
 
