@@ -125,6 +125,7 @@ def parse():
 
 # ---- machine probes and rooflines -------------------------------------------------------
 PROBE_LOG2 = (18, 19, 21, 23, 25, 28)      # 4 MB .. 4 GB tables of 16-byte records
+LDS_PROBE_LOG2 = 11                         # 32 KB: four workgroups' copies fit in a CU's LDS
 
 
 def machine_probes():
@@ -139,6 +140,18 @@ def machine_probes():
     for lg in PROBE_LOG2:
         g, s = api.probe_gather(table, lg, 32, 64 if lg <= 21 else 32)
         out["gather_per_s"][str(16 << lg)] = g / s
+    # what staging rows' tables in LDS could gain per gather: a 32 KB table gathered from
+    # LDS and from device memory (where the caches hold it), as rates (8 streams per lane)
+    # and as the latency of serial gathers (one dependent stream per lane; 16 waves per CU
+    # keep 16 x 64 gathers in flight per CU)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    lds = {"table_bytes": 16 << LDS_PROBE_LOG2, "waves_per_cu": 16}
+    for where in ("global", "lds"):
+        g, s = api.probe_gather(table, LDS_PROBE_LOG2, 16, 256, lds=where == "lds")
+        lds[f"{where}_gathers_per_s"] = g / s
+        g, s = api.probe_gather(table, LDS_PROBE_LOG2, 16, 256, lds=where == "lds", dependent=True)
+        lds[f"{where}_latency_ns"] = 16 * 64 * cus / (g / s) * 1e9
+    out["lds_vs_global"] = lds
     del table
     torch.cuda.empty_cache()
     return out

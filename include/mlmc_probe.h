@@ -28,6 +28,22 @@ extern "C" {
 int mlmc_probe_gather(const void *table, int32_t log2_records, int32_t waves_per_cu,
                       int32_t iters, uint64_t *gathers, double *ms, void *stream);
 
+/* mlmc_probe_gather with a mode (bits):
+ *   MLMC_PROBE_LDS: each workgroup first copies the table's 2^log2_records records into its
+ *     LDS (log2_records <= 12, 64 KB) and gathers from there (the copy is in the timed
+ *     launch; it is small against iters x 8 gathers per lane);
+ *   MLMC_PROBE_DEPENDENT: one index stream per lane, each next index taking in the first
+ *     word of the record just read, so a lane's gathers are serial: the launch then keeps
+ *     waves_per_cu x 64 gathers in flight per compute unit, and that count divided by the
+ *     rate is the latency of one gather.
+ * gathers counts iters x 8 per lane, or iters per lane with MLMC_PROBE_DEPENDENT. Mode 0 is
+ * mlmc_probe_gather. This is what staging rows' tables in LDS could gain per gather. */
+#define MLMC_PROBE_LDS 1
+#define MLMC_PROBE_DEPENDENT 2
+int mlmc_probe_gather_mode(const void *table, int32_t log2_records, int32_t waves_per_cu,
+                           int32_t iters, int32_t mode, uint64_t *gathers, double *ms,
+                           void *stream);
+
 /* Eight chains per lane of a_j = a_j ^ a_{j+1} ^ i (one v_bitop3_b32 each), iters rounds,
  * on waves_per_cu waves per compute unit. lane_ops: HOST, lane-instructions of the timed
  * launch; ms: HOST, its duration. */

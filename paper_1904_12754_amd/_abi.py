@@ -41,9 +41,11 @@ EXPORTS = ("mlmc_expv_plan", "mlmc_expv_plan_info", "mlmc_expv_run", "mlmc_expv_
            "mlmc_expv_proposal_tables", "mlmc_expv_proposal_loss_grad",
            "mlmc_expv_proposal_train", "mlmc_expv_run_learned", "mlmc_status_string",
            "mlmc_last_error",
-           "mlmc_probe_gather", "mlmc_probe_valu")
+           "mlmc_probe_gather", "mlmc_probe_gather_mode", "mlmc_probe_valu")
 
 MLMC_PROPOSAL_PARAMS = 5703
+MLMC_PROBE_LDS = 1
+MLMC_PROBE_DEPENDENT = 2
 MLMC_BATCH_TUNE_MAX = 12
 
 
@@ -253,6 +255,9 @@ def load() -> ctypes.CDLL:
     L.mlmc_expv_run_learned.restype = ctypes.c_int
     L.mlmc_probe_gather.argtypes = [vp, i32, i32, i32, ctypes.POINTER(u64), ctypes.POINTER(f64), vp]
     L.mlmc_probe_gather.restype = ctypes.c_int
+    L.mlmc_probe_gather_mode.argtypes = [vp, i32, i32, i32, i32, ctypes.POINTER(u64),
+                                         ctypes.POINTER(f64), vp]
+    L.mlmc_probe_gather_mode.restype = ctypes.c_int
     L.mlmc_probe_valu.argtypes = [i32, i32, ctypes.POINTER(u64), ctypes.POINTER(f64), vp]
     L.mlmc_probe_valu.restype = ctypes.c_int
     L.mlmc_status_string.argtypes = [ctypes.c_int]

@@ -513,17 +513,20 @@ class Batch:
 
 # ---- measurement probes (include/mlmc_probe.h) -----------------------------------------
 def probe_gather(table: torch.Tensor, log2_records: int, waves_per_cu: int = 16, iters: int = 64,
-                 stream=None):
+                 stream=None, lds: bool = False, dependent: bool = False):
     """Random 16-byte gathers from the first 2^log2_records records of `table` (a device
-    tensor of at least 16 * 2^log2_records bytes). Returns (gathers, seconds) of one timed
-    launch."""
+    tensor of at least 16 * 2^log2_records bytes); lds=True gathers from a copy staged in
+    each workgroup's LDS, dependent=True makes each lane's gathers serial (one stream whose
+    next index takes in the record read). Returns (gathers, seconds) of one timed launch."""
     if not table.is_cuda or table.numel() * table.element_size() < (16 << log2_records):
         raise ValueError("table must be a device tensor of at least 16 * 2^log2_records bytes")
     lib = _abi.load()
     g = ctypes.c_uint64()
     ms = ctypes.c_double()
-    check(lib.mlmc_probe_gather(_dev_ptr(table), int(log2_records), int(waves_per_cu), int(iters),
-                                ctypes.byref(g), ctypes.byref(ms), _stream_ptr(stream)))
+    mode = (_abi.MLMC_PROBE_LDS if lds else 0) | (_abi.MLMC_PROBE_DEPENDENT if dependent else 0)
+    check(lib.mlmc_probe_gather_mode(_dev_ptr(table), int(log2_records), int(waves_per_cu),
+                                     int(iters), mode, ctypes.byref(g), ctypes.byref(ms),
+                                     _stream_ptr(stream)))
     return int(g.value), ms.value * 1e-3
 
 

@@ -79,6 +79,13 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert lib.mlmc_expv_plan(None, None, None, None) == _abi.MLMC_ERR_INVALID_ARG
     assert lib.mlmc_expv_run_learned(None, None, _abi.MLMC_DTYPE_F32, None, None, None, None,
                                      None, None, None) == _abi.MLMC_ERR_INVALID_ARG
+    # probe modes: unknown bits, and an LDS table past 64 KB, are refused before any launch
+    g, ms = ctypes.c_uint64(), ctypes.c_double()
+    fake = ctypes.c_void_p(256)
+    assert lib.mlmc_probe_gather_mode(fake, 10, 16, 1, 4, ctypes.byref(g), ctypes.byref(ms),
+                                      None) == _abi.MLMC_ERR_INVALID_ARG
+    assert lib.mlmc_probe_gather_mode(fake, 13, 16, 1, _abi.MLMC_PROBE_LDS, ctypes.byref(g),
+                                      ctypes.byref(ms), None) == _abi.MLMC_ERR_INVALID_ARG
 
 
 def test_jump_counter_overflow_is_refused_on_the_host():
