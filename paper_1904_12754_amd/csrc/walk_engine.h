@@ -779,6 +779,9 @@ struct SinkDeposit {
         jumps += f.jumps;
         hash += f.hash;
         nonfinite += !isfinite(y);
+        // a sample of exactly zero adds nothing, so it takes no atomics: above the coarsest
+        // level, a walk that never leaves its start row has E_f = E_c exactly
+        if (y == 0.0) return;
         unsafeAtomicAdd(&sum1[f.k], y);
         unsafeAtomicAdd(&sum2[f.k], y * y);
     }
