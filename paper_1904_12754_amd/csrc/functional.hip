@@ -93,17 +93,11 @@ __global__ void forward_combine(const double *__restrict__ sum1, const double *_
 }
 
 // Per-level moments over the entries: sum of (U m_j)^2 and of U^2 (sum2_j / M - m_j^2), in a
-// fixed order (one workgroup).
-__global__ void forward_moments(const double *__restrict__ sum1, const double *__restrict__ sum2, int64_t n,
-                                double U, double M, double *out)
+// fixed order: each workgroup reduces a contiguous range of entries into part[2 b], part[2 b
+// + 1], then one workgroup adds the partial sums in order.
+__device__ __forceinline__ void block_sum2(double &a, double &b)
 {
     __shared__ double s1[256], s2[256];
-    double a = 0.0, b = 0.0;
-    for (int64_t j = threadIdx.x; j < n; j += 256) {
-        const double m = sum1[j] / M;
-        a += (U * m) * (U * m);
-        b += U * U * fmax(sum2[j] / M - m * m, 0.0);
-    }
     s1[threadIdx.x] = a;
     s2[threadIdx.x] = b;
     __syncthreads();
@@ -114,10 +108,55 @@ __global__ void forward_moments(const double *__restrict__ sum1, const double *_
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        out[0] = s1[0];
-        out[1] = s2[0];
+    a = s1[0];
+    b = s2[0];
+}
+
+__global__ __launch_bounds__(256) void forward_moments_partial(const double *__restrict__ sum1,
+                                                               const double *__restrict__ sum2, int64_t n,
+                                                               double U, double M, int64_t per_block,
+                                                               double *part)
+{
+    const int64_t begin = static_cast<int64_t>(blockIdx.x) * per_block;
+    const int64_t end = min(begin + per_block, n);
+    double a = 0.0, b = 0.0;
+    for (int64_t j = begin + threadIdx.x; j < end; j += 256) {
+        const double m = sum1[j] / M;
+        a += (U * m) * (U * m);
+        b += U * U * fmax(sum2[j] / M - m * m, 0.0);
     }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void forward_moments_final(const double *__restrict__ part, int blocks,
+                                                             double *out)
+{
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < blocks; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+// out[0..1] as above; out[2 .. 2 + 2 kMomentBlocks) holds the partial sums.
+hipError_t launch_forward_moments(const double *sum1, const double *sum2, int64_t n, double U, double M,
+                                  double *out, hipStream_t s)
+{
+    const int64_t per_block = std::max<int64_t>((n + kMomentBlocks - 1) / kMomentBlocks, 4096);
+    const int blocks = static_cast<int>(std::max<int64_t>(1, (n + per_block - 1) / per_block));
+    hipLaunchKernelGGL(forward_moments_partial, dim3(blocks), dim3(256), 0, s, sum1, sum2, n, U, M, per_block,
+                       out + 2);
+    hipLaunchKernelGGL(forward_moments_final, dim3(1), dim3(256), 0, s, out + 2, blocks, out);
+    return hipGetLastError();
 }
 
 // Sums of the items' partial sums in a fixed order.
@@ -592,7 +631,7 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
         }
     } lv;
     double *mom = nullptr;
-    if ((rc = dalloc(&mom, 2))) return rc;
+    if ((rc = dalloc(&mom, 2 + 2 * static_cast<size_t>(kMomentBlocks)))) return rc;
     lv.v.push_back(mom);
     std::vector<double *> sums(static_cast<size_t>(max_levels), nullptr);
     std::vector<int64_t> M(static_cast<size_t>(max_levels), 0);
@@ -621,9 +660,7 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
         ++launches;
         double h[2] = {0.0, 0.0};
         if (n > 0) {
-            hipLaunchKernelGGL(forward_moments, dim3(1), dim3(256), 0, s, sums[q], sums[q] + n, n, UU,
-                               static_cast<double>(M[q]), mom);
-            MLMC_HIP_TRY(hipGetLastError());
+            MLMC_HIP_TRY(launch_forward_moments(sums[q], sums[q] + n, n, UU, static_cast<double>(M[q]), mom, s));
             MLMC_HIP_TRY(hipMemcpyAsync(h, mom, sizeof h, hipMemcpyDeviceToHost, s));
             MLMC_HIP_TRY(hipStreamSynchronize(s));
         }
