@@ -352,9 +352,10 @@ LEARN = dict(pilot_walks=64, capture_walks=64, sample_stride=1, steps=16, batch=
              shrink=10.0)
 
 
-def test_learned_run_trains_on_its_pilot_and_judges(api):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_learned_run_trains_on_its_pilot_and_judges(api, precision):
     A, beta, u, exact = _learned_case(api)
-    plan = api.Plan(A, beta, precision="fp32")
+    plan = api.Plan(A, beta, precision=precision)
     l0, eps, M0 = plan.l0, 2e-4, LEARN["pilot_walks"]
     xp, stp = plan.run(u, eps=eps, seed=7, pilot_walks=M0, max_levels=12)
     x, st, tst, params = plan.run_learned(u, eps, _prior_params(), seed=7, train_seed=3,
