@@ -615,7 +615,7 @@ def learned_part(args):
     # the learned run at the target eps: Algorithm 1 whose plain pilot gives the estimate the
     # proposal of l0 is trained on (16 Adam steps on batches of 1024, early stopping), from
     # the network's value-ratio prior alone (zero corrections, alpha = 0.9 sigmoid(3) = 0.857);
-    # the judge compares the pilot's plain level-l0 walks with the same walks under the
+    # the variance judge compares the pilot's plain level-l0 walks with the same walks under the
     # proposal. Timed whole, three times each against the plain solve
     P_run = _init_params(np.random.default_rng(0), alpha_logit=3.0)
     run_opts = dict(capture_walks=4, sample_stride=max(1, A.n // 65536), steps=16, batch=1024,

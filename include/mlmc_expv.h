@@ -58,7 +58,7 @@ extern "C" {
                                       the result is still written                           */
 #define MLMC_ERR_NOT_CONVERGED 6   /* Algorithm 1 hit its level or walk cap before reaching
                                       eps; the best estimate is still written               */
-#define MLMC_ERR_UNSUPPORTED 7     /* a valid request this build does not serve             */
+#define MLMC_ERR_UNSUPPORTED 7     /* a valid request the library does not serve            */
 #define MLMC_ERR_RNG_OVERFLOW 8    /* a Philox counter word would wrap: a walk index reaches
                                       2^32, or a walk's expected number of jumps
                                       (beta * max_i r_i) reaches 2^31 (its jump index is a
@@ -493,15 +493,15 @@ int mlmc_expv_proposal_train(mlmc_plan_t *plan, const void *u, int32_t u_dtype,
  *      mlmc_expv_proposal_train does after its own pilot: capture, Adam with early
  *      stopping, tables. train->pilot_walks and train->judge_walks are not read;
  *      train->num_levels must be 1.
- *   3. The judge: M0 level-l0 walks under the proposal, with the pilot's walk indices.
- *      They replace the plain pilot's level-l0 walks if their mean per-walk variance is
- *      lower; otherwise they are dropped and the run keeps the plain law.
+ *   3. The variance judge: M0 level-l0 walks under the proposal, with the pilot's walk
+ *      indices. They replace the plain pilot's level-l0 walks if their mean per-walk
+ *      variance is lower; otherwise they are dropped and the run keeps the plain law.
  *   4. The rest of Algorithm 1, as mlmc_expv_run.
  * The proposal stays set, and enabled iff it won. Needs nrhs = 1, u FP32 (DEVICE, n
  * entries), a plan over all rows and opts->eps > 0.
  * stats: walks[0] counts the walks of the estimate; steps and jumps count every walk run,
  * the dropped ones included. train_stats (nullable): as mlmc_expv_proposal_train's, with
- * train_ms the device time from the end of the pilot to the judge's verdict.
+ * train_ms the device time from the end of the pilot to the variance judge's decision.
  * params_out: HOST, nullable. Waits for the stream. */
 int mlmc_expv_run_learned(mlmc_plan_t *plan, const void *u, int32_t u_dtype,
                           const mlmc_run_opts_t *opts, const mlmc_train_opts_t *train,

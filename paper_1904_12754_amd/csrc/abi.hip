@@ -801,9 +801,9 @@ int run_impl(mlmc_plan *p, const void *u, int32_t nrhs, int32_t u_dtype, const m
             for (int qq = 0; qq < lv; ++qq) est[qq] = LevelEstimate{level_var(qq), level_cost(qq), level_rms(qq)};
             return MLMC_OK;
         };
-        // learned run: after the pilot, train on its estimate; the judge runs as many level-l0
-        // walks under the proposal (the same walk indices) into the spare pair and keeps them,
-        // in place of the plain ones, if their variance is lower
+        // learned run: after the pilot, train on its estimate; the variance judge runs as many
+        // level-l0 walks under the proposal (the same walk indices) into the spare pair and
+        // keeps them, in place of the plain ones, if their variance is lower
         auto after_pilot = [&](int lv, std::vector<LevelEstimate> &est, bool &again) -> int {
             if (!learn) return MLMC_OK;
             hipEvent_t te[2] = {nullptr, nullptr};

@@ -365,7 +365,7 @@ def test_learned_run_trains_on_its_pilot_and_judges(api, precision):
          f"judge {tst['judge_var_plain']:.3e} -> {tst['judge_var_learned']:.3e}, best step "
          f"{tst['best_step']}, {tst['transitions']} transitions, {tst['train_ms']:.2f} ms")
     assert tst["accepted"] == 1 and tst["judge_var_learned"] < tst["judge_var_plain"]
-    # the judge read exactly the pilot's level-l0 walks: plain, then the same walk indices
+    # the variance judge read exactly the pilot's level-l0 walks: plain, then the same walk indices
     # under the trained proposal (which the run leaves set and enabled)
     plan.enable_proposal(False)
     s1, s2, _ = plan.level_sums(u, l0, 0, M0, seed=7)
