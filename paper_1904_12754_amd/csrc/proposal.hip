@@ -1188,8 +1188,10 @@ int build_tables(mlmc_plan *p, int level, SlotRecIS *out, uint32_t *x_thr, int32
 
 // Copy the parameters and the pilot estimate in, and build the tables of the levels.
 // params: host, or the device when params_on_device (p->prop_P itself is not copied).
+// xhat_prepared: xhat is p->prop_xhat and p->prop_xmax, p->prop_logx already hold its
+// maximum and logarithms.
 int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_levels, hipStream_t s,
-                 bool params_on_device = false)
+                 bool params_on_device = false, bool xhat_prepared = false)
 {
     int rc;
     if ((rc = ensure_proposal_buffers(p, s))) return rc;
@@ -1201,16 +1203,18 @@ int set_proposal(mlmc_plan *p, const float *params, const double *xhat, int num_
         hipLaunchKernelGGL(fragments_kernel, dim3(nblk(NFRAG, 256)), dim3(256), 0, s, p->prop_P, p->prop_frag);
         MLMC_HIP_TRY(hipGetLastError());
     }
-    if (p->n > 0) {
-        if (xhat) {
-            if (xhat != p->prop_xhat)
-                MLMC_HIP_TRY(hipMemcpyAsync(p->prop_xhat, xhat, p->n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        } else {
-            MLMC_HIP_TRY(hipMemsetAsync(p->prop_xhat, 0, p->n * sizeof(double), s));
+    if (!(xhat_prepared && xhat == p->prop_xhat)) {
+        if (p->n > 0) {
+            if (xhat) {
+                if (xhat != p->prop_xhat)
+                    MLMC_HIP_TRY(hipMemcpyAsync(p->prop_xhat, xhat, p->n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            } else {
+                MLMC_HIP_TRY(hipMemsetAsync(p->prop_xhat, 0, p->n * sizeof(double), s));
+            }
         }
+        prepare_xhat(p->prop_xhat, p->n, p->prop_xmax, p->prop_logx, s);
+        MLMC_HIP_TRY(hipGetLastError());
     }
-    prepare_xhat(p->prop_xhat, p->n, p->prop_xmax, p->prop_logx, s);
-    MLMC_HIP_TRY(hipGetLastError());
     if (p->is_slots.size() < static_cast<size_t>(kMaxLevel + 1)) p->is_slots.resize(kMaxLevel + 1, nullptr);
     for (int q = 0; q < num_levels; ++q) {
         const int level = p->l0 + q;
@@ -1321,6 +1325,19 @@ int mlmc_expv_proposal_loss_grad(mlmc_plan_t *p, const float *params, const doub
 namespace mlmc {
 namespace {
 
+// The state of a training before its first step: the kept parameters are the initial ones,
+// Adam's moments and the records are zero.
+__global__ void train_init_kernel(const float *P, float *best, float *m, float *v, double *recs, int n_recs)
+{
+    const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < NPARAM) {
+        best[i] = P[i];
+        m[i] = 0.0f;
+        v[i] = 0.0f;
+    }
+    if (i < n_recs) recs[i] = 0.0;
+}
+
 // What the training steps after the pilot leave: the kept parameters and the records.
 struct CoreOut {
     std::vector<float> P;
@@ -1389,10 +1406,9 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     double *d_loss = recs + 2, *d_val = recs + 2 + n_eval;
     co.P.assign(o->init_params, o->init_params + NPARAM);
     MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, co.P.data(), NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(best, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
-    MLMC_HIP_TRY(hipMemsetAsync(m, 0, NPARAM * sizeof(float), s));
-    MLMC_HIP_TRY(hipMemsetAsync(v, 0, NPARAM * sizeof(float), s));
-    MLMC_HIP_TRY(hipMemsetAsync(recs, 0, n_recs * sizeof(double), s));
+    hipLaunchKernelGGL(train_init_kernel, dim3(nblk(std::max<size_t>(NPARAM, n_recs), 256)), dim3(256), 0, s,
+                       p->prop_P, best, m, v, recs, static_cast<int>(n_recs));
+    MLMC_HIP_TRY(hipGetLastError());
     LevelArgs L = level_args(p, level, o->seed, 4094);
     L.is_slots = nullptr;
     if (walks_cap > 0) {
@@ -1486,7 +1502,7 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
         if (n_val > 0) MLMC_HIP_TRY(hipMemcpyAsync(p->prop_P, best, NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
     // 4. the levels' tables from the kept parameters (on the device) and the pilot estimate
-    if ((rc = set_proposal(p, p->prop_P, p->prop_xhat, o->num_levels, s, true))) return rc;
+    if ((rc = set_proposal(p, p->prop_P, p->prop_xhat, o->num_levels, s, true, true))) return rc;
     // the parameters and the records, read once
     std::vector<double> h(n_recs);
     MLMC_HIP_TRY(hipMemcpyAsync(co.P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -1533,12 +1549,12 @@ int train_from_levels(mlmc_plan *p, const void *u, const mlmc_train_opts_t *o, c
     Session ss(p, p->train_pool, s);
     // the same first buffers as a training call with its own pilot, so that both calls
     // reuse the pooled buffers in the same order
-    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
-    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
+    double *s1 = nullptr, *s2 = nullptr;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n))) return rc;
     MLMC_HIP_TRY(launch_combine(xhat, p->n, p->prop_xhat, s));
-    prepare_xhat(p->prop_xhat, p->n, xmax, p->prop_logx, s);
+    prepare_xhat(p->prop_xhat, p->n, p->prop_xmax, p->prop_logx, s);
     CoreOut co;
-    if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
+    if ((rc = train_core(p, ss, u, o, p->prop_xmax, co, s))) return rc;
     if (st) fill_train_stats(st, o, co);
     if (params_out) std::memcpy(params_out, co.P.data(), NPARAM * sizeof(float));
     return MLMC_OK;
@@ -1574,8 +1590,8 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     // 1. pilot estimate xhat: the level-l0 mean of plain walks (an independent stream family)
     const bool was_on = p->proposal_on;
     p->proposal_on = false;
-    double *s1 = nullptr, *s2 = nullptr, *xmax = nullptr;
-    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n)) || (rc = ss.alloc(&xmax, 1 + kAbsmaxBlocks))) return rc;
+    double *s1 = nullptr, *s2 = nullptr;
+    if ((rc = ss.alloc(&s1, p->n)) || (rc = ss.alloc(&s2, p->n))) return rc;
     rc = mlmc_expv_level_sums(p, u, 1, MLMC_DTYPE_F32, o->seed ^ 0x9E3779B97F4A7C15ull, 4095, level, 0,
                               static_cast<uint32_t>(o->pilot_walks), s1, s2, nullptr, nullptr, stream);
     p->proposal_on = was_on;
@@ -1585,9 +1601,9 @@ int mlmc_expv_proposal_train(mlmc_plan_t *p, const void *u, int32_t u_dtype, con
     ca.s1[0] = s1;
     ca.inv_M[0] = 1.0 / static_cast<double>(o->pilot_walks);
     MLMC_HIP_TRY(launch_combine(ca, p->n, p->prop_xhat, s));
-    prepare_xhat(p->prop_xhat, p->n, xmax, p->prop_logx, s);
+    prepare_xhat(p->prop_xhat, p->n, p->prop_xmax, p->prop_logx, s);
     CoreOut co;
-    if ((rc = train_core(p, ss, u, o, xmax, co, s))) return rc;
+    if ((rc = train_core(p, ss, u, o, p->prop_xmax, co, s))) return rc;
     // 5. the plain law judges: the per-walk variance at l0 (mean over rows) of fresh walks
     //    under the plain law and under the proposal; the proposal stays enabled only if it
     //    is lower
