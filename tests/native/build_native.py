@@ -49,3 +49,21 @@ def log_bound(force: bool = False) -> str | None:
 if __name__ == "__main__":
     print(rocrand_ref(force=True))
     print(log_bound(force=True))
+
+
+def driver_hook(force: bool = False) -> str | None:
+    """Host program checking Algorithm 1's driver and its after-pilot hook on a mock."""
+    src = os.path.join(HERE, "driver_hook.cpp")
+    deps = [src, os.path.join(ROOT, "paper_1904_12754_amd", "csrc", "driver.h"),
+            os.path.join(ROOT, "include", "mlmc_expv.h")]
+    exe = os.path.join(OUT, "driver_hook")
+    if (not force and os.path.exists(exe)
+            and os.path.getmtime(exe) >= max(os.path.getmtime(d) for d in deps)):
+        return exe
+    gxx = shutil.which("g++")
+    if gxx is None:
+        return None
+    os.makedirs(OUT, exist_ok=True)
+    subprocess.check_call([gxx, "-O1", "-std=c++17", "-Wall", "-o", exe + ".tmp", src])
+    os.replace(exe + ".tmp", exe)
+    return exe
