@@ -415,3 +415,42 @@ def test_learned_run_falls_back_to_the_plain_law(api):
     assert st["converged"] and est <= eps and err <= 1.5 * eps
     fresh.close()
     plan.close()
+
+
+def test_learned_run_refuses_what_it_cannot_do(api):
+    """The learned run is adaptive, reads one FP32 right-hand side, trains on a plan over all
+    rows and sets tables for level l0 only; each of these is checked before any walk."""
+    import ctypes
+    from paper_1904_12754_amd import _abi
+
+    A, beta, u, _ = _learned_case(api)
+    P = _prior_params()
+    plan = api.Plan(A, beta, precision="fp32")
+    with pytest.raises(_abi.MLMCError) as e:
+        plan.run_learned(u, 0.0, P)                      # not adaptive
+    assert e.value.code == _abi.MLMC_ERR_INVALID_ARG
+    with pytest.raises(_abi.MLMCError) as e:
+        plan.run_learned(u.double(), 1e-3, P)            # FP64 right-hand side
+    assert e.value.code == _abi.MLMC_ERR_UNSUPPORTED
+    with pytest.raises(_abi.MLMCError) as e:
+        plan.run_learned(u, 1e-3, P, capture_walks=0)    # training options out of range
+    assert e.value.code == _abi.MLMC_ERR_INVALID_ARG
+    # tables for more levels than l0: through the C-ABI, as the binding always asks for one
+    lib = _abi.load()
+    x = torch.empty((A.n, 1), dtype=torch.float64, device="cuda")
+    Pp = np.ascontiguousarray(P, dtype=np.float32)
+    opts = _abi.RunOpts(1, 0, 0, None, 1e-3, 0, 12, 0)
+    topts = _abi.TrainOpts(0, Pp.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0, 16, 1, 16,
+                           1024, 1e-2, 10.0, 2, 0)
+    code = lib.mlmc_expv_run_learned(plan._handle, ctypes.c_void_p(u.data_ptr()),
+                                     _abi.MLMC_DTYPE_F32, ctypes.byref(opts), ctypes.byref(topts),
+                                     None, ctypes.c_void_p(x.data_ptr()), None, None,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert code == _abi.MLMC_ERR_INVALID_ARG
+    plan.close()
+    # a plan over some rows only
+    sub = api.Plan(A, beta, precision="fp32", rows=np.arange(0, A.n, 7))
+    with pytest.raises(_abi.MLMCError) as e:
+        sub.run_learned(u, 1e-3, P)
+    assert e.value.code == _abi.MLMC_ERR_UNSUPPORTED
+    sub.close()
