@@ -78,6 +78,7 @@ void free_plan(mlmc_plan *p)
     (void)hipFree(p->prop_xmax);
     (void)hipFree(p->prop_logp);
     (void)hipFree(p->prop_logx);
+    if (p->pinned) (void)hipHostFree(p->pinned);
     for (auto &b : p->train_pool) (void)hipFree(b.first);
     for (auto &b : p->grad_pool) (void)hipFree(b.first);
     (void)hipFree(p->req_rows);

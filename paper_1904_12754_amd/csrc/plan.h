@@ -65,6 +65,9 @@ struct mlmc_plan {
     int32_t prop_identity = 0;               // 1: the tables are the plain ones (ratio 1)
     // scratch buffers kept between proposal training calls and between gradient calls
     std::vector<std::pair<void *, size_t>> train_pool, grad_pool;
+    // pinned host memory for the small reads of a training call (grown on demand)
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
     // source vector of the current Algorithm 3 call (device, element type of u), else null
     const void *cur_src = nullptr;
     int64_t bytes = 0;

@@ -1338,6 +1338,21 @@ __global__ void train_init_kernel(const float *P, float *best, float *m, float *
     if (i < n_recs) recs[i] = 0.0;
 }
 
+// At least `bytes` of the plan's pinned host memory (its small reads are then direct copies).
+int pinned_host(mlmc_plan *p, size_t bytes, void **out)
+{
+    if (p->pinned_bytes < bytes) {
+        if (p->pinned) (void)hipHostFree(p->pinned);
+        p->pinned = nullptr;
+        p->pinned_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, size_t(64) << 10);   // one allocation for most calls
+        MLMC_HIP_TRY(hipHostMalloc(&p->pinned, want, hipHostMallocDefault));
+        p->pinned_bytes = want;
+    }
+    *out = p->pinned;
+    return MLMC_OK;
+}
+
 // What the training steps after the pilot leave: the kept parameters and the records.
 struct CoreOut {
     std::vector<float> P;
@@ -1430,8 +1445,11 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
         hipLaunchKernelGGL(keep_scatter_kernel, dim3(static_cast<uint32_t>(nb_keep)), dim3(256), 0, s, t_row, t_slot,
                            t_w, T, keep_off, tr_row, tr_slot, tr_w, v_row, v_slot, v_w);
         MLMC_HIP_TRY(hipGetLastError());
-        MLMC_HIP_TRY(hipMemcpyAsync(&kept32, keep_off + nb_keep, sizeof kept32, hipMemcpyDeviceToHost, s));
+        void *hk = nullptr;
+        if ((rc = pinned_host(p, sizeof kept32, &hk))) return rc;
+        MLMC_HIP_TRY(hipMemcpyAsync(hk, keep_off + nb_keep, sizeof kept32, hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
+        std::memcpy(&kept32, hk, sizeof kept32);
     }
     const uint64_t kept = kept32;
     const uint64_t n_val = std::min<uint64_t>(kept / 8, static_cast<uint64_t>(kMaxHeldOut));
@@ -1503,11 +1521,17 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     }
     // 4. the levels' tables from the kept parameters (on the device) and the pilot estimate
     if ((rc = set_proposal(p, p->prop_P, p->prop_xhat, o->num_levels, s, true, true))) return rc;
-    // the parameters and the records, read once
+    // the parameters and the records, read once (through the plan's pinned memory)
     std::vector<double> h(n_recs);
-    MLMC_HIP_TRY(hipMemcpyAsync(co.P.data(), p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(h.data(), recs, n_recs * sizeof(double), hipMemcpyDeviceToHost, s));
+    void *hp = nullptr;
+    const size_t p_bytes = (NPARAM * sizeof(float) + 7) / 8 * 8;
+    if ((rc = pinned_host(p, p_bytes + n_recs * sizeof(double), &hp))) return rc;
+    MLMC_HIP_TRY(hipMemcpyAsync(hp, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(static_cast<char *>(hp) + p_bytes, recs, n_recs * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(co.P.data(), hp, NPARAM * sizeof(float));
+    std::memcpy(h.data(), static_cast<char *>(hp) + p_bytes, n_recs * sizeof(double));
     co.kept = kept;
     co.n_val = n_val;
     co.losses.assign(h.begin() + 2, h.begin() + 2 + e);
