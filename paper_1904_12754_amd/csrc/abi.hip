@@ -133,6 +133,20 @@ void build_alias(std::vector<double> &q, std::vector<uint32_t> &thr, std::vector
 
 namespace mlmc {
 
+int plan_pinned(mlmc_plan *p, size_t bytes, void **out)
+{
+    if (p->pinned_bytes < bytes) {
+        if (p->pinned) (void)hipHostFree(p->pinned);
+        p->pinned = nullptr;
+        p->pinned_bytes = 0;
+        const size_t want = std::max<size_t>(bytes, size_t(64) << 10);   // one allocation for most calls
+        MLMC_HIP_TRY(hipHostMalloc(&p->pinned, want, hipHostMallocDefault));
+        p->pinned_bytes = want;
+    }
+    *out = p->pinned;
+    return MLMC_OK;
+}
+
 int upload_level(mlmc_plan *p, int level, hipStream_t s)
 {
     if (level < 0 || level > kMaxLevel) return fail(MLMC_ERR_INVALID_ARG, "level out of range [0, 28]");
@@ -763,11 +777,16 @@ int run_impl(mlmc_plan *p, const void *u, int32_t nrhs, int32_t u_dtype, const m
             MLMC_HIP_TRY(launch_level_moments(s1_of(qq), s2_of(qq), count, static_cast<double>(M[qq]),
                                               p->moments + 3 * qq, p->moment_scratch, s));
         std::vector<double> h(3 * static_cast<size_t>(levels));
-        MLMC_HIP_TRY(hipMemcpyAsync(h.data(), p->moments, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        const size_t hb = sizeof(double) * h.size(), cb = sizeof(unsigned long long) * 2 * levels;
+        void *pin = nullptr;
+        const int r2 = plan_pinned(p, hb + cb, &pin);
+        if (r2) return r2;
+        MLMC_HIP_TRY(hipMemcpyAsync(pin, p->moments, hb, hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(launch_counter_sum(p->counters, levels, p->counter_sums, s));
-        MLMC_HIP_TRY(hipMemcpyAsync(ctr.data(), p->counter_sums, sizeof(unsigned long long) * 2 * levels,
-                                    hipMemcpyDeviceToHost, s));
+        MLMC_HIP_TRY(hipMemcpyAsync(static_cast<char *>(pin) + hb, p->counter_sums, cb, hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
+        std::memcpy(h.data(), pin, hb);
+        std::memcpy(ctr.data(), static_cast<char *>(pin) + hb, cb);
         for (int qq = 0; qq < levels; ++qq) mom[qq] = Mom{h[3 * qq], h[3 * qq + 1], h[3 * qq + 2]};
         return MLMC_OK;
     };
@@ -836,9 +855,12 @@ int run_impl(mlmc_plan *p, const void *u, int32_t nrhs, int32_t u_dtype, const m
             MLMC_HIP_TRY(launch_level_moments(s1_of(0), s2_of(0), count, static_cast<double>(M[0]), p->moments,
                                               p->moment_scratch, s));
             double h[3];
-            MLMC_HIP_TRY(hipMemcpyAsync(h, p->moments, sizeof h, hipMemcpyDeviceToHost, s));
+            void *pin = nullptr;
+            if ((r2 = plan_pinned(p, sizeof h, &pin))) return r2;
+            MLMC_HIP_TRY(hipMemcpyAsync(pin, p->moments, sizeof h, hipMemcpyDeviceToHost, s));
             MLMC_HIP_TRY(hipEventRecord(te[1], s));
             MLMC_HIP_TRY(hipStreamSynchronize(s));
+            std::memcpy(h, pin, sizeof h);
             const double var_learned = unbiased_var(h[2] / cnt, M[0]);
             const bool accepted = var_learned < var_plain;
             if (!accepted) {

@@ -84,6 +84,10 @@ LevelArgs level_args(const mlmc_plan *p, int level, uint64_t seed, int instance)
 // own pilot and judge (their options are not read). Waits for the stream.
 int train_from_levels(mlmc_plan *p, const void *u, const mlmc_train_opts_t *o, const CombineArgs &xhat,
                       float *params_out, mlmc_train_stats_t *st, hipStream_t s);
+// At least `bytes` of the plan's pinned host memory, for the small reads that wait for the
+// device (direct copies instead of staged ones); grown on demand, freed with the plan. A
+// pointer from an earlier call is invalid after a call that grows it.
+int plan_pinned(mlmc_plan *p, size_t bytes, void **out);
 // The options train_from_levels reads, checked before a run starts.
 int check_learned_opts(const mlmc_plan *p, const mlmc_train_opts_t *o);
 

@@ -1338,21 +1338,6 @@ __global__ void train_init_kernel(const float *P, float *best, float *m, float *
     if (i < n_recs) recs[i] = 0.0;
 }
 
-// At least `bytes` of the plan's pinned host memory (its small reads are then direct copies).
-int pinned_host(mlmc_plan *p, size_t bytes, void **out)
-{
-    if (p->pinned_bytes < bytes) {
-        if (p->pinned) (void)hipHostFree(p->pinned);
-        p->pinned = nullptr;
-        p->pinned_bytes = 0;
-        const size_t want = std::max<size_t>(bytes, size_t(64) << 10);   // one allocation for most calls
-        MLMC_HIP_TRY(hipHostMalloc(&p->pinned, want, hipHostMallocDefault));
-        p->pinned_bytes = want;
-    }
-    *out = p->pinned;
-    return MLMC_OK;
-}
-
 // What the training steps after the pilot leave: the kept parameters and the records.
 struct CoreOut {
     std::vector<float> P;
@@ -1446,7 +1431,7 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
                            t_w, T, keep_off, tr_row, tr_slot, tr_w, v_row, v_slot, v_w);
         MLMC_HIP_TRY(hipGetLastError());
         void *hk = nullptr;
-        if ((rc = pinned_host(p, sizeof kept32, &hk))) return rc;
+        if ((rc = plan_pinned(p, sizeof kept32, &hk))) return rc;
         MLMC_HIP_TRY(hipMemcpyAsync(hk, keep_off + nb_keep, sizeof kept32, hipMemcpyDeviceToHost, s));
         MLMC_HIP_TRY(hipStreamSynchronize(s));
         std::memcpy(&kept32, hk, sizeof kept32);
@@ -1525,7 +1510,7 @@ int train_core(mlmc_plan *p, Session &ss, const void *u, const mlmc_train_opts_t
     std::vector<double> h(n_recs);
     void *hp = nullptr;
     const size_t p_bytes = (NPARAM * sizeof(float) + 7) / 8 * 8;
-    if ((rc = pinned_host(p, p_bytes + n_recs * sizeof(double), &hp))) return rc;
+    if ((rc = plan_pinned(p, p_bytes + n_recs * sizeof(double), &hp))) return rc;
     MLMC_HIP_TRY(hipMemcpyAsync(hp, p->prop_P, NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipMemcpyAsync(static_cast<char *>(hp) + p_bytes, recs, n_recs * sizeof(double),
                                 hipMemcpyDeviceToHost, s));
