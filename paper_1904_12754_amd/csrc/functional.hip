@@ -335,9 +335,14 @@ int run_level(FuncCall &fc, mlmc_plan *p, const void *w, int u_f64, uint64_t see
     MLMC_HIP_TRY(launch_counter_sum(fc.ctr, 1, fc.ctr + kCounterSetU64, s));
     double tot[2];
     unsigned long long c[3];
-    MLMC_HIP_TRY(hipMemcpyAsync(tot, fc.total, sizeof tot, hipMemcpyDeviceToHost, s));
-    MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
+    void *pin = nullptr;
+    if ((rc = plan_pinned(p, sizeof tot + sizeof c, &pin))) return rc;
+    MLMC_HIP_TRY(hipMemcpyAsync(pin, fc.total, sizeof tot, hipMemcpyDeviceToHost, s));
+    MLMC_HIP_TRY(hipMemcpyAsync(static_cast<char *>(pin) + sizeof tot, fc.ctr + kCounterSetU64, sizeof c,
+                                hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(tot, pin, sizeof tot);
+    std::memcpy(c, static_cast<char *>(pin) + sizeof tot, sizeof c);
     (void)hipEventElapsedTime(&out.ms, e0, e1);
     out.s1 = tot[0];
     out.s2 = tot[1];
@@ -389,8 +394,11 @@ int run_forward_level(FuncCall &fc, mlmc_plan *p, uint64_t seed, int instance, i
     MLMC_HIP_TRY(hipEventRecord(e1, s));
     MLMC_HIP_TRY(launch_counter_sum(fc.ctr, 1, fc.ctr + kCounterSetU64, s));
     unsigned long long c[3];
-    MLMC_HIP_TRY(hipMemcpyAsync(c, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
+    void *pin = nullptr;
+    if ((rc = plan_pinned(p, sizeof c, &pin))) return rc;
+    MLMC_HIP_TRY(hipMemcpyAsync(pin, fc.ctr + kCounterSetU64, sizeof c, hipMemcpyDeviceToHost, s));
     MLMC_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(c, pin, sizeof c);
     (void)hipEventElapsedTime(&out.ms, e0, e1);
     out.jumps = c[0];
     out.nonfinite = c[1];
@@ -661,8 +669,11 @@ int mlmc_expv_forward(mlmc_plan_t *p, const void *u, int32_t dtype, const mlmc_r
         double h[2] = {0.0, 0.0};
         if (n > 0) {
             MLMC_HIP_TRY(launch_forward_moments(sums[q], sums[q] + n, n, UU, static_cast<double>(M[q]), mom, s));
-            MLMC_HIP_TRY(hipMemcpyAsync(h, mom, sizeof h, hipMemcpyDeviceToHost, s));
+            void *pin = nullptr;
+            if ((r2 = plan_pinned(p, sizeof h, &pin))) return r2;
+            MLMC_HIP_TRY(hipMemcpyAsync(pin, mom, sizeof h, hipMemcpyDeviceToHost, s));
             MLMC_HIP_TRY(hipStreamSynchronize(s));
+            std::memcpy(h, pin, sizeof h);
         }
         V[q] = unbiased_var(h[1] / nn, M[q]);        // mean over the entries of the per-walk variance
         rms[q] = debiased_rms(h[0] / nn, V[q], M[q]);  // root mean square of the level term
