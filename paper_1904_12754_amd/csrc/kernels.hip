@@ -38,7 +38,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // gathers and long-latency instructions more than it issues, so more resident waves run it
 // faster even at the price of spilled registers: with FP32 weights seven on the coarsest
 // level (72 VGPRs, 26 spilled) and six above it (80, 21 spilled), five under a proposal or
-// with a source term (96, 4 and 10 spilled). With FP64 weights three run faster than two.
+// with a source term (96, 4 and 10 spilled; under a proposal at the coarsest level 94, none
+// spilled, where six waves spill 9 and ran slower). With FP64 weights three run faster than
+// two.
 template <typename R, bool kIS, bool kSrc, bool kBase>
 constexpr int walk_min_waves()
 {
@@ -388,8 +390,8 @@ hipError_t launch_level_walks(const LevelArgs &L, Prec prec, const void *u, int 
             hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, true, false>), grid, block, 0, s, \
                                L, static_cast<const U *>(u), rows, nr, walk0, M, chunk,       \
                                chunks, lpr, out, counters, hash_sums);                        \
-        else if (nrhs == 1 && !(IS) && L.base)   /* the base level, compiled as such */      \
-            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false, !(IS)>), grid, block, 0,   \
+        else if (nrhs == 1 && L.base)   /* the base level, compiled as such */               \
+            hipLaunchKernelGGL((level_walks_r1<R, U, H, IS, false, true>), grid, block, 0,    \
                                s, L, static_cast<const U *>(u), rows, nr, walk0, M, chunk,    \
                                chunks, lpr, out, counters, hash_sums);                        \
         else if (nrhs == 1)                                                                   \
