@@ -58,12 +58,14 @@ BYTES_PER_JUMP = 40
 # HBM traffic of the walk kernel from the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
 # plain copy), recorded with the hash of the kernel source it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_traffic.json")
+# the walk kernel's sources and the build script that holds its compiler flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1904_12754_amd", "csrc", f)
-                  for f in ("kernels.hip", "walk_engine.h", "common.h", "kernels.h")]
+                  for f in ("kernels.hip", "walk_engine.h", "common.h", "kernels.h")] + [
+                      os.path.join(ROOT, "paper_1904_12754_amd", "build.py")]
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of the sources the walk kernel is compiled from."""
+    """Hash of the sources the walk kernel is compiled from and of its build flags."""
     import hashlib
 
     h = hashlib.sha256()

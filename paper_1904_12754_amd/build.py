@@ -23,8 +23,16 @@ OBJDIR = os.path.join(ROOT, "_build", "obj")
 SOURCES = ["kernels.hip", "abi.hip", "batch.hip", "proposal.hip", "functional.hip", "probe.hip"]
 ARCH = os.environ.get("MLMC_OFFLOAD_ARCH", "gfx950")
 
+# The machine scheduler's max-ilp strategy: the walk loops wait on dependent gathers and
+# long-latency instructions, and interleaving independent work serves them better than the
+# default occupancy-driven schedule: the coarsest-level walk kernel spills 18 VGPRs instead
+# of 26, and the plain solve to RMSE 1e-3 on a 128^3 convection-diffusion operator (20 walks
+# per row at the coarsest level) measured 20 % faster, the other workloads level or
+# slightly faster. Scheduling reorders instructions and changes no rounding, so paths and
+# sums are unchanged.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-sched-strategy=max-ilp",
          f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function"]
 
 
